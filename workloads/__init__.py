@@ -1,0 +1,159 @@
+"""Seeded synthetic inputs shared by the oracle, the tests and the benchmark.
+
+This module only builds inputs: closed triangle meshes (icosahedral and
+octahedral spheres, ellipsoids), incidence directions and seeded random
+density vectors.  It contains none of the boundary-element arithmetic, so the
+oracle and the GPU path can both draw their inputs from here without sharing
+any of the method.
+
+Conventions
+-----------
+* Meshes are returned as ``(V, T)`` with ``V`` a float64 ``(nv, 3)`` array of
+  vertex coordinates and ``T`` an int32 ``(nt, 3)`` array of vertex indices.
+* Every triangle is wound counter-clockwise when seen from outside the body,
+  so ``(v1 - v0) x (v2 - v0)`` points out of the body into the fluid.
+"""
+from __future__ import annotations
+
+import math
+from typing import Dict, Tuple
+
+import numpy as np
+
+__all__ = [
+    "icosphere",
+    "octasphere",
+    "ellipsoid",
+    "fibonacci_directions",
+    "complex_normal",
+    "orient_outward",
+    "workload",
+    "WORKLOADS",
+]
+
+
+def orient_outward(V: np.ndarray, T: np.ndarray) -> np.ndarray:
+    """Flip triangles of a star-shaped (about the origin) closed mesh so that
+    their right-hand normals point away from the origin."""
+    T = np.array(T, dtype=np.int32, copy=True)
+    a, b, c = V[T[:, 0]], V[T[:, 1]], V[T[:, 2]]
+    nrm = np.cross(b - a, c - a)
+    flip = np.einsum("ij,ij->i", nrm, (a + b + c) / 3.0) < 0
+    T[flip, 1], T[flip, 2] = T[flip, 2].copy(), T[flip, 1].copy()
+    return T
+
+
+def _faces_from_edge_length(V: np.ndarray, edge: float) -> np.ndarray:
+    """All vertex triples whose three pairwise distances equal ``edge``
+    (the faces of a regular polyhedron)."""
+    n = len(V)
+    d = np.linalg.norm(V[:, None, :] - V[None, :, :], axis=-1)
+    adj = np.abs(d - edge) < 1e-9
+    faces = []
+    for i in range(n):
+        for j in range(i + 1, n):
+            if not adj[i, j]:
+                continue
+            for k in range(j + 1, n):
+                if adj[i, k] and adj[j, k]:
+                    faces.append((i, j, k))
+    return np.array(faces, dtype=np.int32)
+
+
+def _subdivide(V: np.ndarray, T: np.ndarray, levels: int, radius: float):
+    """Midpoint subdivision; every new vertex is pushed onto the sphere."""
+    verts = [tuple(v) for v in V]
+    tris = [tuple(t) for t in T]
+    for _ in range(levels):
+        cache: Dict[Tuple[int, int], int] = {}
+
+        def mid(i: int, j: int) -> int:
+            key = (i, j) if i < j else (j, i)
+            m = cache.get(key)
+            if m is None:
+                p = np.add(verts[i], verts[j]) * 0.5
+                p = p * (radius / np.linalg.norm(p))
+                verts.append(tuple(p))
+                m = len(verts) - 1
+                cache[key] = m
+            return m
+
+        new = []
+        for a, b, c in tris:
+            ab, bc, ca = mid(a, b), mid(b, c), mid(c, a)
+            new += [(a, ab, ca), (b, bc, ab), (c, ca, bc), (ab, bc, ca)]
+        tris = new
+    return np.array(verts, dtype=np.float64), np.array(tris, dtype=np.int32)
+
+
+def icosphere(subdiv: int, radius: float = 0.5):
+    """Icosahedral sphere: 20 * 4**subdiv flat triangles, 10 * 4**subdiv + 2
+    vertices, all vertices on the sphere of the given radius."""
+    phi = (1.0 + math.sqrt(5.0)) / 2.0
+    base = []
+    for s1 in (-1.0, 1.0):
+        for s2 in (-1.0, 1.0):
+            base += [(0.0, s1, s2 * phi), (s1, s2 * phi, 0.0), (s2 * phi, 0.0, s1)]
+    V = np.array(base, dtype=np.float64)
+    T = _faces_from_edge_length(V, 2.0)
+    V = V * (radius / np.linalg.norm(V[0]))
+    T = orient_outward(V, T)
+    V, T = _subdivide(V, T, subdiv, radius)
+    return V, orient_outward(V, T)
+
+
+def octasphere(subdiv: int, radius: float = 1.0):
+    """Octahedral sphere: 8 * 4**subdiv flat triangles (512, 2048, 8192 for
+    subdiv 3, 4, 5)."""
+    V = np.array([[1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1]],
+                 dtype=np.float64)
+    T = _faces_from_edge_length(V, math.sqrt(2.0))
+    V = V * radius
+    T = orient_outward(V, T)
+    V, T = _subdivide(V, T, subdiv, radius)
+    return V, orient_outward(V, T)
+
+
+def ellipsoid(subdiv: int, semi_axes=(0.5, 0.5, 0.5)):
+    """Ellipsoid meshed as a unit icosphere scaled along x, y, z.  Positive
+    scaling keeps the outward winding."""
+    V, T = icosphere(subdiv, 1.0)
+    return V * np.asarray(semi_axes, dtype=np.float64)[None, :], T
+
+
+def fibonacci_directions(n: int) -> np.ndarray:
+    """n unit vectors on a Fibonacci sphere: z_j = 1 - (2j+1)/n,
+    azimuth_j = j * pi * (3 - sqrt(5))."""
+    j = np.arange(n, dtype=np.float64)
+    z = 1.0 - (2.0 * j + 1.0) / n
+    ph = j * math.pi * (3.0 - math.sqrt(5.0))
+    s = np.sqrt(np.maximum(0.0, 1.0 - z * z))
+    return np.stack([s * np.cos(ph), s * np.sin(ph), z], axis=1)
+
+
+def complex_normal(n: int, nrhs: int = 1, seed: int = 0) -> np.ndarray:
+    """Complex standard normal samples (E|x|^2 = 1), shape (n,) or (n, nrhs),
+    from numpy's default_rng(seed)."""
+    rng = np.random.default_rng(seed)
+    shape = (n,) if nrhs == 1 else (n, nrhs)
+    return (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) / math.sqrt(2.0)
+
+
+# Named synthetic workloads.  A rigid sphere of diameter D = 1 (radius 0.5)
+# meshed as an icosphere, a unit plane wave along +z, Burton-Miller coupling
+# alpha = i/k, compression threshold eps = 1e-4, at most 64 elements per leaf,
+# GMRES(50) to a relative residual of 1e-5.
+WORKLOADS = {
+    "sphere1280_kD10": dict(subdiv=3, radius=0.5, k=10.0, eps=1e-4, direction=(0.0, 0.0, 1.0)),
+    "sphere81920_kD100": dict(subdiv=6, radius=0.5, k=100.0, eps=1e-4, direction=(0.0, 0.0, 1.0)),
+    "sphere5120_kD20": dict(subdiv=4, radius=0.5, k=20.0, eps=1e-4, direction=(0.0, 0.0, 1.0)),
+    "sphere20480_kD50": dict(subdiv=5, radius=0.5, k=50.0, eps=1e-4, direction=(0.0, 0.0, 1.0)),
+    "sphere20480_kD100": dict(subdiv=5, radius=0.5, k=100.0, eps=1e-4, direction=(0.0, 0.0, 1.0)),
+}
+
+
+def workload(name: str):
+    """Return (V, T, params) for a named workload."""
+    p = dict(WORKLOADS[name])
+    V, T = icosphere(p["subdiv"], p["radius"])
+    return V, T, p
