@@ -1,0 +1,182 @@
+/*
+ * fda.h -- C ABI of the MI355X fast directional BEM library (libfda.so).
+ *
+ * The library applies and solves the collocation Burton-Miller system of a
+ * rigid (sound-hard) closed surface meshed with flat triangles and
+ * piecewise-constant elements (Cao, Wen, Xiao, "A fast directional boundary
+ * element method for high frequency acoustic problems in three dimensions",
+ * Section 2 eqs. (eq_bm), (eq_sum) and Section 5):
+ *
+ *   (A u)_i = u_i / 2 + sum_j int_{D_j} [ dG/dn_y + alpha d2G/dn_x dn_y ](c_i, y) dy u_j
+ *
+ * with G = exp(ikR)/(4 pi R), c_i the centroid of triangle i and n the normal
+ * pointing into the body (the triangles are wound counter-clockwise seen from
+ * the fluid).  Far interactions are evaluated by the fast directional
+ * algorithm of Section 3 (upward pass, M2L, downward pass, near field;
+ * Algorithm, Steps 1-4) with the compressed translations of Section 4
+ * (eqs. (eq_svdg)-(eq_cmpm2l), (eq_epsk) and the compressed S2M, M2M, L2L,
+ * L2T matrices of Section 4.3).
+ *
+ * Conventions for every entry point:
+ *   - Return 0 on success, a negative FDA_E* code on error, or (bm_solve
+ *     only) the positive FDA_NOTCONV.  fda_last_error() then returns a
+ *     thread-local message describing the failure.
+ *   - Complex vectors are complex128, interleaved (re, im), column-major
+ *     with leading dimension ld >= N (in elements), in the caller's element
+ *     order (the library permutes internally).
+ *   - Pointers named *_dev are device pointers on the plan's device; all
+ *     other pointers are host pointers.  The library never takes ownership
+ *     of caller buffers.
+ *   - stream is a hipStream_t passed as void* (NULL = the default stream).
+ *   - Every entry point needs the GPU except fda_inspect and the two
+ *     version / error helpers.
+ */
+#ifndef FDA_H
+#define FDA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FDA_OK 0
+#define FDA_EINVAL (-1)      /* bad argument: non-finite, k <= 0, eps outside (0,1), nrhs out of range */
+#define FDA_EMESH (-2)       /* zero-area triangle or vertex index out of range */
+#define FDA_ENOMEM (-3)      /* host or device allocation failed */
+#define FDA_EHIP (-4)        /* a HIP / rocBLAS call failed */
+#define FDA_EBREAKDOWN (-5)  /* GMRES breakdown or a non-finite value */
+#define FDA_NOTCONV 1        /* bm_solve: maximum iterations reached (x holds the best iterate) */
+
+/* Precision of the far-field translations and the near-field product. */
+#define FDA_PREC_FP64 0
+#define FDA_PREC_FP32 1
+
+/* Preconditioners for bm_solve. */
+#define FDA_PRECOND_NONE 0
+#define FDA_PRECOND_BLOCK_JACOBI 1
+
+typedef struct fda_plan fda_plan;
+
+/* Build options.  Zero-initialise and call fda_default_options(), then
+ * override fields.  Every field has a documented default. */
+typedef struct fda_options {
+    int32_t max_leaf;      /* leaf capacity (elements per leaf box), default 64 */
+    int32_t p_min;         /* smallest points per cube edge; 0 = ceil(log10(1/eps)) + p0 (Section 5.1) */
+    int32_t p0;            /* the paper's p0, default 1 */
+    double svd_eps;        /* SVD truncation threshold (eqs. (eq_epsg), (eq_epsk)); 0 = eps / 10 */
+    double alpha_re;       /* Burton-Miller coupling; alpha_re = alpha_im = 0 selects i/k */
+    double alpha_im;
+    double hf_wavelengths; /* a box is high-frequency (directional) when its width >= this many
+                              wavelengths, default 1.9 */
+    double rho_c;          /* high-frequency far distance max(2w, rho_c w^2 / lambda), default 1 */
+    double leaf_min_h;     /* leaves are at least this many largest-edges wide, default 2.5 */
+    int32_t prec;          /* FDA_PREC_FP64 (default) or FDA_PREC_FP32 */
+    int32_t nrhs_max;      /* largest nrhs accepted by fda_matvec / bm_solve, default 64 */
+    int32_t device;        /* HIP device ordinal, default 0 */
+    int32_t verbose;       /* print build statistics to stderr, default 0 */
+} fda_options;
+
+/* Plan statistics (filled by fda_inspect / fda_plan_stats). */
+typedef struct fda_stats {
+    int64_t n;                  /* triangles */
+    int32_t depth;              /* leaf level */
+    int32_t top_level;          /* coarsest level with interactions */
+    int64_t nleaf;              /* non-empty leaves */
+    int32_t max_leaf_count;     /* most elements in one leaf */
+    int64_t near_nnz;           /* entries of the near-field block matrix */
+    int64_t boxes[24];          /* non-empty boxes per level */
+    int64_t m2l_pairs[24];      /* interaction-list (target, source) pairs per level */
+    int64_t m2l_offsets[24];    /* distinct translations per level */
+    int32_t hf[24];             /* 1 if the level is directional */
+    int32_t ndir[24];           /* directions per level (0 for non-directional) */
+    int32_t active_dirs[24];    /* directions that carry data */
+    int32_t p[24];              /* points per cube edge per level */
+    int32_t rank_up[24];        /* outgoing compressed rank per level (max over directions) */
+    int32_t rank_dn[24];        /* incoming compressed rank per level */
+    int64_t m2l_flops;          /* real flops of one M2L pass per right-hand side */
+    int64_t m2l_bytes;          /* bytes of the distinct reduced M2L matrices */
+    double h_max;               /* largest mesh edge */
+    double root_width;
+    double build_seconds;       /* wall time of the last build (0 for fda_inspect) */
+    int64_t device_bytes;       /* device memory held by the plan */
+} fda_stats;
+
+/* Fill *opt with the defaults listed above. */
+void fda_default_options(fda_options *opt);
+
+/* Build a plan for mesh (verts: nv x 3 doubles, tris: nt x 3 int32, 0-based),
+ * wavenumber k > 0 and compression threshold eps in (0, 1) (Algorithm,
+ * Step 1; Section 4).  opt may be NULL for the defaults.  The mesh is copied;
+ * the plan owns all device memory and is released by fda_free.  Errors:
+ * FDA_EINVAL, FDA_EMESH, FDA_ENOMEM, FDA_EHIP; *out is NULL on error. */
+int fda_build(const double *verts, int64_t nv, const int32_t *tris, int64_t nt, double k, double eps,
+              const fda_options *opt, fda_plan **out);
+
+/* Host-only dry run of fda_build's tree, list and point-set phase (no GPU
+ * needed): fills *st with the counts a build would have.  Same errors. */
+int fda_inspect(const double *verts, int64_t nv, const int32_t *tris, int64_t nt, double k, double eps,
+                const fda_options *opt, fda_stats *st);
+
+/* y = A x for nrhs columns (Algorithm, Steps 2-4: upward pass, M2L,
+ * downward pass, near field).  x_dev, y_dev: N x nrhs complex128 device
+ * buffers with leading dimension ld (elements); x is not modified; x and y
+ * must not overlap.  Asynchronous on stream.  Errors: FDA_EINVAL (nrhs < 1,
+ * nrhs > nrhs_max, ld < N, null pointers), FDA_EHIP. */
+int fda_matvec(fda_plan *plan, const void *x_dev, void *y_dev, int64_t nrhs, int64_t ld, void *stream);
+
+/* Right-hand side of a rigid body under unit plane waves exp(ik d.x):
+ * b_i = u_inc(c_i) + alpha du_inc/dn(c_i) (eq. (eq_bm) with zero Neumann
+ * data).  dirs: nrhs x 3 host doubles (unit vectors); b_dev: N x nrhs
+ * complex128 device buffer, leading dimension ld.  Asynchronous.  Errors:
+ * FDA_EINVAL, FDA_EHIP. */
+int bm_rhs_planewave(fda_plan *plan, const double *dirs, int64_t nrhs, void *b_dev, int64_t ld, void *stream);
+
+/* Per-solve results. */
+typedef struct bm_stats {
+    int32_t iterations;     /* matrix-vector products used (all columns together) */
+    int32_t restarts;
+    double rel_residual;    /* final true relative residual ||b - A x|| / ||b||, worst column */
+    double seconds;         /* wall time of the solve */
+    int32_t col_iterations[64]; /* per-column iterations (first 64 columns) */
+} bm_stats;
+
+/* Solve A x = b by restarted GMRES(restart) from x = 0 (Section 5: GMRES, no
+ * preconditioner in the paper), stopping when the true relative residual of
+ * every column is <= tol or after maxit products.  Arnoldi orthogonalisation
+ * (classical Gram-Schmidt, applied twice), the residual and the Givens
+ * updates are FP64.  precond: FDA_PRECOND_NONE or FDA_PRECOND_BLOCK_JACOBI
+ * (right preconditioning by the inverses of the leaf self-interaction
+ * blocks).  b_dev, x_dev: N x nrhs device buffers, leading dimension ld;
+ * x is overwritten.  Synchronous: returns when the solve is done.  st may be
+ * NULL.  Returns 0 when converged, FDA_NOTCONV when maxit was reached (x is
+ * the last iterate), FDA_EBREAKDOWN on a non-finite value, or FDA_EINVAL /
+ * FDA_ENOMEM / FDA_EHIP. */
+int bm_solve(fda_plan *plan, const void *b_dev, void *x_dev, int64_t nrhs, int64_t ld, double tol, int32_t restart,
+             int32_t maxit, int32_t precond, bm_stats *st, void *stream);
+
+/* Statistics of a built plan. */
+int fda_plan_stats(const fda_plan *plan, fda_stats *st);
+
+/* Timing of the stages of one fda_matvec (milliseconds, measured with HIP
+ * events on the given stream over `reps` back-to-back products of nrhs
+ * columns): out[0] near field, out[1] S2M, out[2] M2M, out[3] M2L, out[4] L2L,
+ * out[5] L2T + permutations, out[6] whole product.  x_dev/y_dev as in
+ * fda_matvec.  Synchronous. */
+int fda_profile_matvec(fda_plan *plan, const void *x_dev, void *y_dev, int64_t nrhs, int64_t ld, int32_t reps,
+                       void *stream, double *out);
+
+/* Release a plan and all its device memory (NULL is allowed). */
+void fda_free(fda_plan *plan);
+
+/* Thread-local description of the last error ("" if none). */
+const char *fda_last_error(void);
+
+/* Library version string. */
+const char *fda_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FDA_H */

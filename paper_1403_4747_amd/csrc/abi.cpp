@@ -1,0 +1,659 @@
+// C ABI of libfda: plan build and upload, matvec, right-hand side, GMRES.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+
+#include "../../include/fda.h"
+#include "dsetup.hpp"
+#include "kernels.hpp"
+#include "operators.hpp"
+#include "plan.hpp"
+
+using namespace fda;
+
+static thread_local std::string g_last_error;
+
+static int fail(int code, const std::string &msg) {
+    g_last_error = msg;
+    return code;
+}
+
+struct fda_plan {
+    HostPlan hp;
+    DevPlan d;
+    int device = 0;
+    std::vector<void *> allocs;      // build-time device allocations
+    int cap_nrhs = 0;                // capacity of the work buffers below
+    double2 *xt = nullptr, *yt = nullptr;
+    std::vector<void *> work;        // per-capacity allocations
+    fda_stats stats{};
+    int64_t device_bytes = 0;
+};
+
+namespace {
+
+struct HipError {
+    hipError_t e;
+    const char *what;
+};
+
+inline void hip_check(hipError_t e, const char *what) {
+    if (e != hipSuccess) throw HipError{e, what};
+}
+
+template <class T>
+T *dalloc(fda_plan *p, size_t count, std::vector<void *> &list) {
+    if (count == 0) count = 1;
+    void *ptr = nullptr;
+    hipError_t e = hipMalloc(&ptr, sizeof(T) * count);
+    if (e != hipSuccess) throw BuildError{FDA_ENOMEM, "hipMalloc of " + std::to_string(sizeof(T) * count) + " bytes failed"};
+    list.push_back(ptr);
+    p->device_bytes += (int64_t)(sizeof(T) * count);
+    return (T *)ptr;
+}
+
+template <class T>
+T *upload(fda_plan *p, const std::vector<T> &v) {
+    T *d = dalloc<T>(p, v.size(), p->allocs);
+    if (!v.empty()) hip_check(hipMemcpy(d, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice), "upload");
+    return d;
+}
+
+double2 *upload_cplx(fda_plan *p, const std::vector<cplx> &v) {
+    double2 *d = dalloc<double2>(p, v.size(), p->allocs);
+    if (!v.empty()) hip_check(hipMemcpy(d, v.data(), sizeof(double2) * v.size(), hipMemcpyHostToDevice), "upload");
+    return d;
+}
+
+void free_work(fda_plan *p) {
+    for (void *q : p->work) hipFree(q);
+    p->work.clear();
+    p->cap_nrhs = 0;
+    p->xt = p->yt = nullptr;
+    for (auto &l : p->d.lv) l.s = l.c = nullptr;
+}
+
+// Work buffers for `nrhs` right-hand sides: tree-order vectors and the
+// per-level outgoing / incoming states.
+void ensure_capacity(fda_plan *p, int nrhs) {
+    if (nrhs <= p->cap_nrhs) return;
+    free_work(p);
+    const int64_t N = p->d.n;
+    p->xt = dalloc<double2>(p, (size_t)N * nrhs, p->work);
+    p->yt = dalloc<double2>(p, (size_t)N * nrhs, p->work);
+    for (int l = p->d.top; l <= p->d.depth && p->d.has_far; ++l) {
+        DevLevel &lv = p->d.lv[l];
+        lv.s = dalloc<double2>(p, (size_t)lv.sstride * nrhs, p->work);
+        lv.c = dalloc<double2>(p, (size_t)lv.cstride * nrhs, p->work);
+    }
+    p->cap_nrhs = nrhs;
+}
+
+void legendre_nodes(int n, double *x, double *w) {
+    // Newton iteration on P_n from Chebyshev-like initial guesses.
+    const double pi = 3.14159265358979323846;
+    for (int i = 0; i < n; ++i) {
+        double z = std::cos(pi * (i + 0.75) / (n + 0.5)), dp = 1;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1, p1 = z;
+            for (int m = 2; m <= n; ++m) {
+                double p2 = ((2 * m - 1) * z * p1 - (m - 1) * p0) / m;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (z * p1 - p0) / (z * z - 1);
+            double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) break;
+        }
+        double p0 = 1, p1 = z;
+        for (int m = 2; m <= n; ++m) {
+            double p2 = ((2 * m - 1) * z * p1 - (m - 1) * p0) / m;
+            p0 = p1;
+            p1 = p2;
+        }
+        dp = n * (z * p1 - p0) / (z * z - 1);
+        x[i] = z;
+        w[i] = 2.0 / ((1 - z * z) * dp * dp);
+    }
+}
+
+void quadrature_constants() {
+    double b[7][3], w[7], gx[32], gw[32];
+    const double s15 = std::sqrt(15.0);
+    const double a1 = (6.0 - s15) / 21.0, a2 = (6.0 + s15) / 21.0;
+    b[0][0] = b[0][1] = b[0][2] = 1.0 / 3.0;
+    w[0] = 9.0 / 40.0;
+    for (int p = 0; p < 3; ++p) {
+        for (int q = 0; q < 3; ++q) {
+            b[1 + p][q] = (q == p) ? 1 - 2 * a1 : a1;
+            b[4 + p][q] = (q == p) ? 1 - 2 * a2 : a2;
+        }
+        w[1 + p] = (155.0 - s15) / 1200.0;
+        w[4 + p] = (155.0 + s15) / 1200.0;
+    }
+    legendre_nodes(32, gx, gw);
+    hip_check(set_quadrature_constants(b, w, gx, gw), "quadrature constants");
+}
+
+void upload_plan(fda_plan *p, const HostOps &ops, DevTranslations &tr) {
+    HostPlan &hp = p->hp;
+    DevPlan &d = p->d;
+    const int L = hp.depth;
+    d.n = hp.n;
+    d.nleaf = (int)hp.lv[L].nbox;
+    d.depth = L;
+    d.top = hp.top;
+    d.max_leaf = hp.max_leaf_count;
+    d.k = hp.k;
+    d.h_max = hp.h_max;
+    d.alpha = make_double2(hp.alpha.real(), hp.alpha.imag());
+    bool any = false;
+    for (int l = hp.top; l <= L; ++l)
+        if (!hp.lv[l].offsets.empty()) any = true;
+    d.has_far = any;
+
+    d.perm = upload(p, hp.perm);
+    d.tri = upload(p, hp.tri);
+    d.cen = upload(p, hp.cen);
+    d.nrm = upload(p, hp.nrm);
+    d.area = upload(p, hp.area);
+    d.leaf_off = upload(p, hp.leaf_off);
+    // near field
+    std::vector<int32_t> nl_off(hp.nf_list_off.begin(), hp.nf_list_off.end());
+    d.nf_list_off = upload(p, nl_off);
+    d.nf_list = upload(p, hp.nf_list);
+    d.nf_blk_off = upload(p, hp.nf_blk_off);
+    d.nf_ncol = upload(p, hp.nf_ncol);
+    std::vector<int64_t> col_off(d.nleaf + 1, 0);
+    std::vector<int32_t> cols, self_col(d.nleaf, 0);
+    int max_ncol = 0;
+    for (int b = 0; b < d.nleaf; ++b) {
+        int c = 0;
+        for (int64_t q = hp.nf_list_off[b]; q < hp.nf_list_off[b + 1]; ++q) {
+            int s = hp.nf_list[q];
+            if (s == b) self_col[b] = c;
+            for (int64_t e = hp.leaf_off[s]; e < hp.leaf_off[s + 1]; ++e) {
+                cols.push_back((int32_t)e);
+                ++c;
+            }
+        }
+        col_off[b + 1] = (int64_t)cols.size();
+        max_ncol = std::max(max_ncol, c);
+    }
+    if ((size_t)max_ncol * sizeof(double2) > 64 * 1024)
+        throw BuildError{FDA_EINVAL, "near-field row too long for one workgroup (lower max_leaf)"};
+    d.max_ncol = max_ncol;
+    d.nf_col_off = upload(p, col_off);
+    d.nf_cols = upload(p, cols);
+    d.nf_self_col = upload(p, self_col);
+    d.nf_vals = dalloc<double2>(p, (size_t)hp.near_nnz, p->allocs);
+    // block-Jacobi storage
+    std::vector<int64_t> bj_off(d.nleaf + 1, 0);
+    for (int b = 0; b < d.nleaf; ++b) {
+        int64_t n = hp.leaf_off[b + 1] - hp.leaf_off[b];
+        bj_off[b + 1] = bj_off[b] + n * n;
+    }
+    d.bj_off = upload(p, bj_off);
+    d.bj_inv = dalloc<double2>(p, (size_t)bj_off[d.nleaf], p->allocs);
+
+    d.lv.assign(L + 1, DevLevel());
+    if (!d.has_far) return;
+    d.S = upload_cplx(p, ops.S);
+    d.T = upload_cplx(p, ops.T);
+    for (int l = hp.top; l <= L; ++l) {
+        const Level &lv = hp.lv[l];
+        DevLevel &dl = d.lv[l];
+        dl.nbox = lv.nbox;
+        dl.nslot = lv.nslot;
+        dl.ku = lv.ku;
+        dl.kd = lv.kd;
+        if (lv.ku > 1024 || lv.kd > 1024) throw BuildError{FDA_EINVAL, "compressed rank above 1024"};
+        dl.sstride = lv.nbox * lv.nslot * (int64_t)lv.ku;
+        dl.cstride = lv.nbox * lv.nslot * (int64_t)lv.kd;
+        dl.K = tr.K[l];
+        // M2L groups: (target box, slot) -> list of (source state, op)
+        std::vector<int32_t> gt, go{0}, ps, po;
+        for (int64_t b = 0; b < lv.nbox; ++b) {
+            const auto &il = lv.il[b];
+            const auto &io = lv.il_ops[b];
+            std::vector<int> idx(il.size());
+            for (size_t q = 0; q < il.size(); ++q) idx[q] = (int)q;
+            auto slot_of = [&](int q) { return lv.hf ? lv.slot_of_dir[lv.offset_dir[io[q]]] : 0; };
+            std::stable_sort(idx.begin(), idx.end(), [&](int a, int c) { return slot_of(a) < slot_of(c); });
+            int cur = -1;
+            for (int q : idx) {
+                int sl = slot_of(q);
+                if (sl != cur) {
+                    if (cur >= 0) go.push_back((int32_t)ps.size());
+                    gt.push_back((int32_t)(b * lv.nslot + sl));
+                    cur = sl;
+                }
+                ps.push_back((int32_t)(il[q] * lv.nslot + sl));
+                po.push_back(io[q]);
+            }
+            if (cur >= 0) go.push_back((int32_t)ps.size());
+        }
+        dl.ngrp = (int)gt.size();
+        dl.npair = (int64_t)ps.size();
+        dl.grp_tgt = upload(p, gt);
+        dl.grp_off = upload(p, go);
+        dl.pr_src = upload(p, ps);
+        dl.pr_op = upload(p, po);
+        if (l > hp.top) {
+            dl.parent = upload(p, lv.parent);
+            dl.octant = upload(p, lv.octant);
+        }
+        if (l < L) {
+            dl.child_begin = upload(p, lv.child_begin);
+            dl.M = tr.M[l];
+            dl.Lo = tr.Lo[l];
+            dl.cslot = upload(p, lv.cslot);
+            dl.l2l_off = upload(p, lv.l2l_off);
+            dl.l2l_src = upload(p, lv.l2l_src);
+        }
+    }
+}
+
+hipStream_t as_stream(void *s) { return (hipStream_t)s; }
+
+}  // namespace
+
+extern "C" {
+
+void fda_default_options(fda_options *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->max_leaf = 64;
+    o->p_min = 0;
+    o->p0 = 1;
+    o->svd_eps = 0.0;
+    o->alpha_re = 0.0;
+    o->alpha_im = 0.0;
+    o->hf_wavelengths = 1.9;
+    o->rho_c = 1.0;
+    o->leaf_min_h = 2.5;
+    o->prec = FDA_PREC_FP64;
+    o->nrhs_max = 64;
+    o->device = 0;
+    o->verbose = 0;
+}
+
+const char *fda_last_error(void) { return g_last_error.c_str(); }
+
+const char *fda_version(void) { return "fda-mi355x 0.1 (gfx950)"; }
+
+int fda_inspect(const double *verts, int64_t nv, const int32_t *tris, int64_t nt, double k, double eps,
+                const fda_options *opt, fda_stats *st) {
+    g_last_error.clear();
+    if (!st) return fail(FDA_EINVAL, "st is NULL");
+    fda_options o;
+    fda_default_options(&o);
+    if (opt) o = *opt;
+    try {
+        HostPlan hp;
+        host_setup(verts, nv, tris, nt, k, eps, o, hp);
+        fill_stats(hp, st);
+    } catch (const BuildError &e) {
+        return fail(e.code, e.msg);
+    } catch (const std::exception &e) {
+        return fail(FDA_ENOMEM, e.what());
+    }
+    return FDA_OK;
+}
+
+int fda_build(const double *verts, int64_t nv, const int32_t *tris, int64_t nt, double k, double eps,
+              const fda_options *opt, fda_plan **out) {
+    g_last_error.clear();
+    if (!out) return fail(FDA_EINVAL, "out is NULL");
+    *out = nullptr;
+    fda_options o;
+    fda_default_options(&o);
+    if (opt) o = *opt;
+    if (o.nrhs_max < 1 || o.nrhs_max > 4096) return fail(FDA_EINVAL, "nrhs_max must be in [1, 4096]");
+    auto t0 = std::chrono::steady_clock::now();
+    std::unique_ptr<fda_plan> p(new fda_plan());
+    p->device = o.device;
+    rocblas_handle rb = nullptr;
+    DevTranslations tr;
+    try {
+        hip_check(hipSetDevice(o.device), "hipSetDevice");
+        host_setup(verts, nv, tris, nt, k, eps, o, p->hp);
+        bool any = false;
+        for (int l = p->hp.top; l <= p->hp.depth; ++l)
+            if (!p->hp.lv[l].offsets.empty()) any = true;
+        if (any) {
+            if (rocblas_create_handle(&rb) != rocblas_status_success) throw BuildError{FDA_EHIP, "rocblas_create_handle failed"};
+            device_factors(p->hp, rb);
+            device_translations(p->hp, rb, tr);
+            p->allocs.insert(p->allocs.end(), tr.allocs.begin(), tr.allocs.end());
+            p->device_bytes += tr.bytes;
+            tr.allocs.clear();
+        }
+        HostOps ops;
+        form_operators(p->hp, ops);
+        quadrature_constants();
+        upload_plan(p.get(), ops, tr);
+        hip_check(launch_near_blocks(p->d, nullptr), "near-field blocks");
+        hip_check(launch_bj_invert(p->d, nullptr), "block-Jacobi inverses");
+        hip_check(hipDeviceSynchronize(), "build synchronize");
+    } catch (const BuildError &e) {
+        for (void *q : tr.allocs) hipFree(q);
+        for (void *q : p->allocs) hipFree(q);
+        if (rb) rocblas_destroy_handle(rb);
+        return fail(e.code, e.msg);
+    } catch (const HipError &e) {
+        for (void *q : tr.allocs) hipFree(q);
+        for (void *q : p->allocs) hipFree(q);
+        if (rb) rocblas_destroy_handle(rb);
+        return fail(FDA_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
+    } catch (const std::bad_alloc &) {
+        for (void *q : tr.allocs) hipFree(q);
+        for (void *q : p->allocs) hipFree(q);
+        if (rb) rocblas_destroy_handle(rb);
+        return fail(FDA_ENOMEM, "host allocation failed");
+    }
+    if (rb) rocblas_destroy_handle(rb);
+    fill_stats(p->hp, &p->stats);
+    p->stats.build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    p->stats.device_bytes = p->device_bytes;
+    *out = p.release();
+    return FDA_OK;
+}
+
+int fda_plan_stats(const fda_plan *plan, fda_stats *st) {
+    if (!plan || !st) return fail(FDA_EINVAL, "NULL argument");
+    *st = plan->stats;
+    st->device_bytes = plan->device_bytes;
+    return FDA_OK;
+}
+
+void fda_free(fda_plan *plan) {
+    if (!plan) return;
+    hipSetDevice(plan->device);
+    free_work(plan);
+    for (void *q : plan->allocs) hipFree(q);
+    delete plan;
+}
+
+int fda_matvec(fda_plan *plan, const void *x_dev, void *y_dev, int64_t nrhs, int64_t ld, void *stream) {
+    g_last_error.clear();
+    if (!plan || !x_dev || !y_dev) return fail(FDA_EINVAL, "NULL argument");
+    if (nrhs < 1 || nrhs > plan->hp.opt.nrhs_max) return fail(FDA_EINVAL, "nrhs out of range");
+    if (ld < plan->d.n) return fail(FDA_EINVAL, "ld < N");
+    try {
+        hip_check(hipSetDevice(plan->device), "hipSetDevice");
+        ensure_capacity(plan, (int)nrhs);
+        hipStream_t st = as_stream(stream);
+        hip_check(launch_permute_in(plan->d, (const double2 *)x_dev, ld, plan->xt, (int)nrhs, st), "permute");
+        hip_check(launch_matvec_tree(plan->d, plan->xt, plan->yt, (int)nrhs, st, nullptr), "matvec");
+        hip_check(launch_permute_out(plan->d, plan->yt, (double2 *)y_dev, ld, (int)nrhs, st), "permute");
+    } catch (const BuildError &e) {
+        return fail(e.code, e.msg);
+    } catch (const HipError &e) {
+        return fail(FDA_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
+    }
+    return FDA_OK;
+}
+
+int fda_profile_matvec(fda_plan *plan, const void *x_dev, void *y_dev, int64_t nrhs, int64_t ld, int32_t reps,
+                       void *stream, double *out) {
+    g_last_error.clear();
+    if (!plan || !x_dev || !y_dev || !out || reps < 1) return fail(FDA_EINVAL, "bad argument");
+    if (nrhs < 1 || nrhs > plan->hp.opt.nrhs_max || ld < plan->d.n) return fail(FDA_EINVAL, "nrhs / ld out of range");
+    hipEvent_t ev[9];
+    for (auto &e : ev) hipEventCreate(&e);
+    int rc = FDA_OK;
+    try {
+        hip_check(hipSetDevice(plan->device), "hipSetDevice");
+        ensure_capacity(plan, (int)nrhs);
+        hipStream_t st = as_stream(stream);
+        for (int q = 0; q < 7; ++q) out[q] = 0;
+        for (int r = 0; r < reps; ++r) {
+            hip_check(hipEventRecord(ev[7], st), "event");
+            hip_check(launch_permute_in(plan->d, (const double2 *)x_dev, ld, plan->xt, (int)nrhs, st), "permute");
+            hip_check(launch_matvec_tree(plan->d, plan->xt, plan->yt, (int)nrhs, st, ev), "matvec");
+            hip_check(launch_permute_out(plan->d, plan->yt, (double2 *)y_dev, ld, (int)nrhs, st), "permute");
+            hip_check(hipEventRecord(ev[8], st), "event");
+            hip_check(hipEventSynchronize(ev[8]), "sync");
+            float ms;
+            for (int q = 0; q < 5; ++q) {
+                hipEventElapsedTime(&ms, ev[q], ev[q + 1]);
+                out[q] += ms;
+            }
+            float a, b;
+            hipEventElapsedTime(&a, ev[7], ev[0]);
+            hipEventElapsedTime(&b, ev[5], ev[8]);
+            out[5] += a + b;
+            hipEventElapsedTime(&ms, ev[7], ev[8]);
+            out[6] += ms;
+        }
+        for (int q = 0; q < 7; ++q) out[q] /= reps;
+    } catch (const HipError &e) {
+        rc = fail(FDA_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
+    } catch (const BuildError &e) {
+        rc = fail(e.code, e.msg);
+    }
+    for (auto &e : ev) hipEventDestroy(e);
+    return rc;
+}
+
+int bm_rhs_planewave(fda_plan *plan, const double *dirs, int64_t nrhs, void *b_dev, int64_t ld, void *stream) {
+    g_last_error.clear();
+    if (!plan || !dirs || !b_dev) return fail(FDA_EINVAL, "NULL argument");
+    if (nrhs < 1 || ld < plan->d.n) return fail(FDA_EINVAL, "nrhs / ld out of range");
+    for (int64_t i = 0; i < 3 * nrhs; ++i)
+        if (!std::isfinite(dirs[i])) return fail(FDA_EINVAL, "non-finite direction");
+    double *dd = nullptr;
+    try {
+        hip_check(hipSetDevice(plan->device), "hipSetDevice");
+        hip_check(hipMalloc(&dd, sizeof(double) * 3 * nrhs), "hipMalloc");
+        hipStream_t st = as_stream(stream);
+        hip_check(hipMemcpyAsync(dd, dirs, sizeof(double) * 3 * nrhs, hipMemcpyHostToDevice, st), "copy");
+        hip_check(launch_rhs_planewave(plan->d, dd, (int)nrhs, (double2 *)b_dev, ld, st), "rhs");
+        hip_check(hipStreamSynchronize(st), "sync");
+    } catch (const HipError &e) {
+        if (dd) hipFree(dd);
+        return fail(FDA_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
+    }
+    hipFree(dd);
+    return FDA_OK;
+}
+
+// ------------------------------------------------------------------ GMRES
+
+int bm_solve(fda_plan *plan, const void *b_dev, void *x_dev, int64_t nrhs, int64_t ld, double tol, int32_t restart,
+             int32_t maxit, int32_t precond, bm_stats *stp, void *stream) {
+    g_last_error.clear();
+    if (!plan || !b_dev || !x_dev) return fail(FDA_EINVAL, "NULL argument");
+    if (nrhs < 1 || nrhs > plan->hp.opt.nrhs_max || ld < plan->d.n) return fail(FDA_EINVAL, "nrhs / ld out of range");
+    if (!(tol > 0) || restart < 1 || restart > 500 || maxit < 1) return fail(FDA_EINVAL, "bad tol / restart / maxit");
+    if (precond != FDA_PRECOND_NONE && precond != FDA_PRECOND_BLOCK_JACOBI) return fail(FDA_EINVAL, "bad precond");
+    auto t0 = std::chrono::steady_clock::now();
+    bm_stats st{};
+    const int nr = (int)nrhs, m = restart;
+    const int64_t N = plan->d.n;
+    hipStream_t s = as_stream(stream);
+    std::vector<void *> tmp;
+    auto talloc = [&](size_t bytes) {
+        void *q = nullptr;
+        if (hipMalloc(&q, bytes) != hipSuccess) throw BuildError{FDA_ENOMEM, "GMRES workspace allocation failed"};
+        tmp.push_back(q);
+        return q;
+    };
+    int rc = FDA_OK;
+    try {
+        hip_check(hipSetDevice(plan->device), "hipSetDevice");
+        ensure_capacity(plan, nr);
+        const size_t vec = sizeof(double2) * (size_t)N * nr;
+        double2 *V = (double2 *)talloc(vec * (m + 1));
+        double2 *w = (double2 *)talloc(vec);
+        double2 *z = (double2 *)talloc(vec);
+        double2 *bt = (double2 *)talloc(vec);
+        double2 *xt = (double2 *)talloc(vec);
+        double2 *r = (double2 *)talloc(vec);
+        double2 *partial = (double2 *)talloc(sizeof(double2) * kRedBlocks * (m + 1) * nr);
+        double2 *hd = (double2 *)talloc(sizeof(double2) * (m + 1) * nr);
+        double2 *h2 = (double2 *)talloc(sizeof(double2) * (m + 1) * nr);
+        double2 *sc = (double2 *)talloc(sizeof(double2) * nr);
+        int32_t *act_d = (int32_t *)talloc(sizeof(int32_t) * nr);
+        std::vector<int32_t> act(nr, 1);
+
+        auto dots = [&](const double2 *Vb, int mm, const double2 *wv, std::vector<cplx> &outv) {
+            hip_check(launch_multidot(Vb, mm, nr, wv, N, partial, hd, s), "dots");
+            outv.resize((size_t)mm * nr);
+            hip_check(hipMemcpyAsync(outv.data(), hd, sizeof(double2) * mm * nr, hipMemcpyDeviceToHost, s), "d2h");
+            hip_check(hipStreamSynchronize(s), "sync");
+        };
+        auto norms = [&](const double2 *wv, std::vector<double> &nv) {
+            // ||w_c|| via the multidot of w with itself (V = w, m = 1)
+            std::vector<cplx> o;
+            dots(wv, 1, wv, o);
+            nv.resize(nr);
+            for (int c = 0; c < nr; ++c) nv[c] = std::sqrt(std::max(0.0, o[c].real()));
+        };
+        auto apply_A = [&](const double2 *in, double2 *out) {
+            hip_check(launch_matvec_tree(plan->d, in, out, nr, s, nullptr), "matvec");
+        };
+        auto apply_M = [&](const double2 *in, double2 *out) {
+            if (precond == FDA_PRECOND_BLOCK_JACOBI)
+                hip_check(launch_bj_apply(plan->d, in, out, nr, nullptr, s), "precond");
+            else
+                hip_check(hipMemcpyAsync(out, in, vec, hipMemcpyDeviceToDevice, s), "copy");
+        };
+
+        hip_check(launch_permute_in(plan->d, (const double2 *)b_dev, ld, bt, nr, s), "permute");
+        hip_check(launch_fill_zero(xt, (int64_t)N * nr, s), "zero");
+        std::vector<double> bnorm, beta;
+        norms(bt, bnorm);
+        for (int c = 0; c < nr; ++c)
+            if (bnorm[c] == 0) bnorm[c] = 1.0;
+        hip_check(hipMemcpyAsync(r, bt, vec, hipMemcpyDeviceToDevice, s), "copy");
+        int iters = 0;
+        std::vector<int> coliters(nr, 0);
+        double worst = 0;
+        for (;;) {
+            norms(r, beta);
+            worst = 0;
+            bool all = true;
+            for (int c = 0; c < nr; ++c) {
+                double rel = beta[c] / bnorm[c];
+                worst = std::max(worst, rel);
+                act[c] = rel > tol ? 1 : 0;
+                if (act[c]) all = false;
+                if (!std::isfinite(rel)) throw BuildError{FDA_EBREAKDOWN, "non-finite residual"};
+            }
+            if (all) break;
+            if (iters >= maxit) {
+                rc = FDA_NOTCONV;
+                break;
+            }
+            hip_check(hipMemcpyAsync(act_d, act.data(), sizeof(int32_t) * nr, hipMemcpyHostToDevice, s), "h2d");
+            // V_0 = r / beta
+            std::vector<cplx> scl(nr);
+            for (int c = 0; c < nr; ++c) scl[c] = beta[c] > 0 ? 1.0 / beta[c] : 0.0;
+            hip_check(hipMemcpyAsync(sc, scl.data(), sizeof(double2) * nr, hipMemcpyHostToDevice, s), "h2d");
+            hip_check(launch_scale_cols(r, sc, V, N, nr, s), "scale");
+            std::vector<std::vector<cplx>> H(nr, std::vector<cplx>((size_t)(m + 1) * m, 0.0));
+            std::vector<std::vector<cplx>> cs(nr, std::vector<cplx>(m)), sn(nr, std::vector<cplx>(m));
+            std::vector<std::vector<cplx>> g(nr, std::vector<cplx>(m + 1, 0.0));
+            for (int c = 0; c < nr; ++c) g[c][0] = beta[c];
+            int jdone = 0;
+            std::vector<char> done(nr, 0);
+            std::vector<int> jcnt(nr, 0);
+            for (int j = 0; j < m; ++j) {
+                apply_M(V + (size_t)j * N * nr, z);
+                apply_A(z, w);
+                ++iters;
+                // classical Gram-Schmidt, twice
+                std::vector<cplx> h1, h2v;
+                dots(V, j + 1, w, h1);
+                hip_check(launch_multi_axpy(V, j + 1, nr, hd, -1.0, w, N, nullptr, s), "cgs");
+                dots(V, j + 1, w, h2v);
+                hip_check(launch_multi_axpy(V, j + 1, nr, hd, -1.0, w, N, nullptr, s), "cgs");
+                std::vector<double> hn;
+                norms(w, hn);
+                for (int c = 0; c < nr; ++c) scl[c] = hn[c] > 0 ? 1.0 / hn[c] : 0.0;
+                hip_check(hipMemcpyAsync(sc, scl.data(), sizeof(double2) * nr, hipMemcpyHostToDevice, s), "h2d");
+                hip_check(launch_scale_cols(w, sc, V + (size_t)(j + 1) * N * nr, N, nr, s), "scale");
+                bool all_ok = true;
+                for (int c = 0; c < nr; ++c) {
+                    if (!act[c] || done[c]) continue;
+                    coliters[c]++;
+                    jcnt[c] = j + 1;
+                    auto &Hc = H[c];
+                    for (int i = 0; i <= j; ++i) Hc[i + (size_t)j * (m + 1)] = h1[(size_t)c * (j + 1) + i] + h2v[(size_t)c * (j + 1) + i];
+                    Hc[j + 1 + (size_t)j * (m + 1)] = hn[c];
+                    for (int i = 0; i < j; ++i) {
+                        cplx a = Hc[i + (size_t)j * (m + 1)], b = Hc[i + 1 + (size_t)j * (m + 1)];
+                        Hc[i + (size_t)j * (m + 1)] = std::conj(cs[c][i]) * a + std::conj(sn[c][i]) * b;
+                        Hc[i + 1 + (size_t)j * (m + 1)] = -sn[c][i] * a + cs[c][i] * b;
+                    }
+                    cplx a = Hc[j + (size_t)j * (m + 1)], b = Hc[j + 1 + (size_t)j * (m + 1)];
+                    double den = std::sqrt(std::norm(a) + std::norm(b));
+                    if (!std::isfinite(den)) throw BuildError{FDA_EBREAKDOWN, "non-finite Arnoldi value"};
+                    cs[c][j] = den > 0 ? a / den : cplx(1.0);
+                    sn[c][j] = den > 0 ? b / den : cplx(0.0);
+                    Hc[j + (size_t)j * (m + 1)] = den;
+                    Hc[j + 1 + (size_t)j * (m + 1)] = 0.0;
+                    g[c][j + 1] = -sn[c][j] * g[c][j];
+                    g[c][j] = std::conj(cs[c][j]) * g[c][j];
+                    if (std::abs(g[c][j + 1]) / bnorm[c] <= tol || hn[c] == 0.0) done[c] = 1;
+                    if (!done[c]) all_ok = false;
+                }
+                jdone = j + 1;
+                if (all_ok || iters >= maxit) break;
+            }
+            // y = H^-1 g per column, then x += M^-1 V y
+            std::vector<cplx> Y((size_t)(m + 1) * nr, 0.0);
+            for (int c = 0; c < nr; ++c) {
+                if (!act[c]) continue;
+                int jj = jcnt[c];
+                auto &Hc = H[c];
+                for (int i = jj - 1; i >= 0; --i) {
+                    cplx sum = g[c][i];
+                    for (int q = i + 1; q < jj; ++q) sum -= Hc[i + (size_t)q * (m + 1)] * Y[(size_t)c * jdone + q];
+                    Y[(size_t)c * jdone + i] = sum / Hc[i + (size_t)i * (m + 1)];
+                }
+            }
+            hip_check(hipMemcpyAsync(h2, Y.data(), sizeof(double2) * (size_t)jdone * nr, hipMemcpyHostToDevice, s), "h2d");
+            hip_check(launch_fill_zero(w, (int64_t)N * nr, s), "zero");
+            hip_check(launch_multi_axpy(V, jdone, nr, h2, 1.0, w, N, nullptr, s), "update");
+            apply_M(w, z);
+            // x += z on active columns
+            {
+                std::vector<cplx> ones(nr);
+                for (int c = 0; c < nr; ++c) ones[c] = act[c] ? 1.0 : 0.0;
+                hip_check(hipMemcpyAsync(sc, ones.data(), sizeof(double2) * nr, hipMemcpyHostToDevice, s), "h2d");
+                hip_check(launch_multi_axpy(z, 1, nr, sc, 1.0, xt, N, nullptr, s), "x update");
+            }
+            // true residual r = b - A x
+            apply_A(xt, w);
+            hip_check(launch_sub(bt, w, r, (int64_t)N * nr, s), "residual");
+            st.restarts++;
+        }
+        hip_check(launch_permute_out(plan->d, xt, (double2 *)x_dev, ld, nr, s), "permute");
+        hip_check(hipStreamSynchronize(s), "sync");
+        st.iterations = iters;
+        st.rel_residual = worst;
+        for (int c = 0; c < nr && c < 64; ++c) st.col_iterations[c] = coliters[c];
+    } catch (const BuildError &e) {
+        rc = fail(e.code, e.msg);
+    } catch (const HipError &e) {
+        rc = fail(FDA_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
+    }
+    hipStreamSynchronize(s);
+    for (void *q : tmp) hipFree(q);
+    st.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (stp) *stp = st;
+    if (rc == FDA_NOTCONV) g_last_error = "GMRES reached maxit before the tolerance";
+    return rc;
+}
+
+}  // extern "C"

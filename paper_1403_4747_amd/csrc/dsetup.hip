@@ -1,0 +1,382 @@
+// Device part of fda_build: the truncated SVDs of G_up per level and
+// direction (eqs. (eq_svdg), (eq_epsg), (eq_invg); rocSOLVER), and the
+// reduced / compressed translation matrices (eq. (eq_cmpm2l) and the
+// compressed M2M, L2L matrices of Section 4.3), formed as batched products
+// of device-generated kernel matrices (rocBLAS).
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "dsetup.hpp"
+
+namespace fda {
+
+static const double kRin = 1.05, kRout = 2.95;
+static const double kSat = 0.7;
+
+// out[b][i + j m] = G(X_i + t_b, Y_j)
+__global__ void k_green_batched(const double *X, int m, const double *Y, int n, const double *t, double k,
+                                double2 *out) {
+    const int b = blockIdx.y;
+    const int64_t mn = (int64_t)m * n;
+    const double t0 = t[3 * b], t1 = t[3 * b + 1], t2 = t[3 * b + 2];
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < mn; idx += (int64_t)gridDim.x * blockDim.x) {
+        int i = (int)(idx % m), j = (int)(idx / m);
+        double a = X[3 * i] + t0 - Y[3 * j], c = X[3 * i + 1] + t1 - Y[3 * j + 1], d = X[3 * i + 2] + t2 - Y[3 * j + 2];
+        double R = sqrt(a * a + c * c + d * d);
+        double s, cs;
+        sincos(k * R, &s, &cs);
+        double inv = 1.0 / (4.0 * 3.14159265358979323846 * R);
+        out[(int64_t)b * mn + idx] = make_double2(cs * inv, s * inv);
+    }
+}
+
+namespace {
+
+struct Err {
+    int code;
+    std::string msg;
+};
+
+void hchk(hipError_t e, const char *w) {
+    if (e != hipSuccess) throw BuildError{FDA_EHIP, std::string(w) + ": " + hipGetErrorString(e)};
+}
+void rchk(rocblas_status s, const char *w) {
+    if (s != rocblas_status_success) throw BuildError{FDA_EHIP, std::string(w) + ": rocBLAS/rocSOLVER status " + std::to_string((int)s)};
+}
+
+struct DBuf {
+    void *p = nullptr;
+    DBuf() = default;
+    explicit DBuf(size_t bytes) {
+        if (bytes == 0) bytes = 16;
+        if (hipMalloc(&p, bytes) != hipSuccess) throw BuildError{FDA_ENOMEM, "device allocation in build failed"};
+    }
+    ~DBuf() {
+        if (p) hipFree(p);
+    }
+    DBuf(const DBuf &) = delete;
+    DBuf &operator=(const DBuf &) = delete;
+    DBuf(DBuf &&o) noexcept : p(o.p) { o.p = nullptr; }
+    template <class T>
+    T *as() const { return (T *)p; }
+};
+
+template <class T>
+DBuf to_dev(const std::vector<T> &v) {
+    DBuf b(sizeof(T) * std::max<size_t>(1, v.size()));
+    if (!v.empty()) hchk(hipMemcpy(b.p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice), "h2d");
+    return b;
+}
+
+DBuf mat_to_dev(const Mat &M) {
+    DBuf b(sizeof(double2) * std::max<size_t>(1, M.a.size()));
+    hchk(hipMemcpy(b.p, M.a.data(), sizeof(double2) * M.a.size(), hipMemcpyHostToDevice), "h2d");
+    return b;
+}
+
+void green_batched(const DBuf &X, int m, const DBuf &Y, int n, const std::vector<double> &t, double k, double2 *out) {
+    int batch = (int)t.size() / 3;
+    DBuf dt = to_dev(t);
+    int64_t mn = (int64_t)m * n;
+    int gx = (int)std::min<int64_t>((mn + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_green_batched, dim3(gx, batch), dim3(256), 0, nullptr, X.as<double>(), m, Y.as<double>(), n,
+                       dt.as<double>(), k, out);
+    hchk(hipGetLastError(), "green kernel");
+}
+
+std::vector<double> scaled(const std::vector<double> &P, double s) {
+    std::vector<double> o(P);
+    for (auto &v : o) v *= s;
+    return o;
+}
+
+void rot_to(const double *u, double R[9]) {
+    double c = u[2];
+    double v[3] = {-u[1], u[0], 0.0};
+    double vn = std::sqrt(v[0] * v[0] + v[1] * v[1]);
+    if (vn < 1e-14) {
+        double s = c > 0 ? 1.0 : -1.0;
+        double I[9] = {1, 0, 0, 0, s, 0, 0, 0, s};
+        std::memcpy(R, I, sizeof(I));
+        return;
+    }
+    double V[9] = {0, -v[2], v[1], v[2], 0, -v[0], -v[1], v[0], 0};
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double s = 0;
+            for (int q = 0; q < 3; ++q) s += V[3 * i + q] * V[3 * q + j];
+            R[3 * i + j] = (i == j ? 1.0 : 0.0) + V[3 * i + j] + s / (1.0 + c);
+        }
+}
+
+std::vector<double> rotated(const std::vector<double> &P, const double *u, double sign) {
+    double R[9];
+    rot_to(u, R);
+    std::vector<double> o(P.size());
+    for (size_t i = 0; i < P.size() / 3; ++i)
+        for (int a = 0; a < 3; ++a)
+            o[3 * i + a] = sign * (R[3 * a] * P[3 * i] + R[3 * a + 1] * P[3 * i + 1] + R[3 * a + 2] * P[3 * i + 2]);
+    return o;
+}
+
+// Outgoing check points of a level / slot, relative to the box centre.
+std::vector<double> out_check(const Level &lv, int slot) {
+    if (!lv.hf) return scaled(lv.cube, kRout * lv.r);
+    return rotated(lv.far, &lv.dirvec[3 * lv.active[slot]], 1.0);
+}
+// Incoming equivalent points.
+std::vector<double> in_equiv(const Level &lv, int slot) {
+    if (!lv.hf) return scaled(lv.cube, kRout * lv.r);
+    return rotated(lv.far, &lv.dirvec[3 * lv.active[slot]], -1.0);
+}
+
+std::vector<double> cube_points(int p) {
+    std::vector<double> out;
+    for (int i = 0; i < p; ++i)
+        for (int j = 0; j < p; ++j)
+            for (int k = 0; k < p; ++k)
+                if (i == 0 || j == 0 || k == 0 || i == p - 1 || j == p - 1 || k == p - 1) {
+                    out.push_back(-1.0 + 2.0 * i / (p - 1));
+                    out.push_back(-1.0 + 2.0 * j / (p - 1));
+                    out.push_back(-1.0 + 2.0 * k / (p - 1));
+                }
+    return out;
+}
+
+// Batched SVD of `batch` m x n matrices (m >= n) stored contiguously in A
+// (destroyed).  Returns host copies of S (batch x n), U (batch x m x n) and
+// V^H (batch x n x n).
+void svd_batched(rocblas_handle h, double2 *A, int m, int n, int batch, std::vector<double> &S,
+                 std::vector<cplx> &U, std::vector<cplx> &Vh) {
+    DBuf dS(sizeof(double) * (size_t)batch * n), dU(sizeof(double2) * (size_t)batch * m * n),
+        dV(sizeof(double2) * (size_t)batch * n * n), dE(sizeof(double) * (size_t)batch * n),
+        dinfo(sizeof(rocblas_int) * batch);
+    rchk(rocsolver_zgesvd_strided_batched(h, rocblas_svect_singular, rocblas_svect_singular, m, n,
+                                          (rocblas_double_complex *)A, m, (rocblas_stride)m * n, dS.as<double>(), n,
+                                          dU.as<rocblas_double_complex>(), m, (rocblas_stride)m * n,
+                                          dV.as<rocblas_double_complex>(), n, (rocblas_stride)n * n, dE.as<double>(),
+                                          n, rocblas_outofplace, dinfo.as<rocblas_int>(), batch),
+         "zgesvd");
+    S.resize((size_t)batch * n);
+    U.resize((size_t)batch * m * n);
+    Vh.resize((size_t)batch * n * n);
+    std::vector<rocblas_int> info(batch);
+    hchk(hipMemcpy(S.data(), dS.p, sizeof(double) * S.size(), hipMemcpyDeviceToHost), "d2h");
+    hchk(hipMemcpy(U.data(), dU.p, sizeof(double2) * U.size(), hipMemcpyDeviceToHost), "d2h");
+    hchk(hipMemcpy(Vh.data(), dV.p, sizeof(double2) * Vh.size(), hipMemcpyDeviceToHost), "d2h");
+    hchk(hipMemcpy(info.data(), dinfo.p, sizeof(rocblas_int) * batch, hipMemcpyDeviceToHost), "d2h");
+    for (int b = 0; b < batch; ++b)
+        if (info[b] != 0) throw BuildError{FDA_EHIP, "SVD did not converge"};
+}
+
+int trunc_rank(const double *s, int n, double eps) {
+    int r = 0;
+    while (r < n && s[r] >= eps * s[0]) ++r;
+    return std::max(r, 1);
+}
+
+// C_b = op(A) * B_b (+ strides), complex double, column-major.
+void zgemm_sb(rocblas_handle h, rocblas_operation ta, int m, int n, int kk, const double2 *A, int lda,
+              int64_t sa, const double2 *B, int ldb, int64_t sb, double2 *C, int ldc, int64_t sc, int batch) {
+    rocblas_double_complex one = {1.0, 0.0}, zero = {0.0, 0.0};
+    rchk(rocblas_zgemm_strided_batched(h, ta, rocblas_operation_none, m, n, kk, &one, (const rocblas_double_complex *)A,
+                                       lda, sa, (const rocblas_double_complex *)B, ldb, sb, &zero,
+                                       (rocblas_double_complex *)C, ldc, sc, batch),
+         "zgemm");
+}
+
+// Zero-padded copy of the first `cols` columns of an (m x c) host matrix to
+// (m x padc), optionally scaling column j by 1/s[j].
+Mat padded(const Mat &M, int padc, const std::vector<double> *inv_scale) {
+    Mat P(M.m, padc);
+    for (int j = 0; j < std::min(M.n, padc); ++j)
+        for (int i = 0; i < M.m; ++i) P(i, j) = inv_scale ? M(i, j) / (*inv_scale)[j] : M(i, j);
+    return P;
+}
+
+}  // namespace
+
+void device_factors(HostPlan &hp, rocblas_handle h) {
+    const int L = hp.depth;
+    const double k = hp.k;
+    const int pmin = hp.opt.p_min > 0 ? hp.opt.p_min
+                                      : (int)std::ceil(std::log10(1.0 / hp.eps) - 1e-12) + hp.opt.p0;
+    for (int l = hp.top; l <= L; ++l) {
+        Level &lv = hp.lv[l];
+        // adaptive p: smallest p whose G_up rank stays below kSat of the points
+        int p = std::max(3, pmin);
+        for (;; ++p) {
+            std::vector<double> cube = cube_points(p);
+            int nc = (int)cube.size() / 3;
+            std::vector<double> X = lv.hf ? rotated(lv.far, &lv.dirvec[3 * lv.active[0]], 1.0) : scaled(cube, kRout * lv.r);
+            int m = (int)X.size() / 3;
+            DBuf dX = to_dev(X), dY = to_dev(scaled(cube, kRin * lv.r));
+            DBuf G(sizeof(double2) * (size_t)m * nc);
+            green_batched(dX, m, dY, nc, {0.0, 0.0, 0.0}, k, G.as<double2>());
+            std::vector<double> S;
+            std::vector<cplx> U, Vh;
+            svd_batched(h, G.as<double2>(), m, nc, 1, S, U, Vh);
+            int r = trunc_rank(S.data(), nc, hp.svd_eps);
+            lv.cube = cube;
+            if ((double)r <= kSat * nc || p >= 14) break;
+        }
+        lv.p = p;
+        const int nc = (int)lv.cube.size() / 3;
+        std::vector<int> negp(nc);
+        for (int i = 0; i < nc; ++i) negp[i] = nc - 1 - i;
+        // G_up for every slot, batched
+        std::vector<double> X0 = out_check(lv, 0);
+        const int m = (int)X0.size() / 3;
+        DBuf dY = to_dev(scaled(lv.cube, kRin * lv.r));
+        DBuf G(sizeof(double2) * (size_t)lv.nslot * m * nc);
+        for (int s = 0; s < lv.nslot; ++s) {
+            DBuf dX = to_dev(out_check(lv, s));
+            green_batched(dX, m, dY, nc, {0.0, 0.0, 0.0}, k, G.as<double2>() + (size_t)s * m * nc);
+        }
+        std::vector<double> S;
+        std::vector<cplx> U, Vh;
+        svd_batched(h, G.as<double2>(), m, nc, lv.nslot, S, U, Vh);
+        lv.Uu.assign(lv.nslot, Mat());
+        lv.Vu.assign(lv.nslot, Mat());
+        lv.Ud.assign(lv.nslot, Mat());
+        lv.Vd.assign(lv.nslot, Mat());
+        lv.su.assign(lv.nslot, {});
+        lv.sd.assign(lv.nslot, {});
+        lv.ku_s.assign(lv.nslot, 0);
+        lv.kd_s.assign(lv.nslot, 0);
+        for (int s = 0; s < lv.nslot; ++s) {
+            const double *Ss = S.data() + (size_t)s * nc;
+            int r = trunc_rank(Ss, nc, hp.svd_eps);
+            Mat Uu(m, r), Vu(nc, r), Ud(nc, r), Vd(m, r);
+            const cplx *Us = U.data() + (size_t)s * m * nc;
+            const cplx *Vs = Vh.data() + (size_t)s * nc * nc;  // V^H, n x n column-major
+            for (int j = 0; j < r; ++j) {
+                for (int i = 0; i < m; ++i) Uu(i, j) = Us[i + (size_t)j * m];
+                for (int i = 0; i < nc; ++i) Vu(i, j) = std::conj(Vs[j + (size_t)i * nc]);
+            }
+            // G_dn = Pi G_up^T: U_dn = Pi conj(V_up), V_dn = conj(U_up)
+            for (int j = 0; j < r; ++j) {
+                for (int i = 0; i < nc; ++i) Ud(i, j) = std::conj(Vu(lv.hf ? negp[i] : i, j));
+                for (int i = 0; i < m; ++i) Vd(i, j) = std::conj(Uu(i, j));
+            }
+            lv.Uu[s] = std::move(Uu);
+            lv.Vu[s] = std::move(Vu);
+            lv.Ud[s] = std::move(Ud);
+            lv.Vd[s] = std::move(Vd);
+            lv.su[s].assign(Ss, Ss + r);
+            lv.sd[s] = lv.su[s];
+            lv.ku_s[s] = lv.kd_s[s] = r;
+        }
+        lv.ku = *std::max_element(lv.ku_s.begin(), lv.ku_s.end());
+        lv.kd = lv.ku;
+    }
+}
+
+void device_translations(const HostPlan &hp, rocblas_handle h, DevTranslations &out) {
+    const int L = hp.depth;
+    const double k = hp.k;
+    out.K.assign(L + 1, nullptr);
+    out.M.assign(L + 1, nullptr);
+    out.Lo.assign(L + 1, nullptr);
+    auto keep = [&](size_t bytes) {
+        void *q = nullptr;
+        if (hipMalloc(&q, std::max<size_t>(bytes, 16)) != hipSuccess) throw BuildError{FDA_ENOMEM, "hipMalloc failed"};
+        out.allocs.push_back(q);
+        out.bytes += (int64_t)bytes;
+        return (double2 *)q;
+    };
+    for (int l = hp.top; l <= L; ++l) {
+        const Level &lv = hp.lv[l];
+        const int nc = (int)lv.cube.size() / 3;
+        const size_t ksz = (size_t)lv.kd * lv.ku;
+        double2 *K = keep(sizeof(double2) * lv.offsets.size() * ksz);
+        out.K[l] = K;
+        DBuf dcube = to_dev(scaled(lv.cube, kRin * lv.r));
+        // offsets are numbered slot by slot (host_setup sorts them)
+        size_t o0 = 0;
+        for (int s = 0; s < lv.nslot && o0 < lv.offsets.size(); ++s) {
+            size_t o1 = o0;
+            while (o1 < lv.offsets.size() && (lv.hf ? lv.slot_of_dir[lv.offset_dir[o1]] : 0) == s) ++o1;
+            if (o1 == o0) continue;
+            Mat Vu = padded(lv.Vu[s], lv.ku, nullptr), Ud = padded(lv.Ud[s], lv.kd, nullptr);
+            DBuf dVu = mat_to_dev(Vu), dUd = mat_to_dev(Ud);
+            const size_t chunk = std::max<size_t>(1, (size_t)(1u << 30) / (sizeof(double2) * (size_t)nc * nc));
+            for (size_t c0 = o0; c0 < o1; c0 += chunk) {
+                size_t c1 = std::min(o1, c0 + chunk);
+                int batch = (int)(c1 - c0);
+                std::vector<double> t(3 * batch);
+                for (int b = 0; b < batch; ++b)
+                    for (int q = 0; q < 3; ++q) t[3 * b + q] = lv.offsets[c0 + b][q] * lv.w;
+                DBuf Gd(sizeof(double2) * (size_t)batch * nc * nc), W(sizeof(double2) * (size_t)batch * nc * lv.ku);
+                green_batched(dcube, nc, dcube, nc, t, k, Gd.as<double2>());
+                zgemm_sb(h, rocblas_operation_none, nc, lv.ku, nc, Gd.as<double2>(), nc, (int64_t)nc * nc,
+                         dVu.as<double2>(), nc, 0, W.as<double2>(), nc, (int64_t)nc * lv.ku, batch);
+                zgemm_sb(h, rocblas_operation_conjugate_transpose, lv.kd, lv.ku, nc, dUd.as<double2>(), nc, 0,
+                         W.as<double2>(), nc, (int64_t)nc * lv.ku, K + c0 * ksz, lv.kd, (int64_t)ksz, batch);
+                hchk(hipDeviceSynchronize(), "K batch");
+            }
+            o0 = o1;
+        }
+    }
+    // M2M and L2L towards each child level
+    for (int l = hp.top; l < L; ++l) {
+        const Level &P = hp.lv[l], &C = hp.lv[l + 1];
+        const int ncC = (int)C.cube.size() / 3;
+        const size_t msz = (size_t)P.ku * C.ku, lsz = (size_t)C.kd * P.kd;
+        double2 *M = keep(sizeof(double2) * 8 * P.nslot * msz);
+        double2 *Lo = keep(sizeof(double2) * 8 * P.nslot * lsz);
+        out.M[l] = M;
+        out.Lo[l] = Lo;
+        DBuf dcin = to_dev(scaled(C.cube, kRin * C.r));
+        std::vector<double> t(24);
+        for (int o = 0; o < 8; ++o) {
+            t[3 * o] = (o & 4) ? C.r : -C.r;
+            t[3 * o + 1] = (o & 2) ? C.r : -C.r;
+            t[3 * o + 2] = (o & 1) ? C.r : -C.r;
+        }
+        std::vector<double> negt(t);
+        for (auto &v : negt) v = -v;
+        for (int s = 0; s < P.nslot; ++s) {
+            const int cs = hp.cslot_of(l, s);
+            std::vector<double> X = out_check(P, s), Y = in_equiv(P, s);
+            const int nX = (int)X.size() / 3, nY = (int)Y.size() / 3;
+            DBuf dX = to_dev(X), dYp = to_dev(Y);
+            // M~_o = S_P^-1 U_P^H G(X, child equiv + off_o) V_C
+            {
+                Mat Us = padded(P.Uu[s], P.ku, &P.su[s]);  // U S^-1: U^H then carries S^-1
+                Mat Vc = padded(C.Vu[cs], C.ku, nullptr);
+                DBuf dU = mat_to_dev(Us), dV = mat_to_dev(Vc);
+                DBuf E(sizeof(double2) * 8 * (size_t)nX * ncC), W(sizeof(double2) * 8 * (size_t)nX * C.ku);
+                // E_o[i, j] = G(X_i, cin_j + off_o) = G(X_i - off_o, cin_j)
+                green_batched(dX, nX, dcin, ncC, negt, k, E.as<double2>());
+                zgemm_sb(h, rocblas_operation_none, nX, C.ku, ncC, E.as<double2>(), nX, (int64_t)nX * ncC,
+                         dV.as<double2>(), ncC, 0, W.as<double2>(), nX, (int64_t)nX * C.ku, 8);
+                zgemm_sb(h, rocblas_operation_conjugate_transpose, P.ku, C.ku, nX, dU.as<double2>(), nX, 0,
+                         W.as<double2>(), nX, (int64_t)nX * C.ku, M + (size_t)s * msz, P.ku,
+                         (int64_t)P.nslot * msz, 8);
+                hchk(hipDeviceSynchronize(), "M batch");
+            }
+            // L~_o = U_C^H G(child check + off_o, Y) V_dn,P S_P^-1
+            {
+                Mat Vd = padded(P.Vd[s], P.kd, &P.sd[s]);
+                Mat Uc = padded(C.Ud[cs], C.kd, nullptr);
+                DBuf dV = mat_to_dev(Vd), dU = mat_to_dev(Uc);
+                DBuf E(sizeof(double2) * 8 * (size_t)ncC * nY), W(sizeof(double2) * 8 * (size_t)ncC * P.kd);
+                green_batched(dcin, ncC, dYp, nY, t, k, E.as<double2>());
+                zgemm_sb(h, rocblas_operation_none, ncC, P.kd, nY, E.as<double2>(), ncC, (int64_t)ncC * nY,
+                         dV.as<double2>(), nY, 0, W.as<double2>(), ncC, (int64_t)ncC * P.kd, 8);
+                zgemm_sb(h, rocblas_operation_conjugate_transpose, C.kd, P.kd, ncC, dU.as<double2>(), ncC, 0,
+                         W.as<double2>(), ncC, (int64_t)ncC * P.kd, Lo + (size_t)s * lsz, C.kd,
+                         (int64_t)P.nslot * lsz, 8);
+                hchk(hipDeviceSynchronize(), "L batch");
+            }
+        }
+    }
+}
+
+}  // namespace fda

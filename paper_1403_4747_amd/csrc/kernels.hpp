@@ -1,0 +1,71 @@
+// Device-side plan and kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+namespace fda {
+
+struct DevLevel {
+    int64_t nbox = 0;
+    int nslot = 1, ku = 0, kd = 0;
+    int64_t sstride = 0, cstride = 0;  // elements per right-hand side of s and c
+    double2 *s = nullptr, *c = nullptr;
+    // M2L (target-major groups)
+    int ngrp = 0;
+    int64_t npair = 0;
+    int32_t *grp_tgt = nullptr, *grp_off = nullptr, *pr_src = nullptr, *pr_op = nullptr;
+    double2 *K = nullptr;
+    // tree links (this level's boxes)
+    int32_t *parent = nullptr, *octant = nullptr, *child_begin = nullptr;
+    // parent-level operators towards level + 1
+    double2 *M = nullptr, *Lo = nullptr;
+    int32_t *cslot = nullptr, *l2l_off = nullptr, *l2l_src = nullptr;
+};
+
+struct DevPlan {
+    int64_t n = 0;
+    int nleaf = 0, depth = 0, top = 0, max_leaf = 0, max_ncol = 0;
+    bool has_far = false;
+    double k = 0, h_max = 0;
+    double2 alpha;
+    int32_t *perm = nullptr;
+    double *tri = nullptr, *cen = nullptr, *nrm = nullptr, *area = nullptr;
+    int64_t *leaf_off = nullptr;
+    int32_t *nf_list_off = nullptr, *nf_list = nullptr, *nf_ncol = nullptr, *nf_self_col = nullptr, *nf_cols = nullptr;
+    int64_t *nf_blk_off = nullptr, *nf_col_off = nullptr;
+    double2 *nf_vals = nullptr;
+    double2 *S = nullptr, *T = nullptr;
+    std::vector<DevLevel> lv;
+    // block-Jacobi inverses of the leaf diagonal blocks
+    int64_t *bj_off = nullptr;
+    double2 *bj_inv = nullptr;
+};
+
+hipError_t set_quadrature_constants(const double r7b[7][3], const double r7w[7], const double glx[32],
+                                    const double glw[32]);
+hipError_t launch_near_blocks(const DevPlan &d, hipStream_t st);
+hipError_t launch_bj_invert(const DevPlan &d, hipStream_t st);
+hipError_t launch_matvec_tree(const DevPlan &d, const double2 *xt, double2 *yt, int nrhs, hipStream_t st,
+                              hipEvent_t *ev);
+hipError_t launch_permute_in(const DevPlan &d, const double2 *x, int64_t ld, double2 *xt, int nrhs, hipStream_t st);
+hipError_t launch_permute_out(const DevPlan &d, const double2 *yt, double2 *y, int64_t ld, int nrhs, hipStream_t st);
+hipError_t launch_rhs_planewave(const DevPlan &d, const double *dirs_dev, int nrhs, double2 *b, int64_t ld,
+                                hipStream_t st);
+hipError_t launch_multidot(const double2 *V, int m, int nrhs, const double2 *w, int64_t N, double2 *partial,
+                           double2 *out, hipStream_t st);
+hipError_t launch_multi_axpy(const double2 *V, int m, int nrhs, const double2 *h, double sign, double2 *w, int64_t N,
+                             const int32_t *active, hipStream_t st);
+hipError_t launch_scale_cols(const double2 *in, const double2 *scale, double2 *out, int64_t N, int nrhs,
+                             hipStream_t st);
+hipError_t launch_sub(const double2 *b, const double2 *y, double2 *r, int64_t n, hipStream_t st);
+hipError_t launch_bj_apply(const DevPlan &d, const double2 *r, double2 *z, int nrhs, const int32_t *active,
+                           hipStream_t st);
+hipError_t launch_fill_zero(double2 *p, int64_t n, hipStream_t st);
+
+// Blocks used by the two-pass reductions.
+constexpr int kRedBlocks = 240;
+
+}  // namespace fda

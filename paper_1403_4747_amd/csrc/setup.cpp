@@ -1,0 +1,599 @@
+// Host phase of fda_build (Algorithm, Step 1): geometry, octree, near and
+// interaction lists, low/high-frequency regimes, directional cones, the
+// equivalent and check point sets, and the truncated SVDs of G_up / G_dn
+// (Section 4.1.2, eqs. (eq_svdg)-(eq_invg)).
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <map>
+#include <numeric>
+#include <stdexcept>
+
+#include "plan.hpp"
+
+namespace fda {
+
+static const double kPi = 3.14159265358979323846;
+
+// Radial scale factors of the cube-surface point sets relative to the box
+// half width (non-directional levels): outgoing equivalent / incoming check
+// cube just encloses the box; outgoing check / incoming equivalent cube sits
+// just inside the nearest well-separated box (which starts at 3 half widths).
+static const double kRin = 1.05, kRout = 2.95;
+// A point set whose numerical rank exceeds this fraction of its size is
+// treated as under-resolved and p is raised.
+static const double kSat = 0.7;
+static const int kShells = 6, kRings = 8;
+
+cplx green(const double *x, const double *y, double k) {
+    double a = x[0] - y[0], b = x[1] - y[1], c = x[2] - y[2];
+    double R = std::sqrt(a * a + b * b + c * c);
+    return std::exp(cplx(0.0, k * R)) / (4.0 * kPi * R);
+}
+
+// ------------------------------------------------------------- helpers
+
+static uint64_t spread3(uint32_t v) {
+    uint64_t x = v & 0x1fffffu;
+    x = (x | x << 32) & 0x1f00000000ffffULL;
+    x = (x | x << 16) & 0x1f0000ff0000ffULL;
+    x = (x | x << 8) & 0x100f00f00f00f00fULL;
+    x = (x | x << 4) & 0x10c30c30c30c30c3ULL;
+    x = (x | x << 2) & 0x1249249249249249ULL;
+    return x;
+}
+static uint64_t morton(int x, int y, int z) { return spread3(x) << 2 | spread3(y) << 1 | spread3(z); }
+
+// Cube-face cell of a direction vector with n x n cells per face.
+static int dir_index(const double *d, int n) {
+    int a = 0;
+    double m = std::fabs(d[0]);
+    if (std::fabs(d[1]) > m) { a = 1; m = std::fabs(d[1]); }
+    if (std::fabs(d[2]) > m) { a = 2; m = std::fabs(d[2]); }
+    int s = d[a] > 0 ? 1 : 0;
+    int b = (a + 1) % 3, c = (a + 2) % 3;
+    double u = d[b] / m, v = d[c] / m;
+    int i = std::min(n - 1, std::max(0, (int)std::floor((u + 1) * 0.5 * n)));
+    int j = std::min(n - 1, std::max(0, (int)std::floor((v + 1) * 0.5 * n)));
+    return ((a * 2 + s) * n + i) * n + j;
+}
+
+static void dir_vector(int id, int n, double *out) {
+    int j = id % n, i = (id / n) % n, as = id / (n * n);
+    int a = as / 2, s = as % 2;
+    double d[3];
+    d[a] = s ? 1.0 : -1.0;
+    d[(a + 1) % 3] = -1.0 + (2.0 * i + 1.0) / n;
+    d[(a + 2) % 3] = -1.0 + (2.0 * j + 1.0) / n;
+    double l = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    for (int q = 0; q < 3; ++q) out[q] = d[q] / l;
+}
+
+// Rotation taking +z to u (minimal rotation; 180 degrees about x for -z).
+static void rotation_to(const double *u, double R[9]) {
+    double c = u[2];
+    double v[3] = {-u[1], u[0], 0.0};  // z x u
+    double vn = std::sqrt(v[0] * v[0] + v[1] * v[1]);
+    if (vn < 1e-14) {
+        double s = c > 0 ? 1.0 : -1.0;
+        double I[9] = {1, 0, 0, 0, s, 0, 0, 0, s};
+        std::copy(I, I + 9, R);
+        return;
+    }
+    double V[9] = {0, -v[2], v[1], v[2], 0, -v[0], -v[1], v[0], 0};
+    double V2[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double s = 0;
+            for (int q = 0; q < 3; ++q) s += V[3 * i + q] * V[3 * q + j];
+            V2[3 * i + j] = s;
+        }
+    for (int i = 0; i < 9; ++i) R[i] = (i % 4 == 0 ? 1.0 : 0.0) + V[i] + V2[i] / (1.0 + c);
+}
+
+static std::vector<double> cube_points(int p) {
+    std::vector<double> out;
+    for (int i = 0; i < p; ++i)
+        for (int j = 0; j < p; ++j)
+            for (int k = 0; k < p; ++k) {
+                if (i == 0 || j == 0 || k == 0 || i == p - 1 || j == p - 1 || k == p - 1) {
+                    out.push_back(-1.0 + 2.0 * i / (p - 1));
+                    out.push_back(-1.0 + 2.0 * j / (p - 1));
+                    out.push_back(-1.0 + 2.0 * k / (p - 1));
+                }
+            }
+    return out;
+}
+
+// G between point sets: M[i, j] = G(X_i + tx, Y_j).
+static Mat green_matrix(const std::vector<double> &X, const double *tx, const std::vector<double> &Y, double k) {
+    int m = (int)X.size() / 3, n = (int)Y.size() / 3;
+    Mat M(m, n);
+    for (int j = 0; j < n; ++j)
+        for (int i = 0; i < m; ++i) {
+            double x[3] = {X[3 * i] + tx[0], X[3 * i + 1] + tx[1], X[3 * i + 2] + tx[2]};
+            M(i, j) = green(x, &Y[3 * j], k);
+        }
+    return M;
+}
+
+static std::vector<double> scaled(const std::vector<double> &P, double s) {
+    std::vector<double> o(P);
+    for (auto &v : o) v *= s;
+    return o;
+}
+
+static std::vector<double> rotated(const std::vector<double> &P, const double R[9], double sign = 1.0) {
+    std::vector<double> o(P.size());
+    for (size_t i = 0; i < P.size() / 3; ++i)
+        for (int a = 0; a < 3; ++a)
+            o[3 * i + a] = sign * (R[3 * a] * P[3 * i] + R[3 * a + 1] * P[3 * i + 1] + R[3 * a + 2] * P[3 * i + 2]);
+    return o;
+}
+
+// Well-separation test at a level for an integer offset (target - source):
+// not adjacent, and on a directional level at least rho apart.
+static bool well_separated(const Level &L, const int *d) {
+    int m = std::max(std::abs(d[0]), std::max(std::abs(d[1]), std::abs(d[2])));
+    if (m < 2) return false;
+    if (!L.hf) return true;
+    double dist = std::sqrt((double)d[0] * d[0] + (double)d[1] * d[1] + (double)d[2] * d[2]) * L.w;
+    return dist >= L.rho * (1.0 - 1e-12);
+}
+
+static int64_t floordiv2(int64_t a) { return (a >= 0) ? a / 2 : -((-a + 1) / 2); }
+
+// ------------------------------------------------------------- main
+
+void host_setup(const double *V, int64_t nv, const int32_t *T, int64_t nt, double k, double eps,
+                const fda_options &opt, HostPlan &hp) {
+    if (!(k > 0) || !std::isfinite(k)) throw BuildError{FDA_EINVAL, "k must be finite and > 0"};
+    if (!(eps > 0 && eps < 1)) throw BuildError{FDA_EINVAL, "eps must be in (0, 1)"};
+    if (nt <= 0 || nv <= 0 || !V || !T) throw BuildError{FDA_EINVAL, "empty mesh"};
+    if (opt.max_leaf < 1 || opt.max_leaf > 256) throw BuildError{FDA_EINVAL, "max_leaf must be in [1, 256]"};
+    for (int64_t i = 0; i < 3 * nv; ++i)
+        if (!std::isfinite(V[i])) throw BuildError{FDA_EINVAL, "non-finite vertex coordinate"};
+    hp.n = nt;
+    hp.k = k;
+    hp.eps = eps;
+    hp.opt = opt;
+    hp.svd_eps = opt.svd_eps > 0 ? opt.svd_eps : eps / 10.0;
+    hp.alpha = (opt.alpha_re == 0 && opt.alpha_im == 0) ? cplx(0.0, 1.0 / k) : cplx(opt.alpha_re, opt.alpha_im);
+    const double lambda = 2.0 * kPi / k;
+
+    // geometry (caller order)
+    std::vector<double> cen(3 * nt), nrm(3 * nt), area(nt);
+    double h = 0;
+    for (int64_t t = 0; t < nt; ++t) {
+        for (int q = 0; q < 3; ++q)
+            if (T[3 * t + q] < 0 || T[3 * t + q] >= nv) throw BuildError{FDA_EMESH, "vertex index out of range"};
+        const double *a = V + 3 * T[3 * t], *b = V + 3 * T[3 * t + 1], *c = V + 3 * T[3 * t + 2];
+        double e1[3], e2[3], e3[3];
+        for (int q = 0; q < 3; ++q) {
+            e1[q] = b[q] - a[q];
+            e2[q] = c[q] - a[q];
+            e3[q] = c[q] - b[q];
+        }
+        double cr[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+        double ln = std::sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+        if (!(ln > 0)) throw BuildError{FDA_EMESH, "zero-area triangle " + std::to_string(t)};
+        for (int q = 0; q < 3; ++q) {
+            cen[3 * t + q] = (a[q] + b[q] + c[q]) / 3.0;
+            nrm[3 * t + q] = -cr[q] / ln;
+        }
+        area[t] = 0.5 * ln;
+        h = std::max(h, std::sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]));
+        h = std::max(h, std::sqrt(e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2]));
+        h = std::max(h, std::sqrt(e3[0] * e3[0] + e3[1] * e3[1] + e3[2] * e3[2]));
+    }
+    hp.h_max = h;
+
+    // root cube: bounding cube of the vertices, expanded slightly
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int64_t i = 0; i < nv; ++i)
+        for (int q = 0; q < 3; ++q) {
+            lo[q] = std::min(lo[q], V[3 * i + q]);
+            hi[q] = std::max(hi[q], V[3 * i + q]);
+        }
+    double side = std::max(hi[0] - lo[0], std::max(hi[1] - lo[1], hi[2] - lo[2])) * (1.0 + 1e-9);
+    if (!(side > 0)) throw BuildError{FDA_EMESH, "degenerate bounding box"};
+    for (int q = 0; q < 3; ++q) hp.origin[q] = 0.5 * (lo[q] + hi[q]) - 0.5 * side;
+    hp.side = side;
+
+    auto keys_at = [&](int l, int64_t e, int32_t *kk) {
+        double w = side / std::ldexp(1.0, l);
+        int lim = (1 << l) - 1;
+        for (int q = 0; q < 3; ++q) {
+            int v = (int)std::floor((cen[3 * e + q] - hp.origin[q]) / w);
+            kk[q] = std::min(lim, std::max(0, v));
+        }
+    };
+
+    // depth: smallest L with every leaf <= max_leaf, but no leaf narrower
+    // than leaf_min_h * h_max (near-singular pairs must stay in the near field)
+    const double tau = opt.leaf_min_h * h;
+    int L = 0;
+    for (;;) {
+        if (L >= 20) break;
+        double w = side / std::ldexp(1.0, L);
+        if (w * 0.5 < tau) break;
+        std::unordered_map<uint64_t, int> cnt;
+        int mx = 0;
+        for (int64_t e = 0; e < nt; ++e) {
+            int32_t kk[3];
+            keys_at(L, e, kk);
+            mx = std::max(mx, ++cnt[morton(kk[0], kk[1], kk[2])]);
+        }
+        if (mx <= opt.max_leaf) break;
+        ++L;
+    }
+    hp.depth = L;
+    hp.lv.assign(L + 1, Level());
+
+    // boxes per level, Morton ordered
+    std::vector<uint64_t> leafcode(nt);
+    for (int l = 0; l <= L; ++l) {
+        Level &lv = hp.lv[l];
+        lv.w = side / std::ldexp(1.0, l);
+        lv.r = 0.5 * lv.w;
+        std::vector<uint64_t> codes(nt);
+        for (int64_t e = 0; e < nt; ++e) {
+            int32_t kk[3];
+            keys_at(l, e, kk);
+            codes[e] = morton(kk[0], kk[1], kk[2]);
+            if (l == L) leafcode[e] = codes[e];
+        }
+        std::vector<uint64_t> u(codes);
+        std::sort(u.begin(), u.end());
+        u.erase(std::unique(u.begin(), u.end()), u.end());
+        lv.nbox = (int64_t)u.size();
+        lv.key.resize(3 * lv.nbox);
+        for (int64_t b = 0; b < lv.nbox; ++b) {
+            // decode
+            int32_t kk[3] = {0, 0, 0};
+            for (int bit = 0; bit < 21; ++bit) {
+                kk[0] |= (int32_t)((u[b] >> (3 * bit + 2)) & 1) << bit;
+                kk[1] |= (int32_t)((u[b] >> (3 * bit + 1)) & 1) << bit;
+                kk[2] |= (int32_t)((u[b] >> (3 * bit)) & 1) << bit;
+            }
+            for (int q = 0; q < 3; ++q) lv.key[3 * b + q] = kk[q];
+        }
+    }
+    // parents / children (Morton order keeps the children of a box contiguous)
+    for (int l = 1; l <= L; ++l) {
+        Level &lv = hp.lv[l], &pv = hp.lv[l - 1];
+        std::unordered_map<uint64_t, int32_t> pidx;
+        for (int64_t b = 0; b < pv.nbox; ++b) pidx[morton(pv.key[3 * b], pv.key[3 * b + 1], pv.key[3 * b + 2])] = (int32_t)b;
+        lv.parent.resize(lv.nbox);
+        lv.octant.resize(lv.nbox);
+        pv.child_begin.assign(pv.nbox + 1, 0);
+        for (int64_t b = 0; b < lv.nbox; ++b) {
+            const int32_t *kk = &lv.key[3 * b];
+            lv.parent[b] = pidx.at(morton(kk[0] >> 1, kk[1] >> 1, kk[2] >> 1));
+            lv.octant[b] = ((kk[0] & 1) << 2) | ((kk[1] & 1) << 1) | (kk[2] & 1);
+            pv.child_begin[lv.parent[b] + 1]++;
+        }
+        for (int64_t b = 0; b < pv.nbox; ++b) pv.child_begin[b + 1] += pv.child_begin[b];
+    }
+
+    // element permutation: by leaf (Morton), then caller index
+    std::vector<int32_t> perm(nt);
+    std::iota(perm.begin(), perm.end(), 0);
+    std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) { return leafcode[a] < leafcode[b]; });
+    hp.perm = perm;
+    {
+        Level &lf = hp.lv[L];
+        hp.leaf_off.assign(lf.nbox + 1, 0);
+        int64_t b = 0;
+        for (int64_t i = 0; i < nt; ++i) {
+            uint64_t c = leafcode[perm[i]];
+            while (morton(lf.key[3 * b], lf.key[3 * b + 1], lf.key[3 * b + 2]) != c) {
+                hp.leaf_off[++b] = i;
+            }
+        }
+        while (b < lf.nbox) hp.leaf_off[++b] = nt;
+        hp.max_leaf_count = 0;
+        for (int64_t q = 0; q < lf.nbox; ++q)
+            hp.max_leaf_count = std::max<int>(hp.max_leaf_count, (int)(hp.leaf_off[q + 1] - hp.leaf_off[q]));
+    }
+    hp.tri.resize(9 * nt);
+    hp.cen.resize(3 * nt);
+    hp.nrm.resize(3 * nt);
+    hp.area.resize(nt);
+    for (int64_t i = 0; i < nt; ++i) {
+        int64_t e = perm[i];
+        for (int v = 0; v < 3; ++v)
+            for (int q = 0; q < 3; ++q) hp.tri[9 * i + 3 * v + q] = V[3 * T[3 * e + v] + q];
+        for (int q = 0; q < 3; ++q) {
+            hp.cen[3 * i + q] = cen[3 * e + q];
+            hp.nrm[3 * i + q] = nrm[3 * e + q];
+        }
+        hp.area[i] = area[e];
+    }
+
+    // regimes and directions: a level is directional when its boxes are at
+    // least hf_wavelengths wide; directional cells per face edge double per
+    // level upwards, starting from round(w / lambda) at the finest such level
+    int finest_hf = -1;
+    for (int l = 0; l <= L; ++l) {
+        Level &lv = hp.lv[l];
+        lv.hf = lv.w >= opt.hf_wavelengths * lambda * (1.0 - 1e-9) && l > 0;
+        if (lv.hf) finest_hf = l;
+    }
+    if (finest_hf == L && L > 0)
+        throw BuildError{FDA_EINVAL, "leaf boxes are directional (too few elements per wavelength for max_leaf); "
+                                     "raise max_leaf or hf_wavelengths"};
+    if (finest_hf >= 0) {
+        int n0 = std::max(1, (int)std::lround(hp.lv[finest_hf].w / lambda));
+        for (int l = 0; l <= finest_hf; ++l) {
+            Level &lv = hp.lv[l];
+            if (!lv.hf) continue;
+            lv.nface = n0 << (finest_hf - l);
+            lv.ndir = 6 * lv.nface * lv.nface;
+            lv.rho = std::max(2.0 * lv.w, opt.rho_c * lv.w * lv.w / lambda);
+            lv.dirvec.resize(3 * lv.ndir);
+            for (int d = 0; d < lv.ndir; ++d) dir_vector(d, lv.nface, &lv.dirvec[3 * d]);
+        }
+    }
+
+    // near and interaction lists, top-down (Algorithm, Step 1.2-1.5)
+    hp.lv[0].near.assign(1, std::vector<int32_t>{0});
+    hp.lv[0].il.assign(1, {});
+    hp.lv[0].il_ops.assign(1, {});
+    for (int l = 1; l <= L; ++l) {
+        Level &lv = hp.lv[l], &pv = hp.lv[l - 1];
+        lv.near.assign(lv.nbox, {});
+        lv.il.assign(lv.nbox, {});
+        lv.il_ops.assign(lv.nbox, {});
+        std::map<std::array<int32_t, 3>, int32_t> opidx;
+        for (int64_t b = 0; b < lv.nbox; ++b) {
+            int32_t P = lv.parent[b];
+            for (int32_t pn : pv.near[P]) {
+                for (int32_t a = pv.child_begin[pn]; a < pv.child_begin[pn + 1]; ++a) {
+                    int d[3] = {lv.key[3 * b] - lv.key[3 * a], lv.key[3 * b + 1] - lv.key[3 * a + 1],
+                                lv.key[3 * b + 2] - lv.key[3 * a + 2]};
+                    if (well_separated(lv, d)) {
+                        std::array<int32_t, 3> key = {d[0], d[1], d[2]};
+                        auto it = opidx.find(key);
+                        int32_t op;
+                        if (it == opidx.end()) {
+                            op = (int32_t)lv.offsets.size();
+                            opidx[key] = op;
+                            lv.offsets.push_back(key);
+                            if (lv.hf) {
+                                double dv[3] = {(double)d[0], (double)d[1], (double)d[2]};
+                                lv.offset_dir.push_back(dir_index(dv, lv.nface));
+                            } else {
+                                lv.offset_dir.push_back(-1);
+                            }
+                        } else {
+                            op = it->second;
+                        }
+                        lv.il[b].push_back(a);
+                        lv.il_ops[b].push_back(op);
+                    } else {
+                        lv.near[b].push_back(a);
+                    }
+                }
+            }
+        }
+    }
+    hp.top = L;
+    for (int l = 0; l <= L; ++l) {
+        bool any = false;
+        for (auto &x : hp.lv[l].il)
+            if (!x.empty()) { any = true; break; }
+        if (any) { hp.top = l; break; }
+    }
+
+    // near field at the leaves
+    {
+        Level &lf = hp.lv[L];
+        hp.nf_list_off.assign(lf.nbox + 1, 0);
+        hp.nf_blk_off.assign(lf.nbox + 1, 0);
+        hp.nf_ncol.assign(lf.nbox, 0);
+        hp.nf_list.clear();
+        for (int64_t b = 0; b < lf.nbox; ++b) {
+            auto nl = lf.near[b];
+            std::sort(nl.begin(), nl.end());
+            int64_t ncol = 0;
+            for (int32_t s : nl) {
+                hp.nf_list.push_back(s);
+                ncol += hp.leaf_off[s + 1] - hp.leaf_off[s];
+            }
+            hp.nf_list_off[b + 1] = (int64_t)hp.nf_list.size();
+            hp.nf_ncol[b] = (int32_t)ncol;
+            hp.nf_blk_off[b + 1] = hp.nf_blk_off[b] + ncol * (hp.leaf_off[b + 1] - hp.leaf_off[b]);
+        }
+        hp.near_nnz = hp.nf_blk_off[lf.nbox];
+    }
+
+    // active directions, top-down: those used by interaction lists, plus the
+    // child cells of the parent's active directions (needed by M2M / L2L)
+    for (int l = 0; l <= L; ++l) {
+        Level &lv = hp.lv[l];
+        if (!lv.hf) {
+            lv.active = {0};
+            lv.slot_of_dir = {0};
+            lv.nslot = 1;
+            continue;
+        }
+        std::vector<char> used(lv.ndir, 0);
+        for (int32_t op = 0; op < (int32_t)lv.offsets.size(); ++op) used[lv.offset_dir[op]] = 1;
+        if (l > 0 && hp.lv[l - 1].hf && l - 1 >= hp.top) {
+            Level &pv = hp.lv[l - 1];
+            for (int32_t d : pv.active) used[dir_index(&pv.dirvec[3 * d], lv.nface)] = 1;
+        }
+        lv.active.clear();
+        lv.slot_of_dir.assign(lv.ndir, -1);
+        for (int d = 0; d < lv.ndir; ++d)
+            if (used[d]) {
+                lv.slot_of_dir[d] = (int32_t)lv.active.size();
+                lv.active.push_back(d);
+            }
+        lv.nslot = std::max<int>(1, (int)lv.active.size());
+        if (lv.active.empty()) lv.active = {0}, lv.slot_of_dir[0] = 0;
+    }
+
+    // far point sets of the directional levels (top-down), Section 3.1:
+    // a circular cone around +z whose half angle covers every possible
+    // interaction-list target box and the parent's cone, from the nearest
+    // such point to beyond the size of the whole mesh; points are spread on
+    // geometrically spaced shells (denser at the near end).
+    const double tmax = std::sqrt(3.0) * side * 1.05;
+    for (int l = std::max(hp.top, 1); l <= L; ++l) {
+        Level &lv = hp.lv[l];
+        if (!lv.hf) continue;
+        const Level &pv = hp.lv[l - 1];
+        int R = std::min((1 << l) - 1, 24);
+        double th = 0, tm = 1e300;
+        double corner = kRin * lv.r;
+        for (int x = -R; x <= R; ++x)
+            for (int y = -R; y <= R; ++y)
+                for (int z = -R; z <= R; ++z) {
+                    int d[3] = {x, y, z};
+                    if (!well_separated(lv, d)) continue;
+                    bool possible = false;
+                    for (int s = 0; s < 8 && !possible; ++s) {
+                        int sb[3] = {(s >> 2) & 1, (s >> 1) & 1, s & 1};
+                        int dp[3];
+                        for (int q = 0; q < 3; ++q) dp[q] = (int)floordiv2(sb[q] + d[q]);
+                        if (!well_separated(pv, dp)) possible = true;
+                    }
+                    if (!possible) continue;
+                    double dv[3] = {(double)x, (double)y, (double)z};
+                    int di = dir_index(dv, lv.nface);
+                    const double *u = &lv.dirvec[3 * di];
+                    for (int c = 0; c < 8; ++c) {
+                        double P[3] = {x * lv.w + ((c & 4) ? corner : -corner), y * lv.w + ((c & 2) ? corner : -corner),
+                                       z * lv.w + ((c & 1) ? corner : -corner)};
+                        double pn = std::sqrt(P[0] * P[0] + P[1] * P[1] + P[2] * P[2]);
+                        double ca = (P[0] * u[0] + P[1] * u[1] + P[2] * u[2]) / pn;
+                        th = std::max(th, std::acos(std::max(-1.0, std::min(1.0, ca))));
+                        tm = std::min(tm, pn);
+                    }
+                }
+        if (pv.hf && l - 1 >= hp.top && pv.theta > 0) {
+            double off = std::sqrt(3.0) * lv.r;
+            for (int32_t dp : pv.active) {
+                const double *up = &pv.dirvec[3 * dp];
+                const double *uc = &lv.dirvec[3 * dir_index(up, lv.nface)];
+                double ca = up[0] * uc[0] + up[1] * uc[1] + up[2] * uc[2];
+                double a = std::acos(std::max(-1.0, std::min(1.0, ca))) + pv.theta +
+                           std::asin(std::min(1.0, off / pv.tmin));
+                th = std::max(th, a);
+            }
+            tm = std::min(tm, pv.tmin - off);
+        }
+        if (tm == 1e300) { th = 0.5; tm = lv.rho; }
+        if (!(th < 0.95 * kPi) || !(tm > 1.5 * kRin * lv.r * std::sqrt(3.0)))
+            throw BuildError{FDA_EINVAL, "directional cone of level " + std::to_string(l) +
+                                             " is too wide; raise hf_wavelengths or rho_c"};
+        lv.theta = th;
+        lv.tmin = tm;
+        lv.far.clear();
+        for (int si = 0; si < kShells; ++si) {
+            double ts = tm * std::pow(tmax / tm, (double)si / (kShells - 1));
+            for (int a = 0; a < kRings; ++a) {
+                double ta = th * a / (kRings - 1);
+                int m = (a == 0) ? 1 : std::max(1, (int)std::lround(2 * kPi * std::sin(ta) / (th / (kRings - 1))));
+                for (int b = 0; b < m; ++b) {
+                    double ph = 2 * kPi * b / m;
+                    lv.far.push_back(ts * std::sin(ta) * std::cos(ph));
+                    lv.far.push_back(ts * std::sin(ta) * std::sin(ph));
+                    lv.far.push_back(ts * std::cos(ta));
+                }
+            }
+        }
+    }
+
+    // number the distinct offsets of each level slot by slot, so that the
+    // reduced M2L matrices of one direction are contiguous
+    for (int l = 0; l <= L; ++l) {
+        Level &lv = hp.lv[l];
+        const size_t no = lv.offsets.size();
+        if (no == 0) continue;
+        std::vector<int32_t> ord(no);
+        std::iota(ord.begin(), ord.end(), 0);
+        auto slot = [&](int32_t o) { return lv.hf ? lv.slot_of_dir[lv.offset_dir[o]] : 0; };
+        std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) { return slot(a) < slot(b); });
+        std::vector<int32_t> newidx(no);
+        std::vector<std::array<int32_t, 3>> offs(no);
+        std::vector<int32_t> odir(no);
+        for (size_t q = 0; q < no; ++q) {
+            newidx[ord[q]] = (int32_t)q;
+            offs[q] = lv.offsets[ord[q]];
+            odir[q] = lv.offset_dir[ord[q]];
+        }
+        lv.offsets.swap(offs);
+        lv.offset_dir.swap(odir);
+        for (auto &ops : lv.il_ops)
+            for (auto &o : ops) o = newidx[o];
+    }
+
+    // child slot of every slot (M2M source, L2L target) and its inverse
+    for (int l = std::max(hp.top, 0); l < L; ++l) {
+        Level &P = hp.lv[l];
+        const Level &C = hp.lv[l + 1];
+        P.cslot.assign(P.nslot, 0);
+        if (C.hf)
+            for (int s = 0; s < P.nslot; ++s) {
+                int d = dir_index(&P.dirvec[3 * P.active[s]], C.nface);
+                P.cslot[s] = C.slot_of_dir[d];
+                if (P.cslot[s] < 0) throw BuildError{FDA_EINVAL, "internal: inactive child direction"};
+            }
+        P.l2l_off.assign(C.nslot + 1, 0);
+        P.l2l_src.clear();
+        for (int cs = 0; cs < C.nslot; ++cs) {
+            for (int s = 0; s < P.nslot; ++s)
+                if (P.cslot[s] == cs) P.l2l_src.push_back(s);
+            P.l2l_off[cs + 1] = (int32_t)P.l2l_src.size();
+        }
+    }
+
+    if (opt.verbose) {
+        for (int l = 0; l <= L; ++l) {
+            const Level &lv = hp.lv[l];
+            int64_t pairs = 0;
+            for (auto &x : lv.il) pairs += (int64_t)x.size();
+            fprintf(stderr, "[fda] level %d w=%.4g (%.2f lambda) %s boxes=%lld pairs=%lld offsets=%zu dirs=%d/%d p=%d ku=%d theta=%.3f tmin/w=%.3f nfar=%zu\n",
+                    l, lv.w, lv.w / lambda, lv.hf ? "HF" : "LF", (long long)lv.nbox, (long long)pairs, lv.offsets.size(),
+                    lv.hf ? (int)lv.active.size() : 0, lv.ndir, lv.p, lv.ku, lv.theta, lv.tmin / lv.w, lv.far.size() / 3);
+        }
+        fprintf(stderr, "[fda] depth=%d top=%d leaves=%lld max_leaf=%d near_nnz=%lld h_max=%.4g\n", hp.depth, hp.top,
+                (long long)hp.lv[L].nbox, hp.max_leaf_count, (long long)hp.near_nnz, hp.h_max);
+    }
+}
+
+void fill_stats(const HostPlan &hp, fda_stats *st) {
+    std::memset(st, 0, sizeof(*st));
+    st->n = hp.n;
+    st->depth = hp.depth;
+    st->top_level = hp.top;
+    st->nleaf = hp.lv.empty() ? 0 : hp.lv[hp.depth].nbox;
+    st->max_leaf_count = hp.max_leaf_count;
+    st->near_nnz = hp.near_nnz;
+    st->h_max = hp.h_max;
+    st->root_width = hp.side;
+    int64_t flops = 0, bytes = 0;
+    for (int l = 0; l <= hp.depth && l < 24; ++l) {
+        const Level &lv = hp.lv[l];
+        st->boxes[l] = lv.nbox;
+        int64_t pairs = 0;
+        for (auto &x : lv.il) pairs += (int64_t)x.size();
+        st->m2l_pairs[l] = pairs;
+        st->m2l_offsets[l] = (int64_t)lv.offsets.size();
+        st->hf[l] = lv.hf ? 1 : 0;
+        st->ndir[l] = lv.ndir;
+        st->active_dirs[l] = lv.hf ? (int)lv.active.size() : 0;
+        st->p[l] = lv.p;
+        st->rank_up[l] = lv.ku;
+        st->rank_dn[l] = lv.kd;
+        flops += pairs * 8LL * lv.ku * lv.kd;
+        bytes += (int64_t)lv.offsets.size() * 16LL * lv.ku * lv.kd;
+    }
+    st->m2l_flops = flops;
+    st->m2l_bytes = bytes;
+}
+
+}  // namespace fda

@@ -1,0 +1,246 @@
+"""Python binding of libfda (include/fda.h): argument marshalling only.
+
+Every step of the build, matvec and solve runs in the HIP/C++ library; this
+module converts numpy meshes and torch device tensors into pointers and
+sizes.  It raises if the library is missing: there is no fallback path.
+
+Vectors are torch.complex128 device tensors of shape (N,) for one
+right-hand side or (nrhs, N) for several (each row is one column of the
+N x nrhs column-major matrix the C ABI sees), in the caller's element order.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, Optional, Sequence
+
+import numpy as np
+
+__all__ = ["Plan", "inspect", "library", "default_options", "FDAError", "PRECOND", "PREC"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "libfda.so")
+
+PREC = {"fp64": 0, "fp32": 1}
+PRECOND = {"none": 0, "block_jacobi": 1}
+
+FDA_NOTCONV = 1
+
+
+class FDAError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libfda error {code}: {msg}")
+        self.code = code
+
+
+class Options(ctypes.Structure):
+    _fields_ = [
+        ("max_leaf", ctypes.c_int32), ("p_min", ctypes.c_int32), ("p0", ctypes.c_int32),
+        ("svd_eps", ctypes.c_double), ("alpha_re", ctypes.c_double), ("alpha_im", ctypes.c_double),
+        ("hf_wavelengths", ctypes.c_double), ("rho_c", ctypes.c_double), ("leaf_min_h", ctypes.c_double),
+        ("prec", ctypes.c_int32), ("nrhs_max", ctypes.c_int32), ("device", ctypes.c_int32),
+        ("verbose", ctypes.c_int32),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64), ("depth", ctypes.c_int32), ("top_level", ctypes.c_int32),
+        ("nleaf", ctypes.c_int64), ("max_leaf_count", ctypes.c_int32), ("near_nnz", ctypes.c_int64),
+        ("boxes", ctypes.c_int64 * 24), ("m2l_pairs", ctypes.c_int64 * 24), ("m2l_offsets", ctypes.c_int64 * 24),
+        ("hf", ctypes.c_int32 * 24), ("ndir", ctypes.c_int32 * 24), ("active_dirs", ctypes.c_int32 * 24),
+        ("p", ctypes.c_int32 * 24), ("rank_up", ctypes.c_int32 * 24), ("rank_dn", ctypes.c_int32 * 24),
+        ("m2l_flops", ctypes.c_int64), ("m2l_bytes", ctypes.c_int64), ("h_max", ctypes.c_double),
+        ("root_width", ctypes.c_double), ("build_seconds", ctypes.c_double), ("device_bytes", ctypes.c_int64),
+    ]
+
+    def to_dict(self) -> Dict:
+        d = {}
+        L = self.depth
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            if isinstance(v, ctypes.Array):
+                v = list(v)[: L + 1]
+            d[name] = v
+        return d
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [
+        ("iterations", ctypes.c_int32), ("restarts", ctypes.c_int32), ("rel_residual", ctypes.c_double),
+        ("seconds", ctypes.c_double), ("col_iterations", ctypes.c_int32 * 64),
+    ]
+
+
+_lib = None
+
+
+def library():
+    """Load libfda.so (built by paper_1403_4747_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            raise FDAError(-100, f"{_SO} is not built; run `python -m paper_1403_4747_amd.build`")
+        L = ctypes.CDLL(_SO)
+        vp, i64, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double
+        L.fda_default_options.argtypes = [ctypes.POINTER(Options)]
+        L.fda_build.argtypes = [vp, i64, vp, i64, dbl, dbl, ctypes.POINTER(Options), ctypes.POINTER(vp)]
+        L.fda_build.restype = ctypes.c_int
+        L.fda_inspect.argtypes = [vp, i64, vp, i64, dbl, dbl, ctypes.POINTER(Options), ctypes.POINTER(Stats)]
+        L.fda_inspect.restype = ctypes.c_int
+        L.fda_matvec.argtypes = [vp, vp, vp, i64, i64, vp]
+        L.fda_matvec.restype = ctypes.c_int
+        L.bm_rhs_planewave.argtypes = [vp, vp, i64, vp, i64, vp]
+        L.bm_rhs_planewave.restype = ctypes.c_int
+        L.bm_solve.argtypes = [vp, vp, vp, i64, i64, dbl, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                               ctypes.POINTER(SolveStats), vp]
+        L.bm_solve.restype = ctypes.c_int
+        L.fda_plan_stats.argtypes = [vp, ctypes.POINTER(Stats)]
+        L.fda_plan_stats.restype = ctypes.c_int
+        L.fda_profile_matvec.argtypes = [vp, vp, vp, i64, i64, ctypes.c_int32, vp, ctypes.POINTER(ctypes.c_double)]
+        L.fda_profile_matvec.restype = ctypes.c_int
+        L.fda_free.argtypes = [vp]
+        L.fda_last_error.restype = ctypes.c_char_p
+        L.fda_version.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _err(rc: int):
+    if rc < 0:
+        raise FDAError(rc, library().fda_last_error().decode())
+
+
+def default_options(**kw) -> Options:
+    o = Options()
+    library().fda_default_options(ctypes.byref(o))
+    for k, v in kw.items():
+        if k == "prec" and isinstance(v, str):
+            v = PREC[v]
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, v)
+    return o
+
+
+def _mesh(V, T):
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    T = np.ascontiguousarray(T, dtype=np.int32)
+    if V.ndim != 2 or V.shape[1] != 3 or T.ndim != 2 or T.shape[1] != 3:
+        raise ValueError("V must be (nv, 3) float64 and T (nt, 3) int32")
+    return V, T
+
+
+def inspect(V, T, k: float, eps: float = 1e-4, **opts) -> Dict:
+    """Host-only dry run of the build's tree / list phase (no GPU)."""
+    V, T = _mesh(V, T)
+    o = default_options(**opts)
+    st = Stats()
+    rc = library().fda_inspect(V.ctypes.data, len(V), T.ctypes.data, len(T), float(k), float(eps),
+                               ctypes.byref(o), ctypes.byref(st))
+    _err(rc)
+    return st.to_dict()
+
+
+def _stream():
+    import torch
+
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Plan:
+    """A built fast-directional plan on the current GPU (fda_build)."""
+
+    def __init__(self, V, T, k: float, eps: float = 1e-4, **opts):
+        V, T = _mesh(V, T)
+        self.n = len(T)
+        self.k = float(k)
+        o = default_options(**opts)
+        h = ctypes.c_void_p()
+        rc = library().fda_build(V.ctypes.data, len(V), T.ctypes.data, len(T), float(k), float(eps),
+                                 ctypes.byref(o), ctypes.byref(h))
+        _err(rc)
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            library().fda_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    @staticmethod
+    def _check_vec(t, n):
+        import torch
+
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.complex128 or not t.is_cuda:
+            raise TypeError("expected a complex128 CUDA tensor")
+        if not t.is_contiguous() or t.shape[-1] != n or t.dim() not in (1, 2):
+            raise ValueError(f"expected a contiguous (N,) or (nrhs, N) tensor with N = {n}")
+        return 1 if t.dim() == 1 else t.shape[0]
+
+    def matvec(self, x, out=None):
+        """y = A x (fda_matvec)."""
+        import torch
+
+        nrhs = self._check_vec(x, self.n)
+        y = torch.empty_like(x) if out is None else out
+        self._check_vec(y, self.n)
+        rc = library().fda_matvec(self._h, x.data_ptr(), y.data_ptr(), nrhs, self.n, _stream())
+        _err(rc)
+        return y
+
+    def rhs_planewave(self, directions: Sequence) -> "torch.Tensor":
+        """b = u_inc + alpha du_inc/dn for unit plane waves (bm_rhs_planewave)."""
+        import torch
+
+        d = np.ascontiguousarray(np.atleast_2d(np.asarray(directions, dtype=np.float64)))
+        nrhs = d.shape[0]
+        b = torch.empty((nrhs, self.n) if np.ndim(directions) == 2 else (self.n,), dtype=torch.complex128,
+                        device="cuda")
+        rc = library().bm_rhs_planewave(self._h, d.ctypes.data, nrhs, b.data_ptr(), self.n, _stream())
+        _err(rc)
+        return b
+
+    def solve(self, b, tol: float = 1e-5, restart: int = 50, maxit: int = 1000, precond: str = "none", out=None):
+        """GMRES solve of A x = b (bm_solve).  Returns (x, stats dict)."""
+        import torch
+
+        nrhs = self._check_vec(b, self.n)
+        x = torch.empty_like(b) if out is None else out
+        st = SolveStats()
+        rc = library().bm_solve(self._h, b.data_ptr(), x.data_ptr(), nrhs, self.n, float(tol), int(restart),
+                                int(maxit), PRECOND[precond], ctypes.byref(st), _stream())
+        _err(rc)
+        info = dict(iterations=st.iterations, restarts=st.restarts, rel_residual=st.rel_residual,
+                    seconds=st.seconds, col_iterations=list(st.col_iterations)[:nrhs],
+                    converged=(rc == 0))
+        return x, info
+
+    def stats(self) -> Dict:
+        st = Stats()
+        _err(library().fda_plan_stats(self._h, ctypes.byref(st)))
+        return st.to_dict()
+
+    def profile(self, x, reps: int = 10, out=None) -> Dict[str, float]:
+        """Per-stage HIP-event timings (ms) of fda_matvec."""
+        import torch
+
+        nrhs = self._check_vec(x, self.n)
+        y = torch.empty_like(x) if out is None else out
+        res = (ctypes.c_double * 7)()
+        rc = library().fda_profile_matvec(self._h, x.data_ptr(), y.data_ptr(), nrhs, self.n, int(reps), _stream(),
+                                          res)
+        _err(rc)
+        names = ["near", "s2m", "m2m", "m2l", "l2l", "l2t_perm", "total"]
+        return dict(zip(names, list(res)))
