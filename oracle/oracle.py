@@ -37,7 +37,7 @@ __all__ = [
     "r7_rule", "gl_rule", "rows", "assemble", "apply", "matvec",
     "rhs_planewave", "neumann_rhs", "gmres", "solve_dense",
     "mie_rigid_sphere", "mie_rigid_sphere_series", "sphere_n0_eigenvalues",
-    "pulsating_sphere", "point_source_data", "OPS",
+    "pulsating_sphere", "point_source_data", "OPS", "default_alpha",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -154,8 +154,18 @@ def gl_rule():
     return x, w
 
 
+def default_alpha(k):
+    """Burton-Miller coupling.  The paper takes alpha = i/k (Section 2, after
+    eq. (eq_bm)), the choice of the cited analysis, which is stated for the
+    normal pointing into the fluid.  The paper's n points into the body, so
+    the same coupling is alpha = -i/k here.  (With +i/k in this convention
+    part of the spectrum moves to the left half-plane: GMRES(50) needs 77
+    instead of 15 iterations on the 5,120-triangle sphere at kD = 40.)"""
+    return -1j / k
+
+
 def _alpha(k, alpha):
-    return (1j / k) if alpha is None else complex(alpha)
+    return default_alpha(k) if alpha is None else complex(alpha)
 
 
 def rows(V, T, k, row_idx, op="A", alpha=None):
@@ -327,7 +337,7 @@ def mie_rigid_sphere_series(a, k, cos_theta, nmax=None):
     return u
 
 
-def sphere_n0_eigenvalues(a, k) -> Dict[str, complex]:
+def sphere_n0_eigenvalues(a, k, alpha=None) -> Dict[str, complex]:
     """Action of the four layer operators on a constant density over a
     sphere of radius a (paper normal pointing into the sphere), from the
     addition theorem G = ik sum j_n(kr<) h_n(kr>) ...; only n = 0 survives:
@@ -335,14 +345,15 @@ def sphere_n0_eigenvalues(a, k) -> Dict[str, complex]:
         K 1  = 1/2 - i k^2 a^2 j0'(ka) h0(ka)    (direct value, dG/dn_y)
         K' 1 = -1/2 - i k^2 a^2 j0(ka) h0'(ka)   (direct value, dG/dn_x)
         T 1  = i k^3 a^2 j0'(ka) h0'(ka)         (hypersingular)
-    and A 1 = 1/2 + K 1 + (i/k) T 1."""
+    and A 1 = 1/2 + K 1 + alpha T 1 (alpha defaults to default_alpha(k))."""
     j, jp, y, yp = _sph(0, k * a)
     h, hp = j + 1j * y, jp + 1j * yp
     S1 = 1j * k * a * a * j * h
     K1 = 0.5 - 1j * k * k * a * a * jp * h
     Kp1 = -0.5 - 1j * k * k * a * a * j * hp
     T1 = 1j * k ** 3 * a * a * jp * hp
-    return dict(S=S1, K=K1, Kp=Kp1, T=T1, A=0.5 + K1 + (1j / k) * T1)
+    al = _alpha(k, alpha)
+    return dict(S=S1, K=K1, Kp=Kp1, T=T1, A=0.5 + K1 + al * T1)
 
 
 def pulsating_sphere(a, k, vn=1.0):

@@ -220,7 +220,8 @@ def test_graded_rule_self_convergence():
             a, b, c = V[T[j, 0]], V[T[j, 1]], V[T[j, 2]]
             v0 = O.element_integrals(a, b, c, cen[i], nrm[i], k, lev)
             v1 = O.element_integrals(a, b, c, cen[i], nrm[i], k, lev + 1)
-            rel = abs(v0[1] + (1j / k) * v0[3] - v1[1] - (1j / k) * v1[3]) / abs(v1[1] + (1j / k) * v1[3])
+            al = O.default_alpha(k)
+            rel = abs(v0[1] + al * v0[3] - v1[1] - al * v1[3]) / abs(v1[1] + al * v1[3])
             assert rel < tol, (lo, j, rel)
 
 
@@ -286,9 +287,9 @@ def test_discrete_operators_converge_to_sphere_closed_forms(op):
 def test_pulsating_closed_form_consistency():
     """The pulsating-sphere potential satisfies the n = 0 Burton-Miller
     equation exactly: A1 u = B1 with B1 = -alpha/2 + S1 + alpha K'1."""
-    for a, k in ((1.0, math.pi), (0.5, 10.0), (1.0, 25.0)):
-        ev = O.sphere_n0_eigenvalues(a, k)
-        al = 1j / k
+    for a, k, al in ((1.0, math.pi, None), (0.5, 10.0, 1j / 10.0), (1.0, 25.0, None)):
+        ev = O.sphere_n0_eigenvalues(a, k, al)
+        al = O.default_alpha(k) if al is None else al
         u = O.pulsating_sphere(a, k)
         assert abs(ev["A"] * u - (-al / 2 + ev["S"] + al * ev["Kp"])) < 1e-12
 
@@ -307,7 +308,7 @@ def test_planewave_rhs_against_finite_difference():
     ui = lambda x: np.exp(1j * k * x @ d)
     dudn = (ui(cen + h * nrm) - ui(cen - h * nrm)) / (2 * h)
     b = O.rhs_planewave(V, T, k, d)
-    assert np.max(np.abs(b - (ui(cen) + (1j / k) * dudn))) < 1e-8
+    assert np.max(np.abs(b - (ui(cen) + O.default_alpha(k) * dudn))) < 1e-8
     # the paper normal points into the body (towards the origin here)
     assert np.all(np.einsum("ij,ij->i", nrm, cen) < 0)
 
@@ -330,6 +331,18 @@ def test_mie_low_frequency_limit():
 
 
 # ------------------------------------------------------------- solvers
+
+def test_coupling_sign_keeps_spectrum_in_right_half_plane():
+    """The default coupling (i/k for the fluid-side normal, -i/k for the
+    paper's body-pointing normal) keeps the spectrum of A in Re > 0 and
+    GMRES fast; the opposite sign does not."""
+    V, T = W.icosphere(3, 0.5)
+    k = 10.0
+    ev = np.linalg.eigvals(O.assemble(V, T, k))
+    assert ev.real.min() > 0.3
+    ev2 = np.linalg.eigvals(O.assemble(V, T, k, alpha=-O.default_alpha(k)))
+    assert ev2.real.min() < 0
+
 
 def test_gmres_equals_lu():
     V, T = W.icosphere(2, 0.5)
