@@ -65,7 +65,9 @@ typedef struct fda_options {
     int32_t p_min;         /* smallest points per cube edge; 0 = ceil(log10(1/eps)) + p0 (Section 5.1) */
     int32_t p0;            /* the paper's p0, default 1 */
     double svd_eps;        /* SVD truncation threshold (eqs. (eq_epsg), (eq_epsk)); 0 = eps / 10 */
-    double alpha_re;       /* Burton-Miller coupling; alpha_re = alpha_im = 0 selects i/k */
+    double alpha_re;       /* Burton-Miller coupling in the body-pointing normal convention;
+                              alpha_re = alpha_im = 0 selects -i/k, which is the coupling i/k of
+                              Section 2 written for the fluid-side normal */
     double alpha_im;
     double hf_wavelengths; /* a box is high-frequency (directional) when its width >= this many
                               wavelengths, default 1.9 */

@@ -76,7 +76,7 @@ void free_work(fda_plan *p) {
     p->work.clear();
     p->cap_nrhs = 0;
     p->xt = p->yt = nullptr;
-    for (auto &l : p->d.lv) l.s = l.c = nullptr;
+    for (auto &l : p->d.lv) l.s = l.c = l.tmp = nullptr;
 }
 
 // Work buffers for `nrhs` right-hand sides: tree-order vectors and the
@@ -91,6 +91,7 @@ void ensure_capacity(fda_plan *p, int nrhs) {
         DevLevel &lv = p->d.lv[l];
         lv.s = dalloc<double2>(p, (size_t)lv.sstride * nrhs, p->work);
         lv.c = dalloc<double2>(p, (size_t)lv.cstride * nrhs, p->work);
+        lv.tmp = dalloc<double2>(p, (size_t)lv.tstride * nrhs, p->work);
     }
     p->cap_nrhs = nrhs;
 }
@@ -218,34 +219,71 @@ void upload_plan(fda_plan *p, const HostOps &ops, DevTranslations &tr) {
         dl.sstride = lv.nbox * lv.nslot * (int64_t)lv.ku;
         dl.cstride = lv.nbox * lv.nslot * (int64_t)lv.kd;
         dl.K = tr.K[l];
-        // M2L groups: (target box, slot) -> list of (source state, op)
-        std::vector<int32_t> gt, go{0}, ps, po;
-        for (int64_t b = 0; b < lv.nbox; ++b) {
-            const auto &il = lv.il[b];
-            const auto &io = lv.il_ops[b];
-            std::vector<int> idx(il.size());
-            for (size_t q = 0; q < il.size(); ++q) idx[q] = (int)q;
-            auto slot_of = [&](int q) { return lv.hf ? lv.slot_of_dir[lv.offset_dir[io[q]]] : 0; };
-            std::stable_sort(idx.begin(), idx.end(), [&](int a, int c) { return slot_of(a) < slot_of(c); });
-            int cur = -1;
-            for (int q : idx) {
-                int sl = slot_of(q);
-                if (sl != cur) {
-                    if (cur >= 0) go.push_back((int32_t)ps.size());
-                    gt.push_back((int32_t)(b * lv.nslot + sl));
-                    cur = sl;
+        // M2L pairs sorted by translation; work items of <= 32 pairs; the
+        // pairs of every target state in a fixed order
+        {
+            const size_t no = lv.offsets.size();
+            std::vector<std::vector<std::pair<int32_t, int32_t>>> by_op(no);  // (src state, tgt state)
+            for (int64_t b = 0; b < lv.nbox; ++b)
+                for (size_t q = 0; q < lv.il[b].size(); ++q) {
+                    int op = lv.il_ops[b][q];
+                    int sl = lv.hf ? lv.slot_of_dir[lv.offset_dir[op]] : 0;
+                    by_op[op].push_back({(int32_t)(lv.il[b][q] * lv.nslot + sl), (int32_t)(b * lv.nslot + sl)});
                 }
-                ps.push_back((int32_t)(il[q] * lv.nslot + sl));
-                po.push_back(io[q]);
+            std::vector<int32_t> src;
+            std::vector<int32_t> pair_tgt;
+            std::vector<int32_t> wk;
+            for (size_t op = 0; op < no; ++op) {
+                const auto &v = by_op[op];
+                for (size_t q0 = 0; q0 < v.size(); q0 += 32) {
+                    size_t q1 = std::min(v.size(), q0 + 32);
+                    wk.push_back((int32_t)op);
+                    wk.push_back((int32_t)(src.size() + (q0 - 0)));
+                    wk.push_back((int32_t)(q1 - q0));
+                    wk.push_back(0);
+                }
+                // positions are assigned after the whole op block is appended
+                for (auto &pr : v) {
+                    src.push_back(pr.first);
+                    pair_tgt.push_back(pr.second);
+                }
             }
-            if (cur >= 0) go.push_back((int32_t)ps.size());
+            // fix work item starts: they were recorded relative to the op block start
+            {
+                size_t base = 0, w = 0;
+                for (size_t op = 0; op < no; ++op) {
+                    const auto &v = by_op[op];
+                    for (size_t q0 = 0; q0 < v.size(); q0 += 32, ++w) wk[4 * w + 1] = (int32_t)(base + q0);
+                    base += v.size();
+                }
+            }
+            const int64_t nstate = lv.nbox * lv.nslot;
+            std::vector<int32_t> cnt(nstate, 0);
+            for (int32_t t : pair_tgt) cnt[t]++;
+            std::vector<int32_t> tstate, toff{0}, tpairs;
+            std::vector<int32_t> start(nstate, -1);
+            for (int64_t t = 0; t < nstate; ++t)
+                if (cnt[t]) {
+                    start[t] = (int32_t)tstate.size();
+                    tstate.push_back((int32_t)t);
+                    toff.push_back(toff.back() + cnt[t]);
+                }
+            tpairs.assign(pair_tgt.size(), 0);
+            std::vector<int32_t> fill(tstate.size(), 0);
+            for (size_t q = 0; q < pair_tgt.size(); ++q) {
+                int32_t g = start[pair_tgt[q]];
+                tpairs[toff[g] + fill[g]++] = (int32_t)q;
+            }
+            dl.nwork = (int)(wk.size() / 4);
+            dl.npair = (int64_t)src.size();
+            dl.ntgt = (int)tstate.size();
+            dl.tstride = dl.npair * lv.kd;
+            dl.work = (int4 *)upload(p, wk);
+            dl.pp_src = upload(p, src);
+            dl.tg_state = upload(p, tstate);
+            dl.tg_off = upload(p, toff);
+            dl.tg_pairs = upload(p, tpairs);
         }
-        dl.ngrp = (int)gt.size();
-        dl.npair = (int64_t)ps.size();
-        dl.grp_tgt = upload(p, gt);
-        dl.grp_off = upload(p, go);
-        dl.pr_src = upload(p, ps);
-        dl.pr_op = upload(p, po);
         if (l > hp.top) {
             dl.parent = upload(p, lv.parent);
             dl.octant = upload(p, lv.octant);

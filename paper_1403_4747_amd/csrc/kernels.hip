@@ -246,35 +246,75 @@ __global__ void k_m2m(int nslotP, int kuP, const int32_t *child_begin, const int
     }
 }
 
-// Incoming states += reduced M2L translations of the interaction list, one
-// block per (target box, direction slot).
-__global__ void k_m2l(const int32_t *grp_tgt, const int32_t *grp_off, const int32_t *pr_src, const int32_t *pr_op,
-                      const double2 *K, int kd, int ku, const double2 *s, double2 *c, int64_t sstride,
-                      int64_t cstride) {
-    extern __shared__ double2 v[];
-    const int g = blockIdx.x;
+// Reduced M2L translations grouped by translation (eq. (eq_m2l) in the
+// compressed form of eq. (eq_cmpm2l)): every interaction pair with the same
+// lattice offset shares one matrix K~, so each work item multiplies K~ by up
+// to M2L_NB gathered source states (a small complex GEMM) and writes the
+// products to a per-pair buffer.  Work items of one translation are mapped
+// to the same XCD so K~ is shared through that XCD's L2.
+#define M2L_NB 32
+#define M2L_J 32
+__global__ void __launch_bounds__(256) k_m2l_gemm(const int4 *work, const int32_t *pp_src, const double2 *K, int kd,
+                                                  int ku, const double2 *s, double2 *tmp, int64_t sstride,
+                                                  int64_t tstride, int nwork) {
+    __shared__ double2 S[M2L_J][M2L_NB];
+    // XCD-aware mapping: consecutive hardware workgroups go round-robin over
+    // the 8 XCDs; give each XCD a contiguous range of work items (the grid is
+    // a multiple of 8, so each XCD runs exactly `per` workgroups).
+    const int nx = 8;
+    const int per = gridDim.x / nx;
+    const int w = (blockIdx.x % nx) * per + blockIdx.x / nx;
+    if (w >= nwork) return;
+    const int4 wk = work[w];  // (op, first pair, pair count, 0)
+    const double2 *Kp = K + (int64_t)wk.x * kd * ku;
     const double2 *sr = s + (int64_t)blockIdx.y * sstride;
-    double2 acc[FDA_MAXR];
-    for (int q = 0; q < FDA_MAXR; ++q) acc[q] = make_double2(0.0, 0.0);
-    for (int p = grp_off[g]; p < grp_off[g + 1]; ++p) {
-        __syncthreads();
-        const double2 *src = sr + (int64_t)pr_src[p] * ku;
-        for (int j = threadIdx.x; j < ku; j += blockDim.x) v[j] = src[j];
-        __syncthreads();
-        const double2 *Kp = K + (int64_t)pr_op[p] * kd * ku;
-        for (int q = 0; q < FDA_MAXR; ++q) {
-            int r = threadIdx.x + q * blockDim.x;
-            if (r >= kd) break;
-            for (int j = 0; j < ku; ++j) cfma(acc[q], Kp[r + (int64_t)j * kd], v[j]);
+    const int p0 = wk.y, nb = wk.z;
+    for (int r0 = 0; r0 < kd; r0 += blockDim.x) {
+        const int r = r0 + threadIdx.x;
+        double2 acc[M2L_NB];
+#pragma unroll
+        for (int b = 0; b < M2L_NB; ++b) acc[b] = make_double2(0.0, 0.0);
+        for (int j0 = 0; j0 < ku; j0 += M2L_J) {
+            __syncthreads();
+            for (int e = threadIdx.x; e < M2L_J * M2L_NB; e += blockDim.x) {
+                const int jj = e % M2L_J, b = e / M2L_J;
+                double2 v = make_double2(0.0, 0.0);
+                if (b < nb && j0 + jj < ku) v = sr[(int64_t)pp_src[p0 + b] * ku + j0 + jj];
+                S[jj][b] = v;
+            }
+            __syncthreads();
+            if (r < kd) {
+                const int jm = min(M2L_J, ku - j0);
+                const double2 *Kc = Kp + r + (int64_t)j0 * kd;
+                for (int jj = 0; jj < jm; ++jj) {
+                    const double2 a = Kc[(int64_t)jj * kd];
+#pragma unroll
+                    for (int b = 0; b < M2L_NB; ++b) cfma(acc[b], a, S[jj][b]);
+                }
+            }
+        }
+        if (r < kd) {
+            double2 *out = tmp + (int64_t)blockIdx.y * tstride + (int64_t)p0 * kd + r;
+            for (int b = 0; b < nb; ++b) out[(int64_t)b * kd] = acc[b];
         }
     }
-    double2 *out = c + (int64_t)blockIdx.y * cstride + (int64_t)grp_tgt[g] * kd;
-    for (int q = 0; q < FDA_MAXR; ++q) {
-        int r = threadIdx.x + q * blockDim.x;
-        if (r < kd) {
-            double2 o = out[r];
-            out[r] = make_double2(o.x + acc[q].x, o.y + acc[q].y);
+}
+
+// c[target] += sum of the per-pair products of the target's interaction list
+// (fixed order: deterministic).
+__global__ void k_m2l_reduce(const int32_t *tg_state, const int32_t *tg_off, const int32_t *tg_pairs, int kd,
+                             const double2 *tmp, double2 *c, int64_t tstride, int64_t cstride) {
+    const int t = blockIdx.x;
+    const double2 *tr = tmp + (int64_t)blockIdx.y * tstride;
+    double2 *out = c + (int64_t)blockIdx.y * cstride + (int64_t)tg_state[t] * kd;
+    for (int r = threadIdx.x; r < kd; r += blockDim.x) {
+        double2 acc = out[r];
+        for (int q = tg_off[t]; q < tg_off[t + 1]; ++q) {
+            double2 v = tr[(int64_t)tg_pairs[q] * kd + r];
+            acc.x += v.x;
+            acc.y += v.y;
         }
+        out[r] = acc;
     }
 }
 
@@ -605,10 +645,15 @@ hipError_t launch_matvec_tree(const DevPlan &d, const double2 *xt, double2 *yt, 
         int64_t n = lv.cstride * nrhs;
         hipLaunchKernelGGL(k_fill_zero, dim3(grid1(n)), dim3(256), 0, st, lv.c, n);
         CHECK_LAUNCH();
-        if (lv.ngrp > 0) {
-            hipLaunchKernelGGL(k_m2l, dim3(lv.ngrp, nrhs), dim3(256), sizeof(double2) * lv.ku, st, lv.grp_tgt,
-                               lv.grp_off, lv.pr_src, lv.pr_op, lv.K, lv.kd, lv.ku, lv.s, lv.c, lv.sstride,
-                               lv.cstride);
+        if (lv.nwork > 0) {
+            const int bs = std::min(256, ((lv.kd + 63) / 64) * 64);
+            // a multiple of 8 workgroups so every XCD gets the same share
+            const int grid = (lv.nwork + 7) / 8 * 8;
+            hipLaunchKernelGGL(k_m2l_gemm, dim3(grid, nrhs), dim3(bs), 0, st, lv.work, lv.pp_src, lv.K, lv.kd,
+                               lv.ku, lv.s, lv.tmp, lv.sstride, lv.tstride, lv.nwork);
+            CHECK_LAUNCH();
+            hipLaunchKernelGGL(k_m2l_reduce, dim3(lv.ntgt, nrhs), dim3(std::min(256, ((lv.kd + 63) / 64) * 64)), 0,
+                               st, lv.tg_state, lv.tg_off, lv.tg_pairs, lv.kd, lv.tmp, lv.c, lv.tstride, lv.cstride);
             CHECK_LAUNCH();
         }
     }

@@ -13,11 +13,15 @@ struct DevLevel {
     int nslot = 1, ku = 0, kd = 0;
     int64_t sstride = 0, cstride = 0;  // elements per right-hand side of s and c
     double2 *s = nullptr, *c = nullptr;
-    // M2L (target-major groups)
-    int ngrp = 0;
-    int64_t npair = 0;
-    int32_t *grp_tgt = nullptr, *grp_off = nullptr, *pr_src = nullptr, *pr_op = nullptr;
+    // M2L grouped by translation: work items (op, first pair, count), the
+    // source state of every pair (pairs sorted by translation), and per
+    // target state the positions of its pairs
+    int nwork = 0, ntgt = 0;
+    int64_t npair = 0, tstride = 0;
+    int4 *work = nullptr;
+    int32_t *pp_src = nullptr, *tg_state = nullptr, *tg_off = nullptr, *tg_pairs = nullptr;
     double2 *K = nullptr;
+    double2 *tmp = nullptr;  // per-pair products (npair x kd per right-hand side)
     // tree links (this level's boxes)
     int32_t *parent = nullptr, *octant = nullptr, *child_begin = nullptr;
     // parent-level operators towards level + 1

@@ -158,7 +158,8 @@ void host_setup(const double *V, int64_t nv, const int32_t *T, int64_t nt, doubl
     hp.eps = eps;
     hp.opt = opt;
     hp.svd_eps = opt.svd_eps > 0 ? opt.svd_eps : eps / 10.0;
-    hp.alpha = (opt.alpha_re == 0 && opt.alpha_im == 0) ? cplx(0.0, 1.0 / k) : cplx(opt.alpha_re, opt.alpha_im);
+    // i/k for the fluid-side normal, i.e. -i/k for the body-pointing normal n
+    hp.alpha = (opt.alpha_re == 0 && opt.alpha_im == 0) ? cplx(0.0, -1.0 / k) : cplx(opt.alpha_re, opt.alpha_im);
     const double lambda = 2.0 * kPi / k;
 
     // geometry (caller order)

@@ -141,7 +141,8 @@ def complex_normal(n: int, nrhs: int = 1, seed: int = 0) -> np.ndarray:
 
 # Named synthetic workloads.  A rigid sphere of diameter D = 1 (radius 0.5)
 # meshed as an icosphere, a unit plane wave along +z, Burton-Miller coupling
-# alpha = i/k, compression threshold eps = 1e-4, at most 64 elements per leaf,
+# i/k (fluid-side normal), compression threshold eps = 1e-4, at most 64
+# elements per leaf,
 # GMRES(50) to a relative residual of 1e-5.
 WORKLOADS = {
     "sphere1280_kD10": dict(subdiv=3, radius=0.5, k=10.0, eps=1e-4, direction=(0.0, 0.0, 1.0)),
