@@ -88,7 +88,8 @@ def main():
     build_s = time.perf_counter() - t0
     st = plan.stats()
     log(f"[bench] build {build_s:.2f} s; depth {st['depth']} top {st['top_level']} pairs {st['m2l_pairs']} "
-        f"ranks {st['rank_up']} p {st['p']}")
+        f"ranks {st['rank_up']} p {st['p']} m2l low-rank max {st['m2l_rank_max']} mean "
+        f"{[round(v, 1) for v in st['m2l_rank_mean']]}")
 
     x = torch.from_numpy(W.complex_normal(n, 1, seed=0)).to("cuda")
     y = torch.empty_like(x)
@@ -111,14 +112,18 @@ def main():
     log(f"[bench] stages (ms): {prof}")
     y_np = y.cpu().numpy()
 
-    # roofline of the dominant kernel (M2L): algorithmic flops per launch
-    # (8 real flops per complex multiply-add of the reduced translations)
-    m2l_flops = float(st["m2l_flops"])
-    m2l_ms = prof["m2l"]
-    achieved = m2l_flops / (m2l_ms * 1e-3) / 1e12 if m2l_ms > 0 else 0.0
+    # roofline of the dominant kernel: the M2L product launch of the level
+    # that takes longest; algorithmic flops per launch = 8 real flops per
+    # complex multiply-add of that level's (low-rank) reduced translations
+    lv_ms = prof["m2l_gemm"]
+    lv = int(np.argmax(lv_ms))
+    lv_flops = float(st["m2l_level_flops"][lv])
+    achieved = lv_flops / (lv_ms[lv] * 1e-3) / 1e12 if lv_ms[lv] > 0 else 0.0
+    kname = "k_m2l_lowrank" if st["m2l_rank_max"][lv] > 0 else "k_ggemm"
     roofline = dict(bound="mfma", achieved=round(achieved, 3), peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=round(achieved / FP64_PEAK_TFLOPS, 4), traffic=None, kernel="k_m2l (all levels)",
-                    algorithmic_flops=m2l_flops)
+                    frac=round(achieved / FP64_PEAK_TFLOPS, 4), traffic=None,
+                    kernel=f"{kname} (M2L, level {lv})", flops_per_launch=lv_flops,
+                    launch_ms=round(lv_ms[lv], 4))
 
     solve = {}
     if not args.no_solve:
@@ -150,10 +155,12 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "N": n, "k": k, "kD": 2 * 0.5 * k * 2 / 2 if False else k * 1.0,
+        "config": {"workload": args.workload, "N": n, "k": k, "kD": k * 2 * prm["radius"],
                    "eps": prm["eps"], "nrhs": 1, "arm": "plain FP64"},
         "build_seconds": round(build_s, 3),
-        "stages_ms": {q: round(v, 4) for q, v in prof.items()},
+        "stages_ms": {q: round(v, 4) for q, v in prof.items() if q != "m2l_gemm"},
+        "m2l_level_ms": [round(v, 4) for v in prof["m2l_gemm"][: st["depth"] + 1]],
+        "m2l_flops_per_matvec": st["m2l_flops"],
         "time_to_1e-5_s": solve.get("none", {}).get("seconds"),
         "solve": solve,
         "matvec_rel_err_vs_oracle_sampled": err,

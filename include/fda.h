@@ -96,6 +96,9 @@ typedef struct fda_stats {
     int32_t p[24];              /* points per cube edge per level */
     int32_t rank_up[24];        /* outgoing compressed rank per level (max over directions) */
     int32_t rank_dn[24];        /* incoming compressed rank per level */
+    int32_t m2l_rank_max[24];   /* low-rank M2L: largest rank per level (0 = full reduced matrices) */
+    double m2l_rank_mean[24];   /* low-rank M2L: mean numerical rank per level */
+    double m2l_level_flops[24]; /* real flops of the M2L products per level, per right-hand side */
     int64_t m2l_flops;          /* real flops of one M2L pass per right-hand side */
     int64_t m2l_bytes;          /* bytes of the distinct reduced M2L matrices */
     double h_max;               /* largest mesh edge */
@@ -160,13 +163,16 @@ int bm_solve(fda_plan *plan, const void *b_dev, void *x_dev, int64_t nrhs, int64
 /* Statistics of a built plan. */
 int fda_plan_stats(const fda_plan *plan, fda_stats *st);
 
-/* Timing of the stages of one fda_matvec (milliseconds, measured with HIP
- * events on the given stream over `reps` back-to-back products of nrhs
- * columns): out[0] near field, out[1] S2M, out[2] M2M, out[3] M2L, out[4] L2L,
- * out[5] L2T + permutations, out[6] whole product.  x_dev/y_dev as in
- * fda_matvec.  Synchronous. */
+/* Stage timings of fda_matvec (milliseconds, HIP events on the given
+ * stream, averaged over `reps` back-to-back products of nrhs columns). */
+typedef struct fda_profile_result {
+    double near_ms, s2m_ms, m2m_ms, m2l_ms, l2l_ms, l2t_ms, total_ms;
+    double m2l_gemm_ms[24];     /* the M2L product kernel of each level (without its reduction) */
+} fda_profile_result;
+
+/* Profile fda_matvec: x_dev/y_dev as in fda_matvec.  Synchronous. */
 int fda_profile_matvec(fda_plan *plan, const void *x_dev, void *y_dev, int64_t nrhs, int64_t ld, int32_t reps,
-                       void *stream, double *out);
+                       void *stream, fda_profile_result *out);
 
 /* Release a plan and all its device memory (NULL is allowed). */
 void fda_free(fda_plan *plan);

@@ -8,6 +8,7 @@
 #include <cstring>
 #include <memory>
 #include <string>
+#include <unordered_map>
 
 #include "../../include/fda.h"
 #include "dsetup.hpp"
@@ -71,12 +72,62 @@ double2 *upload_cplx(fda_plan *p, const std::vector<cplx> &v) {
     return d;
 }
 
+// Host-side builder of a gathered-GEMM work list (kernels.hpp, GWork).
+struct GWorkHost {
+    std::vector<int32_t> hdr, src;
+    int64_t ncol = 0;
+    std::vector<std::vector<int32_t>> parts;  // per destination: scratch columns
+    std::vector<int32_t> dest;                // destination state of each entry of parts
+    std::unordered_map<int32_t, int32_t> dest_index;
+    // one work item: matrix `mat` times the gathered states `srcs`; the
+    // products go to new scratch columns that are summed into `dsts`
+    void add(int32_t mat, const std::vector<int32_t> &srcs, const std::vector<int32_t> &dsts) {
+        hdr.push_back(mat);
+        hdr.push_back((int32_t)ncol);
+        hdr.push_back((int32_t)srcs.size());
+        hdr.push_back(0);
+        for (int b = 0; b < kGemmCols; ++b) src.push_back(b < (int)srcs.size() ? srcs[b] : -1);
+        for (size_t b = 0; b < dsts.size(); ++b) {
+            auto it = dest_index.find(dsts[b]);
+            int32_t di;
+            if (it == dest_index.end()) {
+                di = (int32_t)dest.size();
+                dest_index[dsts[b]] = di;
+                dest.push_back(dsts[b]);
+                parts.emplace_back();
+            } else {
+                di = it->second;
+            }
+            parts[di].push_back((int32_t)(ncol + b));
+        }
+        ncol += (int64_t)srcs.size();
+    }
+};
+
+GWork upload_gwork(fda_plan *p, const GWorkHost &g) {
+    GWork w;
+    w.nwork = (int)(g.hdr.size() / 4);
+    w.ncol = g.ncol;
+    w.nred = (int)g.dest.size();
+    std::vector<int32_t> off{0}, list;
+    for (const auto &pl : g.parts) {
+        list.insert(list.end(), pl.begin(), pl.end());
+        off.push_back((int32_t)list.size());
+    }
+    w.hdr = (int4 *)upload(p, g.hdr);
+    w.src = upload(p, g.src);
+    w.rd_dst = upload(p, g.dest);
+    w.rd_off = upload(p, off);
+    w.rd_list = upload(p, list);
+    return w;
+}
+
 void free_work(fda_plan *p) {
     for (void *q : p->work) hipFree(q);
     p->work.clear();
     p->cap_nrhs = 0;
     p->xt = p->yt = nullptr;
-    for (auto &l : p->d.lv) l.s = l.c = l.tmp = nullptr;
+    for (auto &l : p->d.lv) l.s = l.c = l.m2l.tmp = l.m2m.tmp = l.l2l.tmp = nullptr;
 }
 
 // Work buffers for `nrhs` right-hand sides: tree-order vectors and the
@@ -91,7 +142,12 @@ void ensure_capacity(fda_plan *p, int nrhs) {
         DevLevel &lv = p->d.lv[l];
         lv.s = dalloc<double2>(p, (size_t)lv.sstride * nrhs, p->work);
         lv.c = dalloc<double2>(p, (size_t)lv.cstride * nrhs, p->work);
-        lv.tmp = dalloc<double2>(p, (size_t)lv.tstride * nrhs, p->work);
+        lv.m2l.tmp = dalloc<double2>(p, (size_t)lv.m2l.ncol * lv.kd * nrhs, p->work);
+        if (l < p->d.depth) {
+            const DevLevel &C = p->d.lv[l + 1];
+            lv.m2m.tmp = dalloc<double2>(p, (size_t)lv.m2m.ncol * lv.ku * nrhs, p->work);
+            lv.l2l.tmp = dalloc<double2>(p, (size_t)lv.l2l.ncol * C.kd * nrhs, p->work);
+        }
     }
     p->cap_nrhs = nrhs;
 }
@@ -219,6 +275,12 @@ void upload_plan(fda_plan *p, const HostOps &ops, DevTranslations &tr) {
         dl.sstride = lv.nbox * lv.nslot * (int64_t)lv.ku;
         dl.cstride = lv.nbox * lv.nslot * (int64_t)lv.kd;
         dl.K = tr.K[l];
+        if (!tr.rmax.empty() && tr.rmax[l] > 0 && lv.kd <= 256) {
+            dl.Ulr = tr.Ulr[l];
+            dl.Vlr = tr.Vlr[l];
+            dl.lr_rank = tr.lr_rank[l];
+            dl.rmax = tr.rmax[l];
+        }
         // M2L pairs sorted by translation; work items of <= 32 pairs; the
         // pairs of every target state in a fixed order
         {
@@ -230,71 +292,67 @@ void upload_plan(fda_plan *p, const HostOps &ops, DevTranslations &tr) {
                     int sl = lv.hf ? lv.slot_of_dir[lv.offset_dir[op]] : 0;
                     by_op[op].push_back({(int32_t)(lv.il[b][q] * lv.nslot + sl), (int32_t)(b * lv.nslot + sl)});
                 }
-            std::vector<int32_t> src;
-            std::vector<int32_t> pair_tgt;
-            std::vector<int32_t> wk;
+            GWorkHost g;
             for (size_t op = 0; op < no; ++op) {
                 const auto &v = by_op[op];
-                for (size_t q0 = 0; q0 < v.size(); q0 += 32) {
-                    size_t q1 = std::min(v.size(), q0 + 32);
-                    wk.push_back((int32_t)op);
-                    wk.push_back((int32_t)(src.size() + (q0 - 0)));
-                    wk.push_back((int32_t)(q1 - q0));
-                    wk.push_back(0);
-                }
-                // positions are assigned after the whole op block is appended
-                for (auto &pr : v) {
-                    src.push_back(pr.first);
-                    pair_tgt.push_back(pr.second);
+                for (size_t q0 = 0; q0 < v.size(); q0 += kGemmCols) {
+                    size_t q1 = std::min(v.size(), q0 + kGemmCols);
+                    std::vector<int32_t> srcs, dsts;
+                    for (size_t q = q0; q < q1; ++q) {
+                        srcs.push_back(v[q].first);
+                        dsts.push_back(v[q].second);
+                    }
+                    g.add((int32_t)op, srcs, dsts);
                 }
             }
-            // fix work item starts: they were recorded relative to the op block start
-            {
-                size_t base = 0, w = 0;
-                for (size_t op = 0; op < no; ++op) {
-                    const auto &v = by_op[op];
-                    for (size_t q0 = 0; q0 < v.size(); q0 += 32, ++w) wk[4 * w + 1] = (int32_t)(base + q0);
-                    base += v.size();
-                }
-            }
-            const int64_t nstate = lv.nbox * lv.nslot;
-            std::vector<int32_t> cnt(nstate, 0);
-            for (int32_t t : pair_tgt) cnt[t]++;
-            std::vector<int32_t> tstate, toff{0}, tpairs;
-            std::vector<int32_t> start(nstate, -1);
-            for (int64_t t = 0; t < nstate; ++t)
-                if (cnt[t]) {
-                    start[t] = (int32_t)tstate.size();
-                    tstate.push_back((int32_t)t);
-                    toff.push_back(toff.back() + cnt[t]);
-                }
-            tpairs.assign(pair_tgt.size(), 0);
-            std::vector<int32_t> fill(tstate.size(), 0);
-            for (size_t q = 0; q < pair_tgt.size(); ++q) {
-                int32_t g = start[pair_tgt[q]];
-                tpairs[toff[g] + fill[g]++] = (int32_t)q;
-            }
-            dl.nwork = (int)(wk.size() / 4);
-            dl.npair = (int64_t)src.size();
-            dl.ntgt = (int)tstate.size();
-            dl.tstride = dl.npair * lv.kd;
-            dl.work = (int4 *)upload(p, wk);
-            dl.pp_src = upload(p, src);
-            dl.tg_state = upload(p, tstate);
-            dl.tg_off = upload(p, toff);
-            dl.tg_pairs = upload(p, tpairs);
-        }
-        if (l > hp.top) {
-            dl.parent = upload(p, lv.parent);
-            dl.octant = upload(p, lv.octant);
+            dl.m2l = upload_gwork(p, g);
         }
         if (l < L) {
-            dl.child_begin = upload(p, lv.child_begin);
+            const Level &C = hp.lv[l + 1];
             dl.M = tr.M[l];
             dl.Lo = tr.Lo[l];
-            dl.cslot = upload(p, lv.cslot);
-            dl.l2l_off = upload(p, lv.l2l_off);
-            dl.l2l_src = upload(p, lv.l2l_src);
+            // M2M: per (child octant, parent slot), the parents with a child
+            // in that octant, in chunks
+            GWorkHost gm;
+            for (int o = 0; o < 8; ++o)
+                for (int s = 0; s < lv.nslot; ++s) {
+                    std::vector<int32_t> srcs, dsts;
+                    auto flush = [&]() {
+                        if (!srcs.empty()) gm.add(o * lv.nslot + s, srcs, dsts);
+                        srcs.clear();
+                        dsts.clear();
+                    };
+                    for (int64_t b = 0; b < lv.nbox; ++b)
+                        for (int32_t c = lv.child_begin[b]; c < lv.child_begin[b + 1]; ++c)
+                            if (C.octant[c] == o) {
+                                srcs.push_back(c * C.nslot + lv.cslot[s]);
+                                dsts.push_back((int32_t)(b * lv.nslot + s));
+                                if ((int)srcs.size() == kGemmCols) flush();
+                            }
+                    flush();
+                }
+            dl.m2m = upload_gwork(p, gm);
+            // L2L: per (child octant, parent slot), the children in that
+            // octant, in chunks; summed into the child slot fed by the parent slot
+            GWorkHost gl;
+            for (int o = 0; o < 8; ++o)
+                for (int s = 0; s < lv.nslot; ++s) {
+                    const int cs = lv.cslot[s];
+                    std::vector<int32_t> srcs, dsts;
+                    auto flush = [&]() {
+                        if (!srcs.empty()) gl.add(o * lv.nslot + s, srcs, dsts);
+                        srcs.clear();
+                        dsts.clear();
+                    };
+                    for (int64_t c = 0; c < C.nbox; ++c)
+                        if (C.octant[c] == o) {
+                            srcs.push_back((int32_t)(C.parent[c] * lv.nslot + s));
+                            dsts.push_back((int32_t)(c * C.nslot + cs));
+                            if ((int)srcs.size() == kGemmCols) flush();
+                        }
+                    flush();
+                }
+            dl.l2l = upload_gwork(p, gl);
         }
     }
 }
@@ -360,6 +418,9 @@ int fda_build(const double *verts, int64_t nv, const int32_t *tris, int64_t nt, 
     p->device = o.device;
     rocblas_handle rb = nullptr;
     DevTranslations tr;
+    std::vector<std::vector<int32_t>> lr_rank_host;
+    std::vector<int> tr_rmax(25, 0);
+    std::vector<double> tr_mean(25, 0.0);
     try {
         hip_check(hipSetDevice(o.device), "hipSetDevice");
         host_setup(verts, nv, tris, nt, k, eps, o, p->hp);
@@ -370,6 +431,17 @@ int fda_build(const double *verts, int64_t nv, const int32_t *tris, int64_t nt, 
             if (rocblas_create_handle(&rb) != rocblas_status_success) throw BuildError{FDA_EHIP, "rocblas_create_handle failed"};
             device_factors(p->hp, rb);
             device_translations(p->hp, rb, tr);
+            device_lowrank_m2l(p->hp, rb, tr, kLowRankMax);
+            lr_rank_host.assign(p->hp.depth + 1, {});
+            for (int l = 0; l <= p->hp.depth; ++l) {
+                tr_rmax[l] = tr.rmax[l];
+                tr_mean[l] = tr.mean_rank[l];
+                if (tr.rmax[l] > 0 && p->hp.lv[l].kd <= 256) {
+                    lr_rank_host[l].resize(p->hp.lv[l].offsets.size());
+                    hip_check(hipMemcpy(lr_rank_host[l].data(), tr.lr_rank[l], sizeof(int32_t) * lr_rank_host[l].size(),
+                                        hipMemcpyDeviceToHost), "rank copy");
+                }
+            }
             p->allocs.insert(p->allocs.end(), tr.allocs.begin(), tr.allocs.end());
             p->device_bytes += tr.bytes;
             tr.allocs.clear();
@@ -399,6 +471,28 @@ int fda_build(const double *verts, int64_t nv, const int32_t *tris, int64_t nt, 
     }
     if (rb) rocblas_destroy_handle(rb);
     fill_stats(p->hp, &p->stats);
+    {
+        // M2L flops per level as executed: low-rank levels count
+        // 8 r (kd + ku) per pair with the padded rank of its translation
+        int64_t tot = 0;
+        for (int l = 0; l <= p->hp.depth && l < 24; ++l) {
+            const Level &lv = p->hp.lv[l];
+            double f = 0;
+            if (!lr_rank_host.empty() && !lr_rank_host[l].empty()) {
+                for (const auto &ops : lv.il_ops)
+                    for (int op : ops) f += 8.0 * lr_rank_host[l][op] * (lv.kd + lv.ku);
+                p->stats.m2l_rank_max[l] = tr_rmax[l];
+            } else {
+                int64_t pairs = 0;
+                for (auto &x : lv.il) pairs += (int64_t)x.size();
+                f = 8.0 * pairs * lv.kd * lv.ku;
+            }
+            p->stats.m2l_rank_mean[l] = tr_mean[l];
+            p->stats.m2l_level_flops[l] = f;
+            tot += (int64_t)f;
+        }
+        p->stats.m2l_flops = tot;
+    }
     p->stats.build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     p->stats.device_bytes = p->device_bytes;
     *out = p.release();
@@ -430,7 +524,7 @@ int fda_matvec(fda_plan *plan, const void *x_dev, void *y_dev, int64_t nrhs, int
         ensure_capacity(plan, (int)nrhs);
         hipStream_t st = as_stream(stream);
         hip_check(launch_permute_in(plan->d, (const double2 *)x_dev, ld, plan->xt, (int)nrhs, st), "permute");
-        hip_check(launch_matvec_tree(plan->d, plan->xt, plan->yt, (int)nrhs, st, nullptr), "matvec");
+        hip_check(launch_matvec_tree(plan->d, plan->xt, plan->yt, (int)nrhs, st, nullptr, nullptr), "matvec");
         hip_check(launch_permute_out(plan->d, plan->yt, (double2 *)y_dev, ld, (int)nrhs, st), "permute");
     } catch (const BuildError &e) {
         return fail(e.code, e.msg);
@@ -441,44 +535,59 @@ int fda_matvec(fda_plan *plan, const void *x_dev, void *y_dev, int64_t nrhs, int
 }
 
 int fda_profile_matvec(fda_plan *plan, const void *x_dev, void *y_dev, int64_t nrhs, int64_t ld, int32_t reps,
-                       void *stream, double *out) {
+                       void *stream, fda_profile_result *out) {
     g_last_error.clear();
     if (!plan || !x_dev || !y_dev || !out || reps < 1) return fail(FDA_EINVAL, "bad argument");
     if (nrhs < 1 || nrhs > plan->hp.opt.nrhs_max || ld < plan->d.n) return fail(FDA_EINVAL, "nrhs / ld out of range");
-    hipEvent_t ev[9];
+    std::memset(out, 0, sizeof(*out));
+    hipEvent_t ev[9], lev[48];
     for (auto &e : ev) hipEventCreate(&e);
+    for (auto &e : lev) hipEventCreate(&e);
     int rc = FDA_OK;
     try {
         hip_check(hipSetDevice(plan->device), "hipSetDevice");
         ensure_capacity(plan, (int)nrhs);
         hipStream_t st = as_stream(stream);
-        for (int q = 0; q < 7; ++q) out[q] = 0;
+        const int L = plan->d.depth;
         for (int r = 0; r < reps; ++r) {
             hip_check(hipEventRecord(ev[7], st), "event");
             hip_check(launch_permute_in(plan->d, (const double2 *)x_dev, ld, plan->xt, (int)nrhs, st), "permute");
-            hip_check(launch_matvec_tree(plan->d, plan->xt, plan->yt, (int)nrhs, st, ev), "matvec");
+            // record every level's pair so elapsed-time queries are valid
+            for (int l = 0; l < 24; ++l) {
+                hipEventRecord(lev[2 * l], st);
+                hipEventRecord(lev[2 * l + 1], st);
+            }
+            hip_check(launch_matvec_tree(plan->d, plan->xt, plan->yt, (int)nrhs, st, ev, lev), "matvec");
             hip_check(launch_permute_out(plan->d, plan->yt, (double2 *)y_dev, ld, (int)nrhs, st), "permute");
             hip_check(hipEventRecord(ev[8], st), "event");
             hip_check(hipEventSynchronize(ev[8]), "sync");
             float ms;
+            double *stage[5] = {&out->near_ms, &out->s2m_ms, &out->m2m_ms, &out->m2l_ms, &out->l2l_ms};
             for (int q = 0; q < 5; ++q) {
                 hipEventElapsedTime(&ms, ev[q], ev[q + 1]);
-                out[q] += ms;
+                *stage[q] += ms;
             }
             float a, b;
             hipEventElapsedTime(&a, ev[7], ev[0]);
             hipEventElapsedTime(&b, ev[5], ev[8]);
-            out[5] += a + b;
+            out->l2t_ms += a + b;
             hipEventElapsedTime(&ms, ev[7], ev[8]);
-            out[6] += ms;
+            out->total_ms += ms;
+            for (int l = 0; l <= L && l < 24; ++l) {
+                hipEventElapsedTime(&ms, lev[2 * l], lev[2 * l + 1]);
+                out->m2l_gemm_ms[l] += ms;
+            }
         }
-        for (int q = 0; q < 7; ++q) out[q] /= reps;
+        double *all[7] = {&out->near_ms, &out->s2m_ms, &out->m2m_ms, &out->m2l_ms, &out->l2l_ms, &out->l2t_ms, &out->total_ms};
+        for (auto *v : all) *v /= reps;
+        for (int l = 0; l < 24; ++l) out->m2l_gemm_ms[l] /= reps;
     } catch (const HipError &e) {
         rc = fail(FDA_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
     } catch (const BuildError &e) {
         rc = fail(e.code, e.msg);
     }
     for (auto &e : ev) hipEventDestroy(e);
+    for (auto &e : lev) hipEventDestroy(e);
     return rc;
 }
 
@@ -557,7 +666,7 @@ int bm_solve(fda_plan *plan, const void *b_dev, void *x_dev, int64_t nrhs, int64
             for (int c = 0; c < nr; ++c) nv[c] = std::sqrt(std::max(0.0, o[c].real()));
         };
         auto apply_A = [&](const double2 *in, double2 *out) {
-            hip_check(launch_matvec_tree(plan->d, in, out, nr, s, nullptr), "matvec");
+            hip_check(launch_matvec_tree(plan->d, in, out, nr, s, nullptr, nullptr), "matvec");
         };
         auto apply_M = [&](const double2 *in, double2 *out) {
             if (precond == FDA_PRECOND_BLOCK_JACOBI)

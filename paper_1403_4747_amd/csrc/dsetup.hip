@@ -379,4 +379,100 @@ void device_translations(const HostPlan &hp, rocblas_handle h, DevTranslations &
     }
 }
 
+// Pack U^ = U[:, :r] and V^ = diag(s[:r]) V^H[:r, :] per translation.
+__global__ void k_pack_lowrank(const double2 *U, const double *S, const double2 *Vh, const int32_t *rank, int kd,
+                               int ku, int mn, int rmax, double2 *Ulr, double2 *Vlr) {
+    const int op = blockIdx.y;
+    const int r = rank[op];
+    const double2 *Uo = U + (int64_t)op * kd * mn;
+    const double2 *Vo = Vh + (int64_t)op * mn * ku;
+    const double *So = S + (int64_t)op * mn;
+    double2 *Uout = Ulr + (int64_t)op * kd * rmax;
+    double2 *Vout = Vlr + (int64_t)op * rmax * ku;
+    const int64_t nU = (int64_t)kd * rmax, nV = (int64_t)rmax * ku;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nU + nV; e += (int64_t)gridDim.x * blockDim.x) {
+        if (e < nU) {
+            const int i = (int)(e % kd), j = (int)(e / kd);
+            Uout[e] = (j < r && j < mn) ? Uo[i + (int64_t)j * kd] : make_double2(0.0, 0.0);
+        } else {
+            const int64_t f = e - nU;
+            const int j = (int)(f % rmax), c = (int)(f / rmax);
+            double2 v = make_double2(0.0, 0.0);
+            if (j < r && j < mn) {
+                const double2 q = Vo[j + (int64_t)c * mn];
+                v = make_double2(So[j] * q.x, So[j] * q.y);
+            }
+            Vout[f] = v;
+        }
+    }
+}
+
+void device_lowrank_m2l(const HostPlan &hp, rocblas_handle h, DevTranslations &out, int max_rank) {
+    const int L = hp.depth;
+    out.Ulr.assign(L + 1, nullptr);
+    out.Vlr.assign(L + 1, nullptr);
+    out.lr_rank.assign(L + 1, nullptr);
+    out.rmax.assign(L + 1, 0);
+    out.mean_rank.assign(L + 1, 0.0);
+    for (int l = hp.top; l <= L; ++l) {
+        const Level &lv = hp.lv[l];
+        const int noff = (int)lv.offsets.size();
+        if (noff == 0) continue;
+        const int kd = lv.kd, ku = lv.ku, mn = std::min(kd, ku);
+        const size_t ksz = (size_t)kd * ku;
+        DBuf A(sizeof(double2) * ksz * noff), dS(sizeof(double) * (size_t)mn * noff),
+            dU(sizeof(double2) * (size_t)kd * mn * noff), dV(sizeof(double2) * (size_t)mn * ku * noff),
+            dE(sizeof(double) * (size_t)mn * noff), dinfo(sizeof(rocblas_int) * noff);
+        hchk(hipMemcpy(A.p, out.K[l], sizeof(double2) * ksz * noff, hipMemcpyDeviceToDevice), "copy K");
+        rchk(rocsolver_zgesvd_strided_batched(h, rocblas_svect_singular, rocblas_svect_singular, kd, ku,
+                                              A.as<rocblas_double_complex>(), kd, (rocblas_stride)ksz, dS.as<double>(),
+                                              mn, dU.as<rocblas_double_complex>(), kd, (rocblas_stride)kd * mn,
+                                              dV.as<rocblas_double_complex>(), mn, (rocblas_stride)mn * ku,
+                                              dE.as<double>(), mn, rocblas_outofplace, dinfo.as<rocblas_int>(), noff),
+             "zgesvd (M2L)");
+        std::vector<double> S((size_t)mn * noff);
+        std::vector<rocblas_int> info(noff);
+        hchk(hipMemcpy(S.data(), dS.p, sizeof(double) * S.size(), hipMemcpyDeviceToHost), "d2h");
+        hchk(hipMemcpy(info.data(), dinfo.p, sizeof(rocblas_int) * noff, hipMemcpyDeviceToHost), "d2h");
+        std::vector<int32_t> rank(noff);
+        int rmax = 0;
+        double rsum = 0;
+        for (int o = 0; o < noff; ++o) {
+            if (info[o] != 0) throw BuildError{FDA_EHIP, "SVD of a reduced M2L matrix did not converge"};
+            const double *so = S.data() + (size_t)o * mn;
+            int r = 0;
+            while (r < mn && so[r] >= hp.svd_eps * so[0] && so[0] > 0) ++r;
+            r = std::max(r, 1);
+            rsum += r;
+            r = std::min(mn, (r + 3) / 4 * 4);
+            rank[o] = r;
+            rmax = std::max(rmax, r);
+        }
+        out.mean_rank[l] = rsum / noff;
+        // low rank pays when 2 r < k (Section 4.2); kernel limit max_rank
+        if (rmax > max_rank || 2 * rmax >= mn) continue;
+        double2 *Ulr = nullptr, *Vlr = nullptr;
+        int32_t *dr = nullptr;
+        auto keep = [&](size_t bytes) {
+            void *q = nullptr;
+            if (hipMalloc(&q, std::max<size_t>(bytes, 16)) != hipSuccess) throw BuildError{FDA_ENOMEM, "hipMalloc failed"};
+            out.allocs.push_back(q);
+            out.bytes += (int64_t)bytes;
+            return q;
+        };
+        Ulr = (double2 *)keep(sizeof(double2) * (size_t)kd * rmax * noff);
+        Vlr = (double2 *)keep(sizeof(double2) * (size_t)rmax * ku * noff);
+        dr = (int32_t *)keep(sizeof(int32_t) * noff);
+        hchk(hipMemcpy(dr, rank.data(), sizeof(int32_t) * noff, hipMemcpyHostToDevice), "h2d");
+        hipLaunchKernelGGL(k_pack_lowrank, dim3(64, noff), dim3(256), 0, nullptr, dU.as<double2>(), dS.as<double>(),
+                           dV.as<double2>(), dr, kd, ku, mn, rmax, Ulr, Vlr);
+        hchk(hipGetLastError(), "pack");
+        hchk(hipDeviceSynchronize(), "pack sync");
+        out.Ulr[l] = Ulr;
+        out.Vlr[l] = Vlr;
+        out.lr_rank[l] = dr;
+        out.rmax[l] = rmax;
+    }
+}
+
 }  // namespace fda

@@ -217,137 +217,243 @@ __global__ void k_s2m(const int64_t *leaf_off, const double2 *S, int ku, const d
 
 #define FDA_MAXR 4  // rows per thread: ranks up to 4 * blockDim
 
-// Parent outgoing states from the children (M2M).
-__global__ void k_m2m(int nslotP, int kuP, const int32_t *child_begin, const int32_t *octant, int nslotC, int kuC,
-                      const int32_t *cslot, const double2 *M, const double2 *sC, double2 *sP, int64_t strideC,
-                      int64_t strideP) {
-    extern __shared__ double2 v[];
-    const int g = blockIdx.x;
-    const int P = g / nslotP, sl = g - P * nslotP;
-    const int cs = cslot[sl];
-    const double2 *sCr = sC + (int64_t)blockIdx.y * strideC;
-    double2 acc[FDA_MAXR];
-    for (int q = 0; q < FDA_MAXR; ++q) acc[q] = make_double2(0.0, 0.0);
-    for (int c = child_begin[P]; c < child_begin[P + 1]; ++c) {
-        __syncthreads();
-        for (int j = threadIdx.x; j < kuC; j += blockDim.x) v[j] = sCr[((int64_t)c * nslotC + cs) * kuC + j];
-        __syncthreads();
-        const double2 *Mo = M + ((int64_t)octant[c] * nslotP + sl) * kuP * kuC;
-        for (int q = 0; q < FDA_MAXR; ++q) {
-            int r = threadIdx.x + q * blockDim.x;
-            if (r >= kuP) break;
-            for (int j = 0; j < kuC; ++j) cfma(acc[q], Mo[r + (int64_t)j * kuP], v[j]);
-        }
-    }
-    double2 *out = sP + (int64_t)blockIdx.y * strideP + ((int64_t)P * nslotP + sl) * kuP;
-    for (int q = 0; q < FDA_MAXR; ++q) {
-        int r = threadIdx.x + q * blockDim.x;
-        if (r < kuP) out[r] = acc[q];
-    }
-}
-
-// Reduced M2L translations grouped by translation (eq. (eq_m2l) in the
-// compressed form of eq. (eq_cmpm2l)): every interaction pair with the same
-// lattice offset shares one matrix K~, so each work item multiplies K~ by up
-// to M2L_NB gathered source states (a small complex GEMM) and writes the
-// products to a per-pair buffer.  Work items of one translation are mapped
-// to the same XCD so K~ is shared through that XCD's L2.
-#define M2L_NB 32
-#define M2L_J 32
-__global__ void __launch_bounds__(256) k_m2l_gemm(const int4 *work, const int32_t *pp_src, const double2 *K, int kd,
-                                                  int ku, const double2 *s, double2 *tmp, int64_t sstride,
-                                                  int64_t tstride, int nwork) {
-    __shared__ double2 S[M2L_J][M2L_NB];
-    // XCD-aware mapping: consecutive hardware workgroups go round-robin over
-    // the 8 XCDs; give each XCD a contiguous range of work items (the grid is
-    // a multiple of 8, so each XCD runs exactly `per` workgroups).
+// Gathered batched GEMM shared by M2M, M2L and L2L, on the FP64 matrix
+// cores (v_mfma_f64_16x16x4f64).  A work item multiplies one translation
+// matrix (m x kin, column-major) by up to GG_NB gathered input states and
+// writes the m-vectors to consecutive columns of a scratch buffer:
+//   T[:, tcol + b] = A[mat] X[src[b]]   (src = -1: zero column).
+//   M2L: one matrix per distinct translation (eq. (eq_m2l) compressed by
+//        eq. (eq_cmpm2l)), columns = the interaction pairs sharing it.
+//   M2M: one matrix per (child octant, direction) (Section 4.3), columns =
+//        the parents with a child in that octant.
+//   L2L: one matrix per (child octant, parent direction), columns = the
+//        children in that octant.
+// A second kernel sums the scratch columns of every destination state in a
+// fixed order (deterministic results).
+// MFMA operand layout per wave: A (16 x 4) lane l holds row l % 16, column
+// l / 16; B (4 x 16) lane l holds row l / 16, column l % 16; the f64 16 x 16
+// result gives lane l rows l / 16 + 4 v (v = 0..3), column l % 16.  A complex
+// product is four real products: Re += Ar Br - Ai Bi, Im += Ar Bi + Ai Br.
+// The 4 waves of a block take row tiles w, w + 4, ... of a 256-row band.
+// Work items of consecutive index are mapped to the same XCD so that the
+// shared translation matrices stay in that XCD's L2.
+#define GG_NB 32
+#define GG_J 32
+typedef double d4_t __attribute__((ext_vector_type(4)));
+#define MF_RT 4
+__global__ void __launch_bounds__(256) k_ggemm(const int4 *hdr, const int32_t *src, const double2 *A, int m, int kin,
+                                               const double2 *X, int64_t xstride, double2 *T, int64_t tstride,
+                                               int nwork) {
+    __shared__ double2 S[GG_J][GG_NB];
     const int nx = 8;
     const int per = gridDim.x / nx;
     const int w = (blockIdx.x % nx) * per + blockIdx.x / nx;
     if (w >= nwork) return;
-    const int4 wk = work[w];  // (op, first pair, pair count, 0)
-    const double2 *Kp = K + (int64_t)wk.x * kd * ku;
-    const double2 *sr = s + (int64_t)blockIdx.y * sstride;
-    const int p0 = wk.y, nb = wk.z;
-    for (int r0 = 0; r0 < kd; r0 += blockDim.x) {
-        const int r = r0 + threadIdx.x;
-        double2 acc[M2L_NB];
+    const int4 h = hdr[w];  // (matrix, first scratch column, column count, 0)
+    const double2 *Xr = X + (int64_t)blockIdx.y * xstride;
+    double2 *Tr = T + (int64_t)blockIdx.y * tstride + (int64_t)h.y * m;
+    const double2 *At = A + (int64_t)h.x * m * kin;
+    const int32_t *st = src + (int64_t)w * GG_NB;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    for (int band = 0; band < m; band += 64 * MF_RT) {
+        const int ntile = min(MF_RT * 4, (m - band + 15) >> 4);
+        d4_t accR[MF_RT][2], accI[MF_RT][2];
 #pragma unroll
-        for (int b = 0; b < M2L_NB; ++b) acc[b] = make_double2(0.0, 0.0);
-        for (int j0 = 0; j0 < ku; j0 += M2L_J) {
+        for (int q = 0; q < MF_RT; ++q)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                accR[q][c] = (d4_t){0.0, 0.0, 0.0, 0.0};
+                accI[q][c] = (d4_t){0.0, 0.0, 0.0, 0.0};
+            }
+        for (int j0 = 0; j0 < kin; j0 += GG_J) {
             __syncthreads();
-            for (int e = threadIdx.x; e < M2L_J * M2L_NB; e += blockDim.x) {
-                const int jj = e % M2L_J, b = e / M2L_J;
+            for (int e = threadIdx.x; e < GG_J * GG_NB; e += blockDim.x) {
+                const int jj = e % GG_J, b = e / GG_J;
+                const int sb = st[b];
                 double2 v = make_double2(0.0, 0.0);
-                if (b < nb && j0 + jj < ku) v = sr[(int64_t)pp_src[p0 + b] * ku + j0 + jj];
+                if (sb >= 0 && j0 + jj < kin) v = Xr[(int64_t)sb * kin + j0 + jj];
                 S[jj][b] = v;
             }
             __syncthreads();
-            if (r < kd) {
-                const int jm = min(M2L_J, ku - j0);
-                const double2 *Kc = Kp + r + (int64_t)j0 * kd;
-                for (int jj = 0; jj < jm; ++jj) {
-                    const double2 a = Kc[(int64_t)jj * kd];
+            const int jm = min(GG_J, kin - j0);
+            for (int kk = 0; kk < jm; kk += 4) {
+                const int kcol = j0 + kk + lk;
+                const double2 b0 = S[kk + lk][li], b1 = S[kk + lk][16 + li];
 #pragma unroll
-                    for (int b = 0; b < M2L_NB; ++b) cfma(acc[b], a, S[jj][b]);
+                for (int q = 0; q < MF_RT; ++q) {
+                    const int rt = wave + 4 * q;
+                    if (rt >= ntile) break;
+                    const int row = band + rt * 16 + li;
+                    double2 a = make_double2(0.0, 0.0);
+                    if (row < m && kcol < kin) a = At[row + (int64_t)kcol * m];
+                    accR[q][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b0.x, accR[q][0], 0, 0, 0);
+                    accR[q][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b0.y, accR[q][0], 0, 0, 0);
+                    accI[q][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b0.y, accI[q][0], 0, 0, 0);
+                    accI[q][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b0.x, accI[q][0], 0, 0, 0);
+                    accR[q][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b1.x, accR[q][1], 0, 0, 0);
+                    accR[q][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b1.y, accR[q][1], 0, 0, 0);
+                    accI[q][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b1.y, accI[q][1], 0, 0, 0);
+                    accI[q][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b1.x, accI[q][1], 0, 0, 0);
                 }
             }
         }
-        if (r < kd) {
-            double2 *out = tmp + (int64_t)blockIdx.y * tstride + (int64_t)p0 * kd + r;
-            for (int b = 0; b < nb; ++b) out[(int64_t)b * kd] = acc[b];
+#pragma unroll
+        for (int q = 0; q < MF_RT; ++q) {
+            const int rt = wave + 4 * q;
+            if (rt >= ntile) break;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const int col = c * 16 + li;
+                if (col >= h.z) continue;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = band + rt * 16 + lk + 4 * v;
+                    if (row < m) Tr[(int64_t)col * m + row] = make_double2(accR[q][c][v], accI[q][c][v]);
+                }
+            }
         }
     }
 }
 
-// c[target] += sum of the per-pair products of the target's interaction list
-// (fixed order: deterministic).
-__global__ void k_m2l_reduce(const int32_t *tg_state, const int32_t *tg_off, const int32_t *tg_pairs, int kd,
-                             const double2 *tmp, double2 *c, int64_t tstride, int64_t cstride) {
+// Low-rank reduced M2L (Section 4.2, eq. (eq_epsk)): K~ = U^ V^ with rank r
+// per translation, so each work item first forms Z = V^ S (r x 32) and then
+// U^ Z (kd x 32), both on the FP64 matrix cores; Z stays in LDS.  Same work
+// list, scratch layout and reduction as k_ggemm.
+#define LR_MAX 80
+__global__ void __launch_bounds__(256) k_m2l_lowrank(const int4 *hdr, const int32_t *src, const double2 *Ulr,
+                                                     const double2 *Vlr, const int32_t *rank, int kd, int ku,
+                                                     int rmax, const double2 *X, int64_t xstride, double2 *T,
+                                                     int64_t tstride, int nwork) {
+    __shared__ double2 S[GG_J][GG_NB];
+    __shared__ double2 Z[LR_MAX][GG_NB];
+    const int nx = 8;
+    const int per = gridDim.x / nx;
+    const int w = (blockIdx.x % nx) * per + blockIdx.x / nx;
+    if (w >= nwork) return;
+    const int4 h = hdr[w];
+    const int op = h.x;
+    const int r = rank[op];
+    const double2 *Xr = X + (int64_t)blockIdx.y * xstride;
+    double2 *Tr = T + (int64_t)blockIdx.y * tstride + (int64_t)h.y * kd;
+    const double2 *Vt = Vlr + (int64_t)op * rmax * ku;
+    const double2 *Ut = Ulr + (int64_t)op * kd * rmax;
+    const int32_t *st = src + (int64_t)w * GG_NB;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    // phase 1: Z = V^[0:r, :] S
+    const int ztiles = (r + 15) >> 4;
+    d4_t zR[2][2], zI[2][2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            zR[q][c] = (d4_t){0.0, 0.0, 0.0, 0.0};
+            zI[q][c] = (d4_t){0.0, 0.0, 0.0, 0.0};
+        }
+    for (int j0 = 0; j0 < ku; j0 += GG_J) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < GG_J * GG_NB; e += blockDim.x) {
+            const int jj = e % GG_J, b = e / GG_J;
+            const int sb = st[b];
+            double2 v = make_double2(0.0, 0.0);
+            if (sb >= 0 && j0 + jj < ku) v = Xr[(int64_t)sb * ku + j0 + jj];
+            S[jj][b] = v;
+        }
+        __syncthreads();
+        const int jm = min(GG_J, ku - j0);
+        for (int kk = 0; kk < jm; kk += 4) {
+            const int kcol = j0 + kk + lk;
+            const double2 b0 = S[kk + lk][li], b1 = S[kk + lk][16 + li];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int zt = wave + 4 * q;
+                if (zt >= ztiles) break;
+                const int row = zt * 16 + li;
+                double2 a = make_double2(0.0, 0.0);
+                if (row < r && kcol < ku) a = Vt[row + (int64_t)kcol * rmax];
+                zR[q][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b0.x, zR[q][0], 0, 0, 0);
+                zR[q][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b0.y, zR[q][0], 0, 0, 0);
+                zI[q][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b0.y, zI[q][0], 0, 0, 0);
+                zI[q][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b0.x, zI[q][0], 0, 0, 0);
+                zR[q][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b1.x, zR[q][1], 0, 0, 0);
+                zR[q][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b1.y, zR[q][1], 0, 0, 0);
+                zI[q][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b1.y, zI[q][1], 0, 0, 0);
+                zI[q][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b1.x, zI[q][1], 0, 0, 0);
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int zt = wave + 4 * q;
+        if (zt >= ztiles) break;
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) Z[zt * 16 + lk + 4 * v][c * 16 + li] = make_double2(zR[q][c][v], zI[q][c][v]);
+    }
+    __syncthreads();
+    // phase 2: Y = U^[:, 0:r] Z
+    const int ntile = (kd + 15) >> 4;
+    d4_t accR[MF_RT][2], accI[MF_RT][2];
+#pragma unroll
+    for (int q = 0; q < MF_RT; ++q)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            accR[q][c] = (d4_t){0.0, 0.0, 0.0, 0.0};
+            accI[q][c] = (d4_t){0.0, 0.0, 0.0, 0.0};
+        }
+    for (int kk = 0; kk < r; kk += 4) {
+        const double2 b0 = Z[kk + lk][li], b1 = Z[kk + lk][16 + li];
+#pragma unroll
+        for (int q = 0; q < MF_RT; ++q) {
+            const int rt = wave + 4 * q;
+            if (rt >= ntile) break;
+            const int row = rt * 16 + li;
+            double2 a = make_double2(0.0, 0.0);
+            if (row < kd) a = Ut[row + (int64_t)(kk + lk) * kd];
+            accR[q][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b0.x, accR[q][0], 0, 0, 0);
+            accR[q][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b0.y, accR[q][0], 0, 0, 0);
+            accI[q][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b0.y, accI[q][0], 0, 0, 0);
+            accI[q][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b0.x, accI[q][0], 0, 0, 0);
+            accR[q][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b1.x, accR[q][1], 0, 0, 0);
+            accR[q][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b1.y, accR[q][1], 0, 0, 0);
+            accI[q][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b1.y, accI[q][1], 0, 0, 0);
+            accI[q][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b1.x, accI[q][1], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < MF_RT; ++q) {
+        const int rt = wave + 4 * q;
+        if (rt >= ntile) break;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int col = c * 16 + li;
+            if (col >= h.z) continue;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = rt * 16 + lk + 4 * v;
+                if (row < kd) Tr[(int64_t)col * kd + row] = make_double2(accR[q][c][v], accI[q][c][v]);
+            }
+        }
+    }
+}
+
+// Y[dst] (+)= sum of the scratch columns listed for dst, in list order.
+__global__ void k_gather_reduce(const int32_t *dst, const int32_t *off, const int32_t *list, int m,
+                                const double2 *T, int64_t tstride, double2 *Y, int64_t ystride, int accumulate) {
     const int t = blockIdx.x;
-    const double2 *tr = tmp + (int64_t)blockIdx.y * tstride;
-    double2 *out = c + (int64_t)blockIdx.y * cstride + (int64_t)tg_state[t] * kd;
-    for (int r = threadIdx.x; r < kd; r += blockDim.x) {
-        double2 acc = out[r];
-        for (int q = tg_off[t]; q < tg_off[t + 1]; ++q) {
-            double2 v = tr[(int64_t)tg_pairs[q] * kd + r];
+    const double2 *Tr = T + (int64_t)blockIdx.y * tstride;
+    double2 *out = Y + (int64_t)blockIdx.y * ystride + (int64_t)dst[t] * m;
+    for (int r = threadIdx.x; r < m; r += blockDim.x) {
+        double2 acc = accumulate ? out[r] : make_double2(0.0, 0.0);
+        for (int q = off[t]; q < off[t + 1]; ++q) {
+            double2 v = Tr[(int64_t)list[q] * m + r];
             acc.x += v.x;
             acc.y += v.y;
         }
         out[r] = acc;
-    }
-}
-
-// Child incoming states += L2L of the parent's incoming states.
-__global__ void k_l2l(int nslotC, int kdC, const int32_t *parent, const int32_t *octant, int nslotP, int kdP,
-                      const int32_t *src_off, const int32_t *src, const double2 *Lo, const double2 *cP, double2 *cC,
-                      int64_t strideP, int64_t strideC) {
-    extern __shared__ double2 v[];
-    const int g = blockIdx.x;
-    const int C = g / nslotC, cs = g - C * nslotC;
-    const int P = parent[C], o = octant[C];
-    const double2 *cPr = cP + (int64_t)blockIdx.y * strideP;
-    double2 acc[FDA_MAXR];
-    for (int q = 0; q < FDA_MAXR; ++q) acc[q] = make_double2(0.0, 0.0);
-    for (int t = src_off[cs]; t < src_off[cs + 1]; ++t) {
-        const int ps = src[t];
-        __syncthreads();
-        for (int j = threadIdx.x; j < kdP; j += blockDim.x) v[j] = cPr[((int64_t)P * nslotP + ps) * kdP + j];
-        __syncthreads();
-        const double2 *Lm = Lo + ((int64_t)o * nslotP + ps) * kdC * kdP;
-        for (int q = 0; q < FDA_MAXR; ++q) {
-            int r = threadIdx.x + q * blockDim.x;
-            if (r >= kdC) break;
-            for (int j = 0; j < kdP; ++j) cfma(acc[q], Lm[r + (int64_t)j * kdC], v[j]);
-        }
-    }
-    double2 *out = cC + (int64_t)blockIdx.y * strideC + ((int64_t)C * nslotC + cs) * kdC;
-    for (int q = 0; q < FDA_MAXR; ++q) {
-        int r = threadIdx.x + q * blockDim.x;
-        if (r < kdC) {
-            double2 ov = out[r];
-            out[r] = make_double2(ov.x + acc[q].x, ov.y + acc[q].y);
-        }
     }
 }
 
@@ -608,6 +714,39 @@ hipError_t launch_bj_invert(const DevPlan &d, hipStream_t st) {
     return hipSuccess;
 }
 
+hipError_t launch_ggemm(const GWork &g, const double2 *A, int m, int kin, const double2 *X, int64_t xstride,
+                        double2 *Y, int64_t ystride, int accumulate, int nrhs, hipStream_t st, hipEvent_t *ev) {
+    if (g.nwork == 0) return hipSuccess;
+    // a multiple of 8 workgroups so every XCD runs the same share
+    const int grid = (g.nwork + 7) / 8 * 8;
+    const int64_t tstride = g.ncol * m;
+    if (ev) hipEventRecord(ev[0], st);
+    hipLaunchKernelGGL(k_ggemm, dim3(grid, nrhs), dim3(256), 0, st, g.hdr, g.src, A, m, kin, X, xstride, g.tmp,
+                       tstride, g.nwork);
+    CHECK_LAUNCH();
+    if (ev) hipEventRecord(ev[1], st);
+    hipLaunchKernelGGL(k_gather_reduce, dim3(g.nred, nrhs), dim3(std::min(256, ((m + 63) / 64) * 64)), 0, st,
+                       g.rd_dst, g.rd_off, g.rd_list, m, g.tmp, tstride, Y, ystride, accumulate);
+    CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+hipError_t launch_m2l_lowrank(const DevLevel &lv, int nrhs, hipStream_t st, hipEvent_t *ev) {
+    const GWork &g = lv.m2l;
+    if (g.nwork == 0) return hipSuccess;
+    const int grid = (g.nwork + 7) / 8 * 8;
+    const int64_t tstride = g.ncol * lv.kd;
+    if (ev) hipEventRecord(ev[0], st);
+    hipLaunchKernelGGL(k_m2l_lowrank, dim3(grid, nrhs), dim3(256), 0, st, g.hdr, g.src, lv.Ulr, lv.Vlr, lv.lr_rank,
+                       lv.kd, lv.ku, lv.rmax, lv.s, lv.sstride, g.tmp, tstride, g.nwork);
+    CHECK_LAUNCH();
+    if (ev) hipEventRecord(ev[1], st);
+    hipLaunchKernelGGL(k_gather_reduce, dim3(g.nred, nrhs), dim3(std::min(256, ((lv.kd + 63) / 64) * 64)), 0, st,
+                       g.rd_dst, g.rd_off, g.rd_list, lv.kd, g.tmp, tstride, lv.c, lv.cstride, 1);
+    CHECK_LAUNCH();
+    return hipSuccess;
+}
+
 static int grid1(int64_t n) {
     int64_t g = (n + 255) / 256;
     return (int)std::min<int64_t>(std::max<int64_t>(g, 1), 4096);
@@ -616,7 +755,7 @@ static int grid1(int64_t n) {
 // Stage timings are recorded when ev != nullptr (7 events: start, after
 // near, after S2M, after M2M, after M2L, after L2L, end).
 hipError_t launch_matvec_tree(const DevPlan &d, const double2 *xt, double2 *yt, int nrhs, hipStream_t st,
-                              hipEvent_t *ev) {
+                              hipEvent_t *ev, hipEvent_t *lev) {
     const int64_t N = d.n;
     if (ev) hipEventRecord(ev[0], st);
     hipLaunchKernelGGL(k_p2p, dim3(d.nleaf, nrhs), dim3(256), sizeof(double2) * d.max_ncol, st, d.leaf_off,
@@ -635,9 +774,8 @@ hipError_t launch_matvec_tree(const DevPlan &d, const double2 *xt, double2 *yt, 
     if (ev) hipEventRecord(ev[2], st);
     for (int l = L - 1; l >= top; --l) {
         const DevLevel &P = d.lv[l], &C = d.lv[l + 1];
-        hipLaunchKernelGGL(k_m2m, dim3(P.nbox * P.nslot, nrhs), dim3(256), sizeof(double2) * C.ku, st, P.nslot, P.ku,
-                           P.child_begin, C.octant, C.nslot, C.ku, P.cslot, P.M, C.s, P.s, C.sstride, P.sstride);
-        CHECK_LAUNCH();
+        hipError_t e = launch_ggemm(P.m2m, P.M, P.ku, C.ku, C.s, C.sstride, P.s, P.sstride, 0, nrhs, st, nullptr);
+        if (e != hipSuccess) return e;
     }
     if (ev) hipEventRecord(ev[3], st);
     for (int l = top; l <= L; ++l) {
@@ -645,25 +783,19 @@ hipError_t launch_matvec_tree(const DevPlan &d, const double2 *xt, double2 *yt, 
         int64_t n = lv.cstride * nrhs;
         hipLaunchKernelGGL(k_fill_zero, dim3(grid1(n)), dim3(256), 0, st, lv.c, n);
         CHECK_LAUNCH();
-        if (lv.nwork > 0) {
-            const int bs = std::min(256, ((lv.kd + 63) / 64) * 64);
-            // a multiple of 8 workgroups so every XCD gets the same share
-            const int grid = (lv.nwork + 7) / 8 * 8;
-            hipLaunchKernelGGL(k_m2l_gemm, dim3(grid, nrhs), dim3(bs), 0, st, lv.work, lv.pp_src, lv.K, lv.kd,
-                               lv.ku, lv.s, lv.tmp, lv.sstride, lv.tstride, lv.nwork);
-            CHECK_LAUNCH();
-            hipLaunchKernelGGL(k_m2l_reduce, dim3(lv.ntgt, nrhs), dim3(std::min(256, ((lv.kd + 63) / 64) * 64)), 0,
-                               st, lv.tg_state, lv.tg_off, lv.tg_pairs, lv.kd, lv.tmp, lv.c, lv.tstride, lv.cstride);
-            CHECK_LAUNCH();
-        }
+        hipError_t e;
+        if (lv.rmax > 0)
+            e = launch_m2l_lowrank(lv, nrhs, st, lev ? lev + 2 * l : nullptr);
+        else
+            e = launch_ggemm(lv.m2l, lv.K, lv.kd, lv.ku, lv.s, lv.sstride, lv.c, lv.cstride, 1, nrhs, st,
+                             lev ? lev + 2 * l : nullptr);
+        if (e != hipSuccess) return e;
     }
     if (ev) hipEventRecord(ev[4], st);
     for (int l = top; l < L; ++l) {
         const DevLevel &P = d.lv[l], &C = d.lv[l + 1];
-        hipLaunchKernelGGL(k_l2l, dim3(C.nbox * C.nslot, nrhs), dim3(256), sizeof(double2) * P.kd, st, C.nslot, C.kd,
-                           C.parent, C.octant, P.nslot, P.kd, P.l2l_off, P.l2l_src, P.Lo, P.c, C.c, P.cstride,
-                           C.cstride);
-        CHECK_LAUNCH();
+        hipError_t e = launch_ggemm(P.l2l, P.Lo, C.kd, P.kd, P.c, P.cstride, C.c, C.cstride, 1, nrhs, st, nullptr);
+        if (e != hipSuccess) return e;
     }
     if (ev) hipEventRecord(ev[5], st);
     hipLaunchKernelGGL(k_l2t, dim3(d.nleaf, nrhs), dim3(64), sizeof(double2) * lf.kd, st, d.leaf_off, d.T, lf.kd,

@@ -8,25 +8,34 @@
 
 namespace fda {
 
+// Work list of the gathered batched GEMM (k_ggemm) and of its reduction:
+// per work item (matrix, first scratch column, column count, 0) and
+// kGemmCols source states; per destination state the scratch columns summed
+// into it.  tmp holds ncol scratch columns of length m per right-hand side.
+struct GWork {
+    int nwork = 0, nred = 0;
+    int64_t ncol = 0;
+    int4 *hdr = nullptr;
+    int32_t *src = nullptr, *rd_dst = nullptr, *rd_off = nullptr, *rd_list = nullptr;
+    double2 *tmp = nullptr;
+};
+
+constexpr int kGemmCols = 32;
+
 struct DevLevel {
     int64_t nbox = 0;
     int nslot = 1, ku = 0, kd = 0;
     int64_t sstride = 0, cstride = 0;  // elements per right-hand side of s and c
     double2 *s = nullptr, *c = nullptr;
-    // M2L grouped by translation: work items (op, first pair, count), the
-    // source state of every pair (pairs sorted by translation), and per
-    // target state the positions of its pairs
-    int nwork = 0, ntgt = 0;
-    int64_t npair = 0, tstride = 0;
-    int4 *work = nullptr;
-    int32_t *pp_src = nullptr, *tg_state = nullptr, *tg_off = nullptr, *tg_pairs = nullptr;
+    // M2L grouped by translation; low-rank factors when rmax > 0
+    GWork m2l;
+    double2 *Ulr = nullptr, *Vlr = nullptr;
+    int32_t *lr_rank = nullptr;
+    int rmax = 0;
     double2 *K = nullptr;
-    double2 *tmp = nullptr;  // per-pair products (npair x kd per right-hand side)
-    // tree links (this level's boxes)
-    int32_t *parent = nullptr, *octant = nullptr, *child_begin = nullptr;
-    // parent-level operators towards level + 1
+    // parent-level operators towards level + 1 and their work lists
     double2 *M = nullptr, *Lo = nullptr;
-    int32_t *cslot = nullptr, *l2l_off = nullptr, *l2l_src = nullptr;
+    GWork m2m, l2l;
 };
 
 struct DevPlan {
@@ -52,8 +61,10 @@ hipError_t set_quadrature_constants(const double r7b[7][3], const double r7w[7],
                                     const double glw[32]);
 hipError_t launch_near_blocks(const DevPlan &d, hipStream_t st);
 hipError_t launch_bj_invert(const DevPlan &d, hipStream_t st);
+// ev: 7 stage events or null; lev: 2 events per level around its M2L
+// product kernel, or null.
 hipError_t launch_matvec_tree(const DevPlan &d, const double2 *xt, double2 *yt, int nrhs, hipStream_t st,
-                              hipEvent_t *ev);
+                              hipEvent_t *ev, hipEvent_t *lev);
 hipError_t launch_permute_in(const DevPlan &d, const double2 *x, int64_t ld, double2 *xt, int nrhs, hipStream_t st);
 hipError_t launch_permute_out(const DevPlan &d, const double2 *yt, double2 *y, int64_t ld, int nrhs, hipStream_t st);
 hipError_t launch_rhs_planewave(const DevPlan &d, const double *dirs_dev, int nrhs, double2 *b, int64_t ld,
@@ -68,6 +79,10 @@ hipError_t launch_sub(const double2 *b, const double2 *y, double2 *r, int64_t n,
 hipError_t launch_bj_apply(const DevPlan &d, const double2 *r, double2 *z, int nrhs, const int32_t *active,
                            hipStream_t st);
 hipError_t launch_fill_zero(double2 *p, int64_t n, hipStream_t st);
+constexpr int kLowRankMax = 80;  // largest rank the low-rank M2L kernel holds in LDS
+hipError_t launch_m2l_lowrank(const DevLevel &lv, int nrhs, hipStream_t st, hipEvent_t *ev);
+hipError_t launch_ggemm(const GWork &g, const double2 *A, int m, int kin, const double2 *X, int64_t xstride,
+                        double2 *Y, int64_t ystride, int accumulate, int nrhs, hipStream_t st, hipEvent_t *ev);
 
 // Blocks used by the two-pass reductions.
 constexpr int kRedBlocks = 240;

@@ -50,7 +50,8 @@ class Stats(ctypes.Structure):
         ("boxes", ctypes.c_int64 * 24), ("m2l_pairs", ctypes.c_int64 * 24), ("m2l_offsets", ctypes.c_int64 * 24),
         ("hf", ctypes.c_int32 * 24), ("ndir", ctypes.c_int32 * 24), ("active_dirs", ctypes.c_int32 * 24),
         ("p", ctypes.c_int32 * 24), ("rank_up", ctypes.c_int32 * 24), ("rank_dn", ctypes.c_int32 * 24),
-        ("m2l_flops", ctypes.c_int64), ("m2l_bytes", ctypes.c_int64), ("h_max", ctypes.c_double),
+        ("m2l_rank_max", ctypes.c_int32 * 24), ("m2l_rank_mean", ctypes.c_double * 24),
+        ("m2l_level_flops", ctypes.c_double * 24), ("m2l_flops", ctypes.c_int64), ("m2l_bytes", ctypes.c_int64), ("h_max", ctypes.c_double),
         ("root_width", ctypes.c_double), ("build_seconds", ctypes.c_double), ("device_bytes", ctypes.c_int64),
     ]
 
@@ -63,6 +64,14 @@ class Stats(ctypes.Structure):
                 v = list(v)[: L + 1]
             d[name] = v
         return d
+
+
+class ProfileResult(ctypes.Structure):
+    _fields_ = [
+        ("near_ms", ctypes.c_double), ("s2m_ms", ctypes.c_double), ("m2m_ms", ctypes.c_double),
+        ("m2l_ms", ctypes.c_double), ("l2l_ms", ctypes.c_double), ("l2t_ms", ctypes.c_double),
+        ("total_ms", ctypes.c_double), ("m2l_gemm_ms", ctypes.c_double * 24),
+    ]
 
 
 class SolveStats(ctypes.Structure):
@@ -97,7 +106,7 @@ def library():
         L.bm_solve.restype = ctypes.c_int
         L.fda_plan_stats.argtypes = [vp, ctypes.POINTER(Stats)]
         L.fda_plan_stats.restype = ctypes.c_int
-        L.fda_profile_matvec.argtypes = [vp, vp, vp, i64, i64, ctypes.c_int32, vp, ctypes.POINTER(ctypes.c_double)]
+        L.fda_profile_matvec.argtypes = [vp, vp, vp, i64, i64, ctypes.c_int32, vp, ctypes.POINTER(ProfileResult)]
         L.fda_profile_matvec.restype = ctypes.c_int
         L.fda_free.argtypes = [vp]
         L.fda_last_error.restype = ctypes.c_char_p
@@ -232,15 +241,17 @@ class Plan:
         _err(library().fda_plan_stats(self._h, ctypes.byref(st)))
         return st.to_dict()
 
-    def profile(self, x, reps: int = 10, out=None) -> Dict[str, float]:
-        """Per-stage HIP-event timings (ms) of fda_matvec."""
+    def profile(self, x, reps: int = 10, out=None) -> Dict:
+        """Per-stage HIP-event timings (ms) of fda_matvec, plus the M2L
+        product kernel of every level (key "m2l_gemm", a list per level)."""
         import torch
 
         nrhs = self._check_vec(x, self.n)
         y = torch.empty_like(x) if out is None else out
-        res = (ctypes.c_double * 7)()
+        res = ProfileResult()
         rc = library().fda_profile_matvec(self._h, x.data_ptr(), y.data_ptr(), nrhs, self.n, int(reps), _stream(),
-                                          res)
+                                          ctypes.byref(res))
         _err(rc)
-        names = ["near", "s2m", "m2m", "m2l", "l2l", "l2t_perm", "total"]
-        return dict(zip(names, list(res)))
+        d = {q: getattr(res, q + "_ms") for q in ("near", "s2m", "m2m", "m2l", "l2l", "l2t", "total")}
+        d["m2l_gemm"] = list(res.m2l_gemm_ms)
+        return d
