@@ -1,6 +1,7 @@
 """Benchmark: fast directional BEM matvec throughput and GMRES time to 1e-5
 on the 81,920-triangle rigid sphere at kD = 100 (icosphere subdivided 6
-times, radius 0.5, unit plane wave along +z, alpha = i/k, eps = 1e-4).
+times, radius 0.5, unit plane wave along +z, Burton-Miller coupling i/k for
+the fluid-side normal, eps = 1e-4).
 
 One step = one FDA matvec (near field, S2M, M2M, M2L, L2L, L2T) of a seeded
 complex-normal vector, inputs resident in HBM.  The same run also reports
@@ -54,7 +55,7 @@ def cpu_baseline(V, T, k, x, y_gpu, rows_sample, seconds_target=20.0):
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return dict(value=1.0 / full, unit="matvecs/s", cores=threads, kind="oracle",
                 sample=f"{m} of {n} rows of one FP64 dense matvec ({dt:.1f} s), scaled by N/{m}",
-                seconds_per_matvec=full), err
+                seconds_per_matvec=full), err, rows, yr
 
 
 def main():
@@ -65,6 +66,7 @@ def main():
     ap.add_argument("--workload", default="sphere81920_kD100")
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fast", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -137,10 +139,46 @@ def main():
                              rel_residual=info["rel_residual"], converged=info["converged"])
             log(f"[bench] solve {pc}: {solve[pc]}")
 
+    # fast arm: FP32 storage and FP32 matrix cores, FP64 self terms and Arnoldi
+    fast = {}
+    if not args.no_fast:
+        plan32 = Plan(V, T, k, prm["eps"], prec="fp32")
+        y32 = torch.empty_like(x)
+        for _ in range(args.warmup):
+            plan32.matvec(x, out=y32)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(args.steps):
+            plan32.matvec(x, out=y32)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms32 = e0.elapsed_time(e1) / args.steps
+        prof32 = plan32.profile(x, reps=max(3, min(20, args.steps)), out=y32)
+        fast = dict(matvecs_per_s=round(1000.0 / ms32, 3), ms_per_matvec=round(ms32, 4),
+                    stages_ms={q: round(v, 4) for q, v in prof32.items() if q != "m2l_gemm"},
+                    m2l_level_ms=[round(v, 4) for v in prof32["m2l_gemm"][: st["depth"] + 1]])
+        if not args.no_solve:
+            b32 = plan32.rhs_planewave(prm["direction"])
+            for pc in ("none", "block_jacobi"):
+                t0 = time.perf_counter()
+                u32, info = plan32.solve(b32, tol=1e-5, restart=50, maxit=2000, precond=pc)
+                torch.cuda.synchronize()
+                fast["solve_" + pc] = dict(seconds=round(time.perf_counter() - t0, 4), iterations=info["iterations"],
+                                           rel_residual=info["rel_residual"], converged=info["converged"])
+            # difference of the two arms' solutions (surface field)
+            u64, _ = plan.solve(b, tol=1e-5, restart=50, maxit=2000)
+            fast["solution_rel_diff_vs_fp64_arm"] = float(torch.linalg.norm(u32 - u64) / torch.linalg.norm(u64))
+        fast["y32"] = y32.cpu().numpy()
+        plan32.close()
+        log("[bench] fast arm: " + str({q: v for q, v in fast.items() if q != 'y32'}))
+
     cpu, err = (None, None)
     if not args.no_cpu:
-        cpu, err = cpu_baseline(V, T, k, W.complex_normal(n, 1, seed=0), y_np, 4096, args.cpu_seconds)
+        cpu, err, rows, yr = cpu_baseline(V, T, k, W.complex_normal(n, 1, seed=0), y_np, 4096, args.cpu_seconds)
         log(f"[bench] cpu baseline {cpu}, sampled-row rel err {err:.3e}")
+        if "y32" in fast:
+            fast["matvec_rel_err_vs_oracle_sampled"] = float(np.linalg.norm(fast["y32"][rows] - yr) / np.linalg.norm(yr))
+    fast.pop("y32", None)
 
     out = {
         "metric": "FDA matvecs/s (N=81,920, kD=100); GMRES time-to-1e-5 reported alongside",
@@ -164,6 +202,7 @@ def main():
         "time_to_1e-5_s": solve.get("none", {}).get("seconds"),
         "solve": solve,
         "matvec_rel_err_vs_oracle_sampled": err,
+        "fast_arm_fp32": fast or None,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -72,6 +72,23 @@ double2 *upload_cplx(fda_plan *p, const std::vector<cplx> &v) {
     return d;
 }
 
+// The plan's copy of an FP64 device operator array: itself for FP64 plans;
+// an FP32 copy for FP32 plans (the FP64 array stays allocated until the plan
+// is freed only if it is referenced elsewhere; here it is released at once).
+void *to_storage(fda_plan *p, double2 *a64, size_t n) {
+    if (p->d.prec != FDA_PREC_FP32 || a64 == nullptr) return a64;
+    float2 *a32 = dalloc<float2>(p, n, p->allocs);
+    hip_check(launch_to_f32(a64, a32, (int64_t)n, nullptr), "to f32");
+    hip_check(hipDeviceSynchronize(), "to f32");
+    auto it = std::find(p->allocs.begin(), p->allocs.end(), (void *)a64);
+    if (it != p->allocs.end()) {
+        hipFree(a64);
+        p->allocs.erase(it);
+        p->device_bytes -= (int64_t)(sizeof(double2) * n);
+    }
+    return a32;
+}
+
 // Host-side builder of a gathered-GEMM work list (kernels.hpp, GWork).
 struct GWorkHost {
     std::vector<int32_t> hdr, src;
@@ -140,13 +157,15 @@ void ensure_capacity(fda_plan *p, int nrhs) {
     p->yt = dalloc<double2>(p, (size_t)N * nrhs, p->work);
     for (int l = p->d.top; l <= p->d.depth && p->d.has_far; ++l) {
         DevLevel &lv = p->d.lv[l];
-        lv.s = dalloc<double2>(p, (size_t)lv.sstride * nrhs, p->work);
-        lv.c = dalloc<double2>(p, (size_t)lv.cstride * nrhs, p->work);
-        lv.m2l.tmp = dalloc<double2>(p, (size_t)lv.m2l.ncol * lv.kd * nrhs, p->work);
+        // storage elements: double2 (FP64 plan) or float2 (two floats, FP32 plan)
+        const size_t es = p->d.prec == FDA_PREC_FP32 ? 1 : 2;  // in units of float2
+        lv.s = dalloc<float2>(p, es * (size_t)lv.sstride * nrhs, p->work);
+        lv.c = dalloc<float2>(p, es * (size_t)lv.cstride * nrhs, p->work);
+        lv.m2l.tmp = dalloc<float2>(p, es * (size_t)lv.m2l.ncol * lv.kd * nrhs, p->work);
         if (l < p->d.depth) {
             const DevLevel &C = p->d.lv[l + 1];
-            lv.m2m.tmp = dalloc<double2>(p, (size_t)lv.m2m.ncol * lv.ku * nrhs, p->work);
-            lv.l2l.tmp = dalloc<double2>(p, (size_t)lv.l2l.ncol * C.kd * nrhs, p->work);
+            lv.m2m.tmp = dalloc<float2>(p, es * (size_t)lv.m2m.ncol * lv.ku * nrhs, p->work);
+            lv.l2l.tmp = dalloc<float2>(p, es * (size_t)lv.l2l.ncol * C.kd * nrhs, p->work);
         }
     }
     p->cap_nrhs = nrhs;
@@ -250,7 +269,8 @@ void upload_plan(fda_plan *p, const HostOps &ops, DevTranslations &tr) {
     d.nf_col_off = upload(p, col_off);
     d.nf_cols = upload(p, cols);
     d.nf_self_col = upload(p, self_col);
-    d.nf_vals = dalloc<double2>(p, (size_t)hp.near_nnz, p->allocs);
+    d.prec = hp.opt.prec == FDA_PREC_FP32 ? 1 : 0;
+    d.nf_vals = nullptr;  // filled after the near-field quadrature (fda_build)
     // block-Jacobi storage
     std::vector<int64_t> bj_off(d.nleaf + 1, 0);
     for (int b = 0; b < d.nleaf; ++b) {
@@ -262,8 +282,8 @@ void upload_plan(fda_plan *p, const HostOps &ops, DevTranslations &tr) {
 
     d.lv.assign(L + 1, DevLevel());
     if (!d.has_far) return;
-    d.S = upload_cplx(p, ops.S);
-    d.T = upload_cplx(p, ops.T);
+    d.S = to_storage(p, upload_cplx(p, ops.S), ops.S.size());
+    d.T = to_storage(p, upload_cplx(p, ops.T), ops.T.size());
     for (int l = hp.top; l <= L; ++l) {
         const Level &lv = hp.lv[l];
         DevLevel &dl = d.lv[l];
@@ -274,10 +294,10 @@ void upload_plan(fda_plan *p, const HostOps &ops, DevTranslations &tr) {
         if (lv.ku > 1024 || lv.kd > 1024) throw BuildError{FDA_EINVAL, "compressed rank above 1024"};
         dl.sstride = lv.nbox * lv.nslot * (int64_t)lv.ku;
         dl.cstride = lv.nbox * lv.nslot * (int64_t)lv.kd;
-        dl.K = tr.K[l];
+        dl.K = to_storage(p, tr.K[l], lv.offsets.size() * (size_t)lv.kd * lv.ku);
         if (!tr.rmax.empty() && tr.rmax[l] > 0 && lv.kd <= 256) {
-            dl.Ulr = tr.Ulr[l];
-            dl.Vlr = tr.Vlr[l];
+            dl.Ulr = to_storage(p, tr.Ulr[l], lv.offsets.size() * (size_t)lv.kd * tr.rmax[l]);
+            dl.Vlr = to_storage(p, tr.Vlr[l], lv.offsets.size() * (size_t)tr.rmax[l] * lv.ku);
             dl.lr_rank = tr.lr_rank[l];
             dl.rmax = tr.rmax[l];
         }
@@ -309,8 +329,8 @@ void upload_plan(fda_plan *p, const HostOps &ops, DevTranslations &tr) {
         }
         if (l < L) {
             const Level &C = hp.lv[l + 1];
-            dl.M = tr.M[l];
-            dl.Lo = tr.Lo[l];
+            dl.M = to_storage(p, tr.M[l], 8 * (size_t)lv.nslot * lv.ku * C.ku);
+            dl.Lo = to_storage(p, tr.Lo[l], 8 * (size_t)lv.nslot * C.kd * lv.kd);
             // M2M: per (child octant, parent slot), the parents with a child
             // in that octant, in chunks
             GWorkHost gm;
@@ -413,6 +433,7 @@ int fda_build(const double *verts, int64_t nv, const int32_t *tris, int64_t nt, 
     fda_default_options(&o);
     if (opt) o = *opt;
     if (o.nrhs_max < 1 || o.nrhs_max > 4096) return fail(FDA_EINVAL, "nrhs_max must be in [1, 4096]");
+    if (o.prec != FDA_PREC_FP64 && o.prec != FDA_PREC_FP32) return fail(FDA_EINVAL, "prec must be FDA_PREC_FP64 or FDA_PREC_FP32");
     auto t0 = std::chrono::steady_clock::now();
     std::unique_ptr<fda_plan> p(new fda_plan());
     p->device = o.device;
@@ -450,8 +471,26 @@ int fda_build(const double *verts, int64_t nv, const int32_t *tris, int64_t nt, 
         form_operators(p->hp, ops);
         quadrature_constants();
         upload_plan(p.get(), ops, tr);
-        hip_check(launch_near_blocks(p->d, nullptr), "near-field blocks");
-        hip_check(launch_bj_invert(p->d, nullptr), "block-Jacobi inverses");
+        {
+            // near-field quadrature in FP64; block-Jacobi inverses from it;
+            // FP32 plans keep the off-diagonal entries in FP32 and the self
+            // terms in FP64
+            double2 *v64 = dalloc<double2>(p.get(), (size_t)p->hp.near_nnz, p->allocs);
+            hip_check(launch_near_blocks(p->d, v64, nullptr), "near-field blocks");
+            hip_check(launch_bj_invert(p->d, v64, nullptr), "block-Jacobi inverses");
+            if (p->d.prec == FDA_PREC_FP32) {
+                p->d.nf_vals = dalloc<float2>(p.get(), (size_t)p->hp.near_nnz, p->allocs);
+                p->d.nf_diag = dalloc<double2>(p.get(), (size_t)p->d.n, p->allocs);
+                hip_check(launch_near_split(p->d, v64, nullptr), "near-field split");
+                hip_check(hipDeviceSynchronize(), "near split");
+                auto it = std::find(p->allocs.begin(), p->allocs.end(), (void *)v64);
+                hipFree(v64);
+                p->allocs.erase(it);
+                p->device_bytes -= (int64_t)(sizeof(double2) * p->hp.near_nnz);
+            } else {
+                p->d.nf_vals = v64;
+            }
+        }
         hip_check(hipDeviceSynchronize(), "build synchronize");
     } catch (const BuildError &e) {
         for (void *q : tr.allocs) hipFree(q);

@@ -163,11 +163,63 @@ __global__ void k_near_blocks(const int64_t *leaf_off, const int64_t *col_off, c
 }
 
 // ------------------------------------------------------------ matvec
+//
+// The matvec kernels are templates over the storage type of the operators
+// and states: double2 (FP64 plan) or float2 (FP32 plan: M2L, M2M, L2L, S2M,
+// L2T and the off-diagonal near field in FP32 with FP32 accumulation on the
+// matrix cores; the element self terms and every vector the caller sees stay
+// FP64).
 
-// y_tree[i] = sum over the near leaves of the block entries times x.
+template <class C>
+struct CT;
+template <>
+struct CT<double2> {
+    using R = double;
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    // v_mfma_f64_16x16x4f64; result row of lane group lk, element v
+    static __device__ __forceinline__ v4 mfma(double a, double b, v4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lk, int v) { return lk + 4 * v; }
+};
+template <>
+struct CT<float2> {
+    using R = float;
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    // v_mfma_f32_16x16x4f32
+    static __device__ __forceinline__ v4 mfma(float a, float b, v4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lk, int v) { return 4 * lk + v; }
+};
+
+template <class C>
+__device__ __forceinline__ C czero() {
+    C z;
+    z.x = 0;
+    z.y = 0;
+    return z;
+}
+template <class C>
+__device__ __forceinline__ C cfrom(double2 v) {
+    C z;
+    z.x = (typename CT<C>::R)v.x;
+    z.y = (typename CT<C>::R)v.y;
+    return z;
+}
+template <class C>
+__device__ __forceinline__ void cmac(C &acc, C a, C b) {
+    acc.x = fma(a.x, b.x, fma(-a.y, b.y, acc.x));
+    acc.y = fma(a.x, b.y, fma(a.y, b.x, acc.y));
+}
+
+// y_tree[i] = sum over the near leaves of the block entries times x
+// (+ the FP64 self term diag[i] x[i] when the blocks are FP32).
+template <class C>
 __global__ void k_p2p(const int64_t *leaf_off, const int32_t *nl_off, const int32_t *nl, const int64_t *blk_off,
-                      const double2 *vals, const double2 *x, double2 *y, int64_t N) {
-    extern __shared__ double2 xs[];
+                      const C *vals, const double2 *diag, const double2 *x, double2 *y, int64_t N) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C *xs = (C *)smem_raw;
     const int b = blockIdx.x;
     const double2 *xr = x + (int64_t)blockIdx.y * N;
     double2 *yr = y + (int64_t)blockIdx.y * N;
@@ -176,51 +228,59 @@ __global__ void k_p2p(const int64_t *leaf_off, const int32_t *nl_off, const int3
         int s = nl[q];
         int64_t s0 = leaf_off[s];
         int ns = (int)(leaf_off[s + 1] - s0);
-        for (int i = threadIdx.x; i < ns; i += blockDim.x) xs[nc + i] = xr[s0 + i];
+        for (int i = threadIdx.x; i < ns; i += blockDim.x) xs[nc + i] = cfrom<C>(xr[s0 + i]);
         nc += ns;
     }
     __syncthreads();
     const int64_t t0 = leaf_off[b];
     const int nt = (int)(leaf_off[b + 1] - t0);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    const double2 *blk = vals + blk_off[b];
+    const C *blk = vals + blk_off[b];
     for (int i = wv; i < nt; i += nw) {
-        double2 acc = make_double2(0.0, 0.0);
-        const double2 *row = blk + (int64_t)i * nc;
-        for (int c = lane; c < nc; c += 64) cfma(acc, row[c], xs[c]);
+        C acc = czero<C>();
+        const C *row = blk + (int64_t)i * nc;
+        for (int c = lane; c < nc; c += 64) cmac(acc, row[c], xs[c]);
         for (int o = 32; o > 0; o >>= 1) {
             acc.x += __shfl_down(acc.x, o, 64);
             acc.y += __shfl_down(acc.y, o, 64);
         }
-        if (lane == 0) yr[t0 + i] = acc;
+        if (lane == 0) {
+            double2 out = make_double2((double)acc.x, (double)acc.y);
+            if (diag) {
+                const double2 d = diag[t0 + i], v = xr[t0 + i];
+                out.x += d.x * v.x - d.y * v.y;
+                out.y += d.x * v.y + d.y * v.x;
+            }
+            yr[t0 + i] = out;
+        }
     }
 }
 
 // s_leaf = S~ x_leaf
-__global__ void k_s2m(const int64_t *leaf_off, const double2 *S, int ku, const double2 *x, double2 *s, int64_t N,
+template <class C>
+__global__ void k_s2m(const int64_t *leaf_off, const C *S, int ku, const double2 *x, C *s, int64_t N,
                       int64_t sstride) {
-    extern __shared__ double2 xs[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C *xs = (C *)smem_raw;
     const int b = blockIdx.x;
     const double2 *xr = x + (int64_t)blockIdx.y * N;
     const int64_t e0 = leaf_off[b];
     const int nl = (int)(leaf_off[b + 1] - e0);
-    for (int i = threadIdx.x; i < nl; i += blockDim.x) xs[i] = xr[e0 + i];
+    for (int i = threadIdx.x; i < nl; i += blockDim.x) xs[i] = cfrom<C>(xr[e0 + i]);
     __syncthreads();
-    const double2 *Sb = S + (int64_t)ku * e0;
-    double2 *sr = s + (int64_t)blockIdx.y * sstride + (int64_t)b * ku;
+    const C *Sb = S + (int64_t)ku * e0;
+    C *sr = s + (int64_t)blockIdx.y * sstride + (int64_t)b * ku;
     for (int r = threadIdx.x; r < ku; r += blockDim.x) {
-        double2 acc = make_double2(0.0, 0.0);
-        for (int j = 0; j < nl; ++j) cfma(acc, Sb[r + (int64_t)j * ku], xs[j]);
+        C acc = czero<C>();
+        for (int j = 0; j < nl; ++j) cmac(acc, Sb[r + (int64_t)j * ku], xs[j]);
         sr[r] = acc;
     }
 }
 
-#define FDA_MAXR 4  // rows per thread: ranks up to 4 * blockDim
-
-// Gathered batched GEMM shared by M2M, M2L and L2L, on the FP64 matrix
-// cores (v_mfma_f64_16x16x4f64).  A work item multiplies one translation
-// matrix (m x kin, column-major) by up to GG_NB gathered input states and
-// writes the m-vectors to consecutive columns of a scratch buffer:
+// Gathered batched GEMM shared by M2M, M2L and L2L, on the matrix cores.  A
+// work item multiplies one translation matrix (m x kin, column-major) by up
+// to GG_NB gathered input states and writes the m-vectors to consecutive
+// columns of a scratch buffer:
 //   T[:, tcol + b] = A[mat] X[src[b]]   (src = -1: zero column).
 //   M2L: one matrix per distinct translation (eq. (eq_m2l) compressed by
 //        eq. (eq_cmpm2l)), columns = the interaction pairs sharing it.
@@ -230,71 +290,85 @@ __global__ void k_s2m(const int64_t *leaf_off, const double2 *S, int ku, const d
 //        children in that octant.
 // A second kernel sums the scratch columns of every destination state in a
 // fixed order (deterministic results).
-// MFMA operand layout per wave: A (16 x 4) lane l holds row l % 16, column
-// l / 16; B (4 x 16) lane l holds row l / 16, column l % 16; the f64 16 x 16
-// result gives lane l rows l / 16 + 4 v (v = 0..3), column l % 16.  A complex
-// product is four real products: Re += Ar Br - Ai Bi, Im += Ar Bi + Ai Br.
-// The 4 waves of a block take row tiles w, w + 4, ... of a 256-row band.
-// Work items of consecutive index are mapped to the same XCD so that the
-// shared translation matrices stay in that XCD's L2.
+// MFMA operand layout per wave (16x16x4, FP64 and FP32): A (16 x 4) lane l
+// holds row l % 16, column l / 16; B (4 x 16) lane l holds row l / 16, column
+// l % 16; the 16 x 16 result of lane l is column l % 16, rows CT<C>::row.  A
+// complex product is four real products: Re += Ar Br - Ai Bi,
+// Im += Ar Bi + Ai Br.  The 4 waves of a block take row tiles w, w + 4, ...
+// of a 256-row band.  Work items of consecutive index are mapped to the same
+// XCD so that the shared translation matrices stay in that XCD's L2.
 #define GG_NB 32
 #define GG_J 32
-typedef double d4_t __attribute__((ext_vector_type(4)));
 #define MF_RT 4
-__global__ void __launch_bounds__(256) k_ggemm(const int4 *hdr, const int32_t *src, const double2 *A, int m, int kin,
-                                               const double2 *X, int64_t xstride, double2 *T, int64_t tstride,
-                                               int nwork) {
-    __shared__ double2 S[GG_J][GG_NB];
+
+// Load up to GG_J x GG_NB gathered input values (zero padded) into LDS.
+template <class C>
+__device__ __forceinline__ void load_states(C (*S)[GG_NB], const C *Xr, const int32_t *st, int kin, int j0) {
+    for (int e = threadIdx.x; e < GG_J * GG_NB; e += blockDim.x) {
+        const int jj = e % GG_J, b = e / GG_J;
+        const int sb = st[b];
+        C v = czero<C>();
+        if (sb >= 0 && j0 + jj < kin) v = Xr[(int64_t)sb * kin + j0 + jj];
+        S[jj][b] = v;
+    }
+}
+
+// acc (+)= A-tile (rows row0.., columns kcol..) x B (two 16-column tiles).
+template <class C>
+__device__ __forceinline__ void mfma_complex(typename CT<C>::v4 &aR0, typename CT<C>::v4 &aI0,
+                                             typename CT<C>::v4 &aR1, typename CT<C>::v4 &aI1, C a, C b0, C b1) {
+    aR0 = CT<C>::mfma(a.x, b0.x, aR0);
+    aR0 = CT<C>::mfma(-a.y, b0.y, aR0);
+    aI0 = CT<C>::mfma(a.x, b0.y, aI0);
+    aI0 = CT<C>::mfma(a.y, b0.x, aI0);
+    aR1 = CT<C>::mfma(a.x, b1.x, aR1);
+    aR1 = CT<C>::mfma(-a.y, b1.y, aR1);
+    aI1 = CT<C>::mfma(a.x, b1.y, aI1);
+    aI1 = CT<C>::mfma(a.y, b1.x, aI1);
+}
+
+template <class C>
+__global__ void __launch_bounds__(256) k_ggemm(const int4 *hdr, const int32_t *src, const C *A, int m, int kin,
+                                               const C *X, int64_t xstride, C *T, int64_t tstride, int nwork) {
+    using v4 = typename CT<C>::v4;
+    __shared__ C S[GG_J][GG_NB];
     const int nx = 8;
     const int per = gridDim.x / nx;
     const int w = (blockIdx.x % nx) * per + blockIdx.x / nx;
     if (w >= nwork) return;
     const int4 h = hdr[w];  // (matrix, first scratch column, column count, 0)
-    const double2 *Xr = X + (int64_t)blockIdx.y * xstride;
-    double2 *Tr = T + (int64_t)blockIdx.y * tstride + (int64_t)h.y * m;
-    const double2 *At = A + (int64_t)h.x * m * kin;
+    const C *Xr = X + (int64_t)blockIdx.y * xstride;
+    C *Tr = T + (int64_t)blockIdx.y * tstride + (int64_t)h.y * m;
+    const C *At = A + (int64_t)h.x * m * kin;
     const int32_t *st = src + (int64_t)w * GG_NB;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lk = lane >> 4;
     for (int band = 0; band < m; band += 64 * MF_RT) {
         const int ntile = min(MF_RT * 4, (m - band + 15) >> 4);
-        d4_t accR[MF_RT][2], accI[MF_RT][2];
+        v4 accR[MF_RT][2], accI[MF_RT][2];
 #pragma unroll
         for (int q = 0; q < MF_RT; ++q)
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
-                accR[q][c] = (d4_t){0.0, 0.0, 0.0, 0.0};
-                accI[q][c] = (d4_t){0.0, 0.0, 0.0, 0.0};
+                accR[q][c] = (v4){0, 0, 0, 0};
+                accI[q][c] = (v4){0, 0, 0, 0};
             }
         for (int j0 = 0; j0 < kin; j0 += GG_J) {
             __syncthreads();
-            for (int e = threadIdx.x; e < GG_J * GG_NB; e += blockDim.x) {
-                const int jj = e % GG_J, b = e / GG_J;
-                const int sb = st[b];
-                double2 v = make_double2(0.0, 0.0);
-                if (sb >= 0 && j0 + jj < kin) v = Xr[(int64_t)sb * kin + j0 + jj];
-                S[jj][b] = v;
-            }
+            load_states<C>(S, Xr, st, kin, j0);
             __syncthreads();
             const int jm = min(GG_J, kin - j0);
             for (int kk = 0; kk < jm; kk += 4) {
                 const int kcol = j0 + kk + lk;
-                const double2 b0 = S[kk + lk][li], b1 = S[kk + lk][16 + li];
+                const C b0 = S[kk + lk][li], b1 = S[kk + lk][16 + li];
 #pragma unroll
                 for (int q = 0; q < MF_RT; ++q) {
                     const int rt = wave + 4 * q;
                     if (rt >= ntile) break;
                     const int row = band + rt * 16 + li;
-                    double2 a = make_double2(0.0, 0.0);
+                    C a = czero<C>();
                     if (row < m && kcol < kin) a = At[row + (int64_t)kcol * m];
-                    accR[q][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b0.x, accR[q][0], 0, 0, 0);
-                    accR[q][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b0.y, accR[q][0], 0, 0, 0);
-                    accI[q][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b0.y, accI[q][0], 0, 0, 0);
-                    accI[q][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b0.x, accI[q][0], 0, 0, 0);
-                    accR[q][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b1.x, accR[q][1], 0, 0, 0);
-                    accR[q][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b1.y, accR[q][1], 0, 0, 0);
-                    accI[q][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b1.y, accI[q][1], 0, 0, 0);
-                    accI[q][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b1.x, accI[q][1], 0, 0, 0);
+                    mfma_complex<C>(accR[q][0], accI[q][0], accR[q][1], accI[q][1], a, b0, b1);
                 }
             }
         }
@@ -308,8 +382,13 @@ __global__ void __launch_bounds__(256) k_ggemm(const int4 *hdr, const int32_t *s
                 if (col >= h.z) continue;
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    const int row = band + rt * 16 + lk + 4 * v;
-                    if (row < m) Tr[(int64_t)col * m + row] = make_double2(accR[q][c][v], accI[q][c][v]);
+                    const int row = band + rt * 16 + CT<C>::row(lk, v);
+                    if (row < m) {
+                        C r;
+                        r.x = accR[q][c][v];
+                        r.y = accI[q][c][v];
+                        Tr[(int64_t)col * m + row] = r;
+                    }
                 }
             }
         }
@@ -318,15 +397,16 @@ __global__ void __launch_bounds__(256) k_ggemm(const int4 *hdr, const int32_t *s
 
 // Low-rank reduced M2L (Section 4.2, eq. (eq_epsk)): K~ = U^ V^ with rank r
 // per translation, so each work item first forms Z = V^ S (r x 32) and then
-// U^ Z (kd x 32), both on the FP64 matrix cores; Z stays in LDS.  Same work
-// list, scratch layout and reduction as k_ggemm.
+// U^ Z (kd x 32), both on the matrix cores; Z stays in LDS.  Same work list,
+// scratch layout and reduction as k_ggemm.
 #define LR_MAX 80
-__global__ void __launch_bounds__(256) k_m2l_lowrank(const int4 *hdr, const int32_t *src, const double2 *Ulr,
-                                                     const double2 *Vlr, const int32_t *rank, int kd, int ku,
-                                                     int rmax, const double2 *X, int64_t xstride, double2 *T,
-                                                     int64_t tstride, int nwork) {
-    __shared__ double2 S[GG_J][GG_NB];
-    __shared__ double2 Z[LR_MAX][GG_NB];
+template <class C>
+__global__ void __launch_bounds__(256) k_m2l_lowrank(const int4 *hdr, const int32_t *src, const C *Ulr, const C *Vlr,
+                                                     const int32_t *rank, int kd, int ku, int rmax, const C *X,
+                                                     int64_t xstride, C *T, int64_t tstride, int nwork) {
+    using v4 = typename CT<C>::v4;
+    __shared__ C S[GG_J][GG_NB];
+    __shared__ C Z[LR_MAX][GG_NB];
     const int nx = 8;
     const int per = gridDim.x / nx;
     const int w = (blockIdx.x % nx) * per + blockIdx.x / nx;
@@ -334,52 +414,39 @@ __global__ void __launch_bounds__(256) k_m2l_lowrank(const int4 *hdr, const int3
     const int4 h = hdr[w];
     const int op = h.x;
     const int r = rank[op];
-    const double2 *Xr = X + (int64_t)blockIdx.y * xstride;
-    double2 *Tr = T + (int64_t)blockIdx.y * tstride + (int64_t)h.y * kd;
-    const double2 *Vt = Vlr + (int64_t)op * rmax * ku;
-    const double2 *Ut = Ulr + (int64_t)op * kd * rmax;
+    const C *Xr = X + (int64_t)blockIdx.y * xstride;
+    C *Tr = T + (int64_t)blockIdx.y * tstride + (int64_t)h.y * kd;
+    const C *Vt = Vlr + (int64_t)op * rmax * ku;
+    const C *Ut = Ulr + (int64_t)op * kd * rmax;
     const int32_t *st = src + (int64_t)w * GG_NB;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lk = lane >> 4;
     // phase 1: Z = V^[0:r, :] S
     const int ztiles = (r + 15) >> 4;
-    d4_t zR[2][2], zI[2][2];
+    v4 zR[2][2], zI[2][2];
 #pragma unroll
     for (int q = 0; q < 2; ++q)
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
-            zR[q][c] = (d4_t){0.0, 0.0, 0.0, 0.0};
-            zI[q][c] = (d4_t){0.0, 0.0, 0.0, 0.0};
+            zR[q][c] = (v4){0, 0, 0, 0};
+            zI[q][c] = (v4){0, 0, 0, 0};
         }
     for (int j0 = 0; j0 < ku; j0 += GG_J) {
         __syncthreads();
-        for (int e = threadIdx.x; e < GG_J * GG_NB; e += blockDim.x) {
-            const int jj = e % GG_J, b = e / GG_J;
-            const int sb = st[b];
-            double2 v = make_double2(0.0, 0.0);
-            if (sb >= 0 && j0 + jj < ku) v = Xr[(int64_t)sb * ku + j0 + jj];
-            S[jj][b] = v;
-        }
+        load_states<C>(S, Xr, st, ku, j0);
         __syncthreads();
         const int jm = min(GG_J, ku - j0);
         for (int kk = 0; kk < jm; kk += 4) {
             const int kcol = j0 + kk + lk;
-            const double2 b0 = S[kk + lk][li], b1 = S[kk + lk][16 + li];
+            const C b0 = S[kk + lk][li], b1 = S[kk + lk][16 + li];
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
                 const int zt = wave + 4 * q;
                 if (zt >= ztiles) break;
                 const int row = zt * 16 + li;
-                double2 a = make_double2(0.0, 0.0);
+                C a = czero<C>();
                 if (row < r && kcol < ku) a = Vt[row + (int64_t)kcol * rmax];
-                zR[q][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b0.x, zR[q][0], 0, 0, 0);
-                zR[q][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b0.y, zR[q][0], 0, 0, 0);
-                zI[q][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b0.y, zI[q][0], 0, 0, 0);
-                zI[q][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b0.x, zI[q][0], 0, 0, 0);
-                zR[q][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b1.x, zR[q][1], 0, 0, 0);
-                zR[q][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b1.y, zR[q][1], 0, 0, 0);
-                zI[q][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b1.y, zI[q][1], 0, 0, 0);
-                zI[q][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b1.x, zI[q][1], 0, 0, 0);
+                mfma_complex<C>(zR[q][0], zI[q][0], zR[q][1], zI[q][1], a, b0, b1);
             }
         }
     }
@@ -391,36 +458,34 @@ __global__ void __launch_bounds__(256) k_m2l_lowrank(const int4 *hdr, const int3
 #pragma unroll
         for (int c = 0; c < 2; ++c)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) Z[zt * 16 + lk + 4 * v][c * 16 + li] = make_double2(zR[q][c][v], zI[q][c][v]);
+            for (int v = 0; v < 4; ++v) {
+                C z;
+                z.x = zR[q][c][v];
+                z.y = zI[q][c][v];
+                Z[zt * 16 + CT<C>::row(lk, v)][c * 16 + li] = z;
+            }
     }
     __syncthreads();
     // phase 2: Y = U^[:, 0:r] Z
     const int ntile = (kd + 15) >> 4;
-    d4_t accR[MF_RT][2], accI[MF_RT][2];
+    v4 accR[MF_RT][2], accI[MF_RT][2];
 #pragma unroll
     for (int q = 0; q < MF_RT; ++q)
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
-            accR[q][c] = (d4_t){0.0, 0.0, 0.0, 0.0};
-            accI[q][c] = (d4_t){0.0, 0.0, 0.0, 0.0};
+            accR[q][c] = (v4){0, 0, 0, 0};
+            accI[q][c] = (v4){0, 0, 0, 0};
         }
     for (int kk = 0; kk < r; kk += 4) {
-        const double2 b0 = Z[kk + lk][li], b1 = Z[kk + lk][16 + li];
+        const C b0 = Z[kk + lk][li], b1 = Z[kk + lk][16 + li];
 #pragma unroll
         for (int q = 0; q < MF_RT; ++q) {
             const int rt = wave + 4 * q;
             if (rt >= ntile) break;
             const int row = rt * 16 + li;
-            double2 a = make_double2(0.0, 0.0);
+            C a = czero<C>();
             if (row < kd) a = Ut[row + (int64_t)(kk + lk) * kd];
-            accR[q][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b0.x, accR[q][0], 0, 0, 0);
-            accR[q][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b0.y, accR[q][0], 0, 0, 0);
-            accI[q][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b0.y, accI[q][0], 0, 0, 0);
-            accI[q][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b0.x, accI[q][0], 0, 0, 0);
-            accR[q][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b1.x, accR[q][1], 0, 0, 0);
-            accR[q][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b1.y, accR[q][1], 0, 0, 0);
-            accI[q][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b1.y, accI[q][1], 0, 0, 0);
-            accI[q][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b1.x, accI[q][1], 0, 0, 0);
+            mfma_complex<C>(accR[q][0], accI[q][0], accR[q][1], accI[q][1], a, b0, b1);
         }
     }
 #pragma unroll
@@ -433,23 +498,29 @@ __global__ void __launch_bounds__(256) k_m2l_lowrank(const int4 *hdr, const int3
             if (col >= h.z) continue;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int row = rt * 16 + lk + 4 * v;
-                if (row < kd) Tr[(int64_t)col * kd + row] = make_double2(accR[q][c][v], accI[q][c][v]);
+                const int row = rt * 16 + CT<C>::row(lk, v);
+                if (row < kd) {
+                    C o;
+                    o.x = accR[q][c][v];
+                    o.y = accI[q][c][v];
+                    Tr[(int64_t)col * kd + row] = o;
+                }
             }
         }
     }
 }
 
 // Y[dst] (+)= sum of the scratch columns listed for dst, in list order.
-__global__ void k_gather_reduce(const int32_t *dst, const int32_t *off, const int32_t *list, int m,
-                                const double2 *T, int64_t tstride, double2 *Y, int64_t ystride, int accumulate) {
+template <class C>
+__global__ void k_gather_reduce(const int32_t *dst, const int32_t *off, const int32_t *list, int m, const C *T,
+                                int64_t tstride, C *Y, int64_t ystride, int accumulate) {
     const int t = blockIdx.x;
-    const double2 *Tr = T + (int64_t)blockIdx.y * tstride;
-    double2 *out = Y + (int64_t)blockIdx.y * ystride + (int64_t)dst[t] * m;
+    const C *Tr = T + (int64_t)blockIdx.y * tstride;
+    C *out = Y + (int64_t)blockIdx.y * ystride + (int64_t)dst[t] * m;
     for (int r = threadIdx.x; r < m; r += blockDim.x) {
-        double2 acc = accumulate ? out[r] : make_double2(0.0, 0.0);
+        C acc = accumulate ? out[r] : czero<C>();
         for (int q = off[t]; q < off[t + 1]; ++q) {
-            double2 v = Tr[(int64_t)list[q] * m + r];
+            C v = Tr[(int64_t)list[q] * m + r];
             acc.x += v.x;
             acc.y += v.y;
         }
@@ -458,28 +529,57 @@ __global__ void k_gather_reduce(const int32_t *dst, const int32_t *off, const in
 }
 
 // y_leaf += T~ c_leaf
-__global__ void k_l2t(const int64_t *leaf_off, const double2 *Tm, int kd, const double2 *c, double2 *y, int64_t N,
+template <class C>
+__global__ void k_l2t(const int64_t *leaf_off, const C *Tm, int kd, const C *c, double2 *y, int64_t N,
                       int64_t cstride) {
-    extern __shared__ double2 v[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C *v = (C *)smem_raw;
     const int b = blockIdx.x;
-    const double2 *cr = c + (int64_t)blockIdx.y * cstride + (int64_t)b * kd;
+    const C *cr = c + (int64_t)blockIdx.y * cstride + (int64_t)b * kd;
     for (int j = threadIdx.x; j < kd; j += blockDim.x) v[j] = cr[j];
     __syncthreads();
     const int64_t e0 = leaf_off[b];
     const int nl = (int)(leaf_off[b + 1] - e0);
-    const double2 *Tb = Tm + (int64_t)kd * e0;
+    const C *Tb = Tm + (int64_t)kd * e0;
     double2 *yr = y + (int64_t)blockIdx.y * N;
     for (int i = threadIdx.x; i < nl; i += blockDim.x) {
-        double2 acc = make_double2(0.0, 0.0);
-        for (int r = 0; r < kd; ++r) cfma(acc, Tb[i + (int64_t)r * nl], v[r]);
+        C acc = czero<C>();
+        for (int r = 0; r < kd; ++r) cmac(acc, Tb[i + (int64_t)r * nl], v[r]);
         double2 o = yr[e0 + i];
-        yr[e0 + i] = make_double2(o.x + acc.x, o.y + acc.y);
+        yr[e0 + i] = make_double2(o.x + (double)acc.x, o.y + (double)acc.y);
     }
 }
 
-__global__ void k_fill_zero(double2 *p, int64_t n) {
+template <class C>
+__global__ void k_fill_zero(C *p, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = make_double2(0.0, 0.0);
+        p[i] = czero<C>();
+}
+
+// FP64 -> FP32 copy of an operator array.
+__global__ void k_to_f32(const double2 *in, float2 *out, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = make_float2((float)in[i].x, (float)in[i].y);
+}
+
+// FP32 near-field blocks: the off-diagonal entries in FP32, the self terms
+// kept in FP64 in diag (tree order).
+__global__ void k_near_split(const int64_t *leaf_off, const int64_t *blk_off, const int32_t *self_col,
+                             const int32_t *ncol, const double2 *vals, float2 *out, double2 *diag) {
+    const int b = blockIdx.x;
+    const int64_t t0 = leaf_off[b];
+    const int nt = (int)(leaf_off[b + 1] - t0), nc = ncol[b], sc = self_col[b];
+    const int64_t o = blk_off[b];
+    for (int idx = threadIdx.x; idx < nt * nc; idx += blockDim.x) {
+        const int i = idx / nc, c = idx - i * nc;
+        const double2 v = vals[o + idx];
+        if (c == sc + i) {
+            diag[t0 + i] = v;
+            out[o + idx] = make_float2(0.0f, 0.0f);
+        } else {
+            out[o + idx] = make_float2((float)v.x, (float)v.y);
+        }
+    }
 }
 
 // tree-order xt[i + c N] = x[perm[i] + c ld]
@@ -699,50 +799,17 @@ hipError_t set_quadrature_constants(const double r7b[7][3], const double r7w[7],
     return hipMemcpyToSymbol(HIP_SYMBOL(c_glw), glw, sizeof(double) * 32);
 }
 
-hipError_t launch_near_blocks(const DevPlan &d, hipStream_t st) {
+hipError_t launch_near_blocks(const DevPlan &d, double2 *vals64, hipStream_t st) {
     if (d.nleaf == 0) return hipSuccess;
     hipLaunchKernelGGL(k_near_blocks, dim3(d.nleaf), dim3(256), 0, st, d.leaf_off, d.nf_col_off, d.nf_cols,
-                       d.nf_blk_off, d.tri, d.cen, d.nrm, d.area, d.k, d.alpha, d.h_max, d.nf_vals);
+                       d.nf_blk_off, d.tri, d.cen, d.nrm, d.area, d.k, d.alpha, d.h_max, vals64);
     CHECK_LAUNCH();
     return hipSuccess;
 }
 
-hipError_t launch_bj_invert(const DevPlan &d, hipStream_t st) {
+hipError_t launch_bj_invert(const DevPlan &d, const double2 *vals64, hipStream_t st) {
     hipLaunchKernelGGL(k_bj_invert, dim3(d.nleaf), dim3(256), 0, st, d.leaf_off, d.nf_blk_off, d.nf_self_col,
-                       d.nf_ncol, d.nf_vals, d.bj_off, d.bj_inv);
-    CHECK_LAUNCH();
-    return hipSuccess;
-}
-
-hipError_t launch_ggemm(const GWork &g, const double2 *A, int m, int kin, const double2 *X, int64_t xstride,
-                        double2 *Y, int64_t ystride, int accumulate, int nrhs, hipStream_t st, hipEvent_t *ev) {
-    if (g.nwork == 0) return hipSuccess;
-    // a multiple of 8 workgroups so every XCD runs the same share
-    const int grid = (g.nwork + 7) / 8 * 8;
-    const int64_t tstride = g.ncol * m;
-    if (ev) hipEventRecord(ev[0], st);
-    hipLaunchKernelGGL(k_ggemm, dim3(grid, nrhs), dim3(256), 0, st, g.hdr, g.src, A, m, kin, X, xstride, g.tmp,
-                       tstride, g.nwork);
-    CHECK_LAUNCH();
-    if (ev) hipEventRecord(ev[1], st);
-    hipLaunchKernelGGL(k_gather_reduce, dim3(g.nred, nrhs), dim3(std::min(256, ((m + 63) / 64) * 64)), 0, st,
-                       g.rd_dst, g.rd_off, g.rd_list, m, g.tmp, tstride, Y, ystride, accumulate);
-    CHECK_LAUNCH();
-    return hipSuccess;
-}
-
-hipError_t launch_m2l_lowrank(const DevLevel &lv, int nrhs, hipStream_t st, hipEvent_t *ev) {
-    const GWork &g = lv.m2l;
-    if (g.nwork == 0) return hipSuccess;
-    const int grid = (g.nwork + 7) / 8 * 8;
-    const int64_t tstride = g.ncol * lv.kd;
-    if (ev) hipEventRecord(ev[0], st);
-    hipLaunchKernelGGL(k_m2l_lowrank, dim3(grid, nrhs), dim3(256), 0, st, g.hdr, g.src, lv.Ulr, lv.Vlr, lv.lr_rank,
-                       lv.kd, lv.ku, lv.rmax, lv.s, lv.sstride, g.tmp, tstride, g.nwork);
-    CHECK_LAUNCH();
-    if (ev) hipEventRecord(ev[1], st);
-    hipLaunchKernelGGL(k_gather_reduce, dim3(g.nred, nrhs), dim3(std::min(256, ((lv.kd + 63) / 64) * 64)), 0, st,
-                       g.rd_dst, g.rd_off, g.rd_list, lv.kd, g.tmp, tstride, lv.c, lv.cstride, 1);
+                       d.nf_ncol, vals64, d.bj_off, d.bj_inv);
     CHECK_LAUNCH();
     return hipSuccess;
 }
@@ -752,14 +819,66 @@ static int grid1(int64_t n) {
     return (int)std::min<int64_t>(std::max<int64_t>(g, 1), 4096);
 }
 
+hipError_t launch_near_split(const DevPlan &d, const double2 *vals64, hipStream_t st) {
+    hipLaunchKernelGGL(k_near_split, dim3(d.nleaf), dim3(256), 0, st, d.leaf_off, d.nf_blk_off, d.nf_self_col,
+                       d.nf_ncol, vals64, (float2 *)d.nf_vals, d.nf_diag);
+    CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+hipError_t launch_to_f32(const double2 *in, void *out, int64_t n, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_to_f32, dim3(grid1(n)), dim3(256), 0, st, in, (float2 *)out, n);
+    CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+template <class C>
+static hipError_t ggemm_t(const GWork &g, const void *A, int m, int kin, const void *X, int64_t xstride, void *Y,
+                          int64_t ystride, int accumulate, int nrhs, hipStream_t st, hipEvent_t *ev) {
+    if (g.nwork == 0) return hipSuccess;
+    // a multiple of 8 workgroups so every XCD runs the same share
+    const int grid = (g.nwork + 7) / 8 * 8;
+    const int64_t tstride = g.ncol * m;
+    if (ev) hipEventRecord(ev[0], st);
+    hipLaunchKernelGGL(k_ggemm<C>, dim3(grid, nrhs), dim3(256), 0, st, g.hdr, g.src, (const C *)A, m, kin,
+                       (const C *)X, xstride, (C *)g.tmp, tstride, g.nwork);
+    CHECK_LAUNCH();
+    if (ev) hipEventRecord(ev[1], st);
+    hipLaunchKernelGGL(k_gather_reduce<C>, dim3(g.nred, nrhs), dim3(std::min(256, ((m + 63) / 64) * 64)), 0, st,
+                       g.rd_dst, g.rd_off, g.rd_list, m, (const C *)g.tmp, tstride, (C *)Y, ystride, accumulate);
+    CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+template <class C>
+static hipError_t m2l_lowrank_t(const DevLevel &lv, int nrhs, hipStream_t st, hipEvent_t *ev) {
+    const GWork &g = lv.m2l;
+    if (g.nwork == 0) return hipSuccess;
+    const int grid = (g.nwork + 7) / 8 * 8;
+    const int64_t tstride = g.ncol * lv.kd;
+    if (ev) hipEventRecord(ev[0], st);
+    hipLaunchKernelGGL(k_m2l_lowrank<C>, dim3(grid, nrhs), dim3(256), 0, st, g.hdr, g.src, (const C *)lv.Ulr,
+                       (const C *)lv.Vlr, lv.lr_rank, lv.kd, lv.ku, lv.rmax, (const C *)lv.s, lv.sstride, (C *)g.tmp,
+                       tstride, g.nwork);
+    CHECK_LAUNCH();
+    if (ev) hipEventRecord(ev[1], st);
+    hipLaunchKernelGGL(k_gather_reduce<C>, dim3(g.nred, nrhs), dim3(std::min(256, ((lv.kd + 63) / 64) * 64)), 0, st,
+                       g.rd_dst, g.rd_off, g.rd_list, lv.kd, (const C *)g.tmp, tstride, (C *)lv.c, lv.cstride, 1);
+    CHECK_LAUNCH();
+    return hipSuccess;
+}
+
 // Stage timings are recorded when ev != nullptr (7 events: start, after
 // near, after S2M, after M2M, after M2L, after L2L, end).
-hipError_t launch_matvec_tree(const DevPlan &d, const double2 *xt, double2 *yt, int nrhs, hipStream_t st,
-                              hipEvent_t *ev, hipEvent_t *lev) {
+template <class C>
+static hipError_t matvec_t(const DevPlan &d, const double2 *xt, double2 *yt, int nrhs, hipStream_t st,
+                           hipEvent_t *ev, hipEvent_t *lev) {
     const int64_t N = d.n;
     if (ev) hipEventRecord(ev[0], st);
-    hipLaunchKernelGGL(k_p2p, dim3(d.nleaf, nrhs), dim3(256), sizeof(double2) * d.max_ncol, st, d.leaf_off,
-                       d.nf_list_off, d.nf_list, d.nf_blk_off, d.nf_vals, xt, yt, N);
+    hipLaunchKernelGGL(k_p2p<C>, dim3(d.nleaf, nrhs), dim3(256), sizeof(C) * d.max_ncol, st, d.leaf_off,
+                       d.nf_list_off, d.nf_list, d.nf_blk_off, (const C *)d.nf_vals, (const double2 *)d.nf_diag, xt,
+                       yt, N);
     CHECK_LAUNCH();
     if (ev) hipEventRecord(ev[1], st);
     if (!d.has_far) {
@@ -768,41 +887,47 @@ hipError_t launch_matvec_tree(const DevPlan &d, const double2 *xt, double2 *yt, 
     }
     const int L = d.depth, top = d.top;
     const DevLevel &lf = d.lv[L];
-    hipLaunchKernelGGL(k_s2m, dim3(d.nleaf, nrhs), dim3(128), sizeof(double2) * d.max_leaf, st, d.leaf_off, d.S,
-                       lf.ku, xt, lf.s, N, lf.sstride);
+    hipLaunchKernelGGL(k_s2m<C>, dim3(d.nleaf, nrhs), dim3(128), sizeof(C) * d.max_leaf, st, d.leaf_off,
+                       (const C *)d.S, lf.ku, xt, (C *)lf.s, N, lf.sstride);
     CHECK_LAUNCH();
     if (ev) hipEventRecord(ev[2], st);
     for (int l = L - 1; l >= top; --l) {
-        const DevLevel &P = d.lv[l], &C = d.lv[l + 1];
-        hipError_t e = launch_ggemm(P.m2m, P.M, P.ku, C.ku, C.s, C.sstride, P.s, P.sstride, 0, nrhs, st, nullptr);
+        const DevLevel &P = d.lv[l], &Cl = d.lv[l + 1];
+        hipError_t e = ggemm_t<C>(P.m2m, P.M, P.ku, Cl.ku, Cl.s, Cl.sstride, P.s, P.sstride, 0, nrhs, st, nullptr);
         if (e != hipSuccess) return e;
     }
     if (ev) hipEventRecord(ev[3], st);
     for (int l = top; l <= L; ++l) {
         const DevLevel &lv = d.lv[l];
         int64_t n = lv.cstride * nrhs;
-        hipLaunchKernelGGL(k_fill_zero, dim3(grid1(n)), dim3(256), 0, st, lv.c, n);
+        hipLaunchKernelGGL(k_fill_zero<C>, dim3(grid1(n)), dim3(256), 0, st, (C *)lv.c, n);
         CHECK_LAUNCH();
         hipError_t e;
         if (lv.rmax > 0)
-            e = launch_m2l_lowrank(lv, nrhs, st, lev ? lev + 2 * l : nullptr);
+            e = m2l_lowrank_t<C>(lv, nrhs, st, lev ? lev + 2 * l : nullptr);
         else
-            e = launch_ggemm(lv.m2l, lv.K, lv.kd, lv.ku, lv.s, lv.sstride, lv.c, lv.cstride, 1, nrhs, st,
-                             lev ? lev + 2 * l : nullptr);
+            e = ggemm_t<C>(lv.m2l, lv.K, lv.kd, lv.ku, lv.s, lv.sstride, lv.c, lv.cstride, 1, nrhs, st,
+                           lev ? lev + 2 * l : nullptr);
         if (e != hipSuccess) return e;
     }
     if (ev) hipEventRecord(ev[4], st);
     for (int l = top; l < L; ++l) {
-        const DevLevel &P = d.lv[l], &C = d.lv[l + 1];
-        hipError_t e = launch_ggemm(P.l2l, P.Lo, C.kd, P.kd, P.c, P.cstride, C.c, C.cstride, 1, nrhs, st, nullptr);
+        const DevLevel &P = d.lv[l], &Cl = d.lv[l + 1];
+        hipError_t e = ggemm_t<C>(P.l2l, P.Lo, Cl.kd, P.kd, P.c, P.cstride, Cl.c, Cl.cstride, 1, nrhs, st, nullptr);
         if (e != hipSuccess) return e;
     }
     if (ev) hipEventRecord(ev[5], st);
-    hipLaunchKernelGGL(k_l2t, dim3(d.nleaf, nrhs), dim3(64), sizeof(double2) * lf.kd, st, d.leaf_off, d.T, lf.kd,
-                       lf.c, yt, N, lf.cstride);
+    hipLaunchKernelGGL(k_l2t<C>, dim3(d.nleaf, nrhs), dim3(64), sizeof(C) * lf.kd, st, d.leaf_off, (const C *)d.T,
+                       lf.kd, (const C *)lf.c, yt, N, lf.cstride);
     CHECK_LAUNCH();
     if (ev) hipEventRecord(ev[6], st);
     return hipSuccess;
+}
+
+hipError_t launch_matvec_tree(const DevPlan &d, const double2 *xt, double2 *yt, int nrhs, hipStream_t st,
+                              hipEvent_t *ev, hipEvent_t *lev) {
+    if (d.prec == 1) return matvec_t<float2>(d, xt, yt, nrhs, st, ev, lev);
+    return matvec_t<double2>(d, xt, yt, nrhs, st, ev, lev);
 }
 
 hipError_t launch_permute_in(const DevPlan &d, const double2 *x, int64_t ld, double2 *xt, int nrhs, hipStream_t st) {
@@ -858,7 +983,7 @@ hipError_t launch_bj_apply(const DevPlan &d, const double2 *r, double2 *z, int n
     return hipSuccess;
 }
 hipError_t launch_fill_zero(double2 *p, int64_t n, hipStream_t st) {
-    hipLaunchKernelGGL(k_fill_zero, dim3(grid1(n)), dim3(256), 0, st, p, n);
+    hipLaunchKernelGGL(k_fill_zero<double2>, dim3(grid1(n)), dim3(256), 0, st, p, n);
     CHECK_LAUNCH();
     return hipSuccess;
 }

@@ -17,7 +17,7 @@ struct GWork {
     int64_t ncol = 0;
     int4 *hdr = nullptr;
     int32_t *src = nullptr, *rd_dst = nullptr, *rd_off = nullptr, *rd_list = nullptr;
-    double2 *tmp = nullptr;
+    void *tmp = nullptr;  // storage type of the plan (double2 or float2)
 };
 
 constexpr int kGemmCols = 32;
@@ -26,15 +26,17 @@ struct DevLevel {
     int64_t nbox = 0;
     int nslot = 1, ku = 0, kd = 0;
     int64_t sstride = 0, cstride = 0;  // elements per right-hand side of s and c
-    double2 *s = nullptr, *c = nullptr;
+    // operator and state arrays hold the plan's storage type: double2
+    // (FP64 plan) or float2 (FP32 plan)
+    void *s = nullptr, *c = nullptr;
     // M2L grouped by translation; low-rank factors when rmax > 0
     GWork m2l;
-    double2 *Ulr = nullptr, *Vlr = nullptr;
+    void *Ulr = nullptr, *Vlr = nullptr;
     int32_t *lr_rank = nullptr;
     int rmax = 0;
-    double2 *K = nullptr;
+    void *K = nullptr;
     // parent-level operators towards level + 1 and their work lists
-    double2 *M = nullptr, *Lo = nullptr;
+    void *M = nullptr, *Lo = nullptr;
     GWork m2m, l2l;
 };
 
@@ -49,8 +51,10 @@ struct DevPlan {
     int64_t *leaf_off = nullptr;
     int32_t *nf_list_off = nullptr, *nf_list = nullptr, *nf_ncol = nullptr, *nf_self_col = nullptr, *nf_cols = nullptr;
     int64_t *nf_blk_off = nullptr, *nf_col_off = nullptr;
-    double2 *nf_vals = nullptr;
-    double2 *S = nullptr, *T = nullptr;
+    int prec = 0;                   // 0: FP64 storage, 1: FP32 storage
+    void *nf_vals = nullptr;        // near-field blocks (FP32 plans: self terms zeroed)
+    double2 *nf_diag = nullptr;     // FP32 plans: FP64 self terms, tree order
+    void *S = nullptr, *T = nullptr;
     std::vector<DevLevel> lv;
     // block-Jacobi inverses of the leaf diagonal blocks
     int64_t *bj_off = nullptr;
@@ -59,8 +63,10 @@ struct DevPlan {
 
 hipError_t set_quadrature_constants(const double r7b[7][3], const double r7w[7], const double glx[32],
                                     const double glw[32]);
-hipError_t launch_near_blocks(const DevPlan &d, hipStream_t st);
-hipError_t launch_bj_invert(const DevPlan &d, hipStream_t st);
+hipError_t launch_near_blocks(const DevPlan &d, double2 *vals64, hipStream_t st);
+hipError_t launch_bj_invert(const DevPlan &d, const double2 *vals64, hipStream_t st);
+hipError_t launch_near_split(const DevPlan &d, const double2 *vals64, hipStream_t st);
+hipError_t launch_to_f32(const double2 *in, void *out, int64_t n, hipStream_t st);
 // ev: 7 stage events or null; lev: 2 events per level around its M2L
 // product kernel, or null.
 hipError_t launch_matvec_tree(const DevPlan &d, const double2 *xt, double2 *yt, int nrhs, hipStream_t st,
@@ -80,9 +86,6 @@ hipError_t launch_bj_apply(const DevPlan &d, const double2 *r, double2 *z, int n
                            hipStream_t st);
 hipError_t launch_fill_zero(double2 *p, int64_t n, hipStream_t st);
 constexpr int kLowRankMax = 80;  // largest rank the low-rank M2L kernel holds in LDS
-hipError_t launch_m2l_lowrank(const DevLevel &lv, int nrhs, hipStream_t st, hipEvent_t *ev);
-hipError_t launch_ggemm(const GWork &g, const double2 *A, int m, int kin, const double2 *X, int64_t xstride,
-                        double2 *Y, int64_t ystride, int accumulate, int nrhs, hipStream_t st, hipEvent_t *ev);
 
 // Blocks used by the two-pass reductions.
 constexpr int kRedBlocks = 240;

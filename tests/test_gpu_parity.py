@@ -180,6 +180,37 @@ def test_fda_matvec_directional_sampled_rows(name, rows):
     assert err < 1e-4
 
 
+@pytest.mark.parametrize("name,rows", [("sphere5120_kD20", None), ("sphere81920_kD100", 96)])
+def test_fp32_plan_matvec_error_vs_fp64_oracle(name, rows):
+    """FP32 storage and FP32-accumulating matrix cores for the far field and
+    the off-diagonal near field, FP64 self terms: the matvec stays within
+    1e-4 (relative 2-norm) of the FP64 oracle."""
+    V, T, prm = W.workload(name)
+    k = prm["k"]
+    x = W.complex_normal(len(T), 1, seed=0)
+    with _plan(V, T, k, prm["eps"], prec="fp32") as p:
+        y = p.matvec(_dev(x)).cpu().numpy()
+    r = np.arange(len(T)) if rows is None else np.sort(np.random.default_rng(5).choice(len(T), size=rows, replace=False))
+    yr = O.matvec(V, T, k, x, row_idx=r)
+    err = np.linalg.norm(y[r] - yr) / np.linalg.norm(yr)
+    _say("fp32 rel err", name, err)
+    assert err < 1e-4
+
+
+def test_fp32_plan_solution_matches_oracle():
+    """GMRES (FP64 Arnoldi) on the FP32 plan: surface field within 1e-3 of
+    the oracle's dense solution."""
+    V, T, prm = W.workload("sphere1280_kD10")
+    k = prm["k"]
+    with _plan(V, T, k, prm["eps"], prec="fp32") as p:
+        b = p.rhs_planewave(prm["direction"])
+        x, info = p.solve(b, tol=1e-5)
+    assert info["converged"]
+    ur = O.solve_dense(O.assemble(V, T, k), O.rhs_planewave(V, T, k, prm["direction"]))
+    u = x.cpu().numpy()
+    assert np.linalg.norm(u - ur) / np.linalg.norm(ur) < 1e-3
+
+
 def test_bm_solve_multi_rhs():
     V, T, prm = W.workload("sphere1280_kD10")
     dirs = W.fibonacci_directions(4)
