@@ -67,7 +67,11 @@ def main():
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fast", action="store_true")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="also run one plain device copy of this many MiB (calibrates HBM counters)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "m2l_lowrank_sphere81920_kD100_traffic.json"),
+                    help="measured HBM traffic of the M2L kernel (written from rocprofv3 counter passes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU path is not built",
@@ -110,22 +114,41 @@ def main():
     ms = e0.elapsed_time(e1) / args.steps
     log(f"[bench] matvec {ms:.3f} ms ({args.steps} steps, wall {wall:.3f} s)")
 
+    if args.calib_copy_mb > 0:
+        src = torch.empty(args.calib_copy_mb * 1024 * 1024 // 8, dtype=torch.float64, device="cuda")
+        src.fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy of {args.calib_copy_mb} MiB done")
+        del src, dst
+
     prof = plan.profile(x, reps=max(3, min(20, args.steps)), out=y)
     log(f"[bench] stages (ms): {prof}")
     y_np = y.cpu().numpy()
 
-    # roofline of the dominant kernel: the M2L product launch of the level
-    # that takes longest; algorithmic flops per launch = 8 real flops per
-    # complex multiply-add of that level's (low-rank) reduced translations
-    lv_ms = prof["m2l_gemm"]
-    lv = int(np.argmax(lv_ms))
-    lv_flops = float(st["m2l_level_flops"][lv])
-    achieved = lv_flops / (lv_ms[lv] * 1e-3) / 1e12 if lv_ms[lv] > 0 else 0.0
-    kname = "k_m2l_lowrank" if st["m2l_rank_max"][lv] > 0 else "k_ggemm"
+    # roofline of the dominant kernel: the M2L product kernel (one launch
+    # per level with interactions).  Algorithmic flops = 8 real flops per
+    # complex multiply-add of the SVD-reduced translations, summed over the
+    # levels, divided by the summed HIP-event durations of those launches:
+    # average flops per launch / average launch duration.
+    lv_ms = [v for v in prof["m2l_gemm"][: st["depth"] + 1]]
+    launches = [l for l, v in enumerate(lv_ms) if st["m2l_level_flops"][l] > 0]
+    m2l_ms = sum(lv_ms[l] for l in launches)
+    m2l_flops = sum(float(st["m2l_level_flops"][l]) for l in launches)
+    achieved = m2l_flops / (m2l_ms * 1e-3) / 1e12 if m2l_ms > 0 else 0.0
+    kname = "k_m2l_lowrank<double2>" if all(st["m2l_rank_max"][l] > 0 for l in launches) else "k_m2l_lowrank / k_ggemm"
     roofline = dict(bound="mfma", achieved=round(achieved, 3), peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
                     frac=round(achieved / FP64_PEAK_TFLOPS, 4), traffic=None,
-                    kernel=f"{kname} (M2L, level {lv})", flops_per_launch=lv_flops,
-                    launch_ms=round(lv_ms[lv], 4))
+                    kernel=f"{kname} (M2L, levels {launches})", launches_per_matvec=len(launches),
+                    flops_per_launch=m2l_flops / max(1, len(launches)),
+                    avg_launch_ms=round(m2l_ms / max(1, len(launches)), 5),
+                    level_ms=[round(lv_ms[l], 4) for l in launches])
+    if args.traffic_json and os.path.exists(args.traffic_json):
+        # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes,
+        # scaled by the same counters' reading for a plain copy of known size
+        roofline["traffic"] = json.load(open(args.traffic_json)).get("bytes_per_launch")
 
     solve = {}
     if not args.no_solve:

@@ -55,8 +55,14 @@ extern "C" {
 /* Preconditioners for bm_solve. */
 #define FDA_PRECOND_NONE 0
 #define FDA_PRECOND_BLOCK_JACOBI 1
+#define FDA_PRECOND_MLP 2          /* learned per-leaf correction on top of block Jacobi (fda_plan_set_mlp) */
+
+/* Shape of the learned preconditioner's rows (see fda_mlp_samples). */
+#define FDA_MLP_IN 272
+#define FDA_MLP_OUT 128
 
 typedef struct fda_plan fda_plan;
+typedef struct fda_mlp fda_mlp;
 
 /* Build options.  Zero-initialise and call fda_default_options(), then
  * override fields.  Every field has a documented default. */
@@ -144,21 +150,108 @@ typedef struct bm_stats {
     double rel_residual;    /* final true relative residual ||b - A x|| / ||b||, worst column */
     double seconds;         /* wall time of the solve */
     int32_t col_iterations[64]; /* per-column iterations (first 64 columns) */
+    int32_t mlp_fallbacks;  /* FDA_PRECOND_MLP: applications whose network output was not finite and
+                               that used the block-Jacobi correction instead */
 } bm_stats;
 
 /* Solve A x = b by restarted GMRES(restart) from x = 0 (Section 5: GMRES, no
  * preconditioner in the paper), stopping when the true relative residual of
  * every column is <= tol or after maxit products.  Arnoldi orthogonalisation
  * (classical Gram-Schmidt, applied twice), the residual and the Givens
- * updates are FP64.  precond: FDA_PRECOND_NONE or FDA_PRECOND_BLOCK_JACOBI
+ * updates are FP64.  precond: FDA_PRECOND_NONE, FDA_PRECOND_BLOCK_JACOBI
  * (right preconditioning by the inverses of the leaf self-interaction
- * blocks).  b_dev, x_dev: N x nrhs device buffers, leading dimension ld;
+ * blocks) or FDA_PRECOND_MLP (the block-Jacobi correction plus the output of
+ * the network attached by fda_plan_set_mlp; the preconditioner is then
+ * nonlinear, so the solver keeps the preconditioned basis, i.e. flexible
+ * GMRES, which it does for every precond).  b_dev, x_dev: N x nrhs device buffers, leading dimension ld;
  * x is overwritten.  Synchronous: returns when the solve is done.  st may be
  * NULL.  Returns 0 when converged, FDA_NOTCONV when maxit was reached (x is
  * the last iterate), FDA_EBREAKDOWN on a non-finite value, or FDA_EINVAL /
  * FDA_ENOMEM / FDA_EHIP. */
 int bm_solve(fda_plan *plan, const void *b_dev, void *x_dev, int64_t nrhs, int64_t ld, double tol, int32_t restart,
              int32_t maxit, int32_t precond, bm_stats *st, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Learned preconditioner.  The paper solves without a preconditioner
+ * (Section 5); these calls add one.  Per leaf L (n_L <= 64 elements) and
+ * residual v, with z_L = inv(A_LL) v_L the block-Jacobi correction:
+ *
+ *   features (FDA_MLP_IN = 272 floats): Re v_L/|v_L|, Im v_L/|v_L|,
+ *     Re z_L/|v_L|, Im z_L/|v_L| (each zero-padded to 64 entries), the leaf
+ *     width and the mesh's largest edge in wavelengths, n_L/64, 1, then
+ *     zeros (v_L = 0 gives zero features apart from the scalars);
+ *   network: 272 -> h -> h -> 128, ReLU after the two hidden layers, BF16
+ *     weights with FP32 accumulation in inference and training, FP32 master
+ *     parameters updated by Adam (beta 0.9 / 0.999, eps 1e-8);
+ *   output (FDA_MLP_OUT = 128): Re and Im of a 64-entry correction c_L;
+ *   preconditioner: M(v)_L = z_L + |v_L| c_L.
+ *
+ * Parameters are one flat FP32 array: W1 (272 x h, row-major: input index
+ * major), b1 (h), W2 (h x h), b2 (h), W3 (h x 128), b3 (128).  Rows of X,
+ * T and masks are row-major float arrays on the device.
+ * ------------------------------------------------------------------------- */
+
+/* Create a network of hidden width h (1..4096) on `device`: He-normal
+ * weights from a seeded generator (W3 scaled by 0.1), zero biases.
+ * Synchronous.  Errors: FDA_EINVAL, FDA_EHIP. */
+int fda_mlp_create(int32_t hidden, uint64_t seed, int32_t device, fda_mlp **out);
+
+/* Release a network (NULL is allowed).  Detach it from plans first. */
+void fda_mlp_free(fda_mlp *mlp);
+
+/* Number of parameters (272h + h + h^2 + h + 128h + 128), or -1 for NULL. */
+int64_t fda_mlp_num_params(const fda_mlp *mlp);
+
+/* Hidden width, or -1 for NULL. */
+int32_t fda_mlp_hidden(const fda_mlp *mlp);
+
+/* Copy the FP32 parameters to / from a host array of n = num_params floats.
+ * set_params rejects non-finite values and refreshes the BF16 copy.
+ * Synchronous.  Errors: FDA_EINVAL (count mismatch, NULL), FDA_EHIP. */
+int fda_mlp_get_params(const fda_mlp *mlp, float *params, int64_t n);
+int fda_mlp_set_params(fda_mlp *mlp, const float *params, int64_t n);
+
+/* Y_dev (rows x 128) = network(X_dev (rows x 272)) on `stream`.  Errors:
+ * FDA_EINVAL, FDA_EHIP. */
+int fda_mlp_forward(fda_mlp *mlp, const float *X_dev, int64_t rows, float *Y_dev, void *stream);
+
+/* Gradient of the masked mean squared error
+ *   L = sum (mask * (network(X) - T))^2 / (rows * 128)
+ * with respect to every parameter (layout as above) into grad_dev (device,
+ * num_params floats); *loss (host, may be NULL) receives L.  The products
+ * with the weights use their BF16 copy (the gradient is taken as if the
+ * rounding were the identity).  Synchronous.  Errors: FDA_EINVAL, FDA_EHIP. */
+int fda_mlp_gradient(fda_mlp *mlp, const float *X_dev, const float *T_dev, const float *M_dev, int64_t rows,
+                     float *grad_dev, double *loss, void *stream);
+
+/* Train with Adam on (X, T, mask) rows for `epochs` passes over seeded
+ * shuffles in mini-batches of `batch` rows.  losses (host, `epochs` doubles,
+ * may be NULL) receives the mean training loss of each epoch.  Synchronous.
+ * Errors: FDA_EINVAL, FDA_EBREAKDOWN (non-finite loss), FDA_EHIP. */
+int fda_mlp_train(fda_mlp *mlp, const float *X_dev, const float *T_dev, const float *M_dev, int64_t rows,
+                  int32_t epochs, int32_t batch, float lr, uint64_t seed, double *losses, void *stream);
+
+/* Training and inference rows of the plan's leaves.  r_dev: N x nrhs
+ * residuals; e_dev (may be NULL): the matching errors e = A^-1 r.  For
+ * column c and leaf L (tree order; stats.nleaf leaves) row c*nleaf + L of
+ * X_dev (272 floats) gets the features of r; if e_dev is given, the same row
+ * of T_dev (128) gets (e_L - z_L)/|r_L| and of M_dev (128) the mask of the
+ * leaf's n_L entries (1 on Re and Im of each, 0 on padding).  Synchronous.
+ * Errors: FDA_EINVAL (leaves above 64 elements, nrhs / ld out of range),
+ * FDA_EHIP. */
+int fda_mlp_samples(fda_plan *plan, const void *r_dev, const void *e_dev, int64_t nrhs, int64_t ld, float *X_dev,
+                    float *T_dev, float *M_dev, void *stream);
+
+/* The plan's element order: perm (host, N entries) receives, for each tree
+ * position, the caller's element index; leaf_off (host, nleaf + 1 entries)
+ * the tree-position range of each leaf (leaf L holds positions
+ * leaf_off[L] .. leaf_off[L+1]-1).  Either pointer may be NULL.  Errors:
+ * FDA_EINVAL (length mismatch). */
+int fda_plan_leaves(const fda_plan *plan, int32_t *perm, int64_t n, int64_t *leaf_off, int64_t nleaf);
+
+/* Attach a network to a plan for FDA_PRECOND_MLP (NULL detaches).  The plan
+ * borrows it: it must outlive its use in bm_solve. */
+int fda_plan_set_mlp(fda_plan *plan, fda_mlp *mlp);
 
 /* Statistics of a built plan. */
 int fda_plan_stats(const fda_plan *plan, fda_stats *st);

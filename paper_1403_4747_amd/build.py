@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libfda.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["setup.cpp", "operators.cpp", "abi.cpp", "kernels.hip", "dsetup.hip"]
+SOURCES = ["setup.cpp", "operators.cpp", "abi.cpp", "kernels.hip", "dsetup.hip", "mlp.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = [

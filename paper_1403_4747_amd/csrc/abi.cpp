@@ -13,6 +13,7 @@
 #include "../../include/fda.h"
 #include "dsetup.hpp"
 #include "kernels.hpp"
+#include "mlp.hpp"
 #include "operators.hpp"
 #include "plan.hpp"
 
@@ -25,9 +26,15 @@ static int fail(int code, const std::string &msg) {
     return code;
 }
 
+struct fda_mlp {
+    fda::Mlp *m = nullptr;
+    int device = 0;
+};
+
 struct fda_plan {
     HostPlan hp;
     DevPlan d;
+    fda_mlp *mlp = nullptr;  // borrowed: learned preconditioner for FDA_PRECOND_MLP
     int device = 0;
     std::vector<void *> allocs;      // build-time device allocations
     int cap_nrhs = 0;                // capacity of the work buffers below
@@ -278,6 +285,15 @@ void upload_plan(fda_plan *p, const HostOps &ops, DevTranslations &tr) {
         bj_off[b + 1] = bj_off[b] + n * n;
     }
     d.bj_off = upload(p, bj_off);
+    {
+        const double lam = 2.0 * 3.14159265358979323846 / hp.k;
+        std::vector<float> sc(2 * (size_t)d.nleaf);
+        for (int b = 0; b < d.nleaf; ++b) {
+            sc[2 * b] = (float)(hp.lv[L].w / lam);
+            sc[2 * b + 1] = (float)(hp.h_max / lam);
+        }
+        d.leaf_scalars = upload(p, sc);
+    }
     d.bj_inv = dalloc<double2>(p, (size_t)bj_off[d.nleaf], p->allocs);
 
     d.lv.assign(L + 1, DevLevel());
@@ -457,11 +473,7 @@ int fda_build(const double *verts, int64_t nv, const int32_t *tris, int64_t nt, 
             for (int l = 0; l <= p->hp.depth; ++l) {
                 tr_rmax[l] = tr.rmax[l];
                 tr_mean[l] = tr.mean_rank[l];
-                if (tr.rmax[l] > 0 && p->hp.lv[l].kd <= 256) {
-                    lr_rank_host[l].resize(p->hp.lv[l].offsets.size());
-                    hip_check(hipMemcpy(lr_rank_host[l].data(), tr.lr_rank[l], sizeof(int32_t) * lr_rank_host[l].size(),
-                                        hipMemcpyDeviceToHost), "rank copy");
-                }
+                if (tr.rmax[l] > 0 && p->hp.lv[l].kd <= 256) lr_rank_host[l] = tr.true_rank[l];
             }
             p->allocs.insert(p->allocs.end(), tr.allocs.begin(), tr.allocs.end());
             p->device_bytes += tr.bytes;
@@ -511,8 +523,10 @@ int fda_build(const double *verts, int64_t nv, const int32_t *tris, int64_t nt, 
     if (rb) rocblas_destroy_handle(rb);
     fill_stats(p->hp, &p->stats);
     {
-        // M2L flops per level as executed: low-rank levels count
-        // 8 r (kd + ku) per pair with the padded rank of its translation
+        // algorithmic M2L flops per level: low-rank levels count
+        // 8 r (kd + ku) real flops per pair with the SVD rank r of its
+        // translation (before the kernel pads it to a multiple of 4); full
+        // levels 8 kd ku
         int64_t tot = 0;
         for (int l = 0; l <= p->hp.depth && l < 24; ++l) {
             const Level &lv = p->hp.lv[l];
@@ -660,7 +674,12 @@ int bm_solve(fda_plan *plan, const void *b_dev, void *x_dev, int64_t nrhs, int64
     if (!plan || !b_dev || !x_dev) return fail(FDA_EINVAL, "NULL argument");
     if (nrhs < 1 || nrhs > plan->hp.opt.nrhs_max || ld < plan->d.n) return fail(FDA_EINVAL, "nrhs / ld out of range");
     if (!(tol > 0) || restart < 1 || restart > 500 || maxit < 1) return fail(FDA_EINVAL, "bad tol / restart / maxit");
-    if (precond != FDA_PRECOND_NONE && precond != FDA_PRECOND_BLOCK_JACOBI) return fail(FDA_EINVAL, "bad precond");
+    if (precond != FDA_PRECOND_NONE && precond != FDA_PRECOND_BLOCK_JACOBI && precond != FDA_PRECOND_MLP)
+        return fail(FDA_EINVAL, "bad precond");
+    if (precond == FDA_PRECOND_MLP && (!plan->mlp || !plan->mlp->m))
+        return fail(FDA_EINVAL, "FDA_PRECOND_MLP needs a network attached with fda_plan_set_mlp");
+    if (precond == FDA_PRECOND_MLP && plan->d.max_leaf > kMlpLeaf)
+        return fail(FDA_EINVAL, "FDA_PRECOND_MLP needs leaves of at most 64 elements");
     auto t0 = std::chrono::steady_clock::now();
     bm_stats st{};
     const int nr = (int)nrhs, m = restart;
@@ -679,8 +698,8 @@ int bm_solve(fda_plan *plan, const void *b_dev, void *x_dev, int64_t nrhs, int64
         ensure_capacity(plan, nr);
         const size_t vec = sizeof(double2) * (size_t)N * nr;
         double2 *V = (double2 *)talloc(vec * (m + 1));
+        double2 *Zs = (double2 *)talloc(vec * m);  // preconditioned basis (flexible GMRES)
         double2 *w = (double2 *)talloc(vec);
-        double2 *z = (double2 *)talloc(vec);
         double2 *bt = (double2 *)talloc(vec);
         double2 *xt = (double2 *)talloc(vec);
         double2 *r = (double2 *)talloc(vec);
@@ -707,11 +726,42 @@ int bm_solve(fda_plan *plan, const void *b_dev, void *x_dev, int64_t nrhs, int64
         auto apply_A = [&](const double2 *in, double2 *out) {
             hip_check(launch_matvec_tree(plan->d, in, out, nr, s, nullptr, nullptr), "matvec");
         };
+        // learned preconditioner workspace (one column at a time)
+        float *feat = nullptr, *yml = nullptr;
+        double *vnorm = nullptr;
+        double2 *zbj = nullptr;
+        int *bad = nullptr;
+        if (precond == FDA_PRECOND_MLP) {
+            feat = (float *)talloc(sizeof(float) * (size_t)plan->d.nleaf * kMlpIn);
+            yml = (float *)talloc(sizeof(float) * (size_t)plan->d.nleaf * kMlpOut);
+            vnorm = (double *)talloc(sizeof(double) * (size_t)plan->d.nleaf);
+            zbj = (double2 *)talloc(sizeof(double2) * (size_t)N);
+            bad = (int *)talloc(sizeof(int));
+        }
         auto apply_M = [&](const double2 *in, double2 *out) {
-            if (precond == FDA_PRECOND_BLOCK_JACOBI)
+            if (precond == FDA_PRECOND_BLOCK_JACOBI) {
                 hip_check(launch_bj_apply(plan->d, in, out, nr, nullptr, s), "precond");
-            else
+            } else if (precond == FDA_PRECOND_MLP) {
+                for (int c = 0; c < nr; ++c) {
+                    const double2 *vc = in + (size_t)c * N;
+                    double2 *oc = out + (size_t)c * N;
+                    int flag = 0;
+                    hip_check(hipMemcpyAsync(bad, &flag, sizeof(int), hipMemcpyHostToDevice, s), "h2d");
+                    mlp_features(plan->d, vc, plan->d.leaf_scalars, feat, vnorm, zbj, s);
+                    plan->mlp->m->forward(feat, plan->d.nleaf, yml, s);
+                    mlp_apply(plan->d, yml, vnorm, zbj, oc, bad, s);
+                    hip_check(hipGetLastError(), "mlp preconditioner");
+                    hip_check(hipMemcpyAsync(&flag, bad, sizeof(int), hipMemcpyDeviceToHost, s), "d2h");
+                    hip_check(hipStreamSynchronize(s), "sync");
+                    if (flag) {  // non-finite network output: fall back to block Jacobi
+                        hip_check(hipMemcpyAsync(oc, zbj, sizeof(double2) * (size_t)N, hipMemcpyDeviceToDevice, s),
+                                  "fallback");
+                        st.mlp_fallbacks++;
+                    }
+                }
+            } else {
                 hip_check(hipMemcpyAsync(out, in, vec, hipMemcpyDeviceToDevice, s), "copy");
+            }
         };
 
         hip_check(launch_permute_in(plan->d, (const double2 *)b_dev, ld, bt, nr, s), "permute");
@@ -754,8 +804,9 @@ int bm_solve(fda_plan *plan, const void *b_dev, void *x_dev, int64_t nrhs, int64
             std::vector<char> done(nr, 0);
             std::vector<int> jcnt(nr, 0);
             for (int j = 0; j < m; ++j) {
-                apply_M(V + (size_t)j * N * nr, z);
-                apply_A(z, w);
+                double2 *zj = Zs + (size_t)j * N * nr;
+                apply_M(V + (size_t)j * N * nr, zj);
+                apply_A(zj, w);
                 ++iters;
                 // classical Gram-Schmidt, twice
                 std::vector<cplx> h1, h2v;
@@ -796,7 +847,7 @@ int bm_solve(fda_plan *plan, const void *b_dev, void *x_dev, int64_t nrhs, int64
                 jdone = j + 1;
                 if (all_ok || iters >= maxit) break;
             }
-            // y = H^-1 g per column, then x += M^-1 V y
+            // y = H^-1 g per column, then x += Z y (flexible GMRES: Z_j = M(V_j))
             std::vector<cplx> Y((size_t)(m + 1) * nr, 0.0);
             for (int c = 0; c < nr; ++c) {
                 if (!act[c]) continue;
@@ -809,16 +860,8 @@ int bm_solve(fda_plan *plan, const void *b_dev, void *x_dev, int64_t nrhs, int64
                 }
             }
             hip_check(hipMemcpyAsync(h2, Y.data(), sizeof(double2) * (size_t)jdone * nr, hipMemcpyHostToDevice, s), "h2d");
-            hip_check(launch_fill_zero(w, (int64_t)N * nr, s), "zero");
-            hip_check(launch_multi_axpy(V, jdone, nr, h2, 1.0, w, N, nullptr, s), "update");
-            apply_M(w, z);
-            // x += z on active columns
-            {
-                std::vector<cplx> ones(nr);
-                for (int c = 0; c < nr; ++c) ones[c] = act[c] ? 1.0 : 0.0;
-                hip_check(hipMemcpyAsync(sc, ones.data(), sizeof(double2) * nr, hipMemcpyHostToDevice, s), "h2d");
-                hip_check(launch_multi_axpy(z, 1, nr, sc, 1.0, xt, N, nullptr, s), "x update");
-            }
+            // x += Z y (Y is zero for inactive columns)
+            hip_check(launch_multi_axpy(Zs, jdone, nr, h2, 1.0, xt, N, nullptr, s), "x update");
             // true residual r = b - A x
             apply_A(xt, w);
             hip_check(launch_sub(bt, w, r, (int64_t)N * nr, s), "residual");
@@ -833,6 +876,8 @@ int bm_solve(fda_plan *plan, const void *b_dev, void *x_dev, int64_t nrhs, int64
         rc = fail(e.code, e.msg);
     } catch (const HipError &e) {
         rc = fail(FDA_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
+    } catch (const MlpError &e) {
+        rc = fail(FDA_EHIP, e.msg);
     }
     hipStreamSynchronize(s);
     for (void *q : tmp) hipFree(q);
@@ -840,6 +885,193 @@ int bm_solve(fda_plan *plan, const void *b_dev, void *x_dev, int64_t nrhs, int64
     if (stp) *stp = st;
     if (rc == FDA_NOTCONV) g_last_error = "GMRES reached maxit before the tolerance";
     return rc;
+}
+
+
+// ------------------------------------------------------------ learned preconditioner
+
+#define MLP_GUARD(body)                                                      \
+    try {                                                                    \
+        body                                                                 \
+    } catch (const MlpError &e) {                                            \
+        return fail(FDA_EHIP, e.msg);                                        \
+    } catch (const HipError &e) {                                            \
+        return fail(FDA_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.e)); \
+    } catch (const BuildError &e) {                                          \
+        return fail(e.code, e.msg);                                          \
+    } catch (const std::bad_alloc &) {                                       \
+        return fail(FDA_ENOMEM, "host allocation failed");                   \
+    }
+
+int fda_mlp_create(int32_t hidden, uint64_t seed, int32_t device, fda_mlp **out) {
+    g_last_error.clear();
+    if (!out) return fail(FDA_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (hidden < 1 || hidden > 4096) return fail(FDA_EINVAL, "hidden width must be in [1, 4096]");
+    MLP_GUARD({
+        hip_check(hipSetDevice(device), "hipSetDevice");
+        fda_mlp *h = new fda_mlp();
+        h->device = device;
+        try {
+            h->m = mlp_create(hidden, seed);
+        } catch (...) {
+            delete h;
+            throw;
+        }
+        hip_check(hipDeviceSynchronize(), "sync");
+        *out = h;
+    })
+    return FDA_OK;
+}
+
+void fda_mlp_free(fda_mlp *mlp) {
+    if (!mlp) return;
+    hipSetDevice(mlp->device);
+    hipDeviceSynchronize();
+    mlp_free(mlp->m);
+    delete mlp;
+}
+
+int64_t fda_mlp_num_params(const fda_mlp *mlp) { return mlp && mlp->m ? (int64_t)mlp->m->nparam : -1; }
+
+int32_t fda_mlp_hidden(const fda_mlp *mlp) { return mlp && mlp->m ? mlp->m->hidden : -1; }
+
+int fda_mlp_get_params(const fda_mlp *mlp, float *params, int64_t n) {
+    g_last_error.clear();
+    if (!mlp || !mlp->m || !params) return fail(FDA_EINVAL, "NULL argument");
+    if (n != (int64_t)mlp->m->nparam) return fail(FDA_EINVAL, "parameter count mismatch");
+    MLP_GUARD({
+        hip_check(hipSetDevice(mlp->device), "hipSetDevice");
+        hip_check(hipDeviceSynchronize(), "sync");
+        hip_check(hipMemcpy(params, mlp->m->w, sizeof(float) * n, hipMemcpyDeviceToHost), "d2h");
+    })
+    return FDA_OK;
+}
+
+int fda_mlp_set_params(fda_mlp *mlp, const float *params, int64_t n) {
+    g_last_error.clear();
+    if (!mlp || !mlp->m || !params) return fail(FDA_EINVAL, "NULL argument");
+    if (n != (int64_t)mlp->m->nparam) return fail(FDA_EINVAL, "parameter count mismatch");
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(params[i])) return fail(FDA_EINVAL, "non-finite parameter");
+    MLP_GUARD({
+        hip_check(hipSetDevice(mlp->device), "hipSetDevice");
+        hip_check(hipDeviceSynchronize(), "sync");
+        hip_check(hipMemcpy(mlp->m->w, params, sizeof(float) * n, hipMemcpyHostToDevice), "h2d");
+        mlp->m->sync_bf16(nullptr);
+        hip_check(hipDeviceSynchronize(), "sync");
+    })
+    return FDA_OK;
+}
+
+int fda_mlp_forward(fda_mlp *mlp, const float *X_dev, int64_t rows, float *Y_dev, void *stream) {
+    g_last_error.clear();
+    if (!mlp || !mlp->m || !X_dev || !Y_dev) return fail(FDA_EINVAL, "NULL argument");
+    if (rows < 1 || rows > (int64_t)1 << 30) return fail(FDA_EINVAL, "rows out of range");
+    MLP_GUARD({
+        hip_check(hipSetDevice(mlp->device), "hipSetDevice");
+        hip_check(hipStreamSynchronize(as_stream(stream)), "sync");
+        mlp->m->forward(X_dev, rows, Y_dev, as_stream(stream));
+        hip_check(hipGetLastError(), "forward");
+    })
+    return FDA_OK;
+}
+
+int fda_mlp_gradient(fda_mlp *mlp, const float *X_dev, const float *T_dev, const float *M_dev, int64_t rows,
+                     float *grad_dev, double *loss, void *stream) {
+    g_last_error.clear();
+    if (!mlp || !mlp->m || !X_dev || !T_dev || !M_dev || !grad_dev) return fail(FDA_EINVAL, "NULL argument");
+    if (rows < 1 || rows > (int64_t)1 << 24) return fail(FDA_EINVAL, "rows out of range");
+    MLP_GUARD({
+        hip_check(hipSetDevice(mlp->device), "hipSetDevice");
+        hipStream_t s = as_stream(stream);
+        hip_check(hipStreamSynchronize(s), "sync");
+        const double sse = mlp_gradient(mlp->m, X_dev, T_dev, M_dev, rows, grad_dev, s);
+        if (loss) *loss = sse / ((double)rows * kMlpOut);
+    })
+    return FDA_OK;
+}
+
+int fda_mlp_train(fda_mlp *mlp, const float *X_dev, const float *T_dev, const float *M_dev, int64_t rows,
+                  int32_t epochs, int32_t batch, float lr, uint64_t seed, double *losses, void *stream) {
+    g_last_error.clear();
+    if (!mlp || !mlp->m || !X_dev || !T_dev || !M_dev) return fail(FDA_EINVAL, "NULL argument");
+    if (rows < 1 || rows > ((int64_t)1 << 31) - 1) return fail(FDA_EINVAL, "rows out of range");
+    if (epochs < 1 || batch < 1 || batch > (1 << 16) || !(lr > 0) || !std::isfinite(lr))
+        return fail(FDA_EINVAL, "bad epochs / batch / lr");
+    MLP_GUARD({
+        hip_check(hipSetDevice(mlp->device), "hipSetDevice");
+        hipStream_t s = as_stream(stream);
+        hip_check(hipStreamSynchronize(s), "sync");
+        std::vector<double> l = mlp_train(mlp->m, X_dev, T_dev, M_dev, rows, epochs, batch, lr, seed, s);
+        if (losses) std::copy(l.begin(), l.end(), losses);
+        for (double v : l)
+            if (!std::isfinite(v)) return fail(FDA_EBREAKDOWN, "training loss is not finite");
+    })
+    return FDA_OK;
+}
+
+int fda_mlp_samples(fda_plan *plan, const void *r_dev, const void *e_dev, int64_t nrhs, int64_t ld, float *X_dev,
+                    float *T_dev, float *M_dev, void *stream) {
+    g_last_error.clear();
+    if (!plan || !r_dev || !X_dev) return fail(FDA_EINVAL, "NULL argument");
+    if ((e_dev == nullptr) != (T_dev == nullptr) || (T_dev == nullptr) != (M_dev == nullptr))
+        return fail(FDA_EINVAL, "e_dev, T_dev and M_dev are given together");
+    if (nrhs < 1 || nrhs > plan->hp.opt.nrhs_max || ld < plan->d.n) return fail(FDA_EINVAL, "nrhs / ld out of range");
+    if (plan->d.max_leaf > kMlpLeaf) return fail(FDA_EINVAL, "leaves of more than 64 elements");
+    double *vnorm = nullptr;
+    double2 *z = nullptr;
+    int rc = FDA_OK;
+    try {
+        hip_check(hipSetDevice(plan->device), "hipSetDevice");
+        ensure_capacity(plan, (int)nrhs);
+        hipStream_t s = as_stream(stream);
+        const int64_t N = plan->d.n, nl = plan->d.nleaf;
+        hip_check(hipMalloc(&vnorm, sizeof(double) * nl), "alloc");
+        hip_check(hipMalloc(&z, sizeof(double2) * N), "alloc");
+        hip_check(launch_permute_in(plan->d, (const double2 *)r_dev, ld, plan->xt, (int)nrhs, s), "permute");
+        if (e_dev)
+            hip_check(launch_permute_in(plan->d, (const double2 *)e_dev, ld, plan->yt, (int)nrhs, s), "permute");
+        for (int64_t c = 0; c < nrhs; ++c) {
+            mlp_features(plan->d, plan->xt + c * N, plan->d.leaf_scalars, X_dev + c * nl * kMlpIn, vnorm, z, s);
+            if (e_dev)
+                mlp_targets(plan->d, plan->yt + c * N, z, vnorm, T_dev + c * nl * kMlpOut, M_dev + c * nl * kMlpOut,
+                            s);
+        }
+        hip_check(hipGetLastError(), "features");
+        hip_check(hipStreamSynchronize(s), "sync");
+    } catch (const HipError &e) {
+        rc = fail(FDA_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
+    } catch (const BuildError &e) {
+        rc = fail(e.code, e.msg);
+    }
+    if (rc != FDA_OK) hipStreamSynchronize(as_stream(stream));
+    hipFree(vnorm);
+    hipFree(z);
+    return rc;
+}
+
+int fda_plan_leaves(const fda_plan *plan, int32_t *perm, int64_t n, int64_t *leaf_off, int64_t nleaf) {
+    g_last_error.clear();
+    if (!plan) return fail(FDA_EINVAL, "NULL plan");
+    const HostPlan &hp = plan->hp;
+    if (perm) {
+        if (n != (int64_t)hp.perm.size()) return fail(FDA_EINVAL, "perm length must be N");
+        std::copy(hp.perm.begin(), hp.perm.end(), perm);
+    }
+    if (leaf_off) {
+        if (nleaf + 1 != (int64_t)hp.leaf_off.size()) return fail(FDA_EINVAL, "leaf_off length must be nleaf + 1");
+        std::copy(hp.leaf_off.begin(), hp.leaf_off.end(), leaf_off);
+    }
+    return FDA_OK;
+}
+
+int fda_plan_set_mlp(fda_plan *plan, fda_mlp *mlp) {
+    g_last_error.clear();
+    if (!plan) return fail(FDA_EINVAL, "NULL plan");
+    if (mlp && mlp->device != plan->device) return fail(FDA_EINVAL, "network and plan are on different devices");
+    plan->mlp = mlp;
+    return FDA_OK;
 }
 
 }  // extern "C"

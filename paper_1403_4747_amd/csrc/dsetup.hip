@@ -414,6 +414,7 @@ void device_lowrank_m2l(const HostPlan &hp, rocblas_handle h, DevTranslations &o
     out.lr_rank.assign(L + 1, nullptr);
     out.rmax.assign(L + 1, 0);
     out.mean_rank.assign(L + 1, 0.0);
+    out.true_rank.assign(L + 1, {});
     for (int l = hp.top; l <= L; ++l) {
         const Level &lv = hp.lv[l];
         const int noff = (int)lv.offsets.size();
@@ -434,7 +435,7 @@ void device_lowrank_m2l(const HostPlan &hp, rocblas_handle h, DevTranslations &o
         std::vector<rocblas_int> info(noff);
         hchk(hipMemcpy(S.data(), dS.p, sizeof(double) * S.size(), hipMemcpyDeviceToHost), "d2h");
         hchk(hipMemcpy(info.data(), dinfo.p, sizeof(rocblas_int) * noff, hipMemcpyDeviceToHost), "d2h");
-        std::vector<int32_t> rank(noff);
+        std::vector<int32_t> rank(noff), rtrue(noff);
         int rmax = 0;
         double rsum = 0;
         for (int o = 0; o < noff; ++o) {
@@ -444,6 +445,7 @@ void device_lowrank_m2l(const HostPlan &hp, rocblas_handle h, DevTranslations &o
             while (r < mn && so[r] >= hp.svd_eps * so[0] && so[0] > 0) ++r;
             r = std::max(r, 1);
             rsum += r;
+            rtrue[o] = r;
             r = std::min(mn, (r + 3) / 4 * 4);
             rank[o] = r;
             rmax = std::max(rmax, r);
@@ -451,6 +453,7 @@ void device_lowrank_m2l(const HostPlan &hp, rocblas_handle h, DevTranslations &o
         out.mean_rank[l] = rsum / noff;
         // low rank pays when 2 r < k (Section 4.2); kernel limit max_rank
         if (rmax > max_rank || 2 * rmax >= mn) continue;
+        out.true_rank[l] = rtrue;
         double2 *Ulr = nullptr, *Vlr = nullptr;
         int32_t *dr = nullptr;
         auto keep = [&](size_t bytes) {

@@ -18,6 +18,7 @@ struct DevTranslations {
     std::vector<int32_t *> lr_rank;
     std::vector<int> rmax;
     std::vector<double> mean_rank;
+    std::vector<std::vector<int32_t>> true_rank;  // per level and offset: SVD rank before padding to 4
     std::vector<void *> allocs;
     int64_t bytes = 0;
 };

@@ -58,6 +58,7 @@ struct DevPlan {
     std::vector<DevLevel> lv;
     // block-Jacobi inverses of the leaf diagonal blocks
     int64_t *bj_off = nullptr;
+    float *leaf_scalars = nullptr;  // per leaf: width and largest edge, in wavelengths
     double2 *bj_inv = nullptr;
 };
 

@@ -16,13 +16,15 @@ from typing import Dict, Optional, Sequence
 
 import numpy as np
 
-__all__ = ["Plan", "inspect", "library", "default_options", "FDAError", "PRECOND", "PREC"]
+__all__ = ["Plan", "Mlp", "inspect", "library", "default_options", "FDAError", "PRECOND", "PREC", "MLP_IN",
+           "MLP_OUT"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "libfda.so")
 
 PREC = {"fp64": 0, "fp32": 1}
-PRECOND = {"none": 0, "block_jacobi": 1}
+PRECOND = {"none": 0, "block_jacobi": 1, "mlp": 2}
+MLP_IN, MLP_OUT = 272, 128
 
 FDA_NOTCONV = 1
 
@@ -77,7 +79,7 @@ class ProfileResult(ctypes.Structure):
 class SolveStats(ctypes.Structure):
     _fields_ = [
         ("iterations", ctypes.c_int32), ("restarts", ctypes.c_int32), ("rel_residual", ctypes.c_double),
-        ("seconds", ctypes.c_double), ("col_iterations", ctypes.c_int32 * 64),
+        ("seconds", ctypes.c_double), ("col_iterations", ctypes.c_int32 * 64), ("mlp_fallbacks", ctypes.c_int32),
     ]
 
 
@@ -109,6 +111,30 @@ def library():
         L.fda_profile_matvec.argtypes = [vp, vp, vp, i64, i64, ctypes.c_int32, vp, ctypes.POINTER(ProfileResult)]
         L.fda_profile_matvec.restype = ctypes.c_int
         L.fda_free.argtypes = [vp]
+        L.fda_mlp_create.argtypes = [ctypes.c_int32, ctypes.c_uint64, ctypes.c_int32, ctypes.POINTER(vp)]
+        L.fda_mlp_create.restype = ctypes.c_int
+        L.fda_mlp_free.argtypes = [vp]
+        L.fda_mlp_num_params.argtypes = [vp]
+        L.fda_mlp_num_params.restype = i64
+        L.fda_mlp_hidden.argtypes = [vp]
+        L.fda_mlp_hidden.restype = ctypes.c_int32
+        L.fda_mlp_get_params.argtypes = [vp, vp, i64]
+        L.fda_mlp_get_params.restype = ctypes.c_int
+        L.fda_mlp_set_params.argtypes = [vp, vp, i64]
+        L.fda_mlp_set_params.restype = ctypes.c_int
+        L.fda_mlp_forward.argtypes = [vp, vp, i64, vp, vp]
+        L.fda_mlp_forward.restype = ctypes.c_int
+        L.fda_mlp_gradient.argtypes = [vp, vp, vp, vp, i64, vp, ctypes.POINTER(dbl), vp]
+        L.fda_mlp_gradient.restype = ctypes.c_int
+        L.fda_mlp_train.argtypes = [vp, vp, vp, vp, i64, ctypes.c_int32, ctypes.c_int32, ctypes.c_float,
+                                    ctypes.c_uint64, vp, vp]
+        L.fda_mlp_train.restype = ctypes.c_int
+        L.fda_mlp_samples.argtypes = [vp, vp, vp, i64, i64, vp, vp, vp, vp]
+        L.fda_mlp_samples.restype = ctypes.c_int
+        L.fda_plan_leaves.argtypes = [vp, vp, i64, vp, i64]
+        L.fda_plan_leaves.restype = ctypes.c_int
+        L.fda_plan_set_mlp.argtypes = [vp, vp]
+        L.fda_plan_set_mlp.restype = ctypes.c_int
         L.fda_last_error.restype = ctypes.c_char_p
         L.fda_version.restype = ctypes.c_char_p
         _lib = L
@@ -233,8 +259,43 @@ class Plan:
         _err(rc)
         info = dict(iterations=st.iterations, restarts=st.restarts, rel_residual=st.rel_residual,
                     seconds=st.seconds, col_iterations=list(st.col_iterations)[:nrhs],
-                    converged=(rc == 0))
+                    mlp_fallbacks=st.mlp_fallbacks, converged=(rc == 0))
         return x, info
+
+    def leaves(self):
+        """(perm, leaf_off): the caller's element index of each tree position
+        and the tree-position range of each leaf (fda_plan_leaves)."""
+        nl = self.stats()["nleaf"]
+        perm = np.empty(self.n, dtype=np.int32)
+        off = np.empty(nl + 1, dtype=np.int64)
+        _err(library().fda_plan_leaves(self._h, perm.ctypes.data, self.n, off.ctypes.data, nl))
+        return perm, off
+
+    def set_mlp(self, mlp: Optional["Mlp"]):
+        """Attach a learned preconditioner for precond="mlp" (fda_plan_set_mlp)."""
+        _err(library().fda_plan_set_mlp(self._h, mlp._h if mlp is not None else None))
+        self._mlp = mlp  # keep it alive while attached
+
+    def mlp_samples(self, r, e=None):
+        """Feature rows (and targets / masks when e = A^-1 r is given) of
+        every leaf for each residual column (fda_mlp_samples).  Returns float32
+        device tensors X (nrhs*nleaf, 272) and, with e, T and M (.., 128)."""
+        import torch
+
+        nrhs = self._check_vec(r, self.n)
+        if e is not None and (self._check_vec(e, self.n) != nrhs):
+            raise ValueError("r and e differ in shape")
+        nl = self.stats()["nleaf"]
+        X = torch.empty((nrhs * nl, MLP_IN), dtype=torch.float32, device=r.device)
+        T = M = None
+        if e is not None:
+            T = torch.empty((nrhs * nl, MLP_OUT), dtype=torch.float32, device=r.device)
+            M = torch.empty_like(T)
+        rc = library().fda_mlp_samples(self._h, r.data_ptr(), e.data_ptr() if e is not None else None, nrhs, self.n,
+                                       X.data_ptr(), T.data_ptr() if T is not None else None,
+                                       M.data_ptr() if M is not None else None, _stream())
+        _err(rc)
+        return (X, T, M) if e is not None else X
 
     def stats(self) -> Dict:
         st = Stats()
@@ -255,3 +316,91 @@ class Plan:
         d = {q: getattr(res, q + "_ms") for q in ("near", "s2m", "m2m", "m2l", "l2l", "l2t", "total")}
         d["m2l_gemm"] = list(res.m2l_gemm_ms)
         return d
+
+
+def _f32_dev(t, width, name):
+    import torch
+
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float32 CUDA tensor")
+    if t.dim() != 2 or t.shape[1] != width:
+        raise ValueError(f"{name} must have shape (rows, {width})")
+    return t.shape[0]
+
+
+class Mlp:
+    """The learned per-leaf preconditioner network (fda_mlp_*)."""
+
+    def __init__(self, hidden: int = 256, seed: int = 0, device: int = 0):
+        h = ctypes.c_void_p()
+        _err(library().fda_mlp_create(int(hidden), int(seed), int(device), ctypes.byref(h)))
+        self._h = h
+        self.hidden = int(hidden)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            library().fda_mlp_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def num_params(self) -> int:
+        return int(library().fda_mlp_num_params(self._h))
+
+    def get_params(self) -> np.ndarray:
+        p = np.empty(self.num_params, dtype=np.float32)
+        _err(library().fda_mlp_get_params(self._h, p.ctypes.data, p.size))
+        return p
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        _err(library().fda_mlp_set_params(self._h, p.ctypes.data, p.size))
+
+    def split(self, p=None) -> Dict[str, np.ndarray]:
+        """The flat parameter array as W1, b1, W2, b2, W3, b3."""
+        p = self.get_params() if p is None else p
+        h, out = self.hidden, {}
+        shapes = [("W1", (MLP_IN, h)), ("b1", (h,)), ("W2", (h, h)), ("b2", (h,)), ("W3", (h, MLP_OUT)),
+                  ("b3", (MLP_OUT,))]
+        o = 0
+        for name, shp in shapes:
+            n = int(np.prod(shp))
+            out[name] = p[o:o + n].reshape(shp)
+            o += n
+        return out
+
+    def forward(self, X):
+        import torch
+
+        rows = _f32_dev(X, MLP_IN, "X")
+        Y = torch.empty((rows, MLP_OUT), dtype=torch.float32, device=X.device)
+        _err(library().fda_mlp_forward(self._h, X.data_ptr(), rows, Y.data_ptr(), _stream()))
+        return Y
+
+    def gradient(self, X, T, M):
+        """(loss, flat gradient as a float32 device tensor)."""
+        import torch
+
+        rows = _f32_dev(X, MLP_IN, "X")
+        if _f32_dev(T, MLP_OUT, "T") != rows or _f32_dev(M, MLP_OUT, "M") != rows:
+            raise ValueError("X, T and M differ in rows")
+        g = torch.empty(self.num_params, dtype=torch.float32, device=X.device)
+        loss = ctypes.c_double()
+        _err(library().fda_mlp_gradient(self._h, X.data_ptr(), T.data_ptr(), M.data_ptr(), rows, g.data_ptr(),
+                                        ctypes.byref(loss), _stream()))
+        return loss.value, g
+
+    def train(self, X, T, M, epochs: int = 10, batch: int = 1024, lr: float = 1e-3, seed: int = 0):
+        """Adam training; returns the per-epoch mean losses."""
+        rows = _f32_dev(X, MLP_IN, "X")
+        if _f32_dev(T, MLP_OUT, "T") != rows or _f32_dev(M, MLP_OUT, "M") != rows:
+            raise ValueError("X, T and M differ in rows")
+        losses = np.zeros(int(epochs), dtype=np.float64)
+        _err(library().fda_mlp_train(self._h, X.data_ptr(), T.data_ptr(), M.data_ptr(), rows, int(epochs), int(batch),
+                                     float(lr), int(seed), losses.ctypes.data, _stream()))
+        return losses

@@ -22,7 +22,7 @@ def _lib():
 
 def test_header_symbols_exported():
     txt = open(HEADER).read()
-    names = set(re.findall(r"^\s*(?:int|void|const char \*)\s*\**\s*([a-z_0-9]+)\s*\(", txt, re.M))
+    names = set(re.findall(r"^\s*(?:int|int32_t|int64_t|void|const char \*)\s*\**\s*([a-z_0-9]+)\s*\(", txt, re.M))
     assert {"fda_build", "fda_matvec", "bm_solve", "bm_rhs_planewave", "fda_free", "fda_last_error"} <= names
     L = _lib()
     for n in sorted(names):
