@@ -95,7 +95,7 @@ def main():
     st = plan.stats()
     log(f"[bench] build {build_s:.2f} s; depth {st['depth']} top {st['top_level']} pairs {st['m2l_pairs']} "
         f"ranks {st['rank_up']} p {st['p']} m2l low-rank max {st['m2l_rank_max']} mean "
-        f"{[round(v, 1) for v in st['m2l_rank_mean']]}")
+        f"{[round(v, 1) for v in st['m2l_rank_mean']]} level flops {[round(v / 1e9, 3) for v in st['m2l_level_flops']]} GF")
 
     x = torch.from_numpy(W.complex_normal(n, 1, seed=0)).to("cuda")
     y = torch.empty_like(x)

@@ -298,78 +298,99 @@ __global__ void k_s2m(const int64_t *leaf_off, const C *S, int ku, const double2
 // of a 256-row band.  Work items of consecutive index are mapped to the same
 // XCD so that the shared translation matrices stay in that XCD's L2.
 #define GG_NB 32
+#define GG_LD (GG_NB + 1)  // padded LDS row: spreads the 4 k-rows of an MFMA operand over the banks
 #define GG_J 32
 #define MF_RT 4
+#define LR_MAX 80
+#define LR_LD (LR_MAX + 1)
 
 // Load up to GG_J x GG_NB gathered input values (zero padded) into LDS.
 template <class C>
-__device__ __forceinline__ void load_states(C (*S)[GG_NB], const C *Xr, const int32_t *st, int kin, int j0) {
+__device__ __forceinline__ void load_states(C (*S)[GG_LD], const C *Xr, const int32_t *sidx, int kin, int j0) {
     for (int e = threadIdx.x; e < GG_J * GG_NB; e += blockDim.x) {
         const int jj = e % GG_J, b = e / GG_J;
-        const int sb = st[b];
+        const int sb = sidx[b];
         C v = czero<C>();
         if (sb >= 0 && j0 + jj < kin) v = Xr[(int64_t)sb * kin + j0 + jj];
         S[jj][b] = v;
     }
 }
 
-// acc (+)= A-tile (rows row0.., columns kcol..) x B (two 16-column tiles).
+// acc (+)= A-fragment x B for one 16-column tile.  The real and imaginary
+// chains alternate so that no MFMA waits on the one just issued.
 template <class C>
-__device__ __forceinline__ void mfma_complex(typename CT<C>::v4 &aR0, typename CT<C>::v4 &aI0,
-                                             typename CT<C>::v4 &aR1, typename CT<C>::v4 &aI1, C a, C b0, C b1) {
+__device__ __forceinline__ void cmfma1(typename CT<C>::v4 &aR, typename CT<C>::v4 &aI, C a, C b) {
+    aR = CT<C>::mfma(a.x, b.x, aR);
+    aI = CT<C>::mfma(a.x, b.y, aI);
+    aR = CT<C>::mfma(-a.y, b.y, aR);
+    aI = CT<C>::mfma(a.y, b.x, aI);
+}
+// ... and for two 16-column tiles sharing the A fragment.
+template <class C>
+__device__ __forceinline__ void cmfma2(typename CT<C>::v4 &aR0, typename CT<C>::v4 &aI0, typename CT<C>::v4 &aR1,
+                                       typename CT<C>::v4 &aI1, C a, C b0, C b1) {
     aR0 = CT<C>::mfma(a.x, b0.x, aR0);
-    aR0 = CT<C>::mfma(-a.y, b0.y, aR0);
     aI0 = CT<C>::mfma(a.x, b0.y, aI0);
-    aI0 = CT<C>::mfma(a.y, b0.x, aI0);
     aR1 = CT<C>::mfma(a.x, b1.x, aR1);
-    aR1 = CT<C>::mfma(-a.y, b1.y, aR1);
     aI1 = CT<C>::mfma(a.x, b1.y, aI1);
+    aR0 = CT<C>::mfma(-a.y, b0.y, aR0);
+    aI0 = CT<C>::mfma(a.y, b0.x, aI0);
+    aR1 = CT<C>::mfma(-a.y, b1.y, aR1);
     aI1 = CT<C>::mfma(a.y, b1.x, aI1);
 }
 
-template <class C>
-__global__ void __launch_bounds__(256) k_ggemm(const int4 *hdr, const int32_t *src, const C *A, int m, int kin,
-                                               const C *X, int64_t xstride, C *T, int64_t tstride, int nwork) {
+// A fragments of the wave's row tiles rt = wave + 4 q at k-column kcol of a
+// column-major matrix (zero outside rows < mrows, columns < kend).
+template <class C, int NT>
+__device__ __forceinline__ void load_afrag(C (&a)[NT], const C *A, int lda, int mrows, int row0, int ntile, int wave,
+                                           int li, int kcol, int kend) {
+#pragma unroll
+    for (int q = 0; q < NT; ++q) {
+        const int rt = wave + 4 * q;
+        const int row = row0 + rt * 16 + li;
+        a[q] = czero<C>();
+        if (rt < ntile && row < mrows && kcol < kend) a[q] = A[row + (int64_t)kcol * lda];
+    }
+}
+
+// Y (m x ncols) = A (m x kin) S-gathered (kin x ncols), NCT 16-column tiles.
+template <class C, int NCT>
+__device__ __forceinline__ void ggemm_body(const int4 h, const int32_t *sidx, const C *At, int m, int kin,
+                                           const C *Xr, C *Tr, C (*S)[GG_LD]) {
     using v4 = typename CT<C>::v4;
-    __shared__ C S[GG_J][GG_NB];
-    const int nx = 8;
-    const int per = gridDim.x / nx;
-    const int w = (blockIdx.x % nx) * per + blockIdx.x / nx;
-    if (w >= nwork) return;
-    const int4 h = hdr[w];  // (matrix, first scratch column, column count, 0)
-    const C *Xr = X + (int64_t)blockIdx.y * xstride;
-    C *Tr = T + (int64_t)blockIdx.y * tstride + (int64_t)h.y * m;
-    const C *At = A + (int64_t)h.x * m * kin;
-    const int32_t *st = src + (int64_t)w * GG_NB;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lk = lane >> 4;
     for (int band = 0; band < m; band += 64 * MF_RT) {
         const int ntile = min(MF_RT * 4, (m - band + 15) >> 4);
-        v4 accR[MF_RT][2], accI[MF_RT][2];
+        v4 accR[MF_RT][NCT], accI[MF_RT][NCT];
 #pragma unroll
         for (int q = 0; q < MF_RT; ++q)
 #pragma unroll
-            for (int c = 0; c < 2; ++c) {
+            for (int c = 0; c < NCT; ++c) {
                 accR[q][c] = (v4){0, 0, 0, 0};
                 accI[q][c] = (v4){0, 0, 0, 0};
             }
         for (int j0 = 0; j0 < kin; j0 += GG_J) {
             __syncthreads();
-            load_states<C>(S, Xr, st, kin, j0);
+            load_states<C>(S, Xr, sidx, kin, j0);
             __syncthreads();
             const int jm = min(GG_J, kin - j0);
+            C a[MF_RT], an[MF_RT];
+            load_afrag<C, MF_RT>(a, At, m, m, band, ntile, wave, li, j0 + lk, kin);
             for (int kk = 0; kk < jm; kk += 4) {
-                const int kcol = j0 + kk + lk;
-                const C b0 = S[kk + lk][li], b1 = S[kk + lk][16 + li];
+                if (kk + 4 < jm) load_afrag<C, MF_RT>(an, At, m, m, band, ntile, wave, li, j0 + kk + 4 + lk, kin);
+                const C b0 = S[kk + lk][li];
+                const C b1 = NCT == 2 ? S[kk + lk][16 + li] : czero<C>();
 #pragma unroll
                 for (int q = 0; q < MF_RT; ++q) {
-                    const int rt = wave + 4 * q;
-                    if (rt >= ntile) break;
-                    const int row = band + rt * 16 + li;
-                    C a = czero<C>();
-                    if (row < m && kcol < kin) a = At[row + (int64_t)kcol * m];
-                    mfma_complex<C>(accR[q][0], accI[q][0], accR[q][1], accI[q][1], a, b0, b1);
+                    if (wave + 4 * q >= ntile) break;
+                    if (NCT == 2)
+                        cmfma2<C>(accR[q][0], accI[q][0], accR[q][NCT - 1], accI[q][NCT - 1], a[q], b0, b1);
+                    else
+                        cmfma1<C>(accR[q][0], accI[q][0], a[q], b0);
                 }
+#pragma unroll
+                for (int q = 0; q < MF_RT; ++q) a[q] = an[q];
             }
         }
 #pragma unroll
@@ -377,7 +398,7 @@ __global__ void __launch_bounds__(256) k_ggemm(const int4 *hdr, const int32_t *s
             const int rt = wave + 4 * q;
             if (rt >= ntile) break;
 #pragma unroll
-            for (int c = 0; c < 2; ++c) {
+            for (int c = 0; c < NCT; ++c) {
                 const int col = c * 16 + li;
                 if (col >= h.z) continue;
 #pragma unroll
@@ -395,18 +416,190 @@ __global__ void __launch_bounds__(256) k_ggemm(const int4 *hdr, const int32_t *s
     }
 }
 
+template <class C>
+__global__ void __launch_bounds__(256) k_ggemm(const int4 *hdr, const int32_t *src, const C *A, int m, int kin,
+                                               const C *X, int64_t xstride, C *T, int64_t tstride, int nwork) {
+    __shared__ C S[GG_J][GG_LD];
+    __shared__ int32_t sidx[GG_NB];
+    const int nx = 8;
+    const int per = gridDim.x / nx;
+    const int w = (blockIdx.x % nx) * per + blockIdx.x / nx;
+    if (w >= nwork) return;
+    const int4 h = hdr[w];  // (matrix, first scratch column, column count, 0)
+    if (threadIdx.x < GG_NB) sidx[threadIdx.x] = src[(int64_t)w * GG_NB + threadIdx.x];
+    const C *Xr = X + (int64_t)blockIdx.y * xstride;
+    C *Tr = T + (int64_t)blockIdx.y * tstride + (int64_t)h.y * m;
+    const C *At = A + (int64_t)h.x * m * kin;
+    if (h.z > 16)
+        ggemm_body<C, 2>(h, sidx, At, m, kin, Xr, Tr, S);
+    else
+        ggemm_body<C, 1>(h, sidx, At, m, kin, Xr, Tr, S);
+}
+
 // Low-rank reduced M2L (Section 4.2, eq. (eq_epsk)): K~ = U^ V^ with rank r
-// per translation, so each work item first forms Z = V^ S (r x 32) and then
-// U^ Z (kd x 32), both on the matrix cores; Z stays in LDS.  Same work list,
-// scratch layout and reduction as k_ggemm.
-#define LR_MAX 80
+// per translation, so each work item first forms Z = V^ S (r x ncols) and
+// then U^ Z (kd x ncols), both on the matrix cores; Z stays in LDS.  Same
+// work list, scratch layout and reduction as k_ggemm.  Phase 1 spreads its
+// (row tile, column tile) outputs over the 4 waves round-robin so that the
+// usual ranks (r <= 32, two column tiles: four tiles) keep every wave busy.
+template <class C, int NCT>
+__device__ __forceinline__ void m2l_body(const int4 h, const int32_t *sidx, const C *Ut, const C *Vt, int r, int kd,
+                                         int ku, int rmax, const C *Xr, C *Tr, C (*S)[GG_LD], C (*Vs)[LR_LD],
+                                         C (*Z)[GG_LD]) {
+    using v4 = typename CT<C>::v4;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    // phase 1: Z = V^[0:r, :] S; tile ti = wave + 4 q is (row tile ti / NCT,
+    // column tile ti % NCT).  Each k-chunk of V^ is staged in LDS next to the
+    // chunk of gathered states, so the MFMA loop reads only LDS.
+    const int ztiles = (r + 15) >> 4;
+    const int ntz = ztiles * NCT;
+    constexpr int ZQ = 3;  // ceil(5 row tiles * 2 column tiles / 4 waves)
+    v4 zR[ZQ], zI[ZQ];
+#pragma unroll
+    for (int q = 0; q < ZQ; ++q) {
+        zR[q] = (v4){0, 0, 0, 0};
+        zI[q] = (v4){0, 0, 0, 0};
+    }
+    // the next chunk is fetched into registers while the current one is
+    // multiplied out of LDS (the MFMA loop issues no global loads, so these
+    // loads are waited for only when they are committed to LDS)
+    constexpr int SPT = GG_J * GG_NB / 256;
+    constexpr int VPT = (LR_MAX * GG_J + 255) / 256;
+    C sreg[SPT], vreg[VPT];
+    auto fetch = [&](int j0) {
+#pragma unroll
+        for (int i = 0; i < SPT; ++i) {
+            const int e = threadIdx.x + 256 * i;
+            const int jj = e % GG_J, b = e / GG_J;
+            const int sb = sidx[b];
+            sreg[i] = czero<C>();
+            if (sb >= 0 && j0 + jj < ku) sreg[i] = Xr[(int64_t)sb * ku + j0 + jj];
+        }
+#pragma unroll
+        for (int i = 0; i < VPT; ++i) {
+            const int e = threadIdx.x + 256 * i;
+            vreg[i] = czero<C>();
+            if (e < r * GG_J) {
+                const int row = e % r, kc = e / r;
+                if (j0 + kc < ku) vreg[i] = Vt[row + (int64_t)(j0 + kc) * rmax];
+            }
+        }
+    };
+    __syncthreads();  // sidx
+    fetch(0);
+    for (int j0 = 0; j0 < ku; j0 += GG_J) {
+        __syncthreads();  // the previous chunk is consumed
+#pragma unroll
+        for (int i = 0; i < SPT; ++i) {
+            const int e = threadIdx.x + 256 * i;
+            S[e % GG_J][e / GG_J] = sreg[i];
+        }
+#pragma unroll
+        for (int i = 0; i < VPT; ++i) {
+            const int e = threadIdx.x + 256 * i;
+            if (e < r * GG_J) Vs[e / r][e % r] = vreg[i];
+        }
+        __syncthreads();
+        if (j0 + GG_J < ku) fetch(j0 + GG_J);
+        const int jm = min(GG_J, ku - j0);
+        for (int kk = 0; kk < jm; kk += 4) {
+#pragma unroll
+            for (int q = 0; q < ZQ; ++q) {
+                const int ti = wave + 4 * q;
+                if (ti >= ntz) break;
+                const int row = (ti / NCT) * 16 + li;
+                C a = czero<C>();
+                if (row < r) a = Vs[kk + lk][row];
+                const C b = S[kk + lk][(ti % NCT) * 16 + li];
+                cmfma1<C>(zR[q], zI[q], a, b);
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < ZQ; ++q) {
+        const int ti = wave + 4 * q;
+        if (ti >= ntz) break;
+        const int zt = ti / NCT, c = ti % NCT;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            C z;
+            z.x = zR[q][v];
+            z.y = zI[q][v];
+            Z[zt * 16 + CT<C>::row(lk, v)][c * 16 + li] = z;
+        }
+    }
+    __syncthreads();
+    // phase 2: Y = U^[:, 0:r] Z (kd <= 256: 16 row tiles, 4 per wave, taken
+    // two at a time to keep the accumulators small)
+    const int ntile = (kd + 15) >> 4;
+    constexpr int P2 = 2;
+    for (int pass = 0; pass < MF_RT / P2; ++pass) {
+        const int rt0 = wave + 4 * P2 * pass;  // this pass: row tiles rt0, rt0 + 4
+        if (rt0 >= ntile) break;
+        v4 accR[P2][NCT], accI[P2][NCT];
+#pragma unroll
+        for (int q = 0; q < P2; ++q)
+#pragma unroll
+            for (int c = 0; c < NCT; ++c) {
+                accR[q][c] = (v4){0, 0, 0, 0};
+                accI[q][c] = (v4){0, 0, 0, 0};
+            }
+        C a[P2], an[P2];
+        load_afrag<C, P2>(a, Ut, kd, kd, 16 * 4 * P2 * pass, ntile - 4 * P2 * pass, wave, li, lk, r);
+        for (int kk = 0; kk < r; kk += 4) {
+            if (kk + 4 < r)
+                load_afrag<C, P2>(an, Ut, kd, kd, 16 * 4 * P2 * pass, ntile - 4 * P2 * pass, wave, li, kk + 4 + lk, r);
+            const C b0 = Z[kk + lk][li];
+            const C b1 = NCT == 2 ? Z[kk + lk][16 + li] : czero<C>();
+#pragma unroll
+            for (int q = 0; q < P2; ++q) {
+                if (rt0 + 4 * q >= ntile) break;
+                if (NCT == 2)
+                    cmfma2<C>(accR[q][0], accI[q][0], accR[q][NCT - 1], accI[q][NCT - 1], a[q], b0, b1);
+                else
+                    cmfma1<C>(accR[q][0], accI[q][0], a[q], b0);
+            }
+#pragma unroll
+            for (int q = 0; q < P2; ++q) a[q] = an[q];
+        }
+#pragma unroll
+        for (int q = 0; q < P2; ++q) {
+            const int rt = rt0 + 4 * q;
+            if (rt >= ntile) break;
+#pragma unroll
+            for (int c = 0; c < NCT; ++c) {
+                const int col = c * 16 + li;
+                if (col >= h.z) continue;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = rt * 16 + CT<C>::row(lk, v);
+                    if (row < kd) {
+                        C o;
+                        o.x = accR[q][c][v];
+                        o.y = accI[q][c][v];
+                        Tr[(int64_t)col * kd + row] = o;
+                    }
+                }
+            }
+        }
+    }
+}
+
 template <class C>
 __global__ void __launch_bounds__(256) k_m2l_lowrank(const int4 *hdr, const int32_t *src, const C *Ulr, const C *Vlr,
                                                      const int32_t *rank, int kd, int ku, int rmax, const C *X,
                                                      int64_t xstride, C *T, int64_t tstride, int nwork) {
-    using v4 = typename CT<C>::v4;
-    __shared__ C S[GG_J][GG_NB];
-    __shared__ C Z[LR_MAX][GG_NB];
+    // LDS: phase 1 stages S (GG_J x GG_LD) and V^ (GG_J x LR_LD); phase 2
+    // reuses the same bytes for Z (LR_MAX x GG_LD) once phase 1 is done
+    constexpr int kStage = GG_J * GG_LD + GG_J * LR_LD;
+    constexpr int kZ = LR_MAX * GG_LD;
+    __shared__ C smem[kStage > kZ ? kStage : kZ];
+    __shared__ int32_t sidx[GG_NB];
+    C(*S)[GG_LD] = (C(*)[GG_LD])smem;
+    C(*Vs)[LR_LD] = (C(*)[LR_LD])(smem + GG_J * GG_LD);
+    C(*Z)[GG_LD] = (C(*)[GG_LD])smem;
     const int nx = 8;
     const int per = gridDim.x / nx;
     const int w = (blockIdx.x % nx) * per + blockIdx.x / nx;
@@ -414,100 +607,15 @@ __global__ void __launch_bounds__(256) k_m2l_lowrank(const int4 *hdr, const int3
     const int4 h = hdr[w];
     const int op = h.x;
     const int r = rank[op];
+    if (threadIdx.x < GG_NB) sidx[threadIdx.x] = src[(int64_t)w * GG_NB + threadIdx.x];
     const C *Xr = X + (int64_t)blockIdx.y * xstride;
     C *Tr = T + (int64_t)blockIdx.y * tstride + (int64_t)h.y * kd;
     const C *Vt = Vlr + (int64_t)op * rmax * ku;
     const C *Ut = Ulr + (int64_t)op * kd * rmax;
-    const int32_t *st = src + (int64_t)w * GG_NB;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int li = lane & 15, lk = lane >> 4;
-    // phase 1: Z = V^[0:r, :] S
-    const int ztiles = (r + 15) >> 4;
-    v4 zR[2][2], zI[2][2];
-#pragma unroll
-    for (int q = 0; q < 2; ++q)
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            zR[q][c] = (v4){0, 0, 0, 0};
-            zI[q][c] = (v4){0, 0, 0, 0};
-        }
-    for (int j0 = 0; j0 < ku; j0 += GG_J) {
-        __syncthreads();
-        load_states<C>(S, Xr, st, ku, j0);
-        __syncthreads();
-        const int jm = min(GG_J, ku - j0);
-        for (int kk = 0; kk < jm; kk += 4) {
-            const int kcol = j0 + kk + lk;
-            const C b0 = S[kk + lk][li], b1 = S[kk + lk][16 + li];
-#pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                const int zt = wave + 4 * q;
-                if (zt >= ztiles) break;
-                const int row = zt * 16 + li;
-                C a = czero<C>();
-                if (row < r && kcol < ku) a = Vt[row + (int64_t)kcol * rmax];
-                mfma_complex<C>(zR[q][0], zI[q][0], zR[q][1], zI[q][1], a, b0, b1);
-            }
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        const int zt = wave + 4 * q;
-        if (zt >= ztiles) break;
-#pragma unroll
-        for (int c = 0; c < 2; ++c)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                C z;
-                z.x = zR[q][c][v];
-                z.y = zI[q][c][v];
-                Z[zt * 16 + CT<C>::row(lk, v)][c * 16 + li] = z;
-            }
-    }
-    __syncthreads();
-    // phase 2: Y = U^[:, 0:r] Z
-    const int ntile = (kd + 15) >> 4;
-    v4 accR[MF_RT][2], accI[MF_RT][2];
-#pragma unroll
-    for (int q = 0; q < MF_RT; ++q)
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            accR[q][c] = (v4){0, 0, 0, 0};
-            accI[q][c] = (v4){0, 0, 0, 0};
-        }
-    for (int kk = 0; kk < r; kk += 4) {
-        const C b0 = Z[kk + lk][li], b1 = Z[kk + lk][16 + li];
-#pragma unroll
-        for (int q = 0; q < MF_RT; ++q) {
-            const int rt = wave + 4 * q;
-            if (rt >= ntile) break;
-            const int row = rt * 16 + li;
-            C a = czero<C>();
-            if (row < kd) a = Ut[row + (int64_t)(kk + lk) * kd];
-            mfma_complex<C>(accR[q][0], accI[q][0], accR[q][1], accI[q][1], a, b0, b1);
-        }
-    }
-#pragma unroll
-    for (int q = 0; q < MF_RT; ++q) {
-        const int rt = wave + 4 * q;
-        if (rt >= ntile) break;
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            const int col = c * 16 + li;
-            if (col >= h.z) continue;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int row = rt * 16 + CT<C>::row(lk, v);
-                if (row < kd) {
-                    C o;
-                    o.x = accR[q][c][v];
-                    o.y = accI[q][c][v];
-                    Tr[(int64_t)col * kd + row] = o;
-                }
-            }
-        }
-    }
+    if (h.z > 16)
+        m2l_body<C, 2>(h, sidx, Ut, Vt, r, kd, ku, rmax, Xr, Tr, S, Vs, Z);
+    else
+        m2l_body<C, 1>(h, sidx, Ut, Vt, r, kd, ku, rmax, Xr, Tr, S, Vs, Z);
 }
 
 // Y[dst] (+)= sum of the scratch columns listed for dst, in list order.
