@@ -126,6 +126,8 @@ def main():
 
     prof = plan.profile(x, reps=max(3, min(20, args.steps)), out=y)
     log(f"[bench] stages (ms): {prof}")
+    log(f"[bench] M2M {st['m2m_flops'] / 1e9:.3f} GF -> {st['m2m_flops'] / (prof['m2m'] * 1e-3) / 1e12:.2f} TF/s; "
+        f"L2L {st['l2l_flops'] / 1e9:.3f} GF -> {st['l2l_flops'] / (prof['l2l'] * 1e-3) / 1e12:.2f} TF/s")
     y_np = y.cpu().numpy()
 
     # roofline of the dominant kernel: the M2L product kernel (one launch

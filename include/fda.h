@@ -111,6 +111,9 @@ typedef struct fda_stats {
     double root_width;
     double build_seconds;       /* wall time of the last build (0 for fda_inspect) */
     int64_t device_bytes;       /* device memory held by the plan */
+    double m2m_flops;           /* real flops of one upward pass (M2M, all levels, 8 per complex
+                                   multiply-add) */
+    double l2l_flops;           /* the same for the downward pass (L2L) */
 } fda_stats;
 
 /* Fill *opt with the defaults listed above. */

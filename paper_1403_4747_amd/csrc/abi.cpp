@@ -42,6 +42,7 @@ struct fda_plan {
     std::vector<void *> work;        // per-capacity allocations
     fda_stats stats{};
     int64_t device_bytes = 0;
+    double m2m_flops = 0, l2l_flops = 0;  // per upward / downward pass
 };
 
 namespace {
@@ -368,6 +369,7 @@ void upload_plan(fda_plan *p, const HostOps &ops, DevTranslations &tr) {
                     flush();
                 }
             dl.m2m = upload_gwork(p, gm);
+            p->m2m_flops += 8.0 * lv.ku * C.ku * (double)gm.ncol;
             // L2L: per (child octant, parent slot), the children in that
             // octant, in chunks; summed into the child slot fed by the parent slot
             GWorkHost gl;
@@ -389,6 +391,7 @@ void upload_plan(fda_plan *p, const HostOps &ops, DevTranslations &tr) {
                     flush();
                 }
             dl.l2l = upload_gwork(p, gl);
+            p->l2l_flops += 8.0 * C.kd * lv.kd * (double)gl.ncol;
         }
     }
 }
@@ -522,6 +525,8 @@ int fda_build(const double *verts, int64_t nv, const int32_t *tris, int64_t nt, 
     }
     if (rb) rocblas_destroy_handle(rb);
     fill_stats(p->hp, &p->stats);
+    p->stats.m2m_flops = p->m2m_flops;
+    p->stats.l2l_flops = p->l2l_flops;
     {
         // algorithmic M2L flops per level: low-rank levels count
         // 8 r (kd + ku) real flops per pair with the SVD rank r of its

@@ -301,8 +301,10 @@ __global__ void k_s2m(const int64_t *leaf_off, const C *S, int ku, const double2
 #define GG_LD (GG_NB + 1)  // padded LDS row: spreads the 4 k-rows of an MFMA operand over the banks
 #define GG_J 32
 #define MF_RT 4
-#define LR_MAX 80
+#define LR_MAX 72
 #define LR_LD (LR_MAX + 1)
+#define LRJ 16   // k-chunk of the low-rank M2L phase 1
+#define LR_P2 1  // row tiles per wave and pass in phase 2
 
 // Load up to GG_J x GG_NB gathered input values (zero padded) into LDS.
 template <class C>
@@ -455,6 +457,13 @@ __device__ __forceinline__ void m2l_body(const int4 h, const int32_t *sidx, cons
     const int ztiles = (r + 15) >> 4;
     const int ntz = ztiles * NCT;
     constexpr int ZQ = 3;  // ceil(5 row tiles * 2 column tiles / 4 waves)
+    // With fewer than 4 output tiles the waves also split the k-steps
+    // (kg_n groups; wave = kg * ntz + tile) and the partial products are
+    // summed in LDS afterwards.
+    const int kg_n = ntz == 1 ? 4 : (ntz == 2 ? 2 : 1);
+    const int kg = kg_n > 1 ? wave / ntz : 0;
+    const int tbase = kg_n > 1 ? wave % ntz : wave;
+    const int tstep = kg_n > 1 ? 64 : 4;  // kg_n > 1: one tile per wave
     v4 zR[ZQ], zI[ZQ];
 #pragma unroll
     for (int q = 0; q < ZQ; ++q) {
@@ -464,14 +473,14 @@ __device__ __forceinline__ void m2l_body(const int4 h, const int32_t *sidx, cons
     // the next chunk is fetched into registers while the current one is
     // multiplied out of LDS (the MFMA loop issues no global loads, so these
     // loads are waited for only when they are committed to LDS)
-    constexpr int SPT = GG_J * GG_NB / 256;
-    constexpr int VPT = (LR_MAX * GG_J + 255) / 256;
+    constexpr int SPT = LRJ * GG_NB / 256;
+    constexpr int VPT = (LR_MAX * LRJ + 255) / 256;
     C sreg[SPT], vreg[VPT];
     auto fetch = [&](int j0) {
 #pragma unroll
         for (int i = 0; i < SPT; ++i) {
             const int e = threadIdx.x + 256 * i;
-            const int jj = e % GG_J, b = e / GG_J;
+            const int jj = e % LRJ, b = e / LRJ;
             const int sb = sidx[b];
             sreg[i] = czero<C>();
             if (sb >= 0 && j0 + jj < ku) sreg[i] = Xr[(int64_t)sb * ku + j0 + jj];
@@ -480,7 +489,7 @@ __device__ __forceinline__ void m2l_body(const int4 h, const int32_t *sidx, cons
         for (int i = 0; i < VPT; ++i) {
             const int e = threadIdx.x + 256 * i;
             vreg[i] = czero<C>();
-            if (e < r * GG_J) {
+            if (e < r * LRJ) {
                 const int row = e % r, kc = e / r;
                 if (j0 + kc < ku) vreg[i] = Vt[row + (int64_t)(j0 + kc) * rmax];
             }
@@ -488,25 +497,25 @@ __device__ __forceinline__ void m2l_body(const int4 h, const int32_t *sidx, cons
     };
     __syncthreads();  // sidx
     fetch(0);
-    for (int j0 = 0; j0 < ku; j0 += GG_J) {
+    for (int j0 = 0; j0 < ku; j0 += LRJ) {
         __syncthreads();  // the previous chunk is consumed
 #pragma unroll
         for (int i = 0; i < SPT; ++i) {
             const int e = threadIdx.x + 256 * i;
-            S[e % GG_J][e / GG_J] = sreg[i];
+            S[e % LRJ][e / LRJ] = sreg[i];
         }
 #pragma unroll
         for (int i = 0; i < VPT; ++i) {
             const int e = threadIdx.x + 256 * i;
-            if (e < r * GG_J) Vs[e / r][e % r] = vreg[i];
+            if (e < r * LRJ) Vs[e / r][e % r] = vreg[i];
         }
         __syncthreads();
-        if (j0 + GG_J < ku) fetch(j0 + GG_J);
-        const int jm = min(GG_J, ku - j0);
-        for (int kk = 0; kk < jm; kk += 4) {
+        if (j0 + LRJ < ku) fetch(j0 + LRJ);
+        const int jm = min(LRJ, ku - j0);
+        for (int kk = 4 * kg; kk < jm; kk += 4 * kg_n) {
 #pragma unroll
             for (int q = 0; q < ZQ; ++q) {
-                const int ti = wave + 4 * q;
+                const int ti = tbase + tstep * q;
                 if (ti >= ntz) break;
                 const int row = (ti / NCT) * 16 + li;
                 C a = czero<C>();
@@ -517,9 +526,10 @@ __device__ __forceinline__ void m2l_body(const int4 h, const int32_t *sidx, cons
         }
     }
     __syncthreads();
+    const int zoff = kg * 16 * ztiles;  // partial sums of k group kg (<= 64 rows in all)
 #pragma unroll
     for (int q = 0; q < ZQ; ++q) {
-        const int ti = wave + 4 * q;
+        const int ti = tbase + tstep * q;
         if (ti >= ntz) break;
         const int zt = ti / NCT, c = ti % NCT;
 #pragma unroll
@@ -527,14 +537,28 @@ __device__ __forceinline__ void m2l_body(const int4 h, const int32_t *sidx, cons
             C z;
             z.x = zR[q][v];
             z.y = zI[q][v];
-            Z[zt * 16 + CT<C>::row(lk, v)][c * 16 + li] = z;
+            Z[zoff + zt * 16 + CT<C>::row(lk, v)][c * 16 + li] = z;
         }
     }
     __syncthreads();
+    if (kg_n > 1) {
+        const int zr = 16 * ztiles, zc = 16 * NCT;
+        for (int e = threadIdx.x; e < zr * zc; e += blockDim.x) {
+            const int row = e / zc, col = e % zc;
+            C s = Z[row][col];
+            for (int g = 1; g < kg_n; ++g) {
+                const C t = Z[g * zr + row][col];
+                s.x += t.x;
+                s.y += t.y;
+            }
+            Z[row][col] = s;
+        }
+        __syncthreads();
+    }
     // phase 2: Y = U^[:, 0:r] Z (kd <= 256: 16 row tiles, 4 per wave, taken
     // two at a time to keep the accumulators small)
     const int ntile = (kd + 15) >> 4;
-    constexpr int P2 = 2;
+    constexpr int P2 = LR_P2;
     for (int pass = 0; pass < MF_RT / P2; ++pass) {
         const int rt0 = wave + 4 * P2 * pass;  // this pass: row tiles rt0, rt0 + 4
         if (rt0 >= ntile) break;
@@ -588,17 +612,17 @@ __device__ __forceinline__ void m2l_body(const int4 h, const int32_t *sidx, cons
 }
 
 template <class C>
-__global__ void __launch_bounds__(256) k_m2l_lowrank(const int4 *hdr, const int32_t *src, const C *Ulr, const C *Vlr,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_m2l_lowrank(const int4 *hdr, const int32_t *src, const C *Ulr, const C *Vlr,
                                                      const int32_t *rank, int kd, int ku, int rmax, const C *X,
                                                      int64_t xstride, C *T, int64_t tstride, int nwork) {
-    // LDS: phase 1 stages S (GG_J x GG_LD) and V^ (GG_J x LR_LD); phase 2
+    // LDS: phase 1 stages S (LRJ x GG_LD) and V^ (LRJ x LR_LD); phase 2
     // reuses the same bytes for Z (LR_MAX x GG_LD) once phase 1 is done
-    constexpr int kStage = GG_J * GG_LD + GG_J * LR_LD;
+    constexpr int kStage = LRJ * GG_LD + LRJ * LR_LD;
     constexpr int kZ = LR_MAX * GG_LD;
     __shared__ C smem[kStage > kZ ? kStage : kZ];
     __shared__ int32_t sidx[GG_NB];
     C(*S)[GG_LD] = (C(*)[GG_LD])smem;
-    C(*Vs)[LR_LD] = (C(*)[LR_LD])(smem + GG_J * GG_LD);
+    C(*Vs)[LR_LD] = (C(*)[LR_LD])(smem + LRJ * GG_LD);
     C(*Z)[GG_LD] = (C(*)[GG_LD])smem;
     const int nx = 8;
     const int per = gridDim.x / nx;

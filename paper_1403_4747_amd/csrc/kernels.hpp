@@ -86,7 +86,7 @@ hipError_t launch_sub(const double2 *b, const double2 *y, double2 *r, int64_t n,
 hipError_t launch_bj_apply(const DevPlan &d, const double2 *r, double2 *z, int nrhs, const int32_t *active,
                            hipStream_t st);
 hipError_t launch_fill_zero(double2 *p, int64_t n, hipStream_t st);
-constexpr int kLowRankMax = 80;  // largest rank the low-rank M2L kernel holds in LDS
+constexpr int kLowRankMax = 72;  // largest rank the low-rank M2L kernel holds in LDS
 
 // Blocks used by the two-pass reductions.
 constexpr int kRedBlocks = 240;

@@ -55,6 +55,7 @@ class Stats(ctypes.Structure):
         ("m2l_rank_max", ctypes.c_int32 * 24), ("m2l_rank_mean", ctypes.c_double * 24),
         ("m2l_level_flops", ctypes.c_double * 24), ("m2l_flops", ctypes.c_int64), ("m2l_bytes", ctypes.c_int64), ("h_max", ctypes.c_double),
         ("root_width", ctypes.c_double), ("build_seconds", ctypes.c_double), ("device_bytes", ctypes.c_int64),
+        ("m2m_flops", ctypes.c_double), ("l2l_flops", ctypes.c_double),
     ]
 
     def to_dict(self) -> Dict:
