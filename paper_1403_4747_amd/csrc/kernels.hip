@@ -301,6 +301,7 @@ __global__ void k_s2m(const int64_t *leaf_off, const C *S, int ku, const double2
 #define GG_LD (GG_NB + 1)  // padded LDS row: spreads the 4 k-rows of an MFMA operand over the banks
 #define GG_J 32
 #define MF_RT 4
+#define GG_RT 2  // row tiles per wave in a band of the gathered GEMM (band = 128 rows)
 #define LR_MAX 72
 #define LR_LD (LR_MAX + 1)
 #define LRJ 16   // k-chunk of the low-rank M2L phase 1
@@ -362,11 +363,11 @@ __device__ __forceinline__ void ggemm_body(const int4 h, const int32_t *sidx, co
     using v4 = typename CT<C>::v4;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lk = lane >> 4;
-    for (int band = 0; band < m; band += 64 * MF_RT) {
-        const int ntile = min(MF_RT * 4, (m - band + 15) >> 4);
-        v4 accR[MF_RT][NCT], accI[MF_RT][NCT];
+    for (int band = 0; band < m; band += 64 * GG_RT) {
+        const int ntile = min(GG_RT * 4, (m - band + 15) >> 4);
+        v4 accR[GG_RT][NCT], accI[GG_RT][NCT];
 #pragma unroll
-        for (int q = 0; q < MF_RT; ++q)
+        for (int q = 0; q < GG_RT; ++q)
 #pragma unroll
             for (int c = 0; c < NCT; ++c) {
                 accR[q][c] = (v4){0, 0, 0, 0};
@@ -377,14 +378,14 @@ __device__ __forceinline__ void ggemm_body(const int4 h, const int32_t *sidx, co
             load_states<C>(S, Xr, sidx, kin, j0);
             __syncthreads();
             const int jm = min(GG_J, kin - j0);
-            C a[MF_RT], an[MF_RT];
-            load_afrag<C, MF_RT>(a, At, m, m, band, ntile, wave, li, j0 + lk, kin);
+            C a[GG_RT], an[GG_RT];
+            load_afrag<C, GG_RT>(a, At, m, m, band, ntile, wave, li, j0 + lk, kin);
             for (int kk = 0; kk < jm; kk += 4) {
-                if (kk + 4 < jm) load_afrag<C, MF_RT>(an, At, m, m, band, ntile, wave, li, j0 + kk + 4 + lk, kin);
+                if (kk + 4 < jm) load_afrag<C, GG_RT>(an, At, m, m, band, ntile, wave, li, j0 + kk + 4 + lk, kin);
                 const C b0 = S[kk + lk][li];
                 const C b1 = NCT == 2 ? S[kk + lk][16 + li] : czero<C>();
 #pragma unroll
-                for (int q = 0; q < MF_RT; ++q) {
+                for (int q = 0; q < GG_RT; ++q) {
                     if (wave + 4 * q >= ntile) break;
                     if (NCT == 2)
                         cmfma2<C>(accR[q][0], accI[q][0], accR[q][NCT - 1], accI[q][NCT - 1], a[q], b0, b1);
@@ -392,11 +393,11 @@ __device__ __forceinline__ void ggemm_body(const int4 h, const int32_t *sidx, co
                         cmfma1<C>(accR[q][0], accI[q][0], a[q], b0);
                 }
 #pragma unroll
-                for (int q = 0; q < MF_RT; ++q) a[q] = an[q];
+                for (int q = 0; q < GG_RT; ++q) a[q] = an[q];
             }
         }
 #pragma unroll
-        for (int q = 0; q < MF_RT; ++q) {
+        for (int q = 0; q < GG_RT; ++q) {
             const int rt = wave + 4 * q;
             if (rt >= ntile) break;
 #pragma unroll
@@ -419,7 +420,7 @@ __device__ __forceinline__ void ggemm_body(const int4 h, const int32_t *sidx, co
 }
 
 template <class C>
-__global__ void __launch_bounds__(256) k_ggemm(const int4 *hdr, const int32_t *src, const C *A, int m, int kin,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_ggemm(const int4 *hdr, const int32_t *src, const C *A, int m, int kin,
                                                const C *X, int64_t xstride, C *T, int64_t tstride, int nwork) {
     __shared__ C S[GG_J][GG_LD];
     __shared__ int32_t sidx[GG_NB];
