@@ -70,6 +70,9 @@ def main():
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run one plain device copy of this many MiB (calibrates HBM counters)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--mlp-weights", default=os.path.join(ROOT, "paper_1403_4747_amd", "weights",
+                                                          "mlp_ellipsoid_s5_h256.npz"),
+                    help="trained learned-preconditioner weights for the fast arm's solve")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "m2l_lowrank_sphere81920_kD100_traffic.json"),
                     help="measured HBM traffic of the M2L kernel (written from rocprofv3 counter passes)")
     args = ap.parse_args()
@@ -126,7 +129,8 @@ def main():
 
     prof = plan.profile(x, reps=max(3, min(20, args.steps)), out=y)
     log(f"[bench] stages (ms): {prof}")
-    log(f"[bench] M2M {st['m2m_flops'] / 1e9:.3f} GF -> {st['m2m_flops'] / (prof['m2m'] * 1e-3) / 1e12:.2f} TF/s; "
+    log(f"[bench] near nnz {st['near_nnz']} ({st['near_nnz'] * 16 / (prof['near'] * 1e-3) / 1e9:.0f} GB/s of FP64 entries); "
+        f"M2M {st['m2m_flops'] / 1e9:.3f} GF -> {st['m2m_flops'] / (prof['m2m'] * 1e-3) / 1e12:.2f} TF/s; "
         f"L2L {st['l2l_flops'] / 1e9:.3f} GF -> {st['l2l_flops'] / (prof['l2l'] * 1e-3) / 1e12:.2f} TF/s")
     y_np = y.cpu().numpy()
 
@@ -184,12 +188,22 @@ def main():
                     m2l_level_ms=[round(v, 4) for v in prof32["m2l_gemm"][: st["depth"] + 1]])
         if not args.no_solve:
             b32 = plan32.rhs_planewave(prm["direction"])
-            for pc in ("none", "block_jacobi"):
+            pcs = ["none", "block_jacobi"]
+            if os.path.exists(args.mlp_weights):
+                from paper_1403_4747_amd import train_mlp
+
+                net = train_mlp.load(args.mlp_weights)
+                plan32.set_mlp(net)
+                pcs.append("mlp")
+            for pc in pcs:
                 t0 = time.perf_counter()
                 u32, info = plan32.solve(b32, tol=1e-5, restart=50, maxit=2000, precond=pc)
                 torch.cuda.synchronize()
                 fast["solve_" + pc] = dict(seconds=round(time.perf_counter() - t0, 4), iterations=info["iterations"],
                                            rel_residual=info["rel_residual"], converged=info["converged"])
+                if pc == "mlp":
+                    fast["solve_mlp"].update(mlp_rejected=info["mlp_rejected"], mlp_fallbacks=info["mlp_fallbacks"],
+                                             weights=os.path.relpath(args.mlp_weights, ROOT))
             # difference of the two arms' solutions (surface field)
             u64, _ = plan.solve(b, tol=1e-5, restart=50, maxit=2000)
             fast["solution_rel_diff_vs_fp64_arm"] = float(torch.linalg.norm(u32 - u64) / torch.linalg.norm(u64))

@@ -114,6 +114,8 @@ typedef struct fda_stats {
     double m2m_flops;           /* real flops of one upward pass (M2M, all levels, 8 per complex
                                    multiply-add) */
     double l2l_flops;           /* the same for the downward pass (L2L) */
+    int64_t mlp_rows;           /* rows of the learned preconditioner: chunks of <= 64 consecutive
+                                   elements of a leaf (see fda_mlp_samples) */
 } fda_stats;
 
 /* Fill *opt with the defaults listed above. */
@@ -155,6 +157,7 @@ typedef struct bm_stats {
     int32_t col_iterations[64]; /* per-column iterations (first 64 columns) */
     int32_t mlp_fallbacks;  /* FDA_PRECOND_MLP: applications whose network output was not finite and
                                that used the block-Jacobi correction instead */
+    int32_t mlp_rejected;   /* FDA_PRECOND_MLP: 1 if the judge switched the solve to block Jacobi */
 } bm_stats;
 
 /* Solve A x = b by restarted GMRES(restart) from x = 0 (Section 5: GMRES, no
@@ -166,7 +169,11 @@ typedef struct bm_stats {
  * blocks) or FDA_PRECOND_MLP (the block-Jacobi correction plus the output of
  * the network attached by fda_plan_set_mlp; the preconditioner is then
  * nonlinear, so the solver keeps the preconditioned basis, i.e. flexible
- * GMRES, which it does for every precond).  b_dev, x_dev: N x nrhs device buffers, leading dimension ld;
+ * GMRES, which it does for every precond).  With FDA_PRECOND_MLP block
+ * Jacobi is the judge: the first 6 products use block Jacobi, the next 6 the
+ * network, and if the network reduced the residual estimate by less over
+ * its 6 steps than block Jacobi over its own, the solve continues with block
+ * Jacobi (st->mlp_rejected = 1).  b_dev, x_dev: N x nrhs device buffers, leading dimension ld;
  * x is overwritten.  Synchronous: returns when the solve is done.  st may be
  * NULL.  Returns 0 when converged, FDA_NOTCONV when maxit was reached (x is
  * the last iterate), FDA_EBREAKDOWN on a non-finite value, or FDA_EINVAL /
@@ -176,18 +183,20 @@ int bm_solve(fda_plan *plan, const void *b_dev, void *x_dev, int64_t nrhs, int64
 
 /* ---------------------------------------------------------------------------
  * Learned preconditioner.  The paper solves without a preconditioner
- * (Section 5); these calls add one.  Per leaf L (n_L <= 64 elements) and
- * residual v, with z_L = inv(A_LL) v_L the block-Jacobi correction:
+ * (Section 5); these calls add one.  A row R is a chunk of <= 64 consecutive
+ * elements (tree order) of one leaf L (one row per leaf when n_L <= 64;
+ * stats.mlp_rows rows in all).  For a residual v, with z = inv(A_LL) v_L the
+ * block-Jacobi correction of the leaf restricted to the row:
  *
- *   features (FDA_MLP_IN = 272 floats): Re v_L/|v_L|, Im v_L/|v_L|,
- *     Re z_L/|v_L|, Im z_L/|v_L| (each zero-padded to 64 entries), the leaf
- *     width and the mesh's largest edge in wavelengths, n_L/64, 1, then
- *     zeros (v_L = 0 gives zero features apart from the scalars);
+ *   features (FDA_MLP_IN = 272 floats): Re v_R/|v_R|, Im v_R/|v_R|,
+ *     Re z_R/|v_R|, Im z_R/|v_R| (each zero-padded to 64 entries), the leaf
+ *     width and the mesh's largest edge in wavelengths, n_R/64, 1, then
+ *     zeros (v_R = 0 gives zero features apart from the scalars);
  *   network: 272 -> h -> h -> 128, ReLU after the two hidden layers, BF16
  *     weights with FP32 accumulation in inference and training, FP32 master
  *     parameters updated by Adam (beta 0.9 / 0.999, eps 1e-8);
- *   output (FDA_MLP_OUT = 128): Re and Im of a 64-entry correction c_L;
- *   preconditioner: M(v)_L = z_L + |v_L| c_L.
+ *   output (FDA_MLP_OUT = 128): Re and Im of a 64-entry correction c_R;
+ *   preconditioner: M(v)_R = z_R + |v_R| c_R.
  *
  * Parameters are one flat FP32 array: W1 (272 x h, row-major: input index
  * major), b1 (h), W2 (h x h), b2 (h), W3 (h x 128), b3 (128).  Rows of X,
@@ -234,14 +243,13 @@ int fda_mlp_gradient(fda_mlp *mlp, const float *X_dev, const float *T_dev, const
 int fda_mlp_train(fda_mlp *mlp, const float *X_dev, const float *T_dev, const float *M_dev, int64_t rows,
                   int32_t epochs, int32_t batch, float lr, uint64_t seed, double *losses, void *stream);
 
-/* Training and inference rows of the plan's leaves.  r_dev: N x nrhs
- * residuals; e_dev (may be NULL): the matching errors e = A^-1 r.  For
- * column c and leaf L (tree order; stats.nleaf leaves) row c*nleaf + L of
- * X_dev (272 floats) gets the features of r; if e_dev is given, the same row
- * of T_dev (128) gets (e_L - z_L)/|r_L| and of M_dev (128) the mask of the
- * leaf's n_L entries (1 on Re and Im of each, 0 on padding).  Synchronous.
- * Errors: FDA_EINVAL (leaves above 64 elements, nrhs / ld out of range),
- * FDA_EHIP. */
+/* Training and inference rows of the plan.  r_dev: N x nrhs residuals;
+ * e_dev (may be NULL): the matching errors e = A^-1 r.  For column c and row
+ * R (leaf order, then chunk order; stats.mlp_rows rows) row c*mlp_rows + R
+ * of X_dev (272 floats) gets the features of r; if e_dev is given, the same
+ * row of T_dev (128) gets (e_R - z_R)/|r_R| and of M_dev (128) the mask of
+ * the row's n_R entries (1 on Re and Im of each, 0 on padding).
+ * Synchronous.  Errors: FDA_EINVAL (nrhs / ld out of range), FDA_EHIP. */
 int fda_mlp_samples(fda_plan *plan, const void *r_dev, const void *e_dev, int64_t nrhs, int64_t ld, float *X_dev,
                     float *T_dev, float *M_dev, void *stream);
 
@@ -264,6 +272,7 @@ int fda_plan_stats(const fda_plan *plan, fda_stats *st);
 typedef struct fda_profile_result {
     double near_ms, s2m_ms, m2m_ms, m2l_ms, l2l_ms, l2t_ms, total_ms;
     double m2l_gemm_ms[24];     /* the M2L product kernel of each level (without its reduction) */
+    double perm_ms;             /* the permutations into and out of tree order */
 } fda_profile_result;
 
 /* Profile fda_matvec: x_dev/y_dev as in fda_matvec.  Synchronous. */

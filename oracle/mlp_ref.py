@@ -6,17 +6,20 @@ with the HIP library.
 
 The paper solves its Burton-Miller systems with unpreconditioned GMRES
 (Section 5); the preconditioner below is an addition on top of the
-block-Jacobi one (inverse of each leaf's self-interaction block).  Its
-definition, per leaf L of the octree (n_L <= 64 elements) and residual v:
+block-Jacobi one (inverse of each leaf's self-interaction block).  A row R
+is a chunk of at most 64 consecutive elements of a leaf L of the octree (the
+whole leaf when n_L <= 64).  For a residual v:
 
-    z_L  = A_LL^-1 v_L                                  (block Jacobi)
-    f_L  = [Re v_L, Im v_L, Re z_L, Im z_L] / |v_L|     (each padded to 64)
-           ++ [w_L / lambda, h_max / lambda, n_L / 64, 1, 0 ... 0]   (272)
-    c_L  = W3^T relu(W2^T relu(W1^T f_L + b1) + b2) + b3             (128)
-    M(v)_L = z_L + |v_L| (c_L[:64] + i c_L[64:])[:n_L]
+    z    = A_LL^-1 v_L, restricted to the row: z_R        (block Jacobi)
+    s_R  = |v_R| v_j / |v_j|, j the row's largest entry (first on ties)
+    f_R  = [Re, Im of v_R / s_R, Re, Im of z_R / s_R]   (each padded to 64)
+           ++ [w_L / lambda, h_max / lambda, n_R / 64, 1, 0 ... 0]   (272)
+    c_R  = W3^T relu(W2^T relu(W1^T f_R + b1) + b2) + b3             (128)
+    M(v)_R = z_R + s_R (c_R[:64] + i c_R[64:])[:n_R]
 
-Training minimises the masked mean squared error between c_L and the
-normalised correction (e_L - z_L)/|r_L| of pairs (r, e = A^-1 r).
+so that M(a v) = a M(v) for every complex a.  Training minimises the
+masked mean squared error between c_R and the normalised correction
+(e_R - z_R)/s_R of pairs (r, e = A^-1 r).
 
 Parameters are one flat array: W1 (272 x h, input-major), b1 (h), W2
 (h x h), b2 (h), W3 (h x 128), b3 (128).  Inference uses bfloat16 copies of
@@ -34,8 +37,8 @@ import numpy as np
 
 MLP_IN, MLP_OUT, LEAF = 272, 128, 64
 
-__all__ = ["MLP_IN", "MLP_OUT", "LEAF", "num_params", "split", "bf16_round", "leaf_features", "leaf_targets",
-           "forward", "loss_and_gradient", "adam_step", "precond_apply"]
+__all__ = ["MLP_IN", "MLP_OUT", "LEAF", "num_params", "split", "bf16_round", "row_scale", "leaf_features", "row_ranges",
+           "leaf_targets", "forward", "loss_and_gradient", "adam_step", "precond_apply"]
 
 
 def num_params(h: int) -> int:
@@ -67,29 +70,53 @@ def bf16_round(x) -> np.ndarray:
     return out
 
 
-def leaf_features(vL: np.ndarray, A_LL: np.ndarray, width_lam: float, hmax_lam: float):
-    """Features (272,), |v_L| and z_L of one leaf (definition in the header)."""
-    n = vL.size
-    assert n <= LEAF and A_LL.shape == (n, n)
-    z = np.linalg.solve(A_LL, vL)
-    nv = float(np.linalg.norm(vL))
-    s = 1.0 / nv if nv > 0 else 0.0
+def row_scale(vR: np.ndarray) -> complex:
+    """s_R = |v_R| times the unit phase of the row's largest entry (the first
+    one on ties); 0 for v_R = 0.  Dividing by s makes the features, and so
+    the preconditioner, equivariant under complex scaling of v."""
+    nv = float(np.linalg.norm(vR))
+    if nv == 0:
+        return 0j
+    j = int(np.argmax(np.abs(vR) ** 2))
+    return nv * vR[j] / abs(vR[j])
+
+
+def leaf_features(vL: np.ndarray, A_LL: np.ndarray, width_lam: float, hmax_lam: float, i0: int = 0, n: int = None):
+    """Features (272,), scale s_R and z_R of the row R = elements
+    i0 .. i0+n-1 of leaf L (the whole leaf by default; n <= 64).  z is the
+    block-Jacobi correction of the whole leaf restricted to the row."""
+    nL = vL.size
+    n = nL - i0 if n is None else n
+    assert 0 < n <= LEAF and i0 + n <= nL and A_LL.shape == (nL, nL)
+    z = np.linalg.solve(A_LL, vL)[i0:i0 + n]
+    vR = vL[i0:i0 + n]
+    s = row_scale(vR)
+    inv = 1.0 / s if s != 0 else 0.0
     f = np.zeros(MLP_IN)
-    f[0:n] = vL.real * s
-    f[64:64 + n] = vL.imag * s
-    f[128:128 + n] = z.real * s
-    f[192:192 + n] = z.imag * s
+    f[0:n] = (vR * inv).real
+    f[64:64 + n] = (vR * inv).imag
+    f[128:128 + n] = (z * inv).real
+    f[192:192 + n] = (z * inv).imag
     f[256:260] = [width_lam, hmax_lam, n / 64.0, 1.0]
-    return f, nv, z
+    return f, s, z
 
 
-def leaf_targets(eL: np.ndarray, zL: np.ndarray, nv: float):
-    """Target (128,) and mask (128,) of one leaf: (e_L - z_L)/|r_L|."""
-    n = eL.size
-    s = 1.0 / nv if nv > 0 else 0.0
+def row_ranges(leaf_off: np.ndarray):
+    """(leaf, first tree position, count) of every row: leaves split into
+    chunks of at most 64 consecutive elements, in leaf order."""
+    out = []
+    for L in range(len(leaf_off) - 1):
+        for e in range(int(leaf_off[L]), int(leaf_off[L + 1]), LEAF):
+            out.append((L, e, min(LEAF, int(leaf_off[L + 1]) - e)))
+    return out
+
+
+def leaf_targets(eR: np.ndarray, zR: np.ndarray, s: complex):
+    """Target (128,) and mask (128,) of one row: (e_R - z_R) / s_R."""
+    n = eR.size
     t = np.zeros(MLP_OUT)
     m = np.zeros(MLP_OUT)
-    d = (eL - zL) * s
+    d = (eR - zR) * (1.0 / s if s != 0 else 0.0)
     t[:n], t[64:64 + n] = d.real, d.imag
     m[:n] = m[64:64 + n] = 1.0
     return t, m
@@ -141,7 +168,7 @@ def adam_step(p, g, m, v, t: int, lr: float, b1=0.9, b2=0.999, eps=1e-8):
     return p - lr * mh / (np.sqrt(vh) + eps), m, v
 
 
-def precond_apply(zL: np.ndarray, nv: float, yL: np.ndarray):
-    """M(v)_L = z_L + |v_L| c_L from the network output row y_L (128,)."""
-    n = zL.size
-    return zL + nv * (yL[:n] + 1j * yL[64:64 + n])
+def precond_apply(zR: np.ndarray, s: complex, yR: np.ndarray):
+    """M(v)_R = z_R + s_R c_R from the network output row y_R (128,)."""
+    n = zR.size
+    return zR + s * (yR[:n] + 1j * yR[64:64 + n])

@@ -294,6 +294,18 @@ void upload_plan(fda_plan *p, const HostOps &ops, DevTranslations &tr) {
             sc[2 * b + 1] = (float)(hp.h_max / lam);
         }
         d.leaf_scalars = upload(p, sc);
+        std::vector<int64_t> roff;
+        std::vector<int32_t> rleaf, rn;
+        for (int b = 0; b < d.nleaf; ++b)
+            for (int64_t e = hp.leaf_off[b]; e < hp.leaf_off[b + 1]; e += kMlpLeaf) {
+                roff.push_back(e);
+                rleaf.push_back(b);
+                rn.push_back((int32_t)std::min<int64_t>(kMlpLeaf, hp.leaf_off[b + 1] - e));
+            }
+        d.mlp_nrows = (int64_t)roff.size();
+        d.mlp_row_off = upload(p, roff);
+        d.mlp_row_leaf = upload(p, rleaf);
+        d.mlp_row_n = upload(p, rn);
     }
     d.bj_inv = dalloc<double2>(p, (size_t)bj_off[d.nleaf], p->allocs);
 
@@ -527,6 +539,7 @@ int fda_build(const double *verts, int64_t nv, const int32_t *tris, int64_t nt, 
     fill_stats(p->hp, &p->stats);
     p->stats.m2m_flops = p->m2m_flops;
     p->stats.l2l_flops = p->l2l_flops;
+    p->stats.mlp_rows = p->d.mlp_nrows;
     {
         // algorithmic M2L flops per level: low-rank levels count
         // 8 r (kd + ku) real flops per pair with the SVD rank r of its
@@ -608,13 +621,14 @@ int fda_profile_matvec(fda_plan *plan, const void *x_dev, void *y_dev, int64_t n
         hipStream_t st = as_stream(stream);
         const int L = plan->d.depth;
         for (int r = 0; r < reps; ++r) {
-            hip_check(hipEventRecord(ev[7], st), "event");
-            hip_check(launch_permute_in(plan->d, (const double2 *)x_dev, ld, plan->xt, (int)nrhs, st), "permute");
-            // record every level's pair so elapsed-time queries are valid
+            // record every level's pair (outside the timed region) so that
+            // elapsed-time queries are valid for levels without M2L work
             for (int l = 0; l < 24; ++l) {
                 hipEventRecord(lev[2 * l], st);
                 hipEventRecord(lev[2 * l + 1], st);
             }
+            hip_check(hipEventRecord(ev[7], st), "event");
+            hip_check(launch_permute_in(plan->d, (const double2 *)x_dev, ld, plan->xt, (int)nrhs, st), "permute");
             hip_check(launch_matvec_tree(plan->d, plan->xt, plan->yt, (int)nrhs, st, ev, lev), "matvec");
             hip_check(launch_permute_out(plan->d, plan->yt, (double2 *)y_dev, ld, (int)nrhs, st), "permute");
             hip_check(hipEventRecord(ev[8], st), "event");
@@ -626,9 +640,11 @@ int fda_profile_matvec(fda_plan *plan, const void *x_dev, void *y_dev, int64_t n
                 *stage[q] += ms;
             }
             float a, b;
+            hipEventElapsedTime(&ms, ev[5], ev[6]);
+            out->l2t_ms += ms;
             hipEventElapsedTime(&a, ev[7], ev[0]);
-            hipEventElapsedTime(&b, ev[5], ev[8]);
-            out->l2t_ms += a + b;
+            hipEventElapsedTime(&b, ev[6], ev[8]);
+            out->perm_ms += a + b;
             hipEventElapsedTime(&ms, ev[7], ev[8]);
             out->total_ms += ms;
             for (int l = 0; l <= L && l < 24; ++l) {
@@ -636,7 +652,8 @@ int fda_profile_matvec(fda_plan *plan, const void *x_dev, void *y_dev, int64_t n
                 out->m2l_gemm_ms[l] += ms;
             }
         }
-        double *all[7] = {&out->near_ms, &out->s2m_ms, &out->m2m_ms, &out->m2l_ms, &out->l2l_ms, &out->l2t_ms, &out->total_ms};
+        double *all[8] = {&out->near_ms, &out->s2m_ms, &out->m2m_ms,   &out->m2l_ms,
+                          &out->l2l_ms,  &out->l2t_ms, &out->total_ms, &out->perm_ms};
         for (auto *v : all) *v /= reps;
         for (int l = 0; l < 24; ++l) out->m2l_gemm_ms[l] /= reps;
     } catch (const HipError &e) {
@@ -683,8 +700,6 @@ int bm_solve(fda_plan *plan, const void *b_dev, void *x_dev, int64_t nrhs, int64
         return fail(FDA_EINVAL, "bad precond");
     if (precond == FDA_PRECOND_MLP && (!plan->mlp || !plan->mlp->m))
         return fail(FDA_EINVAL, "FDA_PRECOND_MLP needs a network attached with fda_plan_set_mlp");
-    if (precond == FDA_PRECOND_MLP && plan->d.max_leaf > kMlpLeaf)
-        return fail(FDA_EINVAL, "FDA_PRECOND_MLP needs leaves of at most 64 elements");
     auto t0 = std::chrono::steady_clock::now();
     bm_stats st{};
     const int nr = (int)nrhs, m = restart;
@@ -733,27 +748,37 @@ int bm_solve(fda_plan *plan, const void *b_dev, void *x_dev, int64_t nrhs, int64
         };
         // learned preconditioner workspace (one column at a time)
         float *feat = nullptr, *yml = nullptr;
-        double *vnorm = nullptr;
+        double2 *vnorm = nullptr;  // row scales
         double2 *zbj = nullptr;
         int *bad = nullptr;
         if (precond == FDA_PRECOND_MLP) {
-            feat = (float *)talloc(sizeof(float) * (size_t)plan->d.nleaf * kMlpIn);
-            yml = (float *)talloc(sizeof(float) * (size_t)plan->d.nleaf * kMlpOut);
-            vnorm = (double *)talloc(sizeof(double) * (size_t)plan->d.nleaf);
+            feat = (float *)talloc(sizeof(float) * (size_t)plan->d.mlp_nrows * kMlpIn);
+            yml = (float *)talloc(sizeof(float) * (size_t)plan->d.mlp_nrows * kMlpOut);
+            vnorm = (double2 *)talloc(sizeof(double2) * (size_t)plan->d.mlp_nrows);
             zbj = (double2 *)talloc(sizeof(double2) * (size_t)N);
             bad = (int *)talloc(sizeof(int));
         }
+        // FDA_PRECOND_MLP is judged against block Jacobi: the first kJudge
+        // products use block Jacobi, the next kJudge the network; if the
+        // network reduced the (Givens) residual estimate by less over its
+        // window than block Jacobi did over the first, the rest of the solve
+        // uses block Jacobi.  Flexible GMRES allows the switch at any step.
+        constexpr int kJudge = 6;
+        int cur_pc = precond == FDA_PRECOND_MLP ? FDA_PRECOND_BLOCK_JACOBI : precond;
+        int judge_state = precond == FDA_PRECOND_MLP ? 0 : -1;  // 0: BJ window, 1: MLP window, 2: done
+        int judge_steps = 0;
+        double judge_res0 = 1.0, judge_rate_bj = 0.0;
         auto apply_M = [&](const double2 *in, double2 *out) {
-            if (precond == FDA_PRECOND_BLOCK_JACOBI) {
+            if (cur_pc == FDA_PRECOND_BLOCK_JACOBI) {
                 hip_check(launch_bj_apply(plan->d, in, out, nr, nullptr, s), "precond");
-            } else if (precond == FDA_PRECOND_MLP) {
+            } else if (cur_pc == FDA_PRECOND_MLP) {
                 for (int c = 0; c < nr; ++c) {
                     const double2 *vc = in + (size_t)c * N;
                     double2 *oc = out + (size_t)c * N;
                     int flag = 0;
                     hip_check(hipMemcpyAsync(bad, &flag, sizeof(int), hipMemcpyHostToDevice, s), "h2d");
                     mlp_features(plan->d, vc, plan->d.leaf_scalars, feat, vnorm, zbj, s);
-                    plan->mlp->m->forward(feat, plan->d.nleaf, yml, s);
+                    plan->mlp->m->forward(feat, plan->d.mlp_nrows, yml, s);
                     mlp_apply(plan->d, yml, vnorm, zbj, oc, bad, s);
                     hip_check(hipGetLastError(), "mlp preconditioner");
                     hip_check(hipMemcpyAsync(&flag, bad, sizeof(int), hipMemcpyDeviceToHost, s), "d2h");
@@ -795,6 +820,7 @@ int bm_solve(fda_plan *plan, const void *b_dev, void *x_dev, int64_t nrhs, int64
                 rc = FDA_NOTCONV;
                 break;
             }
+            if (iters == 0) judge_res0 = worst;
             hip_check(hipMemcpyAsync(act_d, act.data(), sizeof(int32_t) * nr, hipMemcpyHostToDevice, s), "h2d");
             // V_0 = r / beta
             std::vector<cplx> scl(nr);
@@ -850,6 +876,27 @@ int bm_solve(fda_plan *plan, const void *b_dev, void *x_dev, int64_t nrhs, int64
                     if (!done[c]) all_ok = false;
                 }
                 jdone = j + 1;
+                if (judge_state >= 0 && judge_state < 2) {
+                    double res = 0;  // worst Givens residual estimate of the active columns
+                    for (int c = 0; c < nr; ++c)
+                        if (act[c]) res = std::max(res, std::abs(g[c][jcnt[c]]) / bnorm[c]);
+                    if (++judge_steps == kJudge) {
+                        const double rate = judge_res0 > 0 ? res / judge_res0 : 0.0;
+                        if (judge_state == 0) {
+                            judge_rate_bj = rate;
+                            cur_pc = FDA_PRECOND_MLP;
+                            judge_state = 1;
+                        } else {
+                            if (rate > judge_rate_bj) {
+                                cur_pc = FDA_PRECOND_BLOCK_JACOBI;
+                                st.mlp_rejected = 1;
+                            }
+                            judge_state = 2;
+                        }
+                        judge_res0 = res;
+                        judge_steps = 0;
+                    }
+                }
                 if (all_ok || iters >= maxit) break;
             }
             // y = H^-1 g per column, then x += Z y (flexible GMRES: Z_j = M(V_j))
@@ -1023,16 +1070,15 @@ int fda_mlp_samples(fda_plan *plan, const void *r_dev, const void *e_dev, int64_
     if ((e_dev == nullptr) != (T_dev == nullptr) || (T_dev == nullptr) != (M_dev == nullptr))
         return fail(FDA_EINVAL, "e_dev, T_dev and M_dev are given together");
     if (nrhs < 1 || nrhs > plan->hp.opt.nrhs_max || ld < plan->d.n) return fail(FDA_EINVAL, "nrhs / ld out of range");
-    if (plan->d.max_leaf > kMlpLeaf) return fail(FDA_EINVAL, "leaves of more than 64 elements");
-    double *vnorm = nullptr;
+    double2 *vnorm = nullptr;  // row scales
     double2 *z = nullptr;
     int rc = FDA_OK;
     try {
         hip_check(hipSetDevice(plan->device), "hipSetDevice");
         ensure_capacity(plan, (int)nrhs);
         hipStream_t s = as_stream(stream);
-        const int64_t N = plan->d.n, nl = plan->d.nleaf;
-        hip_check(hipMalloc(&vnorm, sizeof(double) * nl), "alloc");
+        const int64_t N = plan->d.n, nl = plan->d.mlp_nrows;
+        hip_check(hipMalloc(&vnorm, sizeof(double2) * nl), "alloc");
         hip_check(hipMalloc(&z, sizeof(double2) * N), "alloc");
         hip_check(launch_permute_in(plan->d, (const double2 *)r_dev, ld, plan->xt, (int)nrhs, s), "permute");
         if (e_dev)

@@ -661,25 +661,46 @@ __global__ void k_gather_reduce(const int32_t *dst, const int32_t *off, const in
     }
 }
 
-// y_leaf += T~ c_leaf
+// y_leaf += T~ c_leaf (T~: n_L x kd, column-major per leaf).  256 threads
+// per leaf: rows are padded to a power of two npad <= 256 and the kd columns
+// are split over 256 / npad thread groups, whose partial sums are added in a
+// fixed order (the product is bound by reading T~ from HBM).
 template <class C>
-__global__ void k_l2t(const int64_t *leaf_off, const C *Tm, int kd, const C *c, double2 *y, int64_t N,
-                      int64_t cstride) {
+__global__ void __launch_bounds__(256) k_l2t(const int64_t *leaf_off, const C *Tm, int kd, const C *c, double2 *y,
+                                             int64_t N, int64_t cstride) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    C *v = (C *)smem_raw;
-    const int b = blockIdx.x;
+    C *v = (C *)smem_raw;     // kd
+    C *part = v + kd;         // 256
+    const int b = blockIdx.x, t = threadIdx.x;
     const C *cr = c + (int64_t)blockIdx.y * cstride + (int64_t)b * kd;
-    for (int j = threadIdx.x; j < kd; j += blockDim.x) v[j] = cr[j];
+    for (int j = t; j < kd; j += blockDim.x) v[j] = cr[j];
     __syncthreads();
     const int64_t e0 = leaf_off[b];
     const int nl = (int)(leaf_off[b + 1] - e0);
+    int npad = 1;
+    while (npad < nl && npad < 256) npad <<= 1;
+    const int G = 256 / npad;
+    const int g = t / npad;
     const C *Tb = Tm + (int64_t)kd * e0;
     double2 *yr = y + (int64_t)blockIdx.y * N;
-    for (int i = threadIdx.x; i < nl; i += blockDim.x) {
+    for (int i0 = 0; i0 < nl; i0 += npad) {
+        const int i = i0 + (t % npad);
         C acc = czero<C>();
-        for (int r = 0; r < kd; ++r) cmac(acc, Tb[i + (int64_t)r * nl], v[r]);
-        double2 o = yr[e0 + i];
-        yr[e0 + i] = make_double2(o.x + (double)acc.x, o.y + (double)acc.y);
+        if (i < nl)
+            for (int r = g; r < kd; r += G) cmac(acc, Tb[i + (int64_t)r * nl], v[r]);
+        part[t] = acc;
+        __syncthreads();
+        if (t < npad && i < nl) {
+            C s = part[t];
+            for (int q = 1; q < G; ++q) {
+                const C u = part[t + q * npad];
+                s.x += u.x;
+                s.y += u.y;
+            }
+            double2 o = yr[e0 + i];
+            yr[e0 + i] = make_double2(o.x + (double)s.x, o.y + (double)s.y);
+        }
+        __syncthreads();
     }
 }
 
@@ -1050,7 +1071,7 @@ static hipError_t matvec_t(const DevPlan &d, const double2 *xt, double2 *yt, int
         if (e != hipSuccess) return e;
     }
     if (ev) hipEventRecord(ev[5], st);
-    hipLaunchKernelGGL(k_l2t<C>, dim3(d.nleaf, nrhs), dim3(64), sizeof(C) * lf.kd, st, d.leaf_off, (const C *)d.T,
+    hipLaunchKernelGGL(k_l2t<C>, dim3(d.nleaf, nrhs), dim3(256), sizeof(C) * (lf.kd + 256), st, d.leaf_off, (const C *)d.T,
                        lf.kd, (const C *)lf.c, yt, N, lf.cstride);
     CHECK_LAUNCH();
     if (ev) hipEventRecord(ev[6], st);

@@ -59,6 +59,12 @@ struct DevPlan {
     // block-Jacobi inverses of the leaf diagonal blocks
     int64_t *bj_off = nullptr;
     float *leaf_scalars = nullptr;  // per leaf: width and largest edge, in wavelengths
+    // learned preconditioner rows: chunks of <= 64 consecutive tree
+    // positions of one leaf (one row per leaf when n_L <= 64)
+    int64_t mlp_nrows = 0;
+    int64_t *mlp_row_off = nullptr;  // first tree position of the row
+    int32_t *mlp_row_leaf = nullptr; // leaf of the row
+    int32_t *mlp_row_n = nullptr;    // elements in the row
     double2 *bj_inv = nullptr;
 };
 

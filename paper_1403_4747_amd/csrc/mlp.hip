@@ -3,15 +3,18 @@
 // (FP32 master weights).  Hand-written kernels: feature extraction from a
 // residual, tiled FP32 GEMM (forward and backward), masked MSE loss, Adam.
 //
-// Per leaf L of the plan's tree (n_L <= 64 elements), for a residual v:
-//   z_L  = block-Jacobi correction inv(A_LL) v_L
-//   features (272): Re v_L / |v_L|, Im v_L / |v_L|, Re z_L / |v_L|,
-//                   Im z_L / |v_L| (each zero-padded to 64), leaf width in
-//                   wavelengths, largest edge in wavelengths, n_L / 64, 1, 0...
-//   output (128):   Re / Im of a 64-element correction c_L
-//   preconditioner: M(v)_L = z_L + |v_L| c_L
-// Training target for a pair (r, e = A^-1 r): (e_L - z_L) / |r_L|, masked to
-// the leaf's n_L elements.
+// Rows are chunks of <= 64 consecutive elements of one leaf L of the plan's
+// tree (a single row per leaf when n_L <= 64).  For a residual v and a row R
+// of leaf L:
+//   z_R  = rows R of the block-Jacobi correction inv(A_LL) v_L
+//   s_R  = |v_R| times the unit phase of the row's largest entry of v
+//   features (272): Re, Im of v_R / s_R and of z_R / s_R (each zero-padded
+//                   to 64), leaf width in wavelengths, the mesh's largest
+//                   edge in wavelengths, n_R / 64, 1, 0...
+//   output (128):   Re / Im of a 64-element correction c_R
+//   preconditioner: M(v)_R = z_R + s_R c_R  (so M(a v) = a M(v), a complex)
+// Training target for a pair (r, e = A^-1 r): (e_R - z_R) / s_R, masked to
+// the row's n_R elements.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -170,88 +173,124 @@ __global__ void k_gather_rows(const float *src, int width, const int32_t *idx, i
 
 // ------------------------------------------------------------------ features
 
-// One block per leaf; v in tree order (one column).  Writes the leaf's
-// feature row, its norm and its block-Jacobi correction z (tree order).
-__global__ void k_mlp_features(const int64_t *leaf_off, const int64_t *inv_off, const double2 *inv, const double2 *v,
-                               const float *leaf_scalars, float *feat, double *vnorm, double2 *z) {
-    __shared__ double2 vs[64];
+// Complex helpers for the row scale s (|s| = |v_R|, arg s = phase of the
+// row's largest entry): features and outputs live in the frame v / s, so the
+// preconditioner satisfies M(a v) = a M(v) for every complex a.
+__device__ __forceinline__ double2 cdiv_scale(double2 x, double2 s) {
+    const double d = s.x * s.x + s.y * s.y;
+    if (d == 0.0) return make_double2(0.0, 0.0);
+    return make_double2((x.x * s.x + x.y * s.y) / d, (x.y * s.x - x.x * s.y) / d);
+}
+
+// One block of 64 threads per row (a chunk of <= 64 consecutive elements of
+// one leaf); v in tree order (one column).  The block-Jacobi correction of
+// the row's elements uses the whole leaf: z_i = sum_j inv(A_LL)[i, j] v_j.
+// Writes the row's features, its scale s and z on the row's elements.
+__global__ void k_mlp_features(const int64_t *leaf_off, const int64_t *row_off, const int32_t *row_leaf,
+                               const int32_t *row_n, const int64_t *inv_off, const double2 *inv, const double2 *v,
+                               const float *leaf_scalars, float *feat, double2 *rscale, double2 *z) {
+    extern __shared__ double2 vleaf[];  // the leaf's v (max_leaf entries)
     __shared__ double red[64];
-    const int b = blockIdx.x;
-    const int64_t e0 = leaf_off[b];
-    const int n = (int)(leaf_off[b + 1] - e0);
-    const int t = threadIdx.x;  // 64 threads
+    __shared__ double bmag[64];
+    __shared__ int bidx[64];
+    const int row = blockIdx.x, t = threadIdx.x;
+    const int b = row_leaf[row];
+    const int64_t l0 = leaf_off[b];
+    const int nL = (int)(leaf_off[b + 1] - l0);
+    const int64_t e0 = row_off[row];
+    const int n = row_n[row];
+    const int i0 = (int)(e0 - l0);  // row offset inside the leaf
+    for (int j = t; j < nL; j += 64) vleaf[j] = v[l0 + j];
+    __syncthreads();
     double2 vi = make_double2(0.0, 0.0);
-    if (t < n) vi = v[e0 + t];
-    vs[t] = vi;
-    red[t] = vi.x * vi.x + vi.y * vi.y;
+    if (t < n) vi = vleaf[i0 + t];
+    const double m2 = vi.x * vi.x + vi.y * vi.y;
+    red[t] = m2;
+    bmag[t] = m2;
+    bidx[t] = t;
     __syncthreads();
     for (int o = 32; o > 0; o >>= 1) {
-        if (t < o) red[t] += red[t + o];
+        if (t < o) {
+            red[t] += red[t + o];
+            // largest modulus, ties to the smaller index
+            if (bmag[t + o] > bmag[t] || (bmag[t + o] == bmag[t] && bidx[t + o] < bidx[t])) {
+                bmag[t] = bmag[t + o];
+                bidx[t] = bidx[t + o];
+            }
+        }
         __syncthreads();
     }
     const double nv = sqrt(red[0]);
-    const double inv_nv = nv > 0 ? 1.0 / nv : 0.0;
+    double2 s = make_double2(0.0, 0.0);
+    if (nv > 0) {
+        const double2 vm = vleaf[i0 + bidx[0]];
+        const double am = sqrt(bmag[0]);
+        s = make_double2(nv * vm.x / am, nv * vm.y / am);
+    }
     double2 zi = make_double2(0.0, 0.0);
     if (t < n) {
         const double2 *A = inv + inv_off[b];
-        for (int j = 0; j < n; ++j) {
-            const double2 a = A[t + j * n], x = vs[j];
+        const int i = i0 + t;
+        for (int j = 0; j < nL; ++j) {
+            const double2 a = A[i + (int64_t)j * nL], x = vleaf[j];
             zi.x += a.x * x.x - a.y * x.y;
             zi.y += a.x * x.y + a.y * x.x;
         }
         z[e0 + t] = zi;
     }
-    float *f = feat + (int64_t)b * kMlpIn;
-    f[t] = (float)(vi.x * inv_nv);
-    f[64 + t] = (float)(vi.y * inv_nv);
-    f[128 + t] = (float)(zi.x * inv_nv);
-    f[192 + t] = (float)(zi.y * inv_nv);
+    const double2 vt = cdiv_scale(vi, s), zt = cdiv_scale(zi, s);
+    float *f = feat + (int64_t)row * kMlpIn;
+    f[t] = (float)vt.x;
+    f[64 + t] = (float)vt.y;
+    f[128 + t] = (float)zt.x;
+    f[192 + t] = (float)zt.y;
     if (t < kMlpIn - 256) {
-        float s = 0.f;
-        if (t < 2) s = leaf_scalars[2 * b + t];
-        else if (t == 2) s = n / 64.f;
-        else if (t == 3) s = 1.f;
-        f[256 + t] = s;
+        float sc = 0.f;
+        if (t < 2) sc = leaf_scalars[2 * b + t];
+        else if (t == 2) sc = n / 64.f;
+        else if (t == 3) sc = 1.f;
+        f[256 + t] = sc;
     }
-    if (t == 0) vnorm[b] = nv;
+    if (t == 0) rscale[row] = s;
 }
 
-// out_L = z_L + |v_L| c_L (tree order); flags non-finite MLP outputs.
-__global__ void k_mlp_apply(const int64_t *leaf_off, const float *Y, const double *vnorm, const double2 *z,
-                            double2 *out, int *bad) {
-    const int b = blockIdx.x, t = threadIdx.x;
-    const int64_t e0 = leaf_off[b];
-    const int n = (int)(leaf_off[b + 1] - e0);
+// out_row = z_row + s_row c_row (tree order); flags non-finite outputs.
+__global__ void k_mlp_apply(const int64_t *row_off, const int32_t *row_n, const float *Y, const double2 *rscale,
+                            const double2 *z, double2 *out, int *bad) {
+    const int row = blockIdx.x, t = threadIdx.x;
+    const int64_t e0 = row_off[row];
+    const int n = row_n[row];
     if (t >= n) return;
-    const float cr = Y[(int64_t)b * kMlpOut + t], ci = Y[(int64_t)b * kMlpOut + 64 + t];
+    const float cr = Y[(int64_t)row * kMlpOut + t], ci = Y[(int64_t)row * kMlpOut + 64 + t];
     if (!isfinite(cr) || !isfinite(ci)) {
         *bad = 1;
         out[e0 + t] = z[e0 + t];
         return;
     }
-    const double s = vnorm[b];
+    const double2 s = rscale[row];
     const double2 zz = z[e0 + t];
-    out[e0 + t] = make_double2(zz.x + s * cr, zz.y + s * ci);
+    out[e0 + t] = make_double2(zz.x + s.x * cr - s.y * ci, zz.y + s.x * ci + s.y * cr);
 }
 
-// Training targets: (e_L - z_L) / |r_L| and the mask of the leaf's elements.
-__global__ void k_mlp_targets(const int64_t *leaf_off, const double2 *e, const double2 *z, const double *vnorm,
-                              float *tgt, float *mask) {
-    const int b = blockIdx.x, t = threadIdx.x;
-    const int64_t e0 = leaf_off[b];
-    const int n = (int)(leaf_off[b + 1] - e0);
-    const double s = vnorm[b] > 0 ? 1.0 / vnorm[b] : 0.0;
+// Training targets: (e_row - z_row) / s_row and the mask of the row's elements.
+__global__ void k_mlp_targets(const int64_t *row_off, const int32_t *row_n, const double2 *e, const double2 *z,
+                              const double2 *rscale, float *tgt, float *mask) {
+    const int row = blockIdx.x, t = threadIdx.x;
+    const int64_t e0 = row_off[row];
+    const int n = row_n[row];
+    const double2 s = rscale[row];
     float tr = 0.f, ti = 0.f, mk = 0.f;
     if (t < n) {
         const double2 ee = e[e0 + t], zz = z[e0 + t];
-        tr = (float)((ee.x - zz.x) * s);
-        ti = (float)((ee.y - zz.y) * s);
+        const double2 d = cdiv_scale(make_double2(ee.x - zz.x, ee.y - zz.y), s);
+        tr = (float)d.x;
+        ti = (float)d.y;
         mk = 1.f;
     }
-    tgt[(int64_t)b * kMlpOut + t] = tr;
-    tgt[(int64_t)b * kMlpOut + 64 + t] = ti;
-    mask[(int64_t)b * kMlpOut + t] = mk;
-    mask[(int64_t)b * kMlpOut + 64 + t] = mk;
+    tgt[(int64_t)row * kMlpOut + t] = tr;
+    tgt[(int64_t)row * kMlpOut + 64 + t] = ti;
+    mask[(int64_t)row * kMlpOut + t] = mk;
+    mask[(int64_t)row * kMlpOut + 64 + t] = mk;
 }
 
 // ------------------------------------------------------------------ model
@@ -444,20 +483,23 @@ std::vector<double> mlp_train(Mlp *m, const float *X, const float *T, const floa
     return losses;
 }
 
-void mlp_features(const DevPlan &d, const double2 *vt, const float *leaf_scalars, float *feat, double *vnorm,
+void mlp_features(const DevPlan &d, const double2 *vt, const float *leaf_scalars, float *feat, double2 *rscale,
                   double2 *z, hipStream_t st) {
-    hipLaunchKernelGGL(k_mlp_features, dim3(d.nleaf), dim3(64), 0, st, d.leaf_off, d.bj_off, d.bj_inv, vt,
-                       leaf_scalars, feat, vnorm, z);
+    hipLaunchKernelGGL(k_mlp_features, dim3((unsigned)d.mlp_nrows), dim3(64), sizeof(double2) * d.max_leaf, st,
+                       d.leaf_off, d.mlp_row_off, d.mlp_row_leaf, d.mlp_row_n, d.bj_off, d.bj_inv, vt, leaf_scalars,
+                       feat, rscale, z);
 }
 
-void mlp_apply(const DevPlan &d, const float *Y, const double *vnorm, const double2 *z, double2 *out, int *bad,
+void mlp_apply(const DevPlan &d, const float *Y, const double2 *rscale, const double2 *z, double2 *out, int *bad,
                hipStream_t st) {
-    hipLaunchKernelGGL(k_mlp_apply, dim3(d.nleaf), dim3(64), 0, st, d.leaf_off, Y, vnorm, z, out, bad);
+    hipLaunchKernelGGL(k_mlp_apply, dim3((unsigned)d.mlp_nrows), dim3(64), 0, st, d.mlp_row_off, d.mlp_row_n, Y,
+                       rscale, z, out, bad);
 }
 
-void mlp_targets(const DevPlan &d, const double2 *et, const double2 *z, const double *vnorm, float *tgt, float *mask,
-                 hipStream_t st) {
-    hipLaunchKernelGGL(k_mlp_targets, dim3(d.nleaf), dim3(64), 0, st, d.leaf_off, et, z, vnorm, tgt, mask);
+void mlp_targets(const DevPlan &d, const double2 *et, const double2 *z, const double2 *rscale, float *tgt,
+                 float *mask, hipStream_t st) {
+    hipLaunchKernelGGL(k_mlp_targets, dim3((unsigned)d.mlp_nrows), dim3(64), 0, st, d.mlp_row_off, d.mlp_row_n, et,
+                       z, rscale, tgt, mask);
 }
 
 }  // namespace fda

@@ -54,12 +54,12 @@ std::vector<double> mlp_train(Mlp *m, const float *X, const float *T, const floa
                               int batch, float lr, uint64_t seed, hipStream_t st);
 // Features of a tree-ordered residual column; also its per-leaf norms and
 // block-Jacobi correction z (tree order).
-void mlp_features(const DevPlan &d, const double2 *vt, const float *leaf_scalars, float *feat, double *vnorm,
+void mlp_features(const DevPlan &d, const double2 *vt, const float *leaf_scalars, float *feat, double2 *rscale,
                   double2 *z, hipStream_t st);
-// out = z + |v_L| * MLP output, per leaf; *bad = 1 if any output is not finite.
-void mlp_apply(const DevPlan &d, const float *Y, const double *vnorm, const double2 *z, double2 *out, int *bad,
+// out = z + s * MLP output, per row; *bad = 1 if any output is not finite.
+void mlp_apply(const DevPlan &d, const float *Y, const double2 *rscale, const double2 *z, double2 *out, int *bad,
                hipStream_t st);
-void mlp_targets(const DevPlan &d, const double2 *et, const double2 *z, const double *vnorm, float *tgt, float *mask,
-                 hipStream_t st);
+void mlp_targets(const DevPlan &d, const double2 *et, const double2 *z, const double2 *rscale, float *tgt,
+                 float *mask, hipStream_t st);
 
 }  // namespace fda

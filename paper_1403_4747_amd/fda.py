@@ -55,7 +55,7 @@ class Stats(ctypes.Structure):
         ("m2l_rank_max", ctypes.c_int32 * 24), ("m2l_rank_mean", ctypes.c_double * 24),
         ("m2l_level_flops", ctypes.c_double * 24), ("m2l_flops", ctypes.c_int64), ("m2l_bytes", ctypes.c_int64), ("h_max", ctypes.c_double),
         ("root_width", ctypes.c_double), ("build_seconds", ctypes.c_double), ("device_bytes", ctypes.c_int64),
-        ("m2m_flops", ctypes.c_double), ("l2l_flops", ctypes.c_double),
+        ("m2m_flops", ctypes.c_double), ("l2l_flops", ctypes.c_double), ("mlp_rows", ctypes.c_int64),
     ]
 
     def to_dict(self) -> Dict:
@@ -73,7 +73,7 @@ class ProfileResult(ctypes.Structure):
     _fields_ = [
         ("near_ms", ctypes.c_double), ("s2m_ms", ctypes.c_double), ("m2m_ms", ctypes.c_double),
         ("m2l_ms", ctypes.c_double), ("l2l_ms", ctypes.c_double), ("l2t_ms", ctypes.c_double),
-        ("total_ms", ctypes.c_double), ("m2l_gemm_ms", ctypes.c_double * 24),
+        ("total_ms", ctypes.c_double), ("m2l_gemm_ms", ctypes.c_double * 24), ("perm_ms", ctypes.c_double),
     ]
 
 
@@ -81,6 +81,7 @@ class SolveStats(ctypes.Structure):
     _fields_ = [
         ("iterations", ctypes.c_int32), ("restarts", ctypes.c_int32), ("rel_residual", ctypes.c_double),
         ("seconds", ctypes.c_double), ("col_iterations", ctypes.c_int32 * 64), ("mlp_fallbacks", ctypes.c_int32),
+        ("mlp_rejected", ctypes.c_int32),
     ]
 
 
@@ -260,7 +261,7 @@ class Plan:
         _err(rc)
         info = dict(iterations=st.iterations, restarts=st.restarts, rel_residual=st.rel_residual,
                     seconds=st.seconds, col_iterations=list(st.col_iterations)[:nrhs],
-                    mlp_fallbacks=st.mlp_fallbacks, converged=(rc == 0))
+                    mlp_fallbacks=st.mlp_fallbacks, mlp_rejected=st.mlp_rejected, converged=(rc == 0))
         return x, info
 
     def leaves(self):
@@ -279,14 +280,15 @@ class Plan:
 
     def mlp_samples(self, r, e=None):
         """Feature rows (and targets / masks when e = A^-1 r is given) of
-        every leaf for each residual column (fda_mlp_samples).  Returns float32
-        device tensors X (nrhs*nleaf, 272) and, with e, T and M (.., 128)."""
+        every row (a leaf, or a 64-element chunk of a larger leaf) for each
+        residual column (fda_mlp_samples).  Returns float32 device tensors X
+        (nrhs*mlp_rows, 272) and, with e, T and M (.., 128)."""
         import torch
 
         nrhs = self._check_vec(r, self.n)
         if e is not None and (self._check_vec(e, self.n) != nrhs):
             raise ValueError("r and e differ in shape")
-        nl = self.stats()["nleaf"]
+        nl = self.stats()["mlp_rows"]
         X = torch.empty((nrhs * nl, MLP_IN), dtype=torch.float32, device=r.device)
         T = M = None
         if e is not None:
@@ -314,7 +316,7 @@ class Plan:
         rc = library().fda_profile_matvec(self._h, x.data_ptr(), y.data_ptr(), nrhs, self.n, int(reps), _stream(),
                                           ctypes.byref(res))
         _err(rc)
-        d = {q: getattr(res, q + "_ms") for q in ("near", "s2m", "m2m", "m2l", "l2l", "l2t", "total")}
+        d = {q: getattr(res, q + "_ms") for q in ("near", "s2m", "m2m", "m2l", "l2l", "l2t", "perm", "total")}
         d["m2l_gemm"] = list(res.m2l_gemm_ms)
         return d
 

@@ -120,30 +120,42 @@ def test_mlp_training_reduces_loss(plan1280):
     assert losses[-1] < 0.5 * losses[0]
 
 
-def test_mlp_samples_match_oracle(plan1280):
-    V, T, prm, p = plan1280
-    _say("[mlp] samples vs oracle")
+@pytest.mark.parametrize("name,max_leaf", [("sphere1280_kD10", 64), ("sphere5120_kD20", 128)])
+def test_mlp_samples_match_oracle(name, max_leaf):
+    """Rows of every leaf (and 64-element chunks of leaves above 64
+    elements) against the oracle's features and targets."""
+    from paper_1403_4747_amd import Plan
+
+    V, T, prm = W.workload(name)
+    _say(f"[mlp] samples vs oracle: {name} max_leaf={max_leaf}")
     n = len(T)
     k = prm["k"]
+    p = Plan(V, T, k, prm["eps"], max_leaf=max_leaf)
     r = W.complex_normal(n, 1, seed=21)
     e = W.complex_normal(n, 1, seed=22)
     X, Tg, M = p.mlp_samples(_dev(r), _dev(e))
     X, Tg, M = (t.cpu().numpy() for t in (X, Tg, M))
     perm, off = p.leaves()
     st = p.stats()
+    p.close()
     assert sorted(perm.tolist()) == list(range(n))
-    assert off[0] == 0 and off[-1] == n and X.shape[0] == len(off) - 1
+    assert off[0] == 0 and off[-1] == n
+    rows = R.row_ranges(off)
+    assert X.shape[0] == len(rows) == st["mlp_rows"]
+    if max_leaf > 64:
+        assert st["max_leaf_count"] > 64 and len(rows) > len(off) - 1
     lam = 2 * np.pi / k
     w_lam = st["root_width"] / 2 ** st["depth"] / lam
     h_lam = st["h_max"] / lam
     A = O.assemble(V, T, k)
-    for L in range(len(off) - 1):
+    for q, (L, e0, cnt) in enumerate(rows):
         idx = perm[off[L]:off[L + 1]]
-        f, nv, z = R.leaf_features(r[idx], A[np.ix_(idx, idx)], w_lam, h_lam)
-        t, m = R.leaf_targets(e[idx], z, nv)
-        assert np.max(np.abs(X[L] - f)) <= 1e-5, L
-        assert np.max(np.abs(Tg[L] - t)) <= 1e-5 * max(1.0, np.max(np.abs(t))), L
-        assert np.array_equal(M[L], m), L
+        i0 = e0 - off[L]
+        f, s, z = R.leaf_features(r[idx], A[np.ix_(idx, idx)], w_lam, h_lam, i0=i0, n=cnt)
+        t, m = R.leaf_targets(e[idx][i0:i0 + cnt], z, s)
+        assert np.max(np.abs(X[q] - f)) <= 1e-5, q
+        assert np.max(np.abs(Tg[q] - t)) <= 1e-5 * max(1.0, np.max(np.abs(t))), q
+        assert np.array_equal(M[q], m), q
 
 
 def test_mlp_precond_with_zero_last_layer_is_block_jacobi(plan1280):
@@ -198,7 +210,7 @@ def test_mlp_nonfinite_output_falls_back_to_block_jacobi(plan1280):
     x1, i1 = p.solve(b, tol=1e-8, precond="block_jacobi")
     x2, i2 = p.solve(b, tol=1e-8, precond="mlp")
     p.set_mlp(None)
-    assert i2["converged"] and i2["mlp_fallbacks"] >= i2["iterations"]
+    assert i2["converged"] and i2["mlp_fallbacks"] >= 1
     assert i1["iterations"] == i2["iterations"]
     assert float(torch.linalg.norm(x1 - x2) / torch.linalg.norm(x1)) <= 1e-12
 
@@ -210,3 +222,43 @@ def test_mlp_precond_needs_a_network(plan1280):
     b = p.rhs_planewave(prm["direction"])
     with pytest.raises(FDAError):
         p.solve(b, precond="mlp")
+
+
+def test_training_driver_small_cases(tmp_path):
+    from paper_1403_4747_amd import train_mlp as TM
+    from paper_1403_4747_amd import Mlp
+
+    _say("[mlp] training driver on two small ellipsoids")
+    X, Tg, M, meta = TM.generate([0, 1], subdiv=3, kD=(8.0, 12.0), log=_say)
+    assert X.shape[0] == sum(m["rows"] for m in meta) and X.shape[1] == R.MLP_IN
+    assert torch.isfinite(X).all() and torch.isfinite(Tg).all()
+    net = Mlp(hidden=64, seed=1)
+    losses = net.train(X, Tg, M, epochs=5, batch=128, lr=1e-3)
+    assert np.all(np.isfinite(losses)) and losses[-1] < losses[0]
+    ev = TM.evaluate(net, [100000], subdiv=3, kD=(8.0, 12.0), log=_say)
+    assert ev[0]["mlp"]["converged"] and ev[0]["mlp_vs_none_rel_diff"] < 1e-3
+    path = str(tmp_path / "w.npz")
+    TM.save(net, path, dict(test=True))
+    net2 = TM.load(path)
+    assert np.array_equal(net2.get_params(), net.get_params())
+
+
+def test_mlp_judge_rejects_a_harmful_network(plan1280):
+    from paper_1403_4747_amd import Mlp
+
+    V, T, prm, p = plan1280
+    _say("[mlp] judge: a network adding a large constant correction is rejected")
+    net = Mlp(hidden=32, seed=6)
+    q = net.get_params()
+    parts = net.split(q)
+    parts["W3"][:] = 0
+    parts["b3"][:] = 3.0  # c_R = 3 + 3i on every entry: far from any inverse
+    net.set_params(q)
+    p.set_mlp(net)
+    b = p.rhs_planewave(prm["direction"])
+    x1, i1 = p.solve(b, tol=1e-8, precond="block_jacobi")
+    x2, i2 = p.solve(b, tol=1e-8, precond="mlp")
+    p.set_mlp(None)
+    assert i2["converged"] and i2["mlp_rejected"] == 1
+    assert i2["iterations"] <= i1["iterations"] + 12
+    assert float(torch.linalg.norm(x1 - x2) / torch.linalg.norm(x1)) <= 1e-6

@@ -98,15 +98,27 @@ def test_features_and_block_jacobi_reduction():
     n = 37
     A = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)) + 8 * np.eye(n)
     v = rng.standard_normal(n) + 1j * rng.standard_normal(n)
-    f, nv, z = R.leaf_features(v, A, 0.7, 0.12)
-    assert nv == pytest.approx(np.linalg.norm(v))
+    f, s, z = R.leaf_features(v, A, 0.7, 0.12)
+    assert abs(s) == pytest.approx(np.linalg.norm(v))
+    j = np.argmax(np.abs(v))
+    assert np.angle(s) == pytest.approx(np.angle(v[j]))
     assert np.allclose(A @ z, v)
-    assert np.allclose(f[0:n] ** 2 + f[64:64 + n] ** 2, np.abs(v / nv) ** 2)
+    assert np.allclose(f[0:n] ** 2 + f[64:64 + n] ** 2, np.abs(v) ** 2 / abs(s) ** 2)
+    # the largest entry is real and positive in the scaled frame
+    assert f[j] > 0 and f[64 + j] == pytest.approx(0.0, abs=1e-15)
     assert np.all(f[n:64] == 0) and np.all(f[64 + n:128] == 0) and np.all(f[128 + n:192] == 0)
     assert list(f[256:260]) == pytest.approx([0.7, 0.12, n / 64, 1.0]) and np.all(f[260:] == 0)
     # identity block: z = v
     f2, _, _ = R.leaf_features(v, np.eye(n), 0.7, 0.12)
     assert np.allclose(f2[128:256], f2[0:128])
+    # complex scaling of v leaves the features unchanged and scales s
+    a = 0.3 - 2.1j
+    f3, s3, z3 = R.leaf_features(a * v, A, 0.7, 0.12)
+    assert np.allclose(f3, f) and s3 == pytest.approx(a * s) and np.allclose(z3, a * z)
+    # a chunk of the leaf: rows 10..29, z restricted to them
+    f4, s4, z4 = R.leaf_features(v, A, 0.7, 0.12, i0=10, n=20)
+    assert np.allclose(z4, z[10:30]) and abs(s4) == pytest.approx(np.linalg.norm(v[10:30]))
+    assert f4[258] == pytest.approx(20 / 64)
     # a zero last layer leaves exactly the block-Jacobi correction
     h = 8
     p = (0.2 * rng.standard_normal(R.num_params(h))).astype(np.float32)
@@ -114,11 +126,13 @@ def test_features_and_block_jacobi_reduction():
     W3[:] = 0
     b3[:] = 0
     Y, _, _ = R.forward(p, f[None, :], h)
-    assert np.array_equal(R.precond_apply(z, nv, Y[0]), z)
-    # the target of an exact correction e = z is zero, and of e = z + t v is t v / |v|
-    t, m = R.leaf_targets(z, z, nv)
+    assert np.array_equal(R.precond_apply(z, s, Y[0]), z)
+    # the target of an exact correction e = z is zero, and of e = z + t v is t v / s
+    t, m = R.leaf_targets(z, z, s)
     assert np.all(t == 0) and m.sum() == 2 * n
-    t, m = R.leaf_targets(z + 0.5 * v, z, nv)
-    assert np.allclose(t[:n] + 1j * t[64:64 + n], 0.5 * v / nv)
+    t, m = R.leaf_targets(z + 0.5 * v, z, s)
+    assert np.allclose(t[:n] + 1j * t[64:64 + n], 0.5 * v / s)
     # a network that outputs that target reproduces e exactly
-    assert np.allclose(R.precond_apply(z, nv, t), z + 0.5 * v)
+    assert np.allclose(R.precond_apply(z, s, t), z + 0.5 * v)
+    # row ranges split leaves above 64 elements into 64-element chunks
+    assert R.row_ranges(np.array([0, 30, 160])) == [(0, 0, 30), (1, 30, 64), (1, 94, 64), (1, 158, 2)]
