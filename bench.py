@@ -118,11 +118,12 @@ def main():
     log(f"[bench] matvec {ms:.3f} ms ({args.steps} steps, wall {wall:.3f} s)")
 
     if args.calib_copy_mb > 0:
+        # one elementwise kernel that reads and writes calib_copy_mb MiB each
         src = torch.empty(args.calib_copy_mb * 1024 * 1024 // 8, dtype=torch.float64, device="cuda")
         src.fill_(1.0)
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
-        dst.copy_(src)
+        torch.mul(src, 2.0, out=dst)
         torch.cuda.synchronize()
         log(f"[bench] calibration copy of {args.calib_copy_mb} MiB done")
         del src, dst
@@ -153,8 +154,14 @@ def main():
                     level_ms=[round(lv_ms[l], 4) for l in launches])
     if args.traffic_json and os.path.exists(args.traffic_json):
         # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes,
-        # scaled by the same counters' reading for a plain copy of known size
-        roofline["traffic"] = json.load(open(args.traffic_json)).get("bytes_per_launch")
+        # scaled by the same counters' reading for a plain copy of known size;
+        # only valid while the kernel source is the one that was measured
+        import hashlib
+
+        tj = json.load(open(args.traffic_json))
+        src = os.path.join(ROOT, tj.get("source", ""))
+        if os.path.exists(src) and hashlib.sha256(open(src, "rb").read()).hexdigest() == tj.get("source_sha256"):
+            roofline["traffic"] = tj.get("bytes_per_launch")
 
     solve = {}
     if not args.no_solve:
