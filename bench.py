@@ -41,10 +41,10 @@ def cpu_baseline(V, T, k, x, y_gpu, rows_sample, seconds_target=20.0):
     n = len(T)
     rng = np.random.default_rng(123)
     # calibrate on a few rows, then size the sample to about seconds_target
-    r0 = np.sort(rng.choice(n, size=8, replace=False))
+    r0 = np.sort(rng.choice(n, size=128, replace=False))
     t0 = time.perf_counter()
     O.matvec(V, T, k, x, row_idx=r0)
-    per_row = (time.perf_counter() - t0) / 8
+    per_row = (time.perf_counter() - t0) / 128
     m = int(max(16, min(rows_sample, seconds_target / max(per_row, 1e-9))))
     rows = np.sort(rng.choice(n, size=m, replace=False))
     t0 = time.perf_counter()
@@ -53,7 +53,14 @@ def cpu_baseline(V, T, k, x, y_gpu, rows_sample, seconds_target=20.0):
     full = dt * n / m
     err = float(np.linalg.norm(y_gpu[rows] - yr) / np.linalg.norm(yr))
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return dict(value=1.0 / full, unit="matvecs/s", cores=threads, kind="oracle",
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
+    return dict(value=1.0 / full, unit="matvecs/s", cores=threads, kind="oracle", cpu_model=model,
+                nproc=os.cpu_count(),
                 sample=f"{m} of {n} rows of one FP64 dense matvec ({dt:.1f} s), scaled by N/{m}",
                 seconds_per_matvec=full), err, rows, yr
 
@@ -70,6 +77,7 @@ def main():
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run one plain device copy of this many MiB (calibrates HBM counters)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--nrhs-multi", type=int, default=64, help="also time products of this many columns (0: skip)")
     ap.add_argument("--mlp-weights", default=os.path.join(ROOT, "paper_1403_4747_amd", "weights",
                                                           "mlp_ellipsoid_s5_h256.npz"),
                     help="trained learned-preconditioner weights for the fast arm's solve")
@@ -116,6 +124,29 @@ def main():
     wall = time.perf_counter() - w0
     ms = e0.elapsed_time(e1) / args.steps
     log(f"[bench] matvec {ms:.3f} ms ({args.steps} steps, wall {wall:.3f} s)")
+
+    # many right-hand sides: 64 columns per product (plane-wave directions
+    # become GEMM columns of every stage), reported as columns per second
+    multi = {}
+    if args.nrhs_multi > 1:
+        xm = torch.from_numpy(np.ascontiguousarray(W.complex_normal(n, args.nrhs_multi, seed=1).T)).to("cuda")
+        ym = torch.empty_like(xm)
+        plan.matvec(xm, out=ym)
+        torch.cuda.synchronize()
+        reps = max(3, args.steps // 10)
+        e0.record(stream)
+        for _ in range(reps):
+            plan.matvec(xm, out=ym)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        msm = e0.elapsed_time(e1) / reps
+        # column 0 against the single-column product of the same vector
+        y0 = plan.matvec(xm[0].contiguous())
+        multi = dict(nrhs=args.nrhs_multi, ms_per_matvec=round(msm, 4),
+                     columns_per_s=round(args.nrhs_multi * 1000.0 / msm, 2),
+                     col0_rel_diff_vs_single=float(torch.linalg.norm(ym[0] - y0) / torch.linalg.norm(y0)))
+        log(f"[bench] nrhs={args.nrhs_multi}: {multi}")
+        del xm, ym
 
     if args.calib_copy_mb > 0:
         # one elementwise kernel that reads and writes calib_copy_mb MiB each
@@ -220,7 +251,7 @@ def main():
 
     cpu, err = (None, None)
     if not args.no_cpu:
-        cpu, err, rows, yr = cpu_baseline(V, T, k, W.complex_normal(n, 1, seed=0), y_np, 4096, args.cpu_seconds)
+        cpu, err, rows, yr = cpu_baseline(V, T, k, W.complex_normal(n, 1, seed=0), y_np, 32768, args.cpu_seconds)
         log(f"[bench] cpu baseline {cpu}, sampled-row rel err {err:.3e}")
         if "y32" in fast:
             fast["matvec_rel_err_vs_oracle_sampled"] = float(np.linalg.norm(fast["y32"][rows] - yr) / np.linalg.norm(yr))
@@ -246,6 +277,8 @@ def main():
         "m2l_level_ms": [round(v, 4) for v in prof["m2l_gemm"][: st["depth"] + 1]],
         "m2l_flops_per_matvec": st["m2l_flops"],
         "time_to_1e-5_s": solve.get("none", {}).get("seconds"),
+        "build_plus_solve_s": round(build_s + solve["none"]["seconds"], 3) if "none" in solve else None,
+        "multi_rhs": multi or None,
         "solve": solve,
         "matvec_rel_err_vs_oracle_sampled": err,
         "fast_arm_fp32": fast or None,

@@ -28,8 +28,12 @@
  *     other pointers are host pointers.  The library never takes ownership
  *     of caller buffers.
  *   - stream is a hipStream_t passed as void* (NULL = the default stream).
- *   - Every entry point needs the GPU except fda_inspect and the two
- *     version / error helpers.
+ *   - Every entry point needs the GPU except fda_inspect, fda_plan_leaves
+ *     and the two version / error helpers.
+ *   - A plan keeps one set of work buffers (tree-order vectors, level
+ *     states, one scratch buffer shared by the M2M / M2L / L2L products):
+ *     calls on one plan must not overlap in time (issue them on one stream
+ *     or synchronise between streams).
  */
 #ifndef FDA_H
 #define FDA_H

@@ -163,17 +163,28 @@ void ensure_capacity(fda_plan *p, int nrhs) {
     const int64_t N = p->d.n;
     p->xt = dalloc<double2>(p, (size_t)N * nrhs, p->work);
     p->yt = dalloc<double2>(p, (size_t)N * nrhs, p->work);
+    // storage elements: double2 (FP64 plan) or float2 (two floats, FP32 plan)
+    const size_t es = p->d.prec == FDA_PREC_FP32 ? 1 : 2;  // in units of float2
+    // the per-pair products of M2M, M2L and L2L share one scratch buffer:
+    // the stages run one after another on the caller's stream
+    size_t scratch = 0;
     for (int l = p->d.top; l <= p->d.depth && p->d.has_far; ++l) {
         DevLevel &lv = p->d.lv[l];
-        // storage elements: double2 (FP64 plan) or float2 (two floats, FP32 plan)
-        const size_t es = p->d.prec == FDA_PREC_FP32 ? 1 : 2;  // in units of float2
         lv.s = dalloc<float2>(p, es * (size_t)lv.sstride * nrhs, p->work);
         lv.c = dalloc<float2>(p, es * (size_t)lv.cstride * nrhs, p->work);
-        lv.m2l.tmp = dalloc<float2>(p, es * (size_t)lv.m2l.ncol * lv.kd * nrhs, p->work);
+        scratch = std::max(scratch, (size_t)lv.m2l.ncol * lv.kd);
         if (l < p->d.depth) {
             const DevLevel &C = p->d.lv[l + 1];
-            lv.m2m.tmp = dalloc<float2>(p, es * (size_t)lv.m2m.ncol * lv.ku * nrhs, p->work);
-            lv.l2l.tmp = dalloc<float2>(p, es * (size_t)lv.l2l.ncol * C.kd * nrhs, p->work);
+            scratch = std::max(scratch, (size_t)lv.m2m.ncol * lv.ku);
+            scratch = std::max(scratch, (size_t)lv.l2l.ncol * C.kd);
+        }
+    }
+    if (scratch > 0) {
+        float2 *tmp = dalloc<float2>(p, es * scratch * nrhs, p->work);
+        for (int l = p->d.top; l <= p->d.depth && p->d.has_far; ++l) {
+            DevLevel &lv = p->d.lv[l];
+            lv.m2l.tmp = tmp;
+            if (l < p->d.depth) lv.m2m.tmp = lv.l2l.tmp = tmp;
         }
     }
     p->cap_nrhs = nrhs;
