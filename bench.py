@@ -166,23 +166,31 @@ def main():
         f"L2L {st['l2l_flops'] / 1e9:.3f} GF -> {st['l2l_flops'] / (prof['l2l'] * 1e-3) / 1e12:.2f} TF/s")
     y_np = y.cpu().numpy()
 
-    # roofline of the dominant kernel: the M2L product kernel (one launch
-    # per level with interactions).  Algorithmic flops = 8 real flops per
-    # complex multiply-add of the SVD-reduced translations, summed over the
-    # levels, divided by the summed HIP-event durations of those launches:
-    # average flops per launch / average launch duration.
-    lv_ms = [v for v in prof["m2l_gemm"][: st["depth"] + 1]]
-    launches = [l for l, v in enumerate(lv_ms) if st["m2l_level_flops"][l] > 0]
-    m2l_ms = sum(lv_ms[l] for l in launches)
-    m2l_flops = sum(float(st["m2l_level_flops"][l]) for l in launches)
-    achieved = m2l_flops / (m2l_ms * 1e-3) / 1e12 if m2l_ms > 0 else 0.0
-    kname = "k_m2l_lowrank<double2>" if all(st["m2l_rank_max"][l] > 0 for l in launches) else "k_m2l_lowrank / k_ggemm"
-    roofline = dict(bound="mfma", achieved=round(achieved, 3), peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=round(achieved / FP64_PEAK_TFLOPS, 4), traffic=None,
-                    kernel=f"{kname} (M2L, levels {launches})", launches_per_matvec=len(launches),
-                    flops_per_launch=m2l_flops / max(1, len(launches)),
-                    avg_launch_ms=round(m2l_ms / max(1, len(launches)), 5),
-                    level_ms=[round(lv_ms[l], 4) for l in launches])
+    # roofline of the dominant kernel: the M2L product kernel.  Every
+    # low-rank level runs in one launch of k_m2l_lowrank; levels whose
+    # translations stay full rank (none at this size) run k_ggemm.
+    # Algorithmic flops = 8 real flops per complex multiply-add of the
+    # SVD-reduced translations (unpadded ranks), summed over the levels,
+    # divided by the HIP-event duration of the launch(es) on the plan's stream.
+    full = [l for l in range(st["depth"] + 1) if st["m2l_level_flops"][l] > 0 and st["m2l_rank_max"][l] == 0]
+    lowr = [l for l in range(st["depth"] + 1) if st["m2l_level_flops"][l] > 0 and st["m2l_rank_max"][l] > 0]
+    lr_flops = sum(float(st["m2l_level_flops"][l]) for l in lowr)
+    lr_ms = prof["m2l_lowrank"]
+    if lowr and lr_ms > 0:
+        achieved = lr_flops / (lr_ms * 1e-3) / 1e12
+        roofline = dict(bound="mfma", achieved=round(achieved, 3), peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
+                        frac=round(achieved / FP64_PEAK_TFLOPS, 4), traffic=None,
+                        kernel=f"k_m2l_lowrank<double2> (M2L, levels {lowr} in one launch)", launches_per_matvec=1,
+                        flops_per_launch=lr_flops, avg_launch_ms=round(lr_ms, 5),
+                        full_rank_levels=full)
+    else:
+        ms_f = sum(prof["m2l_gemm"][l] for l in full)
+        fl_f = sum(float(st["m2l_level_flops"][l]) for l in full)
+        achieved = fl_f / (ms_f * 1e-3) / 1e12 if ms_f > 0 else 0.0
+        roofline = dict(bound="mfma", achieved=round(achieved, 3), peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
+                        frac=round(achieved / FP64_PEAK_TFLOPS, 4), traffic=None,
+                        kernel=f"k_ggemm<double2> (M2L, levels {full})", launches_per_matvec=len(full),
+                        flops_per_launch=fl_f / max(1, len(full)), avg_launch_ms=round(ms_f / max(1, len(full)), 5))
     if args.traffic_json and os.path.exists(args.traffic_json):
         # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes,
         # scaled by the same counters' reading for a plain copy of known size;
@@ -222,8 +230,12 @@ def main():
         ms32 = e0.elapsed_time(e1) / args.steps
         prof32 = plan32.profile(x, reps=max(3, min(20, args.steps)), out=y32)
         fast = dict(matvecs_per_s=round(1000.0 / ms32, 3), ms_per_matvec=round(ms32, 4),
-                    stages_ms={q: round(v, 4) for q, v in prof32.items() if q != "m2l_gemm"},
-                    m2l_level_ms=[round(v, 4) for v in prof32["m2l_gemm"][: st["depth"] + 1]])
+                    stages_ms={q: round(v, 4) for q, v in prof32.items() if q != "m2l_gemm"})
+        if prof32["m2l_lowrank"] > 0:
+            a32 = lr_flops / (prof32["m2l_lowrank"] * 1e-3) / 1e12
+            fast["m2l_roofline"] = dict(achieved=round(a32, 3), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
+                                        frac=round(a32 / FP32_PEAK_TFLOPS, 4),
+                                        kernel="k_m2l_lowrank<float2> (one launch)")
         if not args.no_solve:
             b32 = plan32.rhs_planewave(prm["direction"])
             pcs = ["none", "block_jacobi"]
@@ -274,7 +286,7 @@ def main():
                    "eps": prm["eps"], "nrhs": 1, "arm": "plain FP64"},
         "build_seconds": round(build_s, 3),
         "stages_ms": {q: round(v, 4) for q, v in prof.items() if q != "m2l_gemm"},
-        "m2l_level_ms": [round(v, 4) for v in prof["m2l_gemm"][: st["depth"] + 1]],
+        "m2l_lowrank_ms": round(prof["m2l_lowrank"], 4),
         "m2l_flops_per_matvec": st["m2l_flops"],
         "time_to_1e-5_s": solve.get("none", {}).get("seconds"),
         "build_plus_solve_s": round(build_s + solve["none"]["seconds"], 3) if "none" in solve else None,

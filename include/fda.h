@@ -275,8 +275,11 @@ int fda_plan_stats(const fda_plan *plan, fda_stats *st);
  * stream, averaged over `reps` back-to-back products of nrhs columns). */
 typedef struct fda_profile_result {
     double near_ms, s2m_ms, m2m_ms, m2l_ms, l2l_ms, l2t_ms, total_ms;
-    double m2l_gemm_ms[24];     /* the M2L product kernel of each level (without its reduction) */
+    double m2l_gemm_ms[24];     /* the full-rank M2L product kernel of each level that is not low-rank
+                                   (without its reduction) */
     double perm_ms;             /* the permutations into and out of tree order */
+    double m2l_lowrank_ms;      /* the one launch of the low-rank M2L product kernel that serves every
+                                   low-rank level (without its reduction) */
 } fda_profile_result;
 
 /* Profile fda_matvec: x_dev/y_dev as in fda_matvec.  Synchronous. */

@@ -179,6 +179,8 @@ void ensure_capacity(fda_plan *p, int nrhs) {
             scratch = std::max(scratch, (size_t)lv.l2l.ncol * C.kd);
         }
     }
+    M2LMerged &mm = p->d.m2l_all;
+    scratch = std::max(scratch, (size_t)mm.nscratch);
     if (scratch > 0) {
         float2 *tmp = dalloc<float2>(p, es * scratch * nrhs, p->work);
         for (int l = p->d.top; l <= p->d.depth && p->d.has_far; ++l) {
@@ -186,6 +188,15 @@ void ensure_capacity(fda_plan *p, int nrhs) {
             lv.m2l.tmp = tmp;
             if (l < p->d.depth) lv.m2m.tmp = lv.l2l.tmp = tmp;
         }
+        mm.tmp = tmp;
+    }
+    if (mm.nwork > 0) {
+        for (auto &la : mm.hargs) {
+            la.X = p->d.lv[la.level].s;
+            la.Y = p->d.lv[la.level].c;
+        }
+        hip_check(hipMemcpy(mm.args, mm.hargs.data(), sizeof(M2LLevelArgs) * mm.hargs.size(), hipMemcpyHostToDevice),
+                  "M2L level table");
     }
     p->cap_nrhs = nrhs;
 }
@@ -324,6 +335,12 @@ void upload_plan(fda_plan *p, const HostOps &ops, DevTranslations &tr) {
     if (!d.has_far) return;
     d.S = to_storage(p, upload_cplx(p, ops.S), ops.S.size());
     d.T = to_storage(p, upload_cplx(p, ops.T), ops.T.size());
+    struct {
+        std::vector<int32_t> hdr, src, dst, off{0}, list, lev;
+        std::vector<std::vector<int32_t>> xcd[8];  // per XCD queue: header + sources of each item
+        std::vector<M2LLevelArgs> args;
+        int64_t nscratch = 0;
+    } mh;  // merged low-rank M2L work list
     for (int l = hp.top; l <= L; ++l) {
         const Level &lv = hp.lv[l];
         DevLevel &dl = d.lv[l];
@@ -365,7 +382,48 @@ void upload_plan(fda_plan *p, const HostOps &ops, DevTranslations &tr) {
                     g.add((int32_t)op, srcs, dsts);
                 }
             }
-            dl.m2l = upload_gwork(p, g);
+            if (dl.rmax > 0) {
+                // low-rank level: its items and every one of its states go to
+                // the merged list (states without pairs get an empty sum)
+                dl.merged = true;
+                const int slot = (int)mh.args.size();
+                M2LLevelArgs la;
+                la.U = dl.Ulr;
+                la.V = dl.Vlr;
+                la.rank = dl.lr_rank;
+                la.kd = lv.kd;
+                la.ku = lv.ku;
+                la.rmax = dl.rmax;
+                la.level = l;
+                la.tbase = mh.nscratch;
+                la.xstride = dl.sstride;
+                la.ystride = dl.cstride;
+                mh.args.push_back(la);
+                mh.nscratch += g.ncol * (int64_t)lv.kd;
+                // each level's items are split into 8 contiguous chunks, one
+                // per XCD queue, so every XCD gets the same share of every
+                // level (and consecutive items of a translation share an L2)
+                const int64_t ni = (int64_t)g.hdr.size() / 4;
+                for (int x = 0; x < 8; ++x)
+                    for (int64_t i = ni * x / 8; i < ni * (x + 1) / 8; ++i) {
+                        std::vector<int32_t> item{g.hdr[4 * i], g.hdr[4 * i + 1], g.hdr[4 * i + 2], slot};
+                        item.insert(item.end(), g.src.begin() + i * kGemmCols, g.src.begin() + (i + 1) * kGemmCols);
+                        mh.xcd[x].push_back(std::move(item));
+                    }
+                const int64_t nst = lv.nbox * (int64_t)lv.nslot;
+                for (int64_t s = 0; s < nst; ++s) {
+                    mh.dst.push_back((int32_t)s);
+                    mh.lev.push_back(slot);
+                    auto it = g.dest_index.find((int32_t)s);
+                    if (it != g.dest_index.end()) {
+                        const auto &pl = g.parts[it->second];
+                        mh.list.insert(mh.list.end(), pl.begin(), pl.end());
+                    }
+                    mh.off.push_back((int32_t)mh.list.size());
+                }
+            } else {
+                dl.m2l = upload_gwork(p, g);
+            }
         }
         if (l < L) {
             const Level &C = hp.lv[l + 1];
@@ -416,6 +474,36 @@ void upload_plan(fda_plan *p, const HostOps &ops, DevTranslations &tr) {
             dl.l2l = upload_gwork(p, gl);
             p->l2l_flops += 8.0 * C.kd * lv.kd * (double)gl.ncol;
         }
+    }
+    // launch order: block b runs on XCD b % 8 (round-robin dispatch) and takes
+    // item b / 8 of that XCD's queue; short queues are padded with empty items
+    size_t qmax = 0;
+    for (auto &q : mh.xcd) qmax = std::max(qmax, q.size());
+    for (size_t t = 0; t < qmax; ++t)
+        for (int x = 0; x < 8; ++x) {
+            if (t < mh.xcd[x].size()) {
+                const auto &it = mh.xcd[x][t];
+                mh.hdr.insert(mh.hdr.end(), it.begin(), it.begin() + 4);
+                mh.src.insert(mh.src.end(), it.begin() + 4, it.end());
+            } else {
+                mh.hdr.insert(mh.hdr.end(), {0, 0, 0, 0});
+                mh.src.insert(mh.src.end(), kGemmCols, -1);
+            }
+        }
+    M2LMerged &mm = d.m2l_all;
+    mm.nwork = (int)(mh.hdr.size() / 4);
+    mm.nred = (int)mh.dst.size();
+    mm.nlev = (int)mh.args.size();
+    mm.nscratch = mh.nscratch;
+    mm.hargs = mh.args;
+    if (mm.nwork > 0) {
+        mm.hdr = (int4 *)upload(p, mh.hdr);
+        mm.src = upload(p, mh.src);
+        mm.rd_dst = upload(p, mh.dst);
+        mm.rd_off = upload(p, mh.off);
+        mm.rd_list = upload(p, mh.list);
+        mm.rd_lev = upload(p, mh.lev);
+        mm.args = dalloc<M2LLevelArgs>(p, mh.args.size(), p->allocs);
     }
 }
 
@@ -622,7 +710,7 @@ int fda_profile_matvec(fda_plan *plan, const void *x_dev, void *y_dev, int64_t n
     if (!plan || !x_dev || !y_dev || !out || reps < 1) return fail(FDA_EINVAL, "bad argument");
     if (nrhs < 1 || nrhs > plan->hp.opt.nrhs_max || ld < plan->d.n) return fail(FDA_EINVAL, "nrhs / ld out of range");
     std::memset(out, 0, sizeof(*out));
-    hipEvent_t ev[9], lev[48];
+    hipEvent_t ev[9], lev[50];  // 2 per level (full-rank M2L) + 2 around the merged low-rank M2L
     for (auto &e : ev) hipEventCreate(&e);
     for (auto &e : lev) hipEventCreate(&e);
     int rc = FDA_OK;
@@ -634,7 +722,7 @@ int fda_profile_matvec(fda_plan *plan, const void *x_dev, void *y_dev, int64_t n
         for (int r = 0; r < reps; ++r) {
             // record every level's pair (outside the timed region) so that
             // elapsed-time queries are valid for levels without M2L work
-            for (int l = 0; l < 24; ++l) {
+            for (int l = 0; l < 25; ++l) {
                 hipEventRecord(lev[2 * l], st);
                 hipEventRecord(lev[2 * l + 1], st);
             }
@@ -662,9 +750,11 @@ int fda_profile_matvec(fda_plan *plan, const void *x_dev, void *y_dev, int64_t n
                 hipEventElapsedTime(&ms, lev[2 * l], lev[2 * l + 1]);
                 out->m2l_gemm_ms[l] += ms;
             }
+            hipEventElapsedTime(&ms, lev[48], lev[49]);
+            out->m2l_lowrank_ms += ms;
         }
-        double *all[8] = {&out->near_ms, &out->s2m_ms, &out->m2m_ms,   &out->m2l_ms,
-                          &out->l2l_ms,  &out->l2t_ms, &out->total_ms, &out->perm_ms};
+        double *all[9] = {&out->near_ms, &out->s2m_ms, &out->m2m_ms,  &out->m2l_ms,        &out->l2l_ms,
+                          &out->l2t_ms,  &out->total_ms, &out->perm_ms, &out->m2l_lowrank_ms};
         for (auto *v : all) *v /= reps;
         for (int l = 0; l < 24; ++l) out->m2l_gemm_ms[l] /= reps;
     } catch (const HipError &e) {

@@ -319,28 +319,49 @@ __device__ __forceinline__ void load_states(C (*S)[GG_LD], const C *Xr, const in
     }
 }
 
-// acc (+)= A-fragment x B for one 16-column tile.  The real and imaginary
-// chains alternate so that no MFMA waits on the one just issued.
+// Complex accumulator of one 16 x 16 output tile on the matrix cores.
+// With FDA_GAUSS3M (default) a complex multiply-add takes three real
+// products (Gauss): P1 = Ar Br, P2 = Ai Bi, P3 = (Ar + Ai)(Br + Bi), then
+// Re = P1 - P2 and Im = P3 - P1 - P2; otherwise four (Re += Ar Br - Ai Bi,
+// Im += Ar Bi + Ai Br).  The three / four products go to independent
+// accumulators, so consecutive MFMAs never wait on each other.
+#ifndef FDA_GAUSS3M
+#define FDA_GAUSS3M 1
+#endif
 template <class C>
-__device__ __forceinline__ void cmfma1(typename CT<C>::v4 &aR, typename CT<C>::v4 &aI, C a, C b) {
-    aR = CT<C>::mfma(a.x, b.x, aR);
-    aI = CT<C>::mfma(a.x, b.y, aI);
-    aR = CT<C>::mfma(-a.y, b.y, aR);
-    aI = CT<C>::mfma(a.y, b.x, aI);
-}
-// ... and for two 16-column tiles sharing the A fragment.
-template <class C>
-__device__ __forceinline__ void cmfma2(typename CT<C>::v4 &aR0, typename CT<C>::v4 &aI0, typename CT<C>::v4 &aR1,
-                                       typename CT<C>::v4 &aI1, C a, C b0, C b1) {
-    aR0 = CT<C>::mfma(a.x, b0.x, aR0);
-    aI0 = CT<C>::mfma(a.x, b0.y, aI0);
-    aR1 = CT<C>::mfma(a.x, b1.x, aR1);
-    aI1 = CT<C>::mfma(a.x, b1.y, aI1);
-    aR0 = CT<C>::mfma(-a.y, b0.y, aR0);
-    aI0 = CT<C>::mfma(a.y, b0.x, aI0);
-    aR1 = CT<C>::mfma(-a.y, b1.y, aR1);
-    aI1 = CT<C>::mfma(a.y, b1.x, aI1);
-}
+struct CAcc {
+    using v4 = typename CT<C>::v4;
+    using R = typename CT<C>::R;
+#if FDA_GAUSS3M
+    v4 p1, p2, p3;
+    __device__ __forceinline__ void zero() {
+        p1 = (v4){0, 0, 0, 0};
+        p2 = (v4){0, 0, 0, 0};
+        p3 = (v4){0, 0, 0, 0};
+    }
+    __device__ __forceinline__ void mac(C a, C b) {
+        p1 = CT<C>::mfma(a.x, b.x, p1);
+        p2 = CT<C>::mfma(a.y, b.y, p2);
+        p3 = CT<C>::mfma(a.x + a.y, b.x + b.y, p3);
+    }
+    __device__ __forceinline__ R re(int v) const { return p1[v] - p2[v]; }
+    __device__ __forceinline__ R im(int v) const { return p3[v] - p1[v] - p2[v]; }
+#else
+    v4 r, i;
+    __device__ __forceinline__ void zero() {
+        r = (v4){0, 0, 0, 0};
+        i = (v4){0, 0, 0, 0};
+    }
+    __device__ __forceinline__ void mac(C a, C b) {
+        r = CT<C>::mfma(a.x, b.x, r);
+        i = CT<C>::mfma(a.x, b.y, i);
+        r = CT<C>::mfma(-a.y, b.y, r);
+        i = CT<C>::mfma(a.y, b.x, i);
+    }
+    __device__ __forceinline__ R re(int v) const { return r[v]; }
+    __device__ __forceinline__ R im(int v) const { return i[v]; }
+#endif
+};
 
 // A fragments of the wave's row tiles rt = wave + 4 q at k-column kcol of a
 // column-major matrix (zero outside rows < mrows, columns < kend).
@@ -365,14 +386,11 @@ __device__ __forceinline__ void ggemm_body(const int4 h, const int32_t *sidx, co
     const int li = lane & 15, lk = lane >> 4;
     for (int band = 0; band < m; band += 64 * GG_RT) {
         const int ntile = min(GG_RT * 4, (m - band + 15) >> 4);
-        v4 accR[GG_RT][NCT], accI[GG_RT][NCT];
+        CAcc<C> acc[GG_RT][NCT];
 #pragma unroll
         for (int q = 0; q < GG_RT; ++q)
 #pragma unroll
-            for (int c = 0; c < NCT; ++c) {
-                accR[q][c] = (v4){0, 0, 0, 0};
-                accI[q][c] = (v4){0, 0, 0, 0};
-            }
+            for (int c = 0; c < NCT; ++c) acc[q][c].zero();
         for (int j0 = 0; j0 < kin; j0 += GG_J) {
             __syncthreads();
             load_states<C>(S, Xr, sidx, kin, j0);
@@ -387,10 +405,8 @@ __device__ __forceinline__ void ggemm_body(const int4 h, const int32_t *sidx, co
 #pragma unroll
                 for (int q = 0; q < GG_RT; ++q) {
                     if (wave + 4 * q >= ntile) break;
-                    if (NCT == 2)
-                        cmfma2<C>(accR[q][0], accI[q][0], accR[q][NCT - 1], accI[q][NCT - 1], a[q], b0, b1);
-                    else
-                        cmfma1<C>(accR[q][0], accI[q][0], a[q], b0);
+                    acc[q][0].mac(a[q], b0);
+                    if (NCT == 2) acc[q][NCT - 1].mac(a[q], b1);
                 }
 #pragma unroll
                 for (int q = 0; q < GG_RT; ++q) a[q] = an[q];
@@ -409,8 +425,8 @@ __device__ __forceinline__ void ggemm_body(const int4 h, const int32_t *sidx, co
                     const int row = band + rt * 16 + CT<C>::row(lk, v);
                     if (row < m) {
                         C r;
-                        r.x = accR[q][c][v];
-                        r.y = accI[q][c][v];
+                        r.x = acc[q][c].re(v);
+                        r.y = acc[q][c].im(v);
                         Tr[(int64_t)col * m + row] = r;
                     }
                 }
@@ -419,8 +435,19 @@ __device__ __forceinline__ void ggemm_body(const int4 h, const int32_t *sidx, co
     }
 }
 
+// Waves per SIMD the GEMM kernels are compiled for: FP64 needs more
+// registers per complex accumulator than FP32.
 template <class C>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_ggemm(const int4 *hdr, const int32_t *src, const C *A, int m, int kin,
+struct GemmOcc {
+    static constexpr int waves = FDA_GAUSS3M ? 3 : 4;
+};
+template <>
+struct GemmOcc<float2> {
+    static constexpr int waves = 4;
+};
+
+template <class C>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GemmOcc<C>::waves))) k_ggemm(const int4 *hdr, const int32_t *src, const C *A, int m, int kin,
                                                const C *X, int64_t xstride, C *T, int64_t tstride, int nwork) {
     __shared__ C S[GG_J][GG_LD];
     __shared__ int32_t sidx[GG_NB];
@@ -465,12 +492,9 @@ __device__ __forceinline__ void m2l_body(const int4 h, const int32_t *sidx, cons
     const int kg = kg_n > 1 ? wave / ntz : 0;
     const int tbase = kg_n > 1 ? wave % ntz : wave;
     const int tstep = kg_n > 1 ? 64 : 4;  // kg_n > 1: one tile per wave
-    v4 zR[ZQ], zI[ZQ];
+    CAcc<C> zacc[ZQ];
 #pragma unroll
-    for (int q = 0; q < ZQ; ++q) {
-        zR[q] = (v4){0, 0, 0, 0};
-        zI[q] = (v4){0, 0, 0, 0};
-    }
+    for (int q = 0; q < ZQ; ++q) zacc[q].zero();
     // the next chunk is fetched into registers while the current one is
     // multiplied out of LDS (the MFMA loop issues no global loads, so these
     // loads are waited for only when they are committed to LDS)
@@ -522,7 +546,7 @@ __device__ __forceinline__ void m2l_body(const int4 h, const int32_t *sidx, cons
                 C a = czero<C>();
                 if (row < r) a = Vs[kk + lk][row];
                 const C b = S[kk + lk][(ti % NCT) * 16 + li];
-                cmfma1<C>(zR[q], zI[q], a, b);
+                zacc[q].mac(a, b);
             }
         }
     }
@@ -536,8 +560,8 @@ __device__ __forceinline__ void m2l_body(const int4 h, const int32_t *sidx, cons
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             C z;
-            z.x = zR[q][v];
-            z.y = zI[q][v];
+            z.x = zacc[q].re(v);
+            z.y = zacc[q].im(v);
             Z[zoff + zt * 16 + CT<C>::row(lk, v)][c * 16 + li] = z;
         }
     }
@@ -563,14 +587,11 @@ __device__ __forceinline__ void m2l_body(const int4 h, const int32_t *sidx, cons
     for (int pass = 0; pass < MF_RT / P2; ++pass) {
         const int rt0 = wave + 4 * P2 * pass;  // this pass: row tiles rt0, rt0 + 4
         if (rt0 >= ntile) break;
-        v4 accR[P2][NCT], accI[P2][NCT];
+        CAcc<C> acc[P2][NCT];
 #pragma unroll
         for (int q = 0; q < P2; ++q)
 #pragma unroll
-            for (int c = 0; c < NCT; ++c) {
-                accR[q][c] = (v4){0, 0, 0, 0};
-                accI[q][c] = (v4){0, 0, 0, 0};
-            }
+            for (int c = 0; c < NCT; ++c) acc[q][c].zero();
         C a[P2], an[P2];
         load_afrag<C, P2>(a, Ut, kd, kd, 16 * 4 * P2 * pass, ntile - 4 * P2 * pass, wave, li, lk, r);
         for (int kk = 0; kk < r; kk += 4) {
@@ -581,10 +602,8 @@ __device__ __forceinline__ void m2l_body(const int4 h, const int32_t *sidx, cons
 #pragma unroll
             for (int q = 0; q < P2; ++q) {
                 if (rt0 + 4 * q >= ntile) break;
-                if (NCT == 2)
-                    cmfma2<C>(accR[q][0], accI[q][0], accR[q][NCT - 1], accI[q][NCT - 1], a[q], b0, b1);
-                else
-                    cmfma1<C>(accR[q][0], accI[q][0], a[q], b0);
+                acc[q][0].mac(a[q], b0);
+                if (NCT == 2) acc[q][NCT - 1].mac(a[q], b1);
             }
 #pragma unroll
             for (int q = 0; q < P2; ++q) a[q] = an[q];
@@ -602,8 +621,8 @@ __device__ __forceinline__ void m2l_body(const int4 h, const int32_t *sidx, cons
                     const int row = rt * 16 + CT<C>::row(lk, v);
                     if (row < kd) {
                         C o;
-                        o.x = accR[q][c][v];
-                        o.y = accI[q][c][v];
+                        o.x = acc[q][c].re(v);
+                        o.y = acc[q][c].im(v);
                         Tr[(int64_t)col * kd + row] = o;
                     }
                 }
@@ -612,10 +631,11 @@ __device__ __forceinline__ void m2l_body(const int4 h, const int32_t *sidx, cons
     }
 }
 
+// One launch for the low-rank M2L of every level: the item's level slot
+// (h.w) selects its factors, states and scratch region.
 template <class C>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_m2l_lowrank(const int4 *hdr, const int32_t *src, const C *Ulr, const C *Vlr,
-                                                     const int32_t *rank, int kd, int ku, int rmax, const C *X,
-                                                     int64_t xstride, C *T, int64_t tstride, int nwork) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GemmOcc<C>::waves)))
+k_m2l_lowrank(const int4 *hdr, const int32_t *src, const M2LLevelArgs *args, C *T, int64_t tstride, int nwork) {
     // LDS: phase 1 stages S (LRJ x GG_LD) and V^ (LRJ x LR_LD); phase 2
     // reuses the same bytes for Z (LR_MAX x GG_LD) once phase 1 is done
     constexpr int kStage = LRJ * GG_LD + LRJ * LR_LD;
@@ -625,22 +645,47 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
     C(*S)[GG_LD] = (C(*)[GG_LD])smem;
     C(*Vs)[LR_LD] = (C(*)[LR_LD])(smem + LRJ * GG_LD);
     C(*Z)[GG_LD] = (C(*)[GG_LD])smem;
-    const int nx = 8;
-    const int per = gridDim.x / nx;
-    const int w = (blockIdx.x % nx) * per + blockIdx.x / nx;
+    // the host ordered the items for round-robin XCD dispatch (block b on
+    // XCD b % 8); empty items pad the queues
+    const int w = blockIdx.x;
     if (w >= nwork) return;
     const int4 h = hdr[w];
+    if (h.z == 0) return;
+    const M2LLevelArgs &la = args[h.w];
+    const int kd = la.kd, ku = la.ku, rmax = la.rmax;
     const int op = h.x;
-    const int r = rank[op];
+    const int r = la.rank[op];
     if (threadIdx.x < GG_NB) sidx[threadIdx.x] = src[(int64_t)w * GG_NB + threadIdx.x];
-    const C *Xr = X + (int64_t)blockIdx.y * xstride;
-    C *Tr = T + (int64_t)blockIdx.y * tstride + (int64_t)h.y * kd;
-    const C *Vt = Vlr + (int64_t)op * rmax * ku;
-    const C *Ut = Ulr + (int64_t)op * kd * rmax;
+    const C *Xr = (const C *)la.X + (int64_t)blockIdx.y * la.xstride;
+    C *Tr = T + (int64_t)blockIdx.y * tstride + la.tbase + (int64_t)h.y * kd;
+    const C *Vt = (const C *)la.V + (int64_t)op * rmax * ku;
+    const C *Ut = (const C *)la.U + (int64_t)op * kd * rmax;
     if (h.z > 16)
         m2l_body<C, 2>(h, sidx, Ut, Vt, r, kd, ku, rmax, Xr, Tr, S, Vs, Z);
     else
         m2l_body<C, 1>(h, sidx, Ut, Vt, r, kd, ku, rmax, Xr, Tr, S, Vs, Z);
+}
+
+// c[dst] = sum of the M2L scratch columns listed for dst (every state of the
+// merged levels has an entry; an empty list writes zero), in list order.
+template <class C>
+__global__ void k_gather_reduce_m2l(const int32_t *dst, const int32_t *off, const int32_t *list, const int32_t *lev,
+                                    const M2LLevelArgs *args, const C *T, int64_t tstride) {
+    const int t = blockIdx.x;
+    const M2LLevelArgs &la = args[lev[t]];
+    const int m = la.kd;
+    const C *Tr = T + (int64_t)blockIdx.y * tstride + la.tbase;
+    C *out = (C *)la.Y + (int64_t)blockIdx.y * la.ystride + (int64_t)dst[t] * m;
+    const int q0 = off[t], q1 = off[t + 1];
+    for (int r = threadIdx.x; r < m; r += blockDim.x) {
+        C acc = czero<C>();
+        for (int q = q0; q < q1; ++q) {
+            const C v = Tr[(int64_t)list[q] * m + r];
+            acc.x += v.x;
+            acc.y += v.y;
+        }
+        out[r] = acc;
+    }
 }
 
 // Y[dst] (+)= sum of the scratch columns listed for dst, in list order.
@@ -1005,24 +1050,6 @@ static hipError_t ggemm_t(const GWork &g, const void *A, int m, int kin, const v
     return hipSuccess;
 }
 
-template <class C>
-static hipError_t m2l_lowrank_t(const DevLevel &lv, int nrhs, hipStream_t st, hipEvent_t *ev) {
-    const GWork &g = lv.m2l;
-    if (g.nwork == 0) return hipSuccess;
-    const int grid = (g.nwork + 7) / 8 * 8;
-    const int64_t tstride = g.ncol * lv.kd;
-    if (ev) hipEventRecord(ev[0], st);
-    hipLaunchKernelGGL(k_m2l_lowrank<C>, dim3(grid, nrhs), dim3(256), 0, st, g.hdr, g.src, (const C *)lv.Ulr,
-                       (const C *)lv.Vlr, lv.lr_rank, lv.kd, lv.ku, lv.rmax, (const C *)lv.s, lv.sstride, (C *)g.tmp,
-                       tstride, g.nwork);
-    CHECK_LAUNCH();
-    if (ev) hipEventRecord(ev[1], st);
-    hipLaunchKernelGGL(k_gather_reduce<C>, dim3(g.nred, nrhs), dim3(std::min(256, ((lv.kd + 63) / 64) * 64)), 0, st,
-                       g.rd_dst, g.rd_off, g.rd_list, lv.kd, (const C *)g.tmp, tstride, (C *)lv.c, lv.cstride, 1);
-    CHECK_LAUNCH();
-    return hipSuccess;
-}
-
 // Stage timings are recorded when ev != nullptr (7 events: start, after
 // near, after S2M, after M2M, after M2L, after L2L, end).
 template <class C>
@@ -1051,17 +1078,26 @@ static hipError_t matvec_t(const DevPlan &d, const double2 *xt, double2 *yt, int
         if (e != hipSuccess) return e;
     }
     if (ev) hipEventRecord(ev[3], st);
+    const M2LMerged &mm = d.m2l_all;
+    if (mm.nwork > 0) {
+        const int grid = mm.nwork;  // a multiple of 8, ordered for XCD dispatch
+        if (lev) hipEventRecord(lev[2 * 24], st);
+        hipLaunchKernelGGL(k_m2l_lowrank<C>, dim3(grid, nrhs), dim3(256), 0, st, mm.hdr, mm.src, mm.args, (C *)mm.tmp,
+                           mm.nscratch, mm.nwork);
+        CHECK_LAUNCH();
+        if (lev) hipEventRecord(lev[2 * 24 + 1], st);
+        hipLaunchKernelGGL(k_gather_reduce_m2l<C>, dim3(mm.nred, nrhs), dim3(128), 0, st, mm.rd_dst, mm.rd_off,
+                           mm.rd_list, mm.rd_lev, mm.args, (const C *)mm.tmp, mm.nscratch);
+        CHECK_LAUNCH();
+    }
     for (int l = top; l <= L; ++l) {
         const DevLevel &lv = d.lv[l];
+        if (lv.merged) continue;
         int64_t n = lv.cstride * nrhs;
         hipLaunchKernelGGL(k_fill_zero<C>, dim3(grid1(n)), dim3(256), 0, st, (C *)lv.c, n);
         CHECK_LAUNCH();
-        hipError_t e;
-        if (lv.rmax > 0)
-            e = m2l_lowrank_t<C>(lv, nrhs, st, lev ? lev + 2 * l : nullptr);
-        else
-            e = ggemm_t<C>(lv.m2l, lv.K, lv.kd, lv.ku, lv.s, lv.sstride, lv.c, lv.cstride, 1, nrhs, st,
-                           lev ? lev + 2 * l : nullptr);
+        hipError_t e = ggemm_t<C>(lv.m2l, lv.K, lv.kd, lv.ku, lv.s, lv.sstride, lv.c, lv.cstride, 1, nrhs, st,
+                                  lev ? lev + 2 * l : nullptr);
         if (e != hipSuccess) return e;
     }
     if (ev) hipEventRecord(ev[4], st);

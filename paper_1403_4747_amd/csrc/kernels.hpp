@@ -22,6 +22,30 @@ struct GWork {
 
 constexpr int kGemmCols = 32;
 
+// The low-rank M2L of every level runs as one launch (the levels are
+// independent once the upward pass is done): one work list whose items carry
+// their level, one reduction list that writes every state of those levels
+// (an empty list writes zero), and a per-level argument table.
+struct M2LLevelArgs {
+    const void *U = nullptr, *V = nullptr;  // low-rank factors (storage type)
+    const int32_t *rank = nullptr;          // padded rank per translation
+    const void *X = nullptr;                // outgoing states s of the level
+    void *Y = nullptr;                      // incoming states c of the level
+    int64_t xstride = 0, ystride = 0;       // elements per right-hand side
+    int64_t tbase = 0;                      // first scratch element of the level
+    int32_t kd = 0, ku = 0, rmax = 0, level = 0;
+};
+struct M2LMerged {
+    int nwork = 0, nred = 0, nlev = 0;
+    int64_t nscratch = 0;                  // scratch elements per right-hand side
+    int4 *hdr = nullptr;                   // (translation, level-local scratch column, columns, level slot)
+    int32_t *src = nullptr;
+    int32_t *rd_dst = nullptr, *rd_off = nullptr, *rd_list = nullptr, *rd_lev = nullptr;
+    M2LLevelArgs *args = nullptr;          // device table, refreshed with the work buffers
+    std::vector<M2LLevelArgs> hargs;
+    void *tmp = nullptr;
+};
+
 struct DevLevel {
     int64_t nbox = 0;
     int nslot = 1, ku = 0, kd = 0;
@@ -34,6 +58,7 @@ struct DevLevel {
     void *Ulr = nullptr, *Vlr = nullptr;
     int32_t *lr_rank = nullptr;
     int rmax = 0;
+    bool merged = false;  // M2L runs in DevPlan::m2l_all
     void *K = nullptr;
     // parent-level operators towards level + 1 and their work lists
     void *M = nullptr, *Lo = nullptr;
@@ -42,6 +67,7 @@ struct DevLevel {
 
 struct DevPlan {
     int64_t n = 0;
+    M2LMerged m2l_all;
     int nleaf = 0, depth = 0, top = 0, max_leaf = 0, max_ncol = 0;
     bool has_far = false;
     double k = 0, h_max = 0;

@@ -74,6 +74,7 @@ class ProfileResult(ctypes.Structure):
         ("near_ms", ctypes.c_double), ("s2m_ms", ctypes.c_double), ("m2m_ms", ctypes.c_double),
         ("m2l_ms", ctypes.c_double), ("l2l_ms", ctypes.c_double), ("l2t_ms", ctypes.c_double),
         ("total_ms", ctypes.c_double), ("m2l_gemm_ms", ctypes.c_double * 24), ("perm_ms", ctypes.c_double),
+        ("m2l_lowrank_ms", ctypes.c_double),
     ]
 
 
@@ -306,8 +307,9 @@ class Plan:
         return st.to_dict()
 
     def profile(self, x, reps: int = 10, out=None) -> Dict:
-        """Per-stage HIP-event timings (ms) of fda_matvec, plus the M2L
-        product kernel of every level (key "m2l_gemm", a list per level)."""
+        """Per-stage HIP-event timings (ms) of fda_matvec, plus the merged
+        low-rank M2L product kernel ("m2l_lowrank") and the full-rank M2L
+        product kernel of every other level ("m2l_gemm", a list per level)."""
         import torch
 
         nrhs = self._check_vec(x, self.n)
@@ -316,7 +318,8 @@ class Plan:
         rc = library().fda_profile_matvec(self._h, x.data_ptr(), y.data_ptr(), nrhs, self.n, int(reps), _stream(),
                                           ctypes.byref(res))
         _err(rc)
-        d = {q: getattr(res, q + "_ms") for q in ("near", "s2m", "m2m", "m2l", "l2l", "l2t", "perm", "total")}
+        d = {q: getattr(res, q + "_ms") for q in ("near", "s2m", "m2m", "m2l", "l2l", "l2t", "perm", "total",
+                                                  "m2l_lowrank")}
         d["m2l_gemm"] = list(res.m2l_gemm_ms)
         return d
 
