@@ -104,6 +104,8 @@ def main():
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
     st = plan.stats()
+    log(f"[bench] build phases (s): {[round(v, 3) for v in st['build_phase_seconds'][:7]]} "
+        "(tree, G factors, translations, low-rank M2L, leaf operators, upload, near field)")
     log(f"[bench] build {build_s:.2f} s; depth {st['depth']} top {st['top_level']} pairs {st['m2l_pairs']} "
         f"ranks {st['rank_up']} p {st['p']} m2l low-rank max {st['m2l_rank_max']} mean "
         f"{[round(v, 1) for v in st['m2l_rank_mean']]} level flops {[round(v / 1e9, 3) for v in st['m2l_level_flops']]} GF")
@@ -285,6 +287,7 @@ def main():
         "config": {"workload": args.workload, "N": n, "k": k, "kD": k * 2 * prm["radius"],
                    "eps": prm["eps"], "nrhs": 1, "arm": "plain FP64"},
         "build_seconds": round(build_s, 3),
+        "build_phase_seconds": [round(v, 3) for v in st["build_phase_seconds"][:7]],
         "stages_ms": {q: round(v, 4) for q, v in prof.items() if q != "m2l_gemm"},
         "m2l_lowrank_ms": round(prof["m2l_lowrank"], 4),
         "m2l_flops_per_matvec": st["m2l_flops"],

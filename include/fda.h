@@ -87,6 +87,8 @@ typedef struct fda_options {
     int32_t nrhs_max;      /* largest nrhs accepted by fda_matvec / bm_solve, default 64 */
     int32_t device;        /* HIP device ordinal, default 0 */
     int32_t verbose;       /* print build statistics to stderr, default 0 */
+    int32_t svd_method;    /* batched SVDs of the build (eqs. (eq_svdg), (eq_epsk)): 0 = bidiagonal QR
+                              (rocSOLVER gesvd), 1 = one-sided Jacobi (gesvdj); default 0 */
 } fda_options;
 
 /* Plan statistics (filled by fda_inspect / fda_plan_stats). */
@@ -120,6 +122,9 @@ typedef struct fda_stats {
     double l2l_flops;           /* the same for the downward pass (L2L) */
     int64_t mlp_rows;           /* rows of the learned preconditioner: chunks of <= 64 consecutive
                                    elements of a leaf (see fda_mlp_samples) */
+    double build_phase_seconds[8]; /* fda_build wall time by phase: tree and lists (host), factors of
+                                      G_up / G_dn, translation matrices, low-rank M2L factors, leaf
+                                      operators (host), upload, near-field quadrature; [7] unused */
 } fda_stats;
 
 /* Fill *opt with the defaults listed above. */

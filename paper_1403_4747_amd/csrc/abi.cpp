@@ -529,6 +529,7 @@ void fda_default_options(fda_options *o) {
     o->nrhs_max = 64;
     o->device = 0;
     o->verbose = 0;
+    o->svd_method = 0;
 }
 
 const char *fda_last_error(void) { return g_last_error.c_str(); }
@@ -564,6 +565,7 @@ int fda_build(const double *verts, int64_t nv, const int32_t *tris, int64_t nt, 
     if (opt) o = *opt;
     if (o.nrhs_max < 1 || o.nrhs_max > 4096) return fail(FDA_EINVAL, "nrhs_max must be in [1, 4096]");
     if (o.prec != FDA_PREC_FP64 && o.prec != FDA_PREC_FP32) return fail(FDA_EINVAL, "prec must be FDA_PREC_FP64 or FDA_PREC_FP32");
+    if (o.svd_method != 0 && o.svd_method != 1) return fail(FDA_EINVAL, "svd_method must be 0 or 1");
     auto t0 = std::chrono::steady_clock::now();
     std::unique_ptr<fda_plan> p(new fda_plan());
     p->device = o.device;
@@ -572,17 +574,29 @@ int fda_build(const double *verts, int64_t nv, const int32_t *tris, int64_t nt, 
     std::vector<std::vector<int32_t>> lr_rank_host;
     std::vector<int> tr_rmax(25, 0);
     std::vector<double> tr_mean(25, 0.0);
+    double phase[8] = {0};
+    auto tick = std::chrono::steady_clock::now();
+    auto lap = [&](int q) {  // wall time of build phase q (device work synchronised)
+        hipDeviceSynchronize();
+        auto now = std::chrono::steady_clock::now();
+        phase[q] += std::chrono::duration<double>(now - tick).count();
+        tick = now;
+    };
     try {
         hip_check(hipSetDevice(o.device), "hipSetDevice");
         host_setup(verts, nv, tris, nt, k, eps, o, p->hp);
+        lap(0);
         bool any = false;
         for (int l = p->hp.top; l <= p->hp.depth; ++l)
             if (!p->hp.lv[l].offsets.empty()) any = true;
         if (any) {
             if (rocblas_create_handle(&rb) != rocblas_status_success) throw BuildError{FDA_EHIP, "rocblas_create_handle failed"};
             device_factors(p->hp, rb);
+            lap(1);
             device_translations(p->hp, rb, tr);
+            lap(2);
             device_lowrank_m2l(p->hp, rb, tr, kLowRankMax);
+            lap(3);
             lr_rank_host.assign(p->hp.depth + 1, {});
             for (int l = 0; l <= p->hp.depth; ++l) {
                 tr_rmax[l] = tr.rmax[l];
@@ -595,8 +609,10 @@ int fda_build(const double *verts, int64_t nv, const int32_t *tris, int64_t nt, 
         }
         HostOps ops;
         form_operators(p->hp, ops);
+        lap(4);
         quadrature_constants();
         upload_plan(p.get(), ops, tr);
+        lap(5);
         {
             // near-field quadrature in FP64; block-Jacobi inverses from it;
             // FP32 plans keep the off-diagonal entries in FP32 and the self
@@ -618,6 +634,7 @@ int fda_build(const double *verts, int64_t nv, const int32_t *tris, int64_t nt, 
             }
         }
         hip_check(hipDeviceSynchronize(), "build synchronize");
+        lap(6);
     } catch (const BuildError &e) {
         for (void *q : tr.allocs) hipFree(q);
         for (void *q : p->allocs) hipFree(q);
@@ -664,6 +681,7 @@ int fda_build(const double *verts, int64_t nv, const int32_t *tris, int64_t nt, 
         p->stats.m2l_flops = tot;
     }
     p->stats.build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (int q = 0; q < 8; ++q) p->stats.build_phase_seconds[q] = phase[q];
     p->stats.device_bytes = p->device_bytes;
     *out = p.release();
     return FDA_OK;

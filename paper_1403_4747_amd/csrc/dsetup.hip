@@ -148,20 +148,39 @@ std::vector<double> cube_points(int p) {
     return out;
 }
 
+// Batched thin SVD A = U diag(S) V^H of column-major matrices (rocSOLVER):
+// method 1 = one-sided Jacobi (gesvdj), otherwise bidiagonalisation + QR
+// (gesvd).  V receives V^H (rows = right singular vectors); S descends.
+// E is workspace of min(m, n) doubles per matrix.
+void batched_svd(rocblas_handle h, int method, int m, int n, rocblas_double_complex *A, int lda, rocblas_stride sA,
+                 double *S, rocblas_stride sS, rocblas_double_complex *U, int ldu, rocblas_stride sU,
+                 rocblas_double_complex *V, int ldv, rocblas_stride sV, double *E, rocblas_int *info, int batch,
+                 const char *what) {
+    if (method == 1) {
+        DBuf res(sizeof(double) * (size_t)batch), sweeps(sizeof(rocblas_int) * (size_t)batch);
+        rchk(rocsolver_zgesvdj_strided_batched(h, rocblas_svect_singular, rocblas_svect_singular, m, n, A, lda, sA,
+                                               0.0, res.as<double>(), 100, sweeps.as<rocblas_int>(), S, sS, U, ldu,
+                                               sU, V, ldv, sV, info, batch),
+             what);
+    } else {
+        rchk(rocsolver_zgesvd_strided_batched(h, rocblas_svect_singular, rocblas_svect_singular, m, n, A, lda, sA, S,
+                                              sS, U, ldu, sU, V, ldv, sV, E, std::min(m, n), rocblas_outofplace,
+                                              info, batch),
+             what);
+    }
+}
+
 // Batched SVD of `batch` m x n matrices (m >= n) stored contiguously in A
 // (destroyed).  Returns host copies of S (batch x n), U (batch x m x n) and
 // V^H (batch x n x n).
-void svd_batched(rocblas_handle h, double2 *A, int m, int n, int batch, std::vector<double> &S,
+void svd_batched(rocblas_handle h, int method, double2 *A, int m, int n, int batch, std::vector<double> &S,
                  std::vector<cplx> &U, std::vector<cplx> &Vh) {
     DBuf dS(sizeof(double) * (size_t)batch * n), dU(sizeof(double2) * (size_t)batch * m * n),
         dV(sizeof(double2) * (size_t)batch * n * n), dE(sizeof(double) * (size_t)batch * n),
         dinfo(sizeof(rocblas_int) * batch);
-    rchk(rocsolver_zgesvd_strided_batched(h, rocblas_svect_singular, rocblas_svect_singular, m, n,
-                                          (rocblas_double_complex *)A, m, (rocblas_stride)m * n, dS.as<double>(), n,
-                                          dU.as<rocblas_double_complex>(), m, (rocblas_stride)m * n,
-                                          dV.as<rocblas_double_complex>(), n, (rocblas_stride)n * n, dE.as<double>(),
-                                          n, rocblas_outofplace, dinfo.as<rocblas_int>(), batch),
-         "zgesvd");
+    batched_svd(h, method, m, n, (rocblas_double_complex *)A, m, (rocblas_stride)m * n, dS.as<double>(), n,
+                dU.as<rocblas_double_complex>(), m, (rocblas_stride)m * n, dV.as<rocblas_double_complex>(), n,
+                (rocblas_stride)n * n, dE.as<double>(), dinfo.as<rocblas_int>(), batch, "zgesvd");
     S.resize((size_t)batch * n);
     U.resize((size_t)batch * m * n);
     Vh.resize((size_t)batch * n * n);
@@ -220,7 +239,7 @@ void device_factors(HostPlan &hp, rocblas_handle h) {
             green_batched(dX, m, dY, nc, {0.0, 0.0, 0.0}, k, G.as<double2>());
             std::vector<double> S;
             std::vector<cplx> U, Vh;
-            svd_batched(h, G.as<double2>(), m, nc, 1, S, U, Vh);
+            svd_batched(h, hp.opt.svd_method, G.as<double2>(), m, nc, 1, S, U, Vh);
             int r = trunc_rank(S.data(), nc, hp.svd_eps);
             lv.cube = cube;
             if ((double)r <= kSat * nc || p >= 14) break;
@@ -240,7 +259,7 @@ void device_factors(HostPlan &hp, rocblas_handle h) {
         }
         std::vector<double> S;
         std::vector<cplx> U, Vh;
-        svd_batched(h, G.as<double2>(), m, nc, lv.nslot, S, U, Vh);
+        svd_batched(h, hp.opt.svd_method, G.as<double2>(), m, nc, lv.nslot, S, U, Vh);
         lv.Uu.assign(lv.nslot, Mat());
         lv.Vu.assign(lv.nslot, Mat());
         lv.Ud.assign(lv.nslot, Mat());
@@ -425,12 +444,10 @@ void device_lowrank_m2l(const HostPlan &hp, rocblas_handle h, DevTranslations &o
             dU(sizeof(double2) * (size_t)kd * mn * noff), dV(sizeof(double2) * (size_t)mn * ku * noff),
             dE(sizeof(double) * (size_t)mn * noff), dinfo(sizeof(rocblas_int) * noff);
         hchk(hipMemcpy(A.p, out.K[l], sizeof(double2) * ksz * noff, hipMemcpyDeviceToDevice), "copy K");
-        rchk(rocsolver_zgesvd_strided_batched(h, rocblas_svect_singular, rocblas_svect_singular, kd, ku,
-                                              A.as<rocblas_double_complex>(), kd, (rocblas_stride)ksz, dS.as<double>(),
-                                              mn, dU.as<rocblas_double_complex>(), kd, (rocblas_stride)kd * mn,
-                                              dV.as<rocblas_double_complex>(), mn, (rocblas_stride)mn * ku,
-                                              dE.as<double>(), mn, rocblas_outofplace, dinfo.as<rocblas_int>(), noff),
-             "zgesvd (M2L)");
+        batched_svd(h, hp.opt.svd_method, kd, ku, A.as<rocblas_double_complex>(), kd, (rocblas_stride)ksz,
+                    dS.as<double>(), mn, dU.as<rocblas_double_complex>(), kd, (rocblas_stride)kd * mn,
+                    dV.as<rocblas_double_complex>(), mn, (rocblas_stride)mn * ku, dE.as<double>(),
+                    dinfo.as<rocblas_int>(), noff, "zgesvd (M2L)");
         std::vector<double> S((size_t)mn * noff);
         std::vector<rocblas_int> info(noff);
         hchk(hipMemcpy(S.data(), dS.p, sizeof(double) * S.size(), hipMemcpyDeviceToHost), "d2h");

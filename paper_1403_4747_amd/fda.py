@@ -41,7 +41,7 @@ class Options(ctypes.Structure):
         ("svd_eps", ctypes.c_double), ("alpha_re", ctypes.c_double), ("alpha_im", ctypes.c_double),
         ("hf_wavelengths", ctypes.c_double), ("rho_c", ctypes.c_double), ("leaf_min_h", ctypes.c_double),
         ("prec", ctypes.c_int32), ("nrhs_max", ctypes.c_int32), ("device", ctypes.c_int32),
-        ("verbose", ctypes.c_int32),
+        ("verbose", ctypes.c_int32), ("svd_method", ctypes.c_int32),
     ]
 
 
@@ -56,6 +56,7 @@ class Stats(ctypes.Structure):
         ("m2l_level_flops", ctypes.c_double * 24), ("m2l_flops", ctypes.c_int64), ("m2l_bytes", ctypes.c_int64), ("h_max", ctypes.c_double),
         ("root_width", ctypes.c_double), ("build_seconds", ctypes.c_double), ("device_bytes", ctypes.c_int64),
         ("m2m_flops", ctypes.c_double), ("l2l_flops", ctypes.c_double), ("mlp_rows", ctypes.c_int64),
+        ("build_phase_seconds", ctypes.c_double * 8),
     ]
 
     def to_dict(self) -> Dict:
@@ -64,7 +65,7 @@ class Stats(ctypes.Structure):
         for name, _ in self._fields_:
             v = getattr(self, name)
             if isinstance(v, ctypes.Array):
-                v = list(v)[: L + 1]
+                v = list(v) if name == "build_phase_seconds" else list(v)[: L + 1]
             d[name] = v
         return d
 
