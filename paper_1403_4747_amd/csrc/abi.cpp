@@ -369,11 +369,20 @@ void upload_plan(fda_plan *p, const HostOps &ops, DevTranslations &tr) {
                     int sl = lv.hf ? lv.slot_of_dir[lv.offset_dir[op]] : 0;
                     by_op[op].push_back({(int32_t)(lv.il[b][q] * lv.nslot + sl), (int32_t)(b * lv.nslot + sl)});
                 }
+            // the low-rank kernel holds at most 8 phase-1 tiles per item:
+            // translations of padded rank above 64 get 16-column items
+            std::vector<int32_t> prank(no, 0);
+            if (dl.rmax > 0)
+                for (size_t op = 0; op < no; ++op) {
+                    const int rt = tr.true_rank[l][op];
+                    prank[op] = std::min(std::min(lv.kd, lv.ku), (rt + 3) / 4 * 4);
+                }
             GWorkHost g;
             for (size_t op = 0; op < no; ++op) {
                 const auto &v = by_op[op];
-                for (size_t q0 = 0; q0 < v.size(); q0 += kGemmCols) {
-                    size_t q1 = std::min(v.size(), q0 + kGemmCols);
+                const size_t step = prank[op] > 64 ? 16 : kGemmCols;
+                for (size_t q0 = 0; q0 < v.size(); q0 += step) {
+                    size_t q1 = std::min(v.size(), q0 + step);
                     std::vector<int32_t> srcs, dsts;
                     for (size_t q = q0; q < q1; ++q) {
                         srcs.push_back(v[q].first);

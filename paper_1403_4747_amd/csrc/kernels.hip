@@ -319,20 +319,24 @@ __device__ __forceinline__ void load_states(C (*S)[GG_LD], const C *Xr, const in
     }
 }
 
-// Complex accumulator of one 16 x 16 output tile on the matrix cores.
-// With FDA_GAUSS3M (default) a complex multiply-add takes three real
-// products (Gauss): P1 = Ar Br, P2 = Ai Bi, P3 = (Ar + Ai)(Br + Bi), then
-// Re = P1 - P2 and Im = P3 - P1 - P2; otherwise four (Re += Ar Br - Ai Bi,
-// Im += Ar Bi + Ai Br).  The three / four products go to independent
-// accumulators, so consecutive MFMAs never wait on each other.
-#ifndef FDA_GAUSS3M
-#define FDA_GAUSS3M 1
+// Complex accumulator of one 16 x 16 output tile on the matrix cores.  The
+// three-product form (Gauss) takes P1 = Ar Br, P2 = Ai Bi,
+// P3 = (Ar + Ai)(Br + Bi), then Re = P1 - P2 and Im = P3 - P1 - P2; the
+// four-product form Re += Ar Br - Ai Bi, Im += Ar Bi + Ai Br needs a third
+// fewer accumulator registers.  Independent accumulators keep consecutive
+// MFMAs from waiting on each other.
+#ifndef FDA_GEMM_3M
+#define FDA_GEMM_3M 1  // k_ggemm (M2M, L2L, full-rank M2L)
 #endif
+#ifndef FDA_M2L_3M
+#define FDA_M2L_3M 1  // k_m2l_lowrank (3 waves per SIMD in FP64, 4 in FP32)
+#endif
+template <class C, bool G3>
+struct CAcc;
 template <class C>
-struct CAcc {
+struct CAcc<C, true> {
     using v4 = typename CT<C>::v4;
     using R = typename CT<C>::R;
-#if FDA_GAUSS3M
     v4 p1, p2, p3;
     __device__ __forceinline__ void zero() {
         p1 = (v4){0, 0, 0, 0};
@@ -346,7 +350,11 @@ struct CAcc {
     }
     __device__ __forceinline__ R re(int v) const { return p1[v] - p2[v]; }
     __device__ __forceinline__ R im(int v) const { return p3[v] - p1[v] - p2[v]; }
-#else
+};
+template <class C>
+struct CAcc<C, false> {
+    using v4 = typename CT<C>::v4;
+    using R = typename CT<C>::R;
     v4 r, i;
     __device__ __forceinline__ void zero() {
         r = (v4){0, 0, 0, 0};
@@ -360,7 +368,6 @@ struct CAcc {
     }
     __device__ __forceinline__ R re(int v) const { return r[v]; }
     __device__ __forceinline__ R im(int v) const { return i[v]; }
-#endif
 };
 
 // A fragments of the wave's row tiles rt = wave + 4 q at k-column kcol of a
@@ -386,7 +393,7 @@ __device__ __forceinline__ void ggemm_body(const int4 h, const int32_t *sidx, co
     const int li = lane & 15, lk = lane >> 4;
     for (int band = 0; band < m; band += 64 * GG_RT) {
         const int ntile = min(GG_RT * 4, (m - band + 15) >> 4);
-        CAcc<C> acc[GG_RT][NCT];
+        CAcc<C, FDA_GEMM_3M> acc[GG_RT][NCT];
 #pragma unroll
         for (int q = 0; q < GG_RT; ++q)
 #pragma unroll
@@ -439,7 +446,15 @@ __device__ __forceinline__ void ggemm_body(const int4 h, const int32_t *sidx, co
 // registers per complex accumulator than FP32.
 template <class C>
 struct GemmOcc {
-    static constexpr int waves = FDA_GAUSS3M ? 3 : 4;
+    static constexpr int waves = FDA_GEMM_3M ? 3 : 4;
+};
+template <class C>
+struct M2LOcc {
+    static constexpr int waves = FDA_M2L_3M ? 3 : 4;
+};
+template <>
+struct M2LOcc<float2> {
+    static constexpr int waves = 4;
 };
 template <>
 struct GemmOcc<float2> {
@@ -484,7 +499,7 @@ __device__ __forceinline__ void m2l_body(const int4 h, const int32_t *sidx, cons
     // chunk of gathered states, so the MFMA loop reads only LDS.
     const int ztiles = (r + 15) >> 4;
     const int ntz = ztiles * NCT;
-    constexpr int ZQ = 3;  // ceil(5 row tiles * 2 column tiles / 4 waves)
+    constexpr int ZQ = 2;  // tiles per wave: ntz <= 8 (the host gives ranks above 64 16-column items)
     // With fewer than 4 output tiles the waves also split the k-steps
     // (kg_n groups; wave = kg * ntz + tile) and the partial products are
     // summed in LDS afterwards.
@@ -492,14 +507,14 @@ __device__ __forceinline__ void m2l_body(const int4 h, const int32_t *sidx, cons
     const int kg = kg_n > 1 ? wave / ntz : 0;
     const int tbase = kg_n > 1 ? wave % ntz : wave;
     const int tstep = kg_n > 1 ? 64 : 4;  // kg_n > 1: one tile per wave
-    CAcc<C> zacc[ZQ];
+    CAcc<C, FDA_M2L_3M> zacc[ZQ];
 #pragma unroll
     for (int q = 0; q < ZQ; ++q) zacc[q].zero();
     // the next chunk is fetched into registers while the current one is
     // multiplied out of LDS (the MFMA loop issues no global loads, so these
     // loads are waited for only when they are committed to LDS)
     constexpr int SPT = LRJ * GG_NB / 256;
-    constexpr int VPT = (LR_MAX * LRJ + 255) / 256;
+    constexpr int VPT = 64 * LRJ / 256;  // ranks up to 64 prefetched; rows 64.. read at commit
     C sreg[SPT], vreg[VPT];
     auto fetch = [&](int j0) {
 #pragma unroll
@@ -533,6 +548,12 @@ __device__ __forceinline__ void m2l_body(const int4 h, const int32_t *sidx, cons
         for (int i = 0; i < VPT; ++i) {
             const int e = threadIdx.x + 256 * i;
             if (e < r * LRJ) Vs[e / r][e % r] = vreg[i];
+        }
+        for (int e = threadIdx.x + 256 * VPT; e < r * LRJ; e += 256) {
+            const int row = e % r, kc = e / r;
+            C v = czero<C>();
+            if (j0 + kc < ku) v = Vt[row + (int64_t)(j0 + kc) * rmax];
+            Vs[kc][row] = v;
         }
         __syncthreads();
         if (j0 + LRJ < ku) fetch(j0 + LRJ);
@@ -587,7 +608,7 @@ __device__ __forceinline__ void m2l_body(const int4 h, const int32_t *sidx, cons
     for (int pass = 0; pass < MF_RT / P2; ++pass) {
         const int rt0 = wave + 4 * P2 * pass;  // this pass: row tiles rt0, rt0 + 4
         if (rt0 >= ntile) break;
-        CAcc<C> acc[P2][NCT];
+        CAcc<C, FDA_M2L_3M> acc[P2][NCT];
 #pragma unroll
         for (int q = 0; q < P2; ++q)
 #pragma unroll
@@ -634,7 +655,7 @@ __device__ __forceinline__ void m2l_body(const int4 h, const int32_t *sidx, cons
 // One launch for the low-rank M2L of every level: the item's level slot
 // (h.w) selects its factors, states and scratch region.
 template <class C>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GemmOcc<C>::waves)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M2LOcc<C>::waves)))
 k_m2l_lowrank(const int4 *hdr, const int32_t *src, const M2LLevelArgs *args, C *T, int64_t tstride, int nwork) {
     // LDS: phase 1 stages S (LRJ x GG_LD) and V^ (LRJ x LR_LD); phase 2
     // reuses the same bytes for Z (LR_MAX x GG_LD) once phase 1 is done

@@ -20,7 +20,9 @@ __all__ = ["Plan", "Mlp", "inspect", "library", "default_options", "FDAError", "
            "MLP_OUT"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SO = os.path.join(_HERE, "libfda.so")
+# FDA_LIBRARY may name another build of the same library (e.g. a variant
+# compiled with different kernel options); the default is the in-tree build.
+_SO = os.environ.get("FDA_LIBRARY") or os.path.join(_HERE, "libfda.so")
 
 PREC = {"fp64": 0, "fp32": 1}
 PRECOND = {"none": 0, "block_jacobi": 1, "mlp": 2}
