@@ -296,6 +296,14 @@ void host_setup(const double *V, int64_t nv, const int32_t *T, int64_t nt, doubl
         hp.max_leaf_count = 0;
         for (int64_t q = 0; q < lf.nbox; ++q)
             hp.max_leaf_count = std::max<int>(hp.max_leaf_count, (int)(hp.leaf_off[q + 1] - hp.leaf_off[q]));
+        // leaves wider than leaf_min_h * h_max may hold more elements than
+        // max_leaf on strongly graded meshes; the leaf kernels (block-Jacobi
+        // inversion, near-field rows) hold one leaf in a workgroup
+        if (hp.max_leaf_count > 256)
+            throw BuildError{FDA_EMESH, "a leaf holds " + std::to_string(hp.max_leaf_count) +
+                                            " elements (> 256): the mesh is too strongly graded for leaves at least "
+                                            "leaf_min_h largest edges wide; lower leaf_min_h or refine the large "
+                                            "triangles"};
     }
     hp.tri.resize(9 * nt);
     hp.cen.resize(3 * nt);

@@ -113,3 +113,28 @@ def test_product_path_has_no_oracle_import():
             if f.endswith((".py", ".cpp", ".hip", ".hpp", ".h")):
                 txt = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in txt and "from oracle" not in txt and "bem_oracle" not in txt, f
+
+
+def test_inspect_rejects_leaves_above_256_elements():
+    """A strongly graded mesh (one large triangle beside 400 tiny ones) would
+    need leaves wider than 2.5 largest edges holding > 256 elements: the
+    build refuses it instead of overflowing the per-leaf kernels."""
+    from paper_1403_4747_amd import inspect, FDAError
+
+    rng = np.random.default_rng(0)
+    V, T = [], []
+    for i in range(400):  # tiny triangles scattered in a 0.05 cube
+        c = rng.uniform(0.0, 0.05, size=3)
+        base = len(V)
+        V += [c, c + [1e-3, 0, 0], c + [0, 1e-3, 0]]
+        T.append([base, base + 1, base + 2])
+    base = len(V)
+    V += [[0.0, 0.0, 1.0], [1.0, 0.0, 1.0], [0.0, 1.0, 1.0]]
+    T.append([base, base + 1, base + 2])
+    V, T = np.array(V), np.array(T, dtype=np.int32)
+    with pytest.raises(FDAError) as e:
+        inspect(V, T, 5.0, 1e-4)
+    assert e.value.code == -2 and "256" in str(e.value)
+    # with narrow leaves allowed the same mesh builds
+    st = inspect(V, T, 5.0, 1e-4, leaf_min_h=0.01)
+    assert st["max_leaf_count"] <= 64
