@@ -67,6 +67,7 @@ extern "C" {
 
 typedef struct fda_plan fda_plan;
 typedef struct fda_mlp fda_mlp;
+typedef struct fda_batch fda_batch;
 
 /* Build options.  Zero-initialise and call fda_default_options(), then
  * override fields.  Every field has a documented default. */
@@ -272,6 +273,30 @@ int fda_plan_leaves(const fda_plan *plan, int32_t *perm, int64_t n, int64_t *lea
 /* Attach a network to a plan for FDA_PRECOND_MLP (NULL detaches).  The plan
  * borrows it: it must outlive its use in bm_solve. */
 int fda_plan_set_mlp(fda_plan *plan, fda_mlp *mlp);
+
+/* ---------------------------------------------------------------------------
+ * Many meshes at once.  A batch is one HIP graph that applies A_i x_i = y_i
+ * (fda_matvec) for a set of built plans of any sizes and wavenumbers; the
+ * plans run on up to 16 concurrent branches, so small meshes fill the GPU
+ * together and the whole batch costs one launch.  The graph is captured
+ * once with fixed buffers; the caller refills x_devs between launches.
+ * ------------------------------------------------------------------------- */
+
+/* Capture the batch: plans[i] (distinct, same device), x_devs[i] / y_devs[i]
+ * device buffers of N_i x nrhs[i] complex128 (leading dimension N_i).  The
+ * plans' work buffers are sized here (nothing allocates inside the graph);
+ * while the batch exists, the plans must not run concurrently with it.
+ * Errors: FDA_EINVAL, FDA_ENOMEM, FDA_EHIP; *out is NULL on error. */
+int fda_batch_create(fda_plan *const *plans, int32_t nplans, const void *const *x_devs, void *const *y_devs,
+                     const int64_t *nrhs, fda_batch **out);
+
+/* Launch the captured products on `stream` (asynchronous).  Errors:
+ * FDA_EINVAL, FDA_EHIP. */
+int fda_batch_launch(fda_batch *batch, void *stream);
+
+/* Release a batch (waits for the device; NULL is allowed).  Plans and
+ * buffers are not touched. */
+void fda_batch_free(fda_batch *batch);
 
 /* Statistics of a built plan. */
 int fda_plan_stats(const fda_plan *plan, fda_stats *st);

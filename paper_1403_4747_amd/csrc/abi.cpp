@@ -1253,4 +1253,114 @@ int fda_plan_set_mlp(fda_plan *plan, fda_mlp *mlp) {
     return FDA_OK;
 }
 
+
+// ------------------------------------------------------------ many meshes in one graph
+
+struct fda_batch {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<hipStream_t> streams;
+    std::vector<hipEvent_t> events;
+    int device = 0;
+    int nplans = 0;
+};
+
+static void batch_release(fda_batch *b) {
+    if (!b) return;
+    if (b->exec) hipGraphExecDestroy(b->exec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    for (auto e : b->events) hipEventDestroy(e);
+    for (auto s : b->streams) hipStreamDestroy(s);
+    delete b;
+}
+
+int fda_batch_create(fda_plan *const *plans, int32_t nplans, const void *const *x_devs, void *const *y_devs,
+                     const int64_t *nrhs, fda_batch **out) {
+    g_last_error.clear();
+    if (!out) return fail(FDA_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!plans || !x_devs || !y_devs || !nrhs || nplans < 1 || nplans > 4096)
+        return fail(FDA_EINVAL, "bad plans / buffers / nplans");
+    const int dev = plans[0] ? plans[0]->device : 0;
+    for (int i = 0; i < nplans; ++i) {
+        if (!plans[i] || !x_devs[i] || !y_devs[i]) return fail(FDA_EINVAL, "NULL plan or buffer");
+        if (plans[i]->device != dev) return fail(FDA_EINVAL, "plans on different devices");
+        if (nrhs[i] < 1 || nrhs[i] > plans[i]->hp.opt.nrhs_max) return fail(FDA_EINVAL, "nrhs out of range");
+        for (int j = 0; j < i; ++j)
+            if (plans[j] == plans[i]) return fail(FDA_EINVAL, "a plan appears twice (its work buffers are shared)");
+    }
+    fda_batch *b = new fda_batch();
+    b->device = dev;
+    b->nplans = nplans;
+    hipStream_t s0 = nullptr;
+    bool capturing = false;
+    try {
+        hip_check(hipSetDevice(dev), "hipSetDevice");
+        // work buffers are allocated before capture (nothing allocates inside the graph)
+        for (int i = 0; i < nplans; ++i) ensure_capacity(plans[i], (int)nrhs[i]);
+        hip_check(hipDeviceSynchronize(), "sync");
+        const int nstream = std::min(nplans, 16);
+        b->streams.resize(nstream + 1, nullptr);
+        for (auto &s : b->streams) hip_check(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "stream");
+        b->events.resize(nstream + 1, nullptr);
+        for (auto &e : b->events) hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
+        s0 = b->streams[0];
+        hip_check(hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal), "begin capture");
+        capturing = true;
+        hip_check(hipEventRecord(b->events[0], s0), "fork");
+        for (int q = 1; q <= nstream; ++q) hip_check(hipStreamWaitEvent(b->streams[q], b->events[0], 0), "fork wait");
+        // plans go round-robin to the branch streams; each branch runs its
+        // plans one after another, the branches run concurrently
+        for (int i = 0; i < nplans; ++i) {
+            fda_plan *p = plans[i];
+            hipStream_t st = b->streams[1 + i % nstream];
+            const int nr = (int)nrhs[i];
+            hip_check(launch_permute_in(p->d, (const double2 *)x_devs[i], p->d.n, p->xt, nr, st), "permute");
+            hip_check(launch_matvec_tree(p->d, p->xt, p->yt, nr, st, nullptr, nullptr), "matvec");
+            hip_check(launch_permute_out(p->d, p->yt, (double2 *)y_devs[i], p->d.n, nr, st), "permute");
+        }
+        for (int q = 1; q <= nstream; ++q) {
+            hip_check(hipEventRecord(b->events[q], b->streams[q]), "join");
+            hip_check(hipStreamWaitEvent(s0, b->events[q], 0), "join wait");
+        }
+        capturing = false;
+        hip_check(hipStreamEndCapture(s0, &b->graph), "end capture");
+        hip_check(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "instantiate");
+    } catch (const BuildError &e) {
+        if (capturing) {
+            hipGraph_t g = nullptr;
+            hipStreamEndCapture(s0, &g);
+            if (g) hipGraphDestroy(g);
+        }
+        batch_release(b);
+        return fail(e.code, e.msg);
+    } catch (const HipError &e) {
+        if (capturing) {
+            hipGraph_t g = nullptr;
+            hipStreamEndCapture(s0, &g);
+            if (g) hipGraphDestroy(g);
+        }
+        batch_release(b);
+        return fail(FDA_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
+    }
+    *out = b;
+    return FDA_OK;
+}
+
+int fda_batch_launch(fda_batch *batch, void *stream) {
+    g_last_error.clear();
+    if (!batch || !batch->exec) return fail(FDA_EINVAL, "NULL batch");
+    hipError_t e = hipSetDevice(batch->device);
+    if (e == hipSuccess) e = hipGraphLaunch(batch->exec, as_stream(stream));
+    if (e != hipSuccess) return fail(FDA_EHIP, std::string("graph launch: ") + hipGetErrorString(e));
+    return FDA_OK;
+}
+
+void fda_batch_free(fda_batch *batch) {
+    if (!batch) return;
+    hipSetDevice(batch->device);
+    hipDeviceSynchronize();
+    batch_release(batch);
+}
+
 }  // extern "C"

@@ -16,7 +16,7 @@ from typing import Dict, Optional, Sequence
 
 import numpy as np
 
-__all__ = ["Plan", "Mlp", "inspect", "library", "default_options", "FDAError", "PRECOND", "PREC", "MLP_IN",
+__all__ = ["Plan", "Mlp", "Batch", "inspect", "library", "default_options", "FDAError", "PRECOND", "PREC", "MLP_IN",
            "MLP_OUT"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -139,6 +139,11 @@ def library():
         L.fda_mlp_samples.restype = ctypes.c_int
         L.fda_plan_leaves.argtypes = [vp, vp, i64, vp, i64]
         L.fda_plan_leaves.restype = ctypes.c_int
+        L.fda_batch_create.argtypes = [vp, ctypes.c_int32, vp, vp, vp, ctypes.POINTER(vp)]
+        L.fda_batch_create.restype = ctypes.c_int
+        L.fda_batch_launch.argtypes = [vp, vp]
+        L.fda_batch_launch.restype = ctypes.c_int
+        L.fda_batch_free.argtypes = [vp]
         L.fda_plan_set_mlp.argtypes = [vp, vp]
         L.fda_plan_set_mlp.restype = ctypes.c_int
         L.fda_last_error.restype = ctypes.c_char_p
@@ -413,3 +418,42 @@ class Mlp:
         _err(library().fda_mlp_train(self._h, X.data_ptr(), T.data_ptr(), M.data_ptr(), rows, int(epochs), int(batch),
                                      float(lr), int(seed), losses.ctypes.data, _stream()))
         return losses
+
+
+class Batch:
+    """Products of several plans (different meshes and wavenumbers) captured
+    in one HIP graph (fda_batch_*).  xs[i], ys[i]: complex128 device tensors
+    of shape (N_i,) or (nrhs_i, N_i), fixed for the life of the batch."""
+
+    def __init__(self, plans: Sequence[Plan], xs, ys):
+        if not (len(plans) == len(xs) == len(ys)) or not plans:
+            raise ValueError("plans, xs and ys must have the same nonzero length")
+        nr = []
+        for p, x, y in zip(plans, xs, ys):
+            a = p._check_vec(x, p.n)
+            if p._check_vec(y, p.n) != a:
+                raise ValueError("x and y differ in columns")
+            nr.append(a)
+        n = len(plans)
+        self._keep = (list(plans), list(xs), list(ys))
+        ph = (ctypes.c_void_p * n)(*[p._h.value for p in plans])
+        xh = (ctypes.c_void_p * n)(*[x.data_ptr() for x in xs])
+        yh = (ctypes.c_void_p * n)(*[y.data_ptr() for y in ys])
+        nh = (ctypes.c_int64 * n)(*nr)
+        h = ctypes.c_void_p()
+        _err(library().fda_batch_create(ph, n, xh, yh, nh, ctypes.byref(h)))
+        self._h = h
+
+    def launch(self):
+        _err(library().fda_batch_launch(self._h, _stream()))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            library().fda_batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
