@@ -65,6 +65,64 @@ def cpu_baseline(V, T, k, x, y_gpu, rows_sample, seconds_target=20.0):
                 seconds_per_matvec=full), err, rows, yr
 
 
+def uneven_batch_leg(nmesh, steps, log):
+    """The seeded uneven batch (spheres and ellipsoids, N 5,120-81,920,
+    kD 20-100): every plan's product run one after another on one stream,
+    against all of them in one captured graph (fda_batch)."""
+    import torch
+
+    import workloads as W
+    from paper_1403_4747_amd import Batch, FDAError, Plan
+
+    plans, xs, ys, skipped, nel = [], [], [], [], 0
+    t0 = time.perf_counter()
+    for i, (V, T, k, info) in enumerate(W.uneven_batch(nmesh)):
+        try:
+            p = Plan(V, T, k, 1e-4)
+        except FDAError as e:  # e.g. leaves that would need directional (high-frequency) handling
+            skipped.append(dict(info, error=str(e)[:120]))
+            continue
+        plans.append(p)
+        log(f"[bench] batch mesh {i}: N={len(T)} kD={info['kD']:.1f} built ({time.perf_counter() - t0:.1f} s)")
+        xs.append(torch.from_numpy(W.complex_normal(len(T), 1, seed=100 + i)).to("cuda"))
+        ys.append(torch.empty_like(xs[-1]))
+        nel += len(T)
+    build_s = time.perf_counter() - t0
+    for p, x, y in zip(plans, xs, ys):
+        p.matvec(x, out=y)
+    torch.cuda.synchronize()
+    reps = max(3, steps // 10)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        for p, x, y in zip(plans, xs, ys):
+            p.matvec(x, out=y)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    seq_ms = e0.elapsed_time(e1) / reps
+    want = [y.clone() for y in ys]
+    b = Batch(plans, xs, ys)
+    b.launch()
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        b.launch()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    gr_ms = e0.elapsed_time(e1) / reps
+    same = all(torch.equal(a, c) for a, c in zip(want, ys))
+    b.close()
+    for p in plans:
+        p.close()
+    out = dict(meshes=len(plans), skipped=len(skipped), elements=nel, build_seconds=round(build_s, 2),
+               sequential_ms=round(seq_ms, 3), graph_ms=round(gr_ms, 3),
+               batches_per_s=round(1000.0 / gr_ms, 3), graph_equals_sequential=bool(same),
+               skipped_cases=skipped[:4])
+    log(f"[bench] uneven batch: {out}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,6 +136,8 @@ def main():
                     help="also run one plain device copy of this many MiB (calibrates HBM counters)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--nrhs-multi", type=int, default=64, help="also time products of this many columns (0: skip)")
+    ap.add_argument("--batch", type=int, default=0,
+                    help="also time the uneven multi-mesh batch of this many meshes in one graph (0: skip)")
     ap.add_argument("--mlp-weights", default=os.path.join(ROOT, "paper_1403_4747_amd", "weights",
                                                           "mlp_ellipsoid_s5_h256.npz"),
                     help="trained learned-preconditioner weights for the fast arm's solve")
@@ -263,6 +323,10 @@ def main():
         plan32.close()
         log("[bench] fast arm: " + str({q: v for q, v in fast.items() if q != 'y32'}))
 
+    batch = {}
+    if args.batch > 0:
+        batch = uneven_batch_leg(args.batch, args.steps, log)
+
     cpu, err = (None, None)
     if not args.no_cpu:
         cpu, err, rows, yr = cpu_baseline(V, T, k, W.complex_normal(n, 1, seed=0), y_np, 32768, args.cpu_seconds)
@@ -294,6 +358,7 @@ def main():
         "time_to_1e-5_s": solve.get("none", {}).get("seconds"),
         "build_plus_solve_s": round(build_s + solve["none"]["seconds"], 3) if "none" in solve else None,
         "multi_rhs": multi or None,
+        "uneven_batch": batch or None,
         "solve": solve,
         "matvec_rel_err_vs_oracle_sampled": err,
         "fast_arm_fp32": fast or None,

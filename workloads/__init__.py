@@ -26,6 +26,7 @@ __all__ = [
     "ellipsoid",
     "fibonacci_directions",
     "complex_normal",
+    "uneven_batch",
     "orient_outward",
     "workload",
     "WORKLOADS",
@@ -151,6 +152,28 @@ WORKLOADS = {
     "sphere20480_kD50": dict(subdiv=5, radius=0.5, k=50.0, eps=1e-4, direction=(0.0, 0.0, 1.0)),
     "sphere20480_kD100": dict(subdiv=5, radius=0.5, k=100.0, eps=1e-4, direction=(0.0, 0.0, 1.0)),
 }
+
+
+def uneven_batch(n: int = 32, seed: int = 3, subdivs=(4, 5, 6)):
+    """Seeded uneven multi-mesh batch: n meshes, the first half spheres of
+    radius 0.5, the second half ellipsoids with semi-axes U[0.3, 0.7];
+    subdivision uniform in `subdivs` (5,120 / 20,480 / 81,920 triangles),
+    kD uniform in [20, 100] with D = 2 x the largest semi-axis.  Returns a
+    list of (V, T, k, info)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        s = int(rng.choice(subdivs))
+        if i < n // 2:
+            axes = np.array([0.5, 0.5, 0.5])
+            V, T = icosphere(s, 0.5)
+        else:
+            axes = rng.uniform(0.3, 0.7, size=3)
+            V, T = ellipsoid(s, tuple(axes))
+        kD = float(rng.uniform(20.0, 100.0))
+        k = kD / (2.0 * float(axes.max()))
+        out.append((V, T, k, dict(subdiv=s, semi_axes=axes.tolist(), kD=kD, n=len(T))))
+    return out
 
 
 def workload(name: str):
