@@ -699,8 +699,22 @@ __global__ void k_gather_reduce_m2l(const int32_t *dst, const int32_t *off, cons
     C *out = (C *)la.Y + (int64_t)blockIdx.y * la.ystride + (int64_t)dst[t] * m;
     const int q0 = off[t], q1 = off[t + 1];
     for (int r = threadIdx.x; r < m; r += blockDim.x) {
+        // four independent loads in flight per step; the sum keeps list order
         C acc = czero<C>();
-        for (int q = q0; q < q1; ++q) {
+        int q = q0;
+        for (; q + 4 <= q1; q += 4) {
+            const C v0 = Tr[(int64_t)list[q] * m + r], v1 = Tr[(int64_t)list[q + 1] * m + r];
+            const C v2 = Tr[(int64_t)list[q + 2] * m + r], v3 = Tr[(int64_t)list[q + 3] * m + r];
+            acc.x += v0.x;
+            acc.y += v0.y;
+            acc.x += v1.x;
+            acc.y += v1.y;
+            acc.x += v2.x;
+            acc.y += v2.y;
+            acc.x += v3.x;
+            acc.y += v3.y;
+        }
+        for (; q < q1; ++q) {
             const C v = Tr[(int64_t)list[q] * m + r];
             acc.x += v.x;
             acc.y += v.y;
