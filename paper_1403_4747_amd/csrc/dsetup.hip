@@ -426,6 +426,66 @@ __global__ void k_pack_lowrank(const double2 *U, const double *S, const double2 
     }
 }
 
+// Truncated SVD factors of `count` column-major m x n matrices (stride m*n):
+// A = U^ V^ with U^ = U[:, :r] (m x rmax) and V^ = diag(s[:r]) V^H[:r, :]
+// (rmax x n), r the number of singular values >= svd_eps * s_0, padded to a
+// multiple of 4.  rmax = 0 (nothing kept) when some rank exceeds max_rank or
+// 2 r >= min(m, n) (the factors would not pay; Section 4.2).
+LowRank factor_batch(const HostPlan &hp, rocblas_handle h, const double2 *mats, int m, int n, int count,
+                     int max_rank, DevTranslations &out, const char *what) {
+    LowRank lr;
+    const int mn = std::min(m, n);
+    const size_t msz = (size_t)m * n;
+    DBuf A(sizeof(double2) * msz * count), dS(sizeof(double) * (size_t)mn * count),
+        dU(sizeof(double2) * (size_t)m * mn * count), dV(sizeof(double2) * (size_t)mn * n * count),
+        dE(sizeof(double) * (size_t)mn * count), dinfo(sizeof(rocblas_int) * count);
+    hchk(hipMemcpy(A.p, mats, sizeof(double2) * msz * count, hipMemcpyDeviceToDevice), "copy");
+    batched_svd(h, hp.opt.svd_method, m, n, A.as<rocblas_double_complex>(), m, (rocblas_stride)msz, dS.as<double>(),
+                mn, dU.as<rocblas_double_complex>(), m, (rocblas_stride)m * mn, dV.as<rocblas_double_complex>(), mn,
+                (rocblas_stride)mn * n, dE.as<double>(), dinfo.as<rocblas_int>(), count, what);
+    std::vector<double> S((size_t)mn * count);
+    std::vector<rocblas_int> info(count);
+    hchk(hipMemcpy(S.data(), dS.p, sizeof(double) * S.size(), hipMemcpyDeviceToHost), "d2h");
+    hchk(hipMemcpy(info.data(), dinfo.p, sizeof(rocblas_int) * count, hipMemcpyDeviceToHost), "d2h");
+    std::vector<int32_t> rank(count);
+    lr.rtrue.assign(count, 0);
+    int rmax = 0, rtmax = 0;
+    double rsum = 0;
+    for (int o = 0; o < count; ++o) {
+        if (info[o] != 0) throw BuildError{FDA_EHIP, std::string("SVD did not converge: ") + what};
+        const double *so = S.data() + (size_t)o * mn;
+        int r = 0;
+        while (r < mn && so[r] >= hp.svd_eps * so[0] && so[0] > 0) ++r;
+        r = std::max(r, 1);
+        rsum += r;
+        lr.rtrue[o] = r;
+        rtmax = std::max(rtmax, r);
+        r = std::min(mn, (r + 3) / 4 * 4);
+        rank[o] = r;
+        rmax = std::max(rmax, r);
+    }
+    lr.mean = rsum / std::max(1, count);
+    lr.rtrue_max = rtmax;
+    if (rmax > max_rank || 2 * rmax >= mn) return lr;
+    auto keep = [&](size_t bytes) {
+        void *q = nullptr;
+        if (hipMalloc(&q, std::max<size_t>(bytes, 16)) != hipSuccess) throw BuildError{FDA_ENOMEM, "hipMalloc failed"};
+        out.allocs.push_back(q);
+        out.bytes += (int64_t)bytes;
+        return q;
+    };
+    lr.U = (double2 *)keep(sizeof(double2) * (size_t)m * rmax * count);
+    lr.V = (double2 *)keep(sizeof(double2) * (size_t)rmax * n * count);
+    lr.rank = (int32_t *)keep(sizeof(int32_t) * count);
+    hchk(hipMemcpy(lr.rank, rank.data(), sizeof(int32_t) * count, hipMemcpyHostToDevice), "h2d");
+    hipLaunchKernelGGL(k_pack_lowrank, dim3(64, count), dim3(256), 0, nullptr, dU.as<double2>(), dS.as<double>(),
+                       dV.as<double2>(), lr.rank, m, n, mn, rmax, lr.U, lr.V);
+    hchk(hipGetLastError(), "pack");
+    hchk(hipDeviceSynchronize(), "pack sync");
+    lr.rmax = rmax;
+    return lr;
+}
+
 void device_lowrank_m2l(const HostPlan &hp, rocblas_handle h, DevTranslations &out, int max_rank) {
     const int L = hp.depth;
     out.Ulr.assign(L + 1, nullptr);
@@ -438,60 +498,14 @@ void device_lowrank_m2l(const HostPlan &hp, rocblas_handle h, DevTranslations &o
         const Level &lv = hp.lv[l];
         const int noff = (int)lv.offsets.size();
         if (noff == 0) continue;
-        const int kd = lv.kd, ku = lv.ku, mn = std::min(kd, ku);
-        const size_t ksz = (size_t)kd * ku;
-        DBuf A(sizeof(double2) * ksz * noff), dS(sizeof(double) * (size_t)mn * noff),
-            dU(sizeof(double2) * (size_t)kd * mn * noff), dV(sizeof(double2) * (size_t)mn * ku * noff),
-            dE(sizeof(double) * (size_t)mn * noff), dinfo(sizeof(rocblas_int) * noff);
-        hchk(hipMemcpy(A.p, out.K[l], sizeof(double2) * ksz * noff, hipMemcpyDeviceToDevice), "copy K");
-        batched_svd(h, hp.opt.svd_method, kd, ku, A.as<rocblas_double_complex>(), kd, (rocblas_stride)ksz,
-                    dS.as<double>(), mn, dU.as<rocblas_double_complex>(), kd, (rocblas_stride)kd * mn,
-                    dV.as<rocblas_double_complex>(), mn, (rocblas_stride)mn * ku, dE.as<double>(),
-                    dinfo.as<rocblas_int>(), noff, "zgesvd (M2L)");
-        std::vector<double> S((size_t)mn * noff);
-        std::vector<rocblas_int> info(noff);
-        hchk(hipMemcpy(S.data(), dS.p, sizeof(double) * S.size(), hipMemcpyDeviceToHost), "d2h");
-        hchk(hipMemcpy(info.data(), dinfo.p, sizeof(rocblas_int) * noff, hipMemcpyDeviceToHost), "d2h");
-        std::vector<int32_t> rank(noff), rtrue(noff);
-        int rmax = 0;
-        double rsum = 0;
-        for (int o = 0; o < noff; ++o) {
-            if (info[o] != 0) throw BuildError{FDA_EHIP, "SVD of a reduced M2L matrix did not converge"};
-            const double *so = S.data() + (size_t)o * mn;
-            int r = 0;
-            while (r < mn && so[r] >= hp.svd_eps * so[0] && so[0] > 0) ++r;
-            r = std::max(r, 1);
-            rsum += r;
-            rtrue[o] = r;
-            r = std::min(mn, (r + 3) / 4 * 4);
-            rank[o] = r;
-            rmax = std::max(rmax, r);
-        }
-        out.mean_rank[l] = rsum / noff;
-        // low rank pays when 2 r < k (Section 4.2); kernel limit max_rank
-        if (rmax > max_rank || 2 * rmax >= mn) continue;
-        out.true_rank[l] = rtrue;
-        double2 *Ulr = nullptr, *Vlr = nullptr;
-        int32_t *dr = nullptr;
-        auto keep = [&](size_t bytes) {
-            void *q = nullptr;
-            if (hipMalloc(&q, std::max<size_t>(bytes, 16)) != hipSuccess) throw BuildError{FDA_ENOMEM, "hipMalloc failed"};
-            out.allocs.push_back(q);
-            out.bytes += (int64_t)bytes;
-            return q;
-        };
-        Ulr = (double2 *)keep(sizeof(double2) * (size_t)kd * rmax * noff);
-        Vlr = (double2 *)keep(sizeof(double2) * (size_t)rmax * ku * noff);
-        dr = (int32_t *)keep(sizeof(int32_t) * noff);
-        hchk(hipMemcpy(dr, rank.data(), sizeof(int32_t) * noff, hipMemcpyHostToDevice), "h2d");
-        hipLaunchKernelGGL(k_pack_lowrank, dim3(64, noff), dim3(256), 0, nullptr, dU.as<double2>(), dS.as<double>(),
-                           dV.as<double2>(), dr, kd, ku, mn, rmax, Ulr, Vlr);
-        hchk(hipGetLastError(), "pack");
-        hchk(hipDeviceSynchronize(), "pack sync");
-        out.Ulr[l] = Ulr;
-        out.Vlr[l] = Vlr;
-        out.lr_rank[l] = dr;
-        out.rmax[l] = rmax;
+        LowRank lr = factor_batch(hp, h, out.K[l], lv.kd, lv.ku, noff, max_rank, out, "zgesvd (M2L)");
+        out.mean_rank[l] = lr.mean;
+        if (lr.rmax == 0) continue;
+        out.true_rank[l] = lr.rtrue;
+        out.Ulr[l] = lr.U;
+        out.Vlr[l] = lr.V;
+        out.lr_rank[l] = lr.rank;
+        out.rmax[l] = lr.rmax;
     }
 }
 

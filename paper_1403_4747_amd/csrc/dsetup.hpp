@@ -9,6 +9,16 @@
 
 namespace fda {
 
+// Truncated SVD factors of a batch of matrices (see factor_batch).
+struct LowRank {
+    double2 *U = nullptr, *V = nullptr;  // device, m x rmax and rmax x n per matrix
+    int32_t *rank = nullptr;             // device, padded rank per matrix
+    int rmax = 0;                        // 0: the factors were not kept
+    int rtrue_max = 0;                   // largest unpadded rank
+    double mean = 0;                     // mean unpadded rank
+    std::vector<int32_t> rtrue;          // unpadded rank per matrix
+};
+
 struct DevTranslations {
     std::vector<double2 *> K, M, Lo;  // per level, device arrays (layouts as in DevLevel)
     // low-rank reduced M2L (eq. (eq_epsk)): per level, per translation
