@@ -442,11 +442,108 @@ __device__ __forceinline__ void ggemm_body(const int4 h, const int32_t *sidx, co
     }
 }
 
+// Staged form of the gathered GEMM: every 16-deep k-chunk of the 128-row
+// band of A is staged in LDS beside the chunk of gathered states, and the
+// next chunk of both is fetched into registers while the current one is
+// multiplied (the MFMA loop reads only LDS).
+#define GG_SJ 16                      // k-chunk of the staged form
+#define GG_SB (64 * GG_RT)            // rows per band
+#define GG_SLD (GG_SB + 1)            // padded LDS row of the staged A chunk
+template <class C, int NCT>
+__device__ __forceinline__ void ggemm_body_staged(const int4 h, const int32_t *sidx, const C *At, int m, int kin,
+                                                  const C *Xr, C *Tr, C (*S)[GG_LD], C (*As)[GG_SLD]) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    constexpr int SPT = GG_SJ * GG_NB / 256;
+    constexpr int APT = GG_SB * GG_SJ / 256;
+    for (int band = 0; band < m; band += GG_SB) {
+        const int ntile = min(GG_RT * 4, (m - band + 15) >> 4);
+        const int nrow = min(GG_SB, m - band);
+        CAcc<C, FDA_GEMM_3M> acc[GG_RT][NCT];
+#pragma unroll
+        for (int q = 0; q < GG_RT; ++q)
+#pragma unroll
+            for (int c = 0; c < NCT; ++c) acc[q][c].zero();
+        C sreg[SPT], areg[APT];
+        auto fetch = [&](int j0) {
+#pragma unroll
+            for (int i = 0; i < SPT; ++i) {
+                const int e = threadIdx.x + 256 * i;
+                const int jj = e % GG_SJ, b = e / GG_SJ;
+                const int sb = sidx[b];
+                sreg[i] = czero<C>();
+                if (sb >= 0 && j0 + jj < kin) sreg[i] = Xr[(int64_t)sb * kin + j0 + jj];
+            }
+#pragma unroll
+            for (int i = 0; i < APT; ++i) {
+                const int e = threadIdx.x + 256 * i;
+                const int row = e % GG_SB, kc = e / GG_SB;
+                areg[i] = czero<C>();
+                if (row < nrow && j0 + kc < kin) areg[i] = At[band + row + (int64_t)(j0 + kc) * m];
+            }
+        };
+        __syncthreads();  // sidx, and the previous band's last chunk is consumed
+        fetch(0);
+        for (int j0 = 0; j0 < kin; j0 += GG_SJ) {
+            __syncthreads();  // the previous chunk is consumed
+#pragma unroll
+            for (int i = 0; i < SPT; ++i) {
+                const int e = threadIdx.x + 256 * i;
+                S[e % GG_SJ][e / GG_SJ] = sreg[i];
+            }
+#pragma unroll
+            for (int i = 0; i < APT; ++i) {
+                const int e = threadIdx.x + 256 * i;
+                As[e / GG_SB][e % GG_SB] = areg[i];
+            }
+            __syncthreads();
+            if (j0 + GG_SJ < kin) fetch(j0 + GG_SJ);
+            const int jm = min(GG_SJ, kin - j0);
+            for (int kk = 0; kk < jm; kk += 4) {
+                const C b0 = S[kk + lk][li];
+                const C b1 = NCT == 2 ? S[kk + lk][16 + li] : czero<C>();
+#pragma unroll
+                for (int q = 0; q < GG_RT; ++q) {
+                    const int rt = wave + 4 * q;
+                    if (rt >= ntile) break;
+                    const C av = As[kk + lk][rt * 16 + li];
+                    acc[q][0].mac(av, b0);
+                    if (NCT == 2) acc[q][NCT - 1].mac(av, b1);
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < GG_RT; ++q) {
+            const int rt = wave + 4 * q;
+            if (rt >= ntile) break;
+#pragma unroll
+            for (int c = 0; c < NCT; ++c) {
+                const int col = c * 16 + li;
+                if (col >= h.z) continue;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = band + rt * 16 + CT<C>::row(lk, v);
+                    if (row < m) {
+                        C r;
+                        r.x = acc[q][c].re(v);
+                        r.y = acc[q][c].im(v);
+                        Tr[(int64_t)col * m + row] = r;
+                    }
+                }
+            }
+        }
+    }
+}
+
+#ifndef FDA_GEMM_STAGED
+#define FDA_GEMM_STAGED 1
+#endif
+
 // Waves per SIMD the GEMM kernels are compiled for: FP64 needs more
 // registers per complex accumulator than FP32.
 template <class C>
 struct GemmOcc {
-    static constexpr int waves = FDA_GEMM_3M ? 3 : 4;
+    static constexpr int waves = FDA_GEMM_STAGED ? 2 : (FDA_GEMM_3M ? 3 : 4);
 };
 template <class C>
 struct M2LOcc {
@@ -458,13 +555,19 @@ struct M2LOcc<float2> {
 };
 template <>
 struct GemmOcc<float2> {
-    static constexpr int waves = 4;
+    static constexpr int waves = FDA_GEMM_STAGED ? 3 : 4;
 };
 
 template <class C>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GemmOcc<C>::waves))) k_ggemm(const int4 *hdr, const int32_t *src, const C *A, int m, int kin,
-                                               const C *X, int64_t xstride, C *T, int64_t tstride, int nwork) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GemmOcc<C>::waves)))
+k_ggemm(const int4 *hdr, const int32_t *src, const C *A, int m, int kin, const C *X, int64_t xstride, C *T,
+        int64_t tstride, int nwork) {
+#if FDA_GEMM_STAGED
+    __shared__ C S[GG_SJ][GG_LD];
+    __shared__ C As[GG_SJ][GG_SLD];
+#else
     __shared__ C S[GG_J][GG_LD];
+#endif
     __shared__ int32_t sidx[GG_NB];
     const int nx = 8;
     const int per = gridDim.x / nx;
@@ -475,10 +578,17 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GemmOc
     const C *Xr = X + (int64_t)blockIdx.y * xstride;
     C *Tr = T + (int64_t)blockIdx.y * tstride + (int64_t)h.y * m;
     const C *At = A + (int64_t)h.x * m * kin;
+#if FDA_GEMM_STAGED
+    if (h.z > 16)
+        ggemm_body_staged<C, 2>(h, sidx, At, m, kin, Xr, Tr, S, As);
+    else
+        ggemm_body_staged<C, 1>(h, sidx, At, m, kin, Xr, Tr, S, As);
+#else
     if (h.z > 16)
         ggemm_body<C, 2>(h, sidx, At, m, kin, Xr, Tr, S);
     else
         ggemm_body<C, 1>(h, sidx, At, m, kin, Xr, Tr, S);
+#endif
 }
 
 // Low-rank reduced M2L (Section 4.2, eq. (eq_epsk)): K~ = U^ V^ with rank r
