@@ -446,7 +446,9 @@ __device__ __forceinline__ void ggemm_body(const int4 h, const int32_t *sidx, co
 // band of A is staged in LDS beside the chunk of gathered states, and the
 // next chunk of both is fetched into registers while the current one is
 // multiplied (the MFMA loop reads only LDS).
-#define GG_SJ 16                      // k-chunk of the staged form
+#ifndef GG_SJ
+#define GG_SJ 8  // k-chunk of the staged form
+#endif
 #define GG_SB (64 * GG_RT)            // rows per band
 #define GG_SLD (GG_SB + 1)            // padded LDS row of the staged A chunk
 template <class C, int NCT>
@@ -541,9 +543,12 @@ __device__ __forceinline__ void ggemm_body_staged(const int4 h, const int32_t *s
 
 // Waves per SIMD the GEMM kernels are compiled for: FP64 needs more
 // registers per complex accumulator than FP32.
+#ifndef FDA_GEMM_WAVES64
+#define FDA_GEMM_WAVES64 3
+#endif
 template <class C>
 struct GemmOcc {
-    static constexpr int waves = FDA_GEMM_STAGED ? 2 : (FDA_GEMM_3M ? 3 : 4);
+    static constexpr int waves = FDA_GEMM_WAVES64;
 };
 template <class C>
 struct M2LOcc {
@@ -553,9 +558,12 @@ template <>
 struct M2LOcc<float2> {
     static constexpr int waves = 4;
 };
+#ifndef FDA_GEMM_WAVES32
+#define FDA_GEMM_WAVES32 (FDA_GEMM_STAGED ? 3 : 4)
+#endif
 template <>
 struct GemmOcc<float2> {
-    static constexpr int waves = FDA_GEMM_STAGED ? 3 : 4;
+    static constexpr int waves = FDA_GEMM_WAVES32;
 };
 
 template <class C>
