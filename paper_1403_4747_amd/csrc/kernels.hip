@@ -731,11 +731,13 @@ __device__ __forceinline__ void m2l_body(const int4 h, const int32_t *sidx, cons
         for (int q = 0; q < P2; ++q)
 #pragma unroll
             for (int c = 0; c < NCT; ++c) acc[q][c].zero();
-        C a[P2], an[P2];
-        load_afrag<C, P2>(a, Ut, kd, kd, 16 * 4 * P2 * pass, ntile - 4 * P2 * pass, wave, li, lk, r);
+        // U^ fragments two k-steps ahead (a phase-2 step is only a few MFMAs)
+        C a[P2], an[P2], ann[P2];
+        const int prow = 16 * 4 * P2 * pass, pnt = ntile - 4 * P2 * pass;
+        load_afrag<C, P2>(a, Ut, kd, kd, prow, pnt, wave, li, lk, r);
+        load_afrag<C, P2>(an, Ut, kd, kd, prow, pnt, wave, li, 4 + lk, r);
         for (int kk = 0; kk < r; kk += 4) {
-            if (kk + 4 < r)
-                load_afrag<C, P2>(an, Ut, kd, kd, 16 * 4 * P2 * pass, ntile - 4 * P2 * pass, wave, li, kk + 4 + lk, r);
+            if (kk + 8 < r) load_afrag<C, P2>(ann, Ut, kd, kd, prow, pnt, wave, li, kk + 8 + lk, r);
             const C b0 = Z[kk + lk][li];
             const C b1 = NCT == 2 ? Z[kk + lk][16 + li] : czero<C>();
 #pragma unroll
@@ -745,7 +747,10 @@ __device__ __forceinline__ void m2l_body(const int4 h, const int32_t *sidx, cons
                 if (NCT == 2) acc[q][NCT - 1].mac(a[q], b1);
             }
 #pragma unroll
-            for (int q = 0; q < P2; ++q) a[q] = an[q];
+            for (int q = 0; q < P2; ++q) {
+                a[q] = an[q];
+                an[q] = ann[q];
+            }
         }
 #pragma unroll
         for (int q = 0; q < P2; ++q) {
