@@ -306,6 +306,9 @@ __global__ void k_s2m(const int64_t *leaf_off, const C *S, int ku, const double2
 #define LR_LD (LR_MAX + 1)
 #define LRJ 16   // k-chunk of the low-rank M2L phase 1
 #define LR_P2 1  // row tiles per wave and pass in phase 2
+#ifndef M2L_PD
+#define M2L_PD 5  // phase-2 factor fragments in flight (k-steps of look-ahead + 1)
+#endif
 
 // Load up to GG_J x GG_NB gathered input values (zero padded) into LDS.
 template <class C>
@@ -731,26 +734,27 @@ __device__ __forceinline__ void m2l_body(const int4 h, const int32_t *sidx, cons
         for (int q = 0; q < P2; ++q)
 #pragma unroll
             for (int c = 0; c < NCT; ++c) acc[q][c].zero();
-        // U^ fragments two k-steps ahead (a phase-2 step is only a few MFMAs)
-        C a[P2], an[P2], ann[P2];
+        // U^ fragments PD k-steps ahead (a phase-2 step is only a few MFMAs)
+        constexpr int PD = M2L_PD;
+        C af[PD][P2];
         const int prow = 16 * 4 * P2 * pass, pnt = ntile - 4 * P2 * pass;
-        load_afrag<C, P2>(a, Ut, kd, kd, prow, pnt, wave, li, lk, r);
-        load_afrag<C, P2>(an, Ut, kd, kd, prow, pnt, wave, li, 4 + lk, r);
+#pragma unroll
+        for (int d = 0; d < PD - 1; ++d) load_afrag<C, P2>(af[d], Ut, kd, kd, prow, pnt, wave, li, 4 * d + lk, r);
         for (int kk = 0; kk < r; kk += 4) {
-            if (kk + 8 < r) load_afrag<C, P2>(ann, Ut, kd, kd, prow, pnt, wave, li, kk + 8 + lk, r);
+            if (kk + 4 * (PD - 1) < r)
+                load_afrag<C, P2>(af[PD - 1], Ut, kd, kd, prow, pnt, wave, li, kk + 4 * (PD - 1) + lk, r);
             const C b0 = Z[kk + lk][li];
             const C b1 = NCT == 2 ? Z[kk + lk][16 + li] : czero<C>();
 #pragma unroll
             for (int q = 0; q < P2; ++q) {
                 if (rt0 + 4 * q >= ntile) break;
-                acc[q][0].mac(a[q], b0);
-                if (NCT == 2) acc[q][NCT - 1].mac(a[q], b1);
+                acc[q][0].mac(af[0][q], b0);
+                if (NCT == 2) acc[q][NCT - 1].mac(af[0][q], b1);
             }
 #pragma unroll
-            for (int q = 0; q < P2; ++q) {
-                a[q] = an[q];
-                an[q] = ann[q];
-            }
+            for (int d = 0; d < PD - 1; ++d)
+#pragma unroll
+                for (int q = 0; q < P2; ++q) af[d][q] = af[d + 1][q];
         }
 #pragma unroll
         for (int q = 0; q < P2; ++q) {
