@@ -354,7 +354,7 @@ void upload_plan(fda_plan *p, const HostOps &ops, DevTranslations &tr) {
         dl.K = to_storage(p, tr.K[l], lv.offsets.size() * (size_t)lv.kd * lv.ku);
         if (!tr.rmax.empty() && tr.rmax[l] > 0 && lv.kd <= 256) {
             dl.Ulr = to_storage(p, tr.Ulr[l], lv.offsets.size() * (size_t)lv.kd * tr.rmax[l]);
-            dl.Vlr = to_storage(p, tr.Vlr[l], lv.offsets.size() * (size_t)tr.rmax[l] * lv.ku);
+            dl.Vlr = to_storage(p, tr.Vlr[l], lv.offsets.size() * (size_t)tr.rmax[l] * ((lv.ku + 3) / 4 * 4));
             dl.lr_rank = tr.lr_rank[l];
             dl.rmax = tr.rmax[l];
         }

@@ -398,17 +398,18 @@ void device_translations(const HostPlan &hp, rocblas_handle h, DevTranslations &
     }
 }
 
-// Pack U^ = U[:, :r] and V^ = diag(s[:r]) V^H[:r, :] per translation.
+// Pack U^ = U[:, :r] and V^ = diag(s[:r]) V^H[:r, :] per translation; V^
+// gets zero columns up to nld (ku rounded up to 4).
 __global__ void k_pack_lowrank(const double2 *U, const double *S, const double2 *Vh, const int32_t *rank, int kd,
-                               int ku, int mn, int rmax, double2 *Ulr, double2 *Vlr) {
+                               int ku, int nld, int mn, int rmax, double2 *Ulr, double2 *Vlr) {
     const int op = blockIdx.y;
     const int r = rank[op];
     const double2 *Uo = U + (int64_t)op * kd * mn;
     const double2 *Vo = Vh + (int64_t)op * mn * ku;
     const double *So = S + (int64_t)op * mn;
     double2 *Uout = Ulr + (int64_t)op * kd * rmax;
-    double2 *Vout = Vlr + (int64_t)op * rmax * ku;
-    const int64_t nU = (int64_t)kd * rmax, nV = (int64_t)rmax * ku;
+    double2 *Vout = Vlr + (int64_t)op * rmax * nld;
+    const int64_t nU = (int64_t)kd * rmax, nV = (int64_t)rmax * nld;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nU + nV; e += (int64_t)gridDim.x * blockDim.x) {
         if (e < nU) {
             const int i = (int)(e % kd), j = (int)(e / kd);
@@ -417,7 +418,7 @@ __global__ void k_pack_lowrank(const double2 *U, const double *S, const double2 
             const int64_t f = e - nU;
             const int j = (int)(f % rmax), c = (int)(f / rmax);
             double2 v = make_double2(0.0, 0.0);
-            if (j < r && j < mn) {
+            if (j < r && j < mn && c < ku) {
                 const double2 q = Vo[j + (int64_t)c * mn];
                 v = make_double2(So[j] * q.x, So[j] * q.y);
             }
@@ -428,7 +429,8 @@ __global__ void k_pack_lowrank(const double2 *U, const double *S, const double2 
 
 // Truncated SVD factors of `count` column-major m x n matrices (stride m*n):
 // A = U^ V^ with U^ = U[:, :r] (m x rmax) and V^ = diag(s[:r]) V^H[:r, :]
-// (rmax x n), r the number of singular values >= svd_eps * s_0, padded to a
+// (rmax x n, stored with n rounded up to a multiple of 4 and zero columns
+// there), r the number of singular values >= svd_eps * s_0, padded to a
 // multiple of 4.  rmax = 0 (nothing kept) when some rank exceeds max_rank or
 // 2 r >= min(m, n) (the factors would not pay; Section 4.2).
 LowRank factor_batch(const HostPlan &hp, rocblas_handle h, const double2 *mats, int m, int n, int count,
@@ -475,11 +477,12 @@ LowRank factor_batch(const HostPlan &hp, rocblas_handle h, const double2 *mats, 
         return q;
     };
     lr.U = (double2 *)keep(sizeof(double2) * (size_t)m * rmax * count);
-    lr.V = (double2 *)keep(sizeof(double2) * (size_t)rmax * n * count);
+    const int nld = (n + 3) / 4 * 4;
+    lr.V = (double2 *)keep(sizeof(double2) * (size_t)rmax * nld * count);
     lr.rank = (int32_t *)keep(sizeof(int32_t) * count);
     hchk(hipMemcpy(lr.rank, rank.data(), sizeof(int32_t) * count, hipMemcpyHostToDevice), "h2d");
     hipLaunchKernelGGL(k_pack_lowrank, dim3(64, count), dim3(256), 0, nullptr, dU.as<double2>(), dS.as<double>(),
-                       dV.as<double2>(), lr.rank, m, n, mn, rmax, lr.U, lr.V);
+                       dV.as<double2>(), lr.rank, m, n, nld, mn, rmax, lr.U, lr.V);
     hchk(hipGetLastError(), "pack");
     hchk(hipDeviceSynchronize(), "pack sync");
     lr.rmax = rmax;

@@ -175,6 +175,7 @@ struct CT;
 template <>
 struct CT<double2> {
     using R = double;
+    typedef double v2 __attribute__((ext_vector_type(2)));
     typedef double v4 __attribute__((ext_vector_type(4)));
     // v_mfma_f64_16x16x4f64; result row of lane group lk, element v
     static __device__ __forceinline__ v4 mfma(double a, double b, v4 c) {
@@ -185,6 +186,7 @@ struct CT<double2> {
 template <>
 struct CT<float2> {
     using R = float;
+    typedef float v2 __attribute__((ext_vector_type(2)));
     typedef float v4 __attribute__((ext_vector_type(4)));
     // v_mfma_f32_16x16x4f32
     static __device__ __forceinline__ v4 mfma(float a, float b, v4 c) {
@@ -192,6 +194,21 @@ struct CT<float2> {
     }
     static __device__ __forceinline__ int row(int lk, int v) { return 4 * lk + v; }
 };
+
+// Load of one complex value from global memory.  A pointer read out of a
+// device-side table is generic to the compiler, which then emits flat loads;
+// those count against the LDS wait counter as well, so every wait for an LDS
+// read would also wait for all loads in flight.  Reading through a
+// global-space pointer keeps the two counters apart.
+template <class C>
+__device__ __forceinline__ C gload(const C *p) {
+    using v2 = typename CT<C>::v2;
+    const v2 v = *(const __attribute__((address_space(1))) v2 *)p;
+    C c;
+    c.x = v.x;
+    c.y = v.y;
+    return c;
+}
 
 template <class C>
 __device__ __forceinline__ C czero() {
@@ -304,8 +321,22 @@ __global__ void k_s2m(const int64_t *leaf_off, const C *S, int ku, const double2
 #define GG_RT 2  // row tiles per wave in a band of the gathered GEMM (band = 128 rows)
 #define LR_MAX 72
 #define LR_LD (LR_MAX + 1)
-#define LRJ 16   // k-chunk of the low-rank M2L phase 1
+#ifndef LRJ
+#define LRJ 16  // k-chunk of the low-rank M2L phase 1
+#endif
 #define LR_P2 1  // row tiles per wave and pass in phase 2
+#ifndef FDA_M2L_WAVES64
+#define FDA_M2L_WAVES64 4  // k_m2l_lowrank<double2> waves per SIMD
+#endif
+#ifndef FDA_M2L_DIRECT64
+#define FDA_M2L_DIRECT64 1  // FP64 phase 1: operands straight into registers (no LDS staging, no barriers)
+#endif
+#ifndef FDA_M2L_DIRECT32
+#define FDA_M2L_DIRECT32 0  // FP32 phase 1: staged through LDS
+#endif
+#ifndef M2L_P1D
+#define M2L_P1D 4  // phase-1 k-steps in flight per wave (direct form)
+#endif
 #ifndef M2L_PD
 #define M2L_PD 5  // phase-2 factor fragments in flight (k-steps of look-ahead + 1)
 #endif
@@ -383,7 +414,7 @@ __device__ __forceinline__ void load_afrag(C (&a)[NT], const C *A, int lda, int 
         const int rt = wave + 4 * q;
         const int row = row0 + rt * 16 + li;
         a[q] = czero<C>();
-        if (rt < ntile && row < mrows && kcol < kend) a[q] = A[row + (int64_t)kcol * lda];
+        if (rt < ntile && row < mrows && kcol < kend) a[q] = gload(A + row + (int64_t)kcol * lda);
     }
 }
 
@@ -555,11 +586,13 @@ struct GemmOcc {
 };
 template <class C>
 struct M2LOcc {
-    static constexpr int waves = FDA_M2L_3M ? 3 : 4;
+    static constexpr int waves = FDA_M2L_WAVES64;
+    static constexpr bool direct = FDA_M2L_DIRECT64;
 };
 template <>
 struct M2LOcc<float2> {
     static constexpr int waves = 4;
+    static constexpr bool direct = FDA_M2L_DIRECT32;
 };
 #ifndef FDA_GEMM_WAVES32
 #define FDA_GEMM_WAVES32 (FDA_GEMM_STAGED ? 3 : 4)
@@ -602,6 +635,42 @@ k_ggemm(const int4 *hdr, const int32_t *src, const C *A, int m, int kin, const C
 #endif
 }
 
+// Phase 1 of the low-rank M2L in the direct form: NQ row tiles of V^ (rows
+// vrow[q]) times one column tile of gathered states (column xcol), k-steps
+// kb0, kb0 + kstep, ... below ku.  Operands are loaded PD steps ahead into a
+// ring of registers; the main loop issues exactly PD loads per trip and the
+// tail none, so the waits count loads instead of draining them.
+template <class C, int NQ, int PD>
+__device__ __forceinline__ void m2l_p1_direct(CAcc<C, FDA_M2L_3M> *zacc, const C *xcol, const C *const *vrow, int rmax,
+                                              int ku, int kb0, int kstep, int lk) {
+    const int ku4 = (ku + 3) & ~3;
+    auto fetch = [&](C (&av)[NQ], C &bv, int kc) {
+        bv = gload(xcol + min(kc, ku - 1));
+        const int64_t vc = (int64_t)min(kc, ku4 - 1) * rmax;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) av[q] = gload(vrow[q] + vc);
+    };
+    C ar[PD][NQ], br[PD];
+#pragma unroll
+    for (int d = 0; d < PD; ++d) fetch(ar[d], br[d], kb0 + d * kstep + lk);
+    const int nsteps = kb0 < ku ? (ku - kb0 + kstep - 1) / kstep : 0;
+    int s = 0;
+    for (; s + PD <= nsteps; s += PD) {
+#pragma unroll
+        for (int d = 0; d < PD; ++d) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) zacc[q].mac(ar[d][q], br[d]);
+            fetch(ar[d], br[d], kb0 + (s + d + PD) * kstep + lk);  // slot d now holds step s + d + PD
+        }
+    }
+#pragma unroll
+    for (int d = 0; d < PD; ++d)
+        if (s + d < nsteps) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) zacc[q].mac(ar[d][q], br[d]);
+        }
+}
+
 // Low-rank reduced M2L (Section 4.2, eq. (eq_epsk)): K~ = U^ V^ with rank r
 // per translation, so each work item first forms Z = V^ S (r x ncols) and
 // then U^ Z (kd x ncols), both on the matrix cores; Z stays in LDS.  Same
@@ -631,68 +700,95 @@ __device__ __forceinline__ void m2l_body(const int4 h, const int32_t *sidx, cons
     CAcc<C, FDA_M2L_3M> zacc[ZQ];
 #pragma unroll
     for (int q = 0; q < ZQ; ++q) zacc[q].zero();
-    // the next chunk is fetched into registers while the current one is
-    // multiplied out of LDS (the MFMA loop issues no global loads, so these
-    // loads are waited for only when they are committed to LDS)
-    constexpr int SPT = LRJ * GG_NB / 256;
-    constexpr int VPT = 64 * LRJ / 256;  // ranks up to 64 prefetched; rows 64.. read at commit
-    C sreg[SPT], vreg[VPT];
-    auto fetch = [&](int j0) {
+    if constexpr (M2LOcc<C>::direct) {
+        // Every wave multiplies its own tiles with operands loaded straight from
+        // memory into MFMA registers, M2L_P1D k-steps ahead of their use: the
+        // V^ rows of its row tiles and the gathered state columns of its column
+        // tile (all tiles of a wave share one column tile: the tile stride is 4
+        // and NCT divides 4).  No LDS staging and no barriers in the k loop.
+        __syncthreads();  // sidx
+        if (tbase < ntz) {
+            // Every load is unconditional (a skipped load would make the
+            // compiler wait for all loads in flight): addresses are clamped
+            // into the operands instead.  A padding column (no source) reads
+            // state 0, and its products are never stored; rows of V^ from r
+            // on are zero up to rmax and the Z rows they give are never read;
+            // the columns of V^ from ku to ku4 are zero, so the clamped state
+            // element they meet adds nothing.
+            const int sb = sidx[(tbase % NCT) * 16 + li];
+            const C *xcol = Xr + (int64_t)(sb >= 0 ? sb : 0) * ku;
+            const C *vrow[ZQ];
 #pragma unroll
-        for (int i = 0; i < SPT; ++i) {
-            const int e = threadIdx.x + 256 * i;
-            const int jj = e % LRJ, b = e / LRJ;
-            const int sb = sidx[b];
-            sreg[i] = czero<C>();
-            if (sb >= 0 && j0 + jj < ku) sreg[i] = Xr[(int64_t)sb * ku + j0 + jj];
+            for (int q = 0; q < ZQ; ++q) vrow[q] = Vt + min(((tbase + tstep * q) / NCT) * 16 + li, rmax - 1);
+            if (tbase + tstep < ntz)
+                m2l_p1_direct<C, 2, M2L_P1D>(zacc, xcol, vrow, rmax, ku, 4 * kg, 4 * kg_n, lk);
+            else
+                m2l_p1_direct<C, 1, M2L_P1D>(zacc, xcol, vrow, rmax, ku, 4 * kg, 4 * kg_n, lk);
         }
+    } else {
+        // the next chunk is fetched into registers while the current one is
+        // multiplied out of LDS (the MFMA loop issues no global loads, so these
+        // loads are waited for only when they are committed to LDS)
+        constexpr int SPT = LRJ * GG_NB / 256;
+        constexpr int VPT = 64 * LRJ / 256;  // ranks up to 64 prefetched; rows 64.. read at commit
+        C sreg[SPT], vreg[VPT];
+        auto fetch = [&](int j0) {
 #pragma unroll
-        for (int i = 0; i < VPT; ++i) {
-            const int e = threadIdx.x + 256 * i;
-            vreg[i] = czero<C>();
-            if (e < r * LRJ) {
-                const int row = e % r, kc = e / r;
-                if (j0 + kc < ku) vreg[i] = Vt[row + (int64_t)(j0 + kc) * rmax];
+            for (int i = 0; i < SPT; ++i) {
+                const int e = threadIdx.x + 256 * i;
+                const int jj = e % LRJ, b = e / LRJ;
+                const int sb = sidx[b];
+                sreg[i] = czero<C>();
+                if (sb >= 0 && j0 + jj < ku) sreg[i] = gload(Xr + (int64_t)sb * ku + j0 + jj);
             }
-        }
-    };
-    __syncthreads();  // sidx
-    fetch(0);
-    for (int j0 = 0; j0 < ku; j0 += LRJ) {
-        __syncthreads();  // the previous chunk is consumed
 #pragma unroll
-        for (int i = 0; i < SPT; ++i) {
-            const int e = threadIdx.x + 256 * i;
-            S[e % LRJ][e / LRJ] = sreg[i];
-        }
+            for (int i = 0; i < VPT; ++i) {
+                const int e = threadIdx.x + 256 * i;
+                vreg[i] = czero<C>();
+                if (e < r * LRJ) {
+                    const int row = e % r, kc = e / r;
+                    if (j0 + kc < ku) vreg[i] = gload(Vt + row + (int64_t)(j0 + kc) * rmax);
+                }
+            }
+        };
+        __syncthreads();  // sidx
+        fetch(0);
+        for (int j0 = 0; j0 < ku; j0 += LRJ) {
+            __syncthreads();  // the previous chunk is consumed
 #pragma unroll
-        for (int i = 0; i < VPT; ++i) {
-            const int e = threadIdx.x + 256 * i;
-            if (e < r * LRJ) Vs[e / r][e % r] = vreg[i];
-        }
-        for (int e = threadIdx.x + 256 * VPT; e < r * LRJ; e += 256) {
-            const int row = e % r, kc = e / r;
-            C v = czero<C>();
-            if (j0 + kc < ku) v = Vt[row + (int64_t)(j0 + kc) * rmax];
-            Vs[kc][row] = v;
+            for (int i = 0; i < SPT; ++i) {
+                const int e = threadIdx.x + 256 * i;
+                S[e % LRJ][e / LRJ] = sreg[i];
+            }
+#pragma unroll
+            for (int i = 0; i < VPT; ++i) {
+                const int e = threadIdx.x + 256 * i;
+                if (e < r * LRJ) Vs[e / r][e % r] = vreg[i];
+            }
+            for (int e = threadIdx.x + 256 * VPT; e < r * LRJ; e += 256) {
+                const int row = e % r, kc = e / r;
+                C v = czero<C>();
+                if (j0 + kc < ku) v = gload(Vt + row + (int64_t)(j0 + kc) * rmax);
+                Vs[kc][row] = v;
+            }
+            __syncthreads();
+            if (j0 + LRJ < ku) fetch(j0 + LRJ);
+            const int jm = min(LRJ, ku - j0);
+            for (int kk = 4 * kg; kk < jm; kk += 4 * kg_n) {
+#pragma unroll
+                for (int q = 0; q < ZQ; ++q) {
+                    const int ti = tbase + tstep * q;
+                    if (ti >= ntz) break;
+                    const int row = (ti / NCT) * 16 + li;
+                    C a = czero<C>();
+                    if (row < r) a = Vs[kk + lk][row];
+                    const C b = S[kk + lk][(ti % NCT) * 16 + li];
+                    zacc[q].mac(a, b);
+                }
+            }
         }
         __syncthreads();
-        if (j0 + LRJ < ku) fetch(j0 + LRJ);
-        const int jm = min(LRJ, ku - j0);
-        for (int kk = 4 * kg; kk < jm; kk += 4 * kg_n) {
-#pragma unroll
-            for (int q = 0; q < ZQ; ++q) {
-                const int ti = tbase + tstep * q;
-                if (ti >= ntz) break;
-                const int row = (ti / NCT) * 16 + li;
-                C a = czero<C>();
-                if (row < r) a = Vs[kk + lk][row];
-                const C b = S[kk + lk][(ti % NCT) * 16 + li];
-                zacc[q].mac(a, b);
-            }
-        }
     }
-    __syncthreads();
     const int zoff = kg * 16 * ztiles;  // partial sums of k group kg (<= 64 rows in all)
 #pragma unroll
     for (int q = 0; q < ZQ; ++q) {
@@ -704,7 +800,10 @@ __device__ __forceinline__ void m2l_body(const int4 h, const int32_t *sidx, cons
             C z;
             z.x = zacc[q].re(v);
             z.y = zacc[q].im(v);
-            Z[zoff + zt * 16 + CT<C>::row(lk, v)][c * 16 + li] = z;
+            // rows from r on are never read; for r > 64 the fifth row tile
+            // would run past the LR_MAX rows of Z
+            const int zr = zoff + zt * 16 + CT<C>::row(lk, v);
+            if (zr < LR_MAX) Z[zr][c * 16 + li] = z;
         }
     }
     __syncthreads();
@@ -734,28 +833,45 @@ __device__ __forceinline__ void m2l_body(const int4 h, const int32_t *sidx, cons
         for (int q = 0; q < P2; ++q)
 #pragma unroll
             for (int c = 0; c < NCT; ++c) acc[q][c].zero();
-        // U^ fragments PD k-steps ahead (a phase-2 step is only a few MFMAs)
+        // U^ fragments PD k-steps ahead of their use (a phase-2 step is only
+        // a few MFMAs); slot d is refilled right after it is consumed, so no
+        // register moves tie a step to the load just issued.  Loads are
+        // unconditional: rows from kd on are clamped (they feed output rows
+        // that are never stored) and so are columns from r on (prefetches
+        // past the last step, never used).
         constexpr int PD = M2L_PD;
         C af[PD][P2];
-        const int prow = 16 * 4 * P2 * pass, pnt = ntile - 4 * P2 * pass;
+        const C *urow[P2];
 #pragma unroll
-        for (int d = 0; d < PD - 1; ++d) load_afrag<C, P2>(af[d], Ut, kd, kd, prow, pnt, wave, li, 4 * d + lk, r);
-        for (int kk = 0; kk < r; kk += 4) {
-            if (kk + 4 * (PD - 1) < r)
-                load_afrag<C, P2>(af[PD - 1], Ut, kd, kd, prow, pnt, wave, li, kk + 4 * (PD - 1) + lk, r);
+        for (int q = 0; q < P2; ++q) urow[q] = Ut + min((rt0 + 4 * q) * 16 + li, kd - 1);
+        auto uload = [&](C (&av)[P2], int kc) {
+            const int64_t o = (int64_t)min(kc, r - 1) * kd;
+#pragma unroll
+            for (int q = 0; q < P2; ++q) av[q] = gload(urow[q] + o);
+        };
+#pragma unroll
+        for (int d = 0; d < PD; ++d) uload(af[d], 4 * d + lk);
+        auto step = [&](const C (&av)[P2], int kk) {
             const C b0 = Z[kk + lk][li];
             const C b1 = NCT == 2 ? Z[kk + lk][16 + li] : czero<C>();
 #pragma unroll
             for (int q = 0; q < P2; ++q) {
-                if (rt0 + 4 * q >= ntile) break;
-                acc[q][0].mac(af[0][q], b0);
-                if (NCT == 2) acc[q][NCT - 1].mac(af[0][q], b1);
+                acc[q][0].mac(av[q], b0);
+                if (NCT == 2) acc[q][NCT - 1].mac(av[q], b1);
             }
+        };
+        const int nsteps = r >> 2;  // r is a multiple of 4
+        int s = 0;
+        for (; s + PD <= nsteps; s += PD) {
 #pragma unroll
-            for (int d = 0; d < PD - 1; ++d)
-#pragma unroll
-                for (int q = 0; q < P2; ++q) af[d][q] = af[d + 1][q];
+            for (int d = 0; d < PD; ++d) {
+                step(af[d], 4 * (s + d));
+                uload(af[d], 4 * (s + d + PD) + lk);
+            }
         }
+#pragma unroll
+        for (int d = 0; d < PD; ++d)
+            if (s + d < nsteps) step(af[d], 4 * (s + d));
 #pragma unroll
         for (int q = 0; q < P2; ++q) {
             const int rt = rt0 + 4 * q;
@@ -786,7 +902,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M2LOcc
 k_m2l_lowrank(const int4 *hdr, const int32_t *src, const M2LLevelArgs *args, C *T, int64_t tstride, int nwork) {
     // LDS: phase 1 stages S (LRJ x GG_LD) and V^ (LRJ x LR_LD); phase 2
     // reuses the same bytes for Z (LR_MAX x GG_LD) once phase 1 is done
-    constexpr int kStage = LRJ * GG_LD + LRJ * LR_LD;
+    constexpr int kStage = M2LOcc<C>::direct ? 0 : LRJ * GG_LD + LRJ * LR_LD;
     constexpr int kZ = LR_MAX * GG_LD;
     __shared__ C smem[kStage > kZ ? kStage : kZ];
     __shared__ int32_t sidx[GG_NB];
@@ -806,7 +922,7 @@ k_m2l_lowrank(const int4 *hdr, const int32_t *src, const M2LLevelArgs *args, C *
     if (threadIdx.x < GG_NB) sidx[threadIdx.x] = src[(int64_t)w * GG_NB + threadIdx.x];
     const C *Xr = (const C *)la.X + (int64_t)blockIdx.y * la.xstride;
     C *Tr = T + (int64_t)blockIdx.y * tstride + la.tbase + (int64_t)h.y * kd;
-    const C *Vt = (const C *)la.V + (int64_t)op * rmax * ku;
+    const C *Vt = (const C *)la.V + (int64_t)op * rmax * ((ku + 3) & ~3);
     const C *Ut = (const C *)la.U + (int64_t)op * kd * rmax;
     if (h.z > 16)
         m2l_body<C, 2>(h, sidx, Ut, Vt, r, kd, ku, rmax, Xr, Tr, S, Vs, Z);

@@ -27,7 +27,8 @@ constexpr int kGemmCols = 32;
 // their level, one reduction list that writes every state of those levels
 // (an empty list writes zero), and a per-level argument table.
 struct M2LLevelArgs {
-    const void *U = nullptr, *V = nullptr;  // low-rank factors (storage type)
+    const void *U = nullptr, *V = nullptr;  // low-rank factors (storage type): per translation
+                                            // U^ kd x rmax, V^ rmax x (ku rounded up to 4)
     const int32_t *rank = nullptr;          // padded rank per translation
     const void *X = nullptr;                // outgoing states s of the level
     void *Y = nullptr;                      // incoming states c of the level
