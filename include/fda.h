@@ -147,8 +147,12 @@ int fda_inspect(const double *verts, int64_t nv, const int32_t *tris, int64_t nt
 /* y = A x for nrhs columns (Algorithm, Steps 2-4: upward pass, M2L,
  * downward pass, near field).  x_dev, y_dev: N x nrhs complex128 device
  * buffers with leading dimension ld (elements); x is not modified; x and y
- * must not overlap.  Asynchronous on stream.  Errors: FDA_EINVAL (nrhs < 1,
- * nrhs > nrhs_max, ld < N, null pointers), FDA_EHIP. */
+ * must not overlap.  Asynchronous on stream: the near field may run on a
+ * stream the plan owns, concurrently with the far field, but it is ordered
+ * after the work already on `stream` and the product completes on `stream`
+ * (while `stream` is being captured into a graph everything stays on it).
+ * Errors: FDA_EINVAL (nrhs < 1, nrhs > nrhs_max, ld < N, null pointers),
+ * FDA_EHIP. */
 int fda_matvec(fda_plan *plan, const void *x_dev, void *y_dev, int64_t nrhs, int64_t ld, void *stream);
 
 /* Right-hand side of a rigid body under unit plane waves exp(ik d.x):

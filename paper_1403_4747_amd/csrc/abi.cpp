@@ -692,6 +692,21 @@ int fda_build(const double *verts, int64_t nv, const int32_t *tris, int64_t nt, 
     p->stats.build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     for (int q = 0; q < 8; ++q) p->stats.build_phase_seconds[q] = phase[q];
     p->stats.device_bytes = p->device_bytes;
+    if (p->d.has_far) {
+        // a side stream (default priority) for the near field; without it
+        // the near field runs on the caller's stream before the far field
+        fda::DevPlan &d = p->d;
+        if (hipStreamCreateWithFlags(&d.side, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&d.fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&d.join, hipEventDisableTiming) != hipSuccess) {
+            if (d.side) hipStreamDestroy(d.side);
+            if (d.fork) hipEventDestroy(d.fork);
+            if (d.join) hipEventDestroy(d.join);
+            d.side = nullptr;
+            d.fork = d.join = nullptr;
+            hipGetLastError();
+        }
+    }
     *out = p.release();
     return FDA_OK;
 }
@@ -706,6 +721,12 @@ int fda_plan_stats(const fda_plan *plan, fda_stats *st) {
 void fda_free(fda_plan *plan) {
     if (!plan) return;
     hipSetDevice(plan->device);
+    if (plan->d.side) {
+        hipStreamSynchronize(plan->d.side);
+        hipStreamDestroy(plan->d.side);
+        hipEventDestroy(plan->d.fork);
+        hipEventDestroy(plan->d.join);
+    }
     free_work(plan);
     for (void *q : plan->allocs) hipFree(q);
     delete plan;

@@ -1328,17 +1328,48 @@ static hipError_t ggemm_t(const GWork &g, const void *A, int m, int kin, const v
     return hipSuccess;
 }
 
+#ifndef FDA_NEAR_FORK
+#define FDA_NEAR_FORK 1  // 0: the side-stream near field starts with the matvec; 1: with the M2L
+#endif
 // Stage timings are recorded when ev != nullptr (7 events: start, after
 // near, after S2M, after M2M, after M2L, after L2L, end).
 template <class C>
 static hipError_t matvec_t(const DevPlan &d, const double2 *xt, double2 *yt, int nrhs, hipStream_t st,
                            hipEvent_t *ev, hipEvent_t *lev) {
     const int64_t N = d.n;
+    // The near field (HBM-bound) overlaps the far-field chain (matrix cores)
+    // on the plan's side stream, unless stage timings are taken or the
+    // caller's stream is being captured into a graph (a fork onto the side
+    // stream inside a capture has crashed the runtime; captured branches
+    // run concurrently anyway).
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (d.side) {
+        const hipError_t e = hipStreamIsCapturing(st, &cs);
+        if (e != hipSuccess) return e;
+    }
+    const bool overlap = !ev && d.side && d.has_far && cs == hipStreamCaptureStatusNone;
+    // near field on the side stream, forked from st at this point
+    auto near_side = [&]() -> hipError_t {
+        hipError_t e = hipEventRecord(d.fork, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(d.side, d.fork, 0);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_p2p<C>, dim3(d.nleaf, nrhs), dim3(256), sizeof(C) * d.max_ncol, d.side, d.leaf_off,
+                           d.nf_list_off, d.nf_list, d.nf_blk_off, (const C *)d.nf_vals, (const double2 *)d.nf_diag,
+                           xt, yt, N);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipEventRecord(d.join, d.side);
+        return e;
+    };
     if (ev) hipEventRecord(ev[0], st);
-    hipLaunchKernelGGL(k_p2p<C>, dim3(d.nleaf, nrhs), dim3(256), sizeof(C) * d.max_ncol, st, d.leaf_off,
-                       d.nf_list_off, d.nf_list, d.nf_blk_off, (const C *)d.nf_vals, (const double2 *)d.nf_diag, xt,
-                       yt, N);
-    CHECK_LAUNCH();
+    if (!overlap) {
+        hipLaunchKernelGGL(k_p2p<C>, dim3(d.nleaf, nrhs), dim3(256), sizeof(C) * d.max_ncol, st, d.leaf_off,
+                           d.nf_list_off, d.nf_list, d.nf_blk_off, (const C *)d.nf_vals, (const double2 *)d.nf_diag,
+                           xt, yt, N);
+        CHECK_LAUNCH();
+    } else if (FDA_NEAR_FORK == 0) {
+        const hipError_t e = near_side();
+        if (e != hipSuccess) return e;
+    }
     if (ev) hipEventRecord(ev[1], st);
     if (!d.has_far) {
         for (int q = 2; q < 7 && ev; ++q) hipEventRecord(ev[q], st);
@@ -1356,6 +1387,10 @@ static hipError_t matvec_t(const DevPlan &d, const double2 *xt, double2 *yt, int
         if (e != hipSuccess) return e;
     }
     if (ev) hipEventRecord(ev[3], st);
+    if (overlap && FDA_NEAR_FORK == 1) {
+        const hipError_t e = near_side();
+        if (e != hipSuccess) return e;
+    }
     const M2LMerged &mm = d.m2l_all;
     if (mm.nwork > 0) {
         const int grid = mm.nwork;  // a multiple of 8, ordered for XCD dispatch
@@ -1385,6 +1420,10 @@ static hipError_t matvec_t(const DevPlan &d, const double2 *xt, double2 *yt, int
         if (e != hipSuccess) return e;
     }
     if (ev) hipEventRecord(ev[5], st);
+    if (overlap) {
+        hipError_t e = hipStreamWaitEvent(st, d.join, 0);  // L2T adds to the near-field result
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(k_l2t<C>, dim3(d.nleaf, nrhs), dim3(256), sizeof(C) * (lf.kd + 256), st, d.leaf_off, (const C *)d.T,
                        lf.kd, (const C *)lf.c, yt, N, lf.cstride);
     CHECK_LAUNCH();

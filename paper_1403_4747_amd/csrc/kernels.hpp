@@ -93,6 +93,11 @@ struct DevPlan {
     int32_t *mlp_row_leaf = nullptr; // leaf of the row
     int32_t *mlp_row_n = nullptr;    // elements in the row
     double2 *bj_inv = nullptr;
+    // The near field runs on `side`, concurrently with the far-field chain
+    // (fork after the permutation of x, join before L2T adds the far field);
+    // null: everything on the caller's stream.
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
 };
 
 hipError_t set_quadrature_constants(const double r7b[7][3], const double r7w[7], const double glx[32],
