@@ -65,7 +65,7 @@ def cpu_baseline(V, T, k, x, y_gpu, rows_sample, seconds_target=20.0):
                 seconds_per_matvec=full), err, rows, yr
 
 
-def uneven_batch_leg(nmesh, steps, log):
+def uneven_batch_leg(nmesh, steps, log, tune=True):
     """The seeded uneven batch (spheres and ellipsoids, N 5,120-81,920,
     kD 20-100): every plan's product run one after another on one stream,
     against all of them in one captured graph (fda_batch)."""
@@ -88,6 +88,18 @@ def uneven_batch_leg(nmesh, steps, log):
         ys.append(torch.empty_like(xs[-1]))
         nel += len(T)
     build_s = time.perf_counter() - t0
+    # the M2L launch autotuner per mesh (before the graph is captured)
+    tuned = dict(changed=0, m2l_ms_before=0.0, m2l_ms_after=0.0, seconds=0.0)
+    if tune:
+        t0 = time.perf_counter()
+        for p in plans:
+            r = p.autotune(reps=10)
+            tuned["changed"] += int(r["best"] != dict(variant=0, xcd_order=1,
+                                                       width={l: 32 for l in r["best"]["width"]}))
+            tuned["m2l_ms_before"] += r["ms_before"]
+            tuned["m2l_ms_after"] += r["ms_after"]
+        tuned = {q: (round(v, 3) if isinstance(v, float) else v) for q, v in tuned.items()}
+        tuned["seconds"] = round(time.perf_counter() - t0, 2)
     for p, x, y in zip(plans, xs, ys):
         p.matvec(x, out=y)
     torch.cuda.synchronize()
@@ -118,7 +130,7 @@ def uneven_batch_leg(nmesh, steps, log):
     out = dict(meshes=len(plans), skipped=len(skipped), elements=nel, build_seconds=round(build_s, 2),
                sequential_ms=round(seq_ms, 3), graph_ms=round(gr_ms, 3),
                batches_per_s=round(1000.0 / gr_ms, 3), graph_equals_sequential=bool(same),
-               skipped_cases=skipped[:4])
+               m2l_autotune=tuned if tune else None, skipped_cases=skipped[:4])
     log(f"[bench] uneven batch: {out}")
     return out
 
@@ -132,6 +144,7 @@ def main():
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fast", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="skip the M2L launch autotuner (fda_autotune) after the build")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run one plain device copy of this many MiB (calibrates HBM counters)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
@@ -169,6 +182,14 @@ def main():
     log(f"[bench] build {build_s:.2f} s; depth {st['depth']} top {st['top_level']} pairs {st['m2l_pairs']} "
         f"ranks {st['rank_up']} p {st['p']} m2l low-rank max {st['m2l_rank_max']} mean "
         f"{[round(v, 1) for v in st['m2l_rank_mean']]} level flops {[round(v / 1e9, 3) for v in st['m2l_level_flops']]} GF")
+
+    # the M2L launch autotuner (setup, outside the timed region)
+    tune = None
+    if not args.no_tune:
+        t0 = time.perf_counter()
+        tune = plan.autotune(reps=20)
+        tune["seconds"] = round(time.perf_counter() - t0, 3)
+        log(f"[bench] M2L autotune: {tune}")
 
     x = torch.from_numpy(W.complex_normal(n, 1, seed=0)).to("cuda")
     y = torch.empty_like(x)
@@ -280,6 +301,7 @@ def main():
     fast = {}
     if not args.no_fast:
         plan32 = Plan(V, T, k, prm["eps"], prec="fp32")
+        tune32 = None if args.no_tune else plan32.autotune(reps=20)
         y32 = torch.empty_like(x)
         for _ in range(args.warmup):
             plan32.matvec(x, out=y32)
@@ -292,7 +314,7 @@ def main():
         ms32 = e0.elapsed_time(e1) / args.steps
         prof32 = plan32.profile(x, reps=max(3, min(20, args.steps)), out=y32)
         fast = dict(matvecs_per_s=round(1000.0 / ms32, 3), ms_per_matvec=round(ms32, 4),
-                    stages_ms={q: round(v, 4) for q, v in prof32.items() if q != "m2l_gemm"})
+                    stages_ms={q: round(v, 4) for q, v in prof32.items() if q != "m2l_gemm"}, m2l_autotune=tune32)
         if prof32["m2l_lowrank"] > 0:
             a32 = lr_flops / (prof32["m2l_lowrank"] * 1e-3) / 1e12
             fast["m2l_roofline"] = dict(achieved=round(a32, 3), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
@@ -325,7 +347,7 @@ def main():
 
     batch = {}
     if args.batch > 0:
-        batch = uneven_batch_leg(args.batch, args.steps, log)
+        batch = uneven_batch_leg(args.batch, args.steps, log, tune=not args.no_tune)
 
     cpu, err = (None, None)
     if not args.no_cpu:
@@ -351,6 +373,7 @@ def main():
         "config": {"workload": args.workload, "N": n, "k": k, "kD": k * 2 * prm["radius"],
                    "eps": prm["eps"], "nrhs": 1, "arm": "plain FP64"},
         "build_seconds": round(build_s, 3),
+        "m2l_autotune": tune,
         "build_phase_seconds": [round(v, 3) for v in st["build_phase_seconds"][:7]],
         "stages_ms": {q: round(v, 4) for q, v in prof.items() if q != "m2l_gemm"},
         "m2l_lowrank_ms": round(prof["m2l_lowrank"], 4),

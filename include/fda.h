@@ -316,6 +316,52 @@ typedef struct fda_profile_result {
                                    low-rank level (without its reduction) */
 } fda_profile_result;
 
+/* Configuration of the merged low-rank M2L launch (Section 4.2: the
+ * reduced translations grouped by translation into batched products).  The
+ * kernel variant and the item order do not change the product (bit for bit);
+ * the width changes how the waves of an item split the first product's
+ * k-loop, so products of different widths agree to rounding.
+ *   variant    kernel variant 0 .. FDA_M2L_VARIANTS - 1 (register-ring depths
+ *              of the two product phases)
+ *   xcd_order  1: work items dealt into eight per-XCD queues (block b runs on
+ *              XCD b mod 8), 0: items in translation order
+ *   width[l]   pairs per work item at tree level l: 32 or 16 (translations of
+ *              rank above 64 always take 16); 0 for levels without low-rank M2L */
+#define FDA_M2L_VARIANTS 4
+typedef struct fda_m2l_config {
+    int32_t variant;
+    int32_t xcd_order;
+    int32_t width[24];
+} fda_m2l_config;
+
+/* The plan's current configuration (the default after fda_build: variant 0,
+ * xcd_order 1, width 32).  Errors: FDA_EINVAL. */
+int fda_m2l_get_config(const fda_plan *plan, fda_m2l_config *out);
+
+/* Rebuild the merged M2L work list for *cfg (width entries of levels without
+ * low-rank M2L are ignored).  Synchronises the device first (the old list
+ * may be in use); not for use during graph capture.  Errors: FDA_EINVAL
+ * (variant out of range, xcd_order not 0/1, a width other than 16 or 32),
+ * FDA_ENOMEM, FDA_EHIP; on error the previous configuration stays. */
+int fda_m2l_set_config(fda_plan *plan, const fda_m2l_config *cfg);
+
+/* Autotuner of the merged M2L launch: starting from the current
+ * configuration it times (HIP events on `stream`, median of `reps` launches
+ * of the M2L product kernel plus its reduction, one right-hand side) every
+ * kernel variant, then the other item order, then width 16 / 32 per level,
+ * keeping a change when it is at least 1 % faster, and leaves the plan in the
+ * best configuration found.  The plan's work buffers are overwritten.
+ * Synchronous.  Errors: FDA_EINVAL (reps < 1 or > 1000), FDA_ENOMEM,
+ * FDA_EHIP. */
+typedef struct fda_tune_result {
+    fda_m2l_config best;
+    double ms_before;    /* configuration on entry */
+    double ms_after;     /* best configuration, timed again */
+    int32_t candidates;  /* configurations timed */
+    int32_t nlevels;     /* low-rank levels in the merged launch */
+} fda_tune_result;
+int fda_autotune(fda_plan *plan, int32_t reps, void *stream, fda_tune_result *out);
+
 /* Profile fda_matvec: x_dev/y_dev as in fda_matvec.  Synchronous. */
 int fda_profile_matvec(fda_plan *plan, const void *x_dev, void *y_dev, int64_t nrhs, int64_t ld, int32_t reps,
                        void *stream, fda_profile_result *out);

@@ -43,6 +43,20 @@ struct fda_plan {
     fda_stats stats{};
     int64_t device_bytes = 0;
     double m2m_flops = 0, l2l_flops = 0;  // per upward / downward pass
+    // The low-rank M2L pairs of every merged level stay on the host so that
+    // the merged work list can be rebuilt for another configuration
+    // (fda_m2l_set_config, fda_autotune).
+    struct M2LLevelHost {
+        int level = 0;
+        int64_t nstates = 0;                                          // states of the level
+        std::vector<std::vector<std::pair<int32_t, int32_t>>> by_op;  // per translation: (source, target) state
+        std::vector<int32_t> prank;                                   // padded rank per translation
+        fda::M2LLevelArgs la;                                         // tbase set when the list is built
+    };
+    std::vector<M2LLevelHost> m2l_host;
+    std::vector<void *> m2l_allocs;  // device arrays of the merged list
+    int64_t m2l_bytes = 0;
+    fda_m2l_config m2l_cfg{};
 };
 
 namespace {
@@ -248,6 +262,135 @@ void quadrature_constants() {
     hip_check(set_quadrature_constants(b, w, gx, gw), "quadrature constants");
 }
 
+template <class T>
+T *upload_to(fda_plan *p, const std::vector<T> &v, std::vector<void *> &list) {
+    T *d = dalloc<T>(p, v.size(), list);
+    if (!v.empty()) hip_check(hipMemcpy(d, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice), "upload");
+    return d;
+}
+
+void build_m2l_list(fda_plan *p, M2LMerged &mm, std::vector<void *> &fresh);
+
+// The merged low-rank M2L work list of the plan's configuration p->m2l_cfg:
+// per level, the pairs of every translation in work items of `width` pairs
+// (16 for ranks above 64: the kernel holds at most 8 phase-1 tiles per item)
+// and a reduction entry for every state of the level, summing its pair
+// products in a fixed order (translation, then pair: the same for every
+// configuration).  The new device arrays
+// replace the previous list's only once all of them are in place (on an
+// error the previous list stays); the caller has made sure that none of the
+// previous arrays is in use.
+void build_m2l_merged(fda_plan *p) {
+    std::vector<void *> fresh;
+    const int64_t bytes0 = p->device_bytes;
+    M2LMerged nm;
+    try {
+        build_m2l_list(p, nm, fresh);
+    } catch (...) {
+        for (void *q : fresh) hipFree(q);
+        p->device_bytes = bytes0;
+        throw;
+    }
+    M2LMerged &mm = p->d.m2l_all;
+    nm.tmp = mm.tmp;
+    mm = std::move(nm);
+    for (void *q : p->m2l_allocs) hipFree(q);
+    p->device_bytes -= p->m2l_bytes;
+    p->m2l_allocs = std::move(fresh);
+    p->m2l_bytes = p->device_bytes - bytes0;
+}
+
+void build_m2l_list(fda_plan *p, M2LMerged &mm, std::vector<void *> &fresh) {
+    std::vector<int32_t> hdr, src, dst, off{0}, list, lev;
+    std::vector<std::vector<int32_t>> queue[8];  // per XCD queue (or queue 0 only): header + sources of each item
+    std::vector<M2LLevelArgs> args;
+    int64_t nscratch = 0;
+    const bool xcd = p->m2l_cfg.xcd_order != 0;
+    for (const auto &lh : p->m2l_host) {
+        const size_t width = p->m2l_cfg.width[lh.level] == 16 ? 16 : kGemmCols;
+        GWorkHost g;
+        for (size_t op = 0; op < lh.by_op.size(); ++op) {
+            const auto &v = lh.by_op[op];
+            const size_t step = lh.prank[op] > 64 ? 16 : width;
+            for (size_t q0 = 0; q0 < v.size(); q0 += step) {
+                size_t q1 = std::min(v.size(), q0 + step);
+                std::vector<int32_t> srcs, dsts;
+                for (size_t q = q0; q < q1; ++q) {
+                    srcs.push_back(v[q].first);
+                    dsts.push_back(v[q].second);
+                }
+                g.add((int32_t)op, srcs, dsts);
+            }
+        }
+        const int slot = (int)args.size();
+        M2LLevelArgs la = lh.la;
+        la.tbase = nscratch;
+        args.push_back(la);
+        nscratch += g.ncol * (int64_t)la.kd;
+        // XCD order: each level's items are split into 8 contiguous chunks,
+        // one per XCD queue, so every XCD gets the same share of every level
+        // (and consecutive items of a translation share an L2)
+        const int64_t ni = (int64_t)g.hdr.size() / 4;
+        for (int x = 0; x < (xcd ? 8 : 1); ++x)
+            for (int64_t i = xcd ? ni * x / 8 : 0; i < (xcd ? ni * (x + 1) / 8 : ni); ++i) {
+                std::vector<int32_t> item{g.hdr[4 * i], g.hdr[4 * i + 1], g.hdr[4 * i + 2], slot};
+                item.insert(item.end(), g.src.begin() + i * kGemmCols, g.src.begin() + (i + 1) * kGemmCols);
+                queue[x].push_back(std::move(item));
+            }
+        for (int64_t s = 0; s < lh.nstates; ++s) {
+            dst.push_back((int32_t)s);
+            lev.push_back(slot);
+            auto it = g.dest_index.find((int32_t)s);
+            if (it != g.dest_index.end()) {
+                const auto &pl = g.parts[it->second];
+                list.insert(list.end(), pl.begin(), pl.end());
+            }
+            off.push_back((int32_t)list.size());
+        }
+    }
+    // launch order: XCD order has block b run on XCD b % 8 (round-robin
+    // dispatch) take item b / 8 of that XCD's queue, short queues padded
+    // with empty items; otherwise block b takes item b
+    size_t qmax = 0;
+    for (auto &q : queue) qmax = std::max(qmax, q.size());
+    for (size_t t = 0; t < qmax; ++t)
+        for (int x = 0; x < (xcd ? 8 : 1); ++x) {
+            if (t < queue[x].size()) {
+                const auto &it = queue[x][t];
+                hdr.insert(hdr.end(), it.begin(), it.begin() + 4);
+                src.insert(src.end(), it.begin() + 4, it.end());
+            } else {
+                hdr.insert(hdr.end(), {0, 0, 0, 0});
+                src.insert(src.end(), kGemmCols, -1);
+            }
+        }
+    mm.nwork = (int)(hdr.size() / 4);
+    mm.nred = (int)dst.size();
+    mm.nlev = (int)args.size();
+    mm.nscratch = nscratch;
+    mm.hargs = args;
+    mm.variant = p->m2l_cfg.variant;
+    if (mm.nwork > 0) {
+        mm.hdr = (int4 *)upload_to(p, hdr, fresh);
+        mm.src = upload_to(p, src, fresh);
+        mm.rd_dst = upload_to(p, dst, fresh);
+        mm.rd_off = upload_to(p, off, fresh);
+        mm.rd_list = upload_to(p, list, fresh);
+        mm.rd_lev = upload_to(p, lev, fresh);
+        mm.args = dalloc<M2LLevelArgs>(p, args.size(), fresh);
+        if (p->cap_nrhs > 0) {
+            // work buffers exist: point the level table at them
+            for (auto &la : mm.hargs) {
+                la.X = p->d.lv[la.level].s;
+                la.Y = p->d.lv[la.level].c;
+            }
+            hip_check(hipMemcpy(mm.args, mm.hargs.data(), sizeof(M2LLevelArgs) * mm.hargs.size(),
+                                hipMemcpyHostToDevice),
+                      "M2L level table");
+        }
+    }
+}
+
 void upload_plan(fda_plan *p, const HostOps &ops, DevTranslations &tr) {
     HostPlan &hp = p->hp;
     DevPlan &d = p->d;
@@ -260,6 +403,8 @@ void upload_plan(fda_plan *p, const HostOps &ops, DevTranslations &tr) {
     d.k = hp.k;
     d.h_max = hp.h_max;
     d.alpha = make_double2(hp.alpha.real(), hp.alpha.imag());
+    p->m2l_cfg.variant = 0;
+    p->m2l_cfg.xcd_order = 1;
     bool any = false;
     for (int l = hp.top; l <= L; ++l)
         if (!hp.lv[l].offsets.empty()) any = true;
@@ -335,12 +480,6 @@ void upload_plan(fda_plan *p, const HostOps &ops, DevTranslations &tr) {
     if (!d.has_far) return;
     d.S = to_storage(p, upload_cplx(p, ops.S), ops.S.size());
     d.T = to_storage(p, upload_cplx(p, ops.T), ops.T.size());
-    struct {
-        std::vector<int32_t> hdr, src, dst, off{0}, list, lev;
-        std::vector<std::vector<int32_t>> xcd[8];  // per XCD queue: header + sources of each item
-        std::vector<M2LLevelArgs> args;
-        int64_t nscratch = 0;
-    } mh;  // merged low-rank M2L work list
     for (int l = hp.top; l <= L; ++l) {
         const Level &lv = hp.lv[l];
         DevLevel &dl = d.lv[l];
@@ -377,60 +516,40 @@ void upload_plan(fda_plan *p, const HostOps &ops, DevTranslations &tr) {
                     const int rt = tr.true_rank[l][op];
                     prank[op] = std::min(std::min(lv.kd, lv.ku), (rt + 3) / 4 * 4);
                 }
-            GWorkHost g;
-            for (size_t op = 0; op < no; ++op) {
-                const auto &v = by_op[op];
-                const size_t step = prank[op] > 64 ? 16 : kGemmCols;
-                for (size_t q0 = 0; q0 < v.size(); q0 += step) {
-                    size_t q1 = std::min(v.size(), q0 + step);
-                    std::vector<int32_t> srcs, dsts;
-                    for (size_t q = q0; q < q1; ++q) {
-                        srcs.push_back(v[q].first);
-                        dsts.push_back(v[q].second);
-                    }
-                    g.add((int32_t)op, srcs, dsts);
-                }
-            }
             if (dl.rmax > 0) {
-                // low-rank level: its items and every one of its states go to
-                // the merged list (states without pairs get an empty sum)
+                // low-rank level: its pairs go to the merged list, built
+                // below for the plan's configuration
                 dl.merged = true;
-                const int slot = (int)mh.args.size();
-                M2LLevelArgs la;
-                la.U = dl.Ulr;
-                la.V = dl.Vlr;
-                la.rank = dl.lr_rank;
-                la.kd = lv.kd;
-                la.ku = lv.ku;
-                la.rmax = dl.rmax;
-                la.level = l;
-                la.tbase = mh.nscratch;
-                la.xstride = dl.sstride;
-                la.ystride = dl.cstride;
-                mh.args.push_back(la);
-                mh.nscratch += g.ncol * (int64_t)lv.kd;
-                // each level's items are split into 8 contiguous chunks, one
-                // per XCD queue, so every XCD gets the same share of every
-                // level (and consecutive items of a translation share an L2)
-                const int64_t ni = (int64_t)g.hdr.size() / 4;
-                for (int x = 0; x < 8; ++x)
-                    for (int64_t i = ni * x / 8; i < ni * (x + 1) / 8; ++i) {
-                        std::vector<int32_t> item{g.hdr[4 * i], g.hdr[4 * i + 1], g.hdr[4 * i + 2], slot};
-                        item.insert(item.end(), g.src.begin() + i * kGemmCols, g.src.begin() + (i + 1) * kGemmCols);
-                        mh.xcd[x].push_back(std::move(item));
-                    }
-                const int64_t nst = lv.nbox * (int64_t)lv.nslot;
-                for (int64_t s = 0; s < nst; ++s) {
-                    mh.dst.push_back((int32_t)s);
-                    mh.lev.push_back(slot);
-                    auto it = g.dest_index.find((int32_t)s);
-                    if (it != g.dest_index.end()) {
-                        const auto &pl = g.parts[it->second];
-                        mh.list.insert(mh.list.end(), pl.begin(), pl.end());
-                    }
-                    mh.off.push_back((int32_t)mh.list.size());
-                }
+                fda_plan::M2LLevelHost lh;
+                lh.level = l;
+                lh.nstates = lv.nbox * (int64_t)lv.nslot;
+                lh.by_op = std::move(by_op);
+                lh.prank = std::move(prank);
+                lh.la.U = dl.Ulr;
+                lh.la.V = dl.Vlr;
+                lh.la.rank = dl.lr_rank;
+                lh.la.kd = lv.kd;
+                lh.la.ku = lv.ku;
+                lh.la.rmax = dl.rmax;
+                lh.la.level = l;
+                lh.la.xstride = dl.sstride;
+                lh.la.ystride = dl.cstride;
+                p->m2l_host.push_back(std::move(lh));
+                p->m2l_cfg.width[l] = kGemmCols;
             } else {
+                GWorkHost g;
+                for (size_t op = 0; op < no; ++op) {
+                    const auto &v = by_op[op];
+                    for (size_t q0 = 0; q0 < v.size(); q0 += kGemmCols) {
+                        size_t q1 = std::min(v.size(), q0 + kGemmCols);
+                        std::vector<int32_t> srcs, dsts;
+                        for (size_t q = q0; q < q1; ++q) {
+                            srcs.push_back(v[q].first);
+                            dsts.push_back(v[q].second);
+                        }
+                        g.add((int32_t)op, srcs, dsts);
+                    }
+                }
                 dl.m2l = upload_gwork(p, g);
             }
         }
@@ -484,36 +603,7 @@ void upload_plan(fda_plan *p, const HostOps &ops, DevTranslations &tr) {
             p->l2l_flops += 8.0 * C.kd * lv.kd * (double)gl.ncol;
         }
     }
-    // launch order: block b runs on XCD b % 8 (round-robin dispatch) and takes
-    // item b / 8 of that XCD's queue; short queues are padded with empty items
-    size_t qmax = 0;
-    for (auto &q : mh.xcd) qmax = std::max(qmax, q.size());
-    for (size_t t = 0; t < qmax; ++t)
-        for (int x = 0; x < 8; ++x) {
-            if (t < mh.xcd[x].size()) {
-                const auto &it = mh.xcd[x][t];
-                mh.hdr.insert(mh.hdr.end(), it.begin(), it.begin() + 4);
-                mh.src.insert(mh.src.end(), it.begin() + 4, it.end());
-            } else {
-                mh.hdr.insert(mh.hdr.end(), {0, 0, 0, 0});
-                mh.src.insert(mh.src.end(), kGemmCols, -1);
-            }
-        }
-    M2LMerged &mm = d.m2l_all;
-    mm.nwork = (int)(mh.hdr.size() / 4);
-    mm.nred = (int)mh.dst.size();
-    mm.nlev = (int)mh.args.size();
-    mm.nscratch = mh.nscratch;
-    mm.hargs = mh.args;
-    if (mm.nwork > 0) {
-        mm.hdr = (int4 *)upload(p, mh.hdr);
-        mm.src = upload(p, mh.src);
-        mm.rd_dst = upload(p, mh.dst);
-        mm.rd_off = upload(p, mh.off);
-        mm.rd_list = upload(p, mh.list);
-        mm.rd_lev = upload(p, mh.lev);
-        mm.args = dalloc<M2LLevelArgs>(p, mh.args.size(), p->allocs);
-    }
+    build_m2l_merged(p);
 }
 
 hipStream_t as_stream(void *s) { return (hipStream_t)s; }
@@ -728,6 +818,7 @@ void fda_free(fda_plan *plan) {
         hipEventDestroy(plan->d.join);
     }
     free_work(plan);
+    for (void *q : plan->m2l_allocs) hipFree(q);
     for (void *q : plan->allocs) hipFree(q);
     delete plan;
 }
@@ -812,6 +903,137 @@ int fda_profile_matvec(fda_plan *plan, const void *x_dev, void *y_dev, int64_t n
     }
     for (auto &e : ev) hipEventDestroy(e);
     for (auto &e : lev) hipEventDestroy(e);
+    return rc;
+}
+
+int fda_m2l_get_config(const fda_plan *plan, fda_m2l_config *out) {
+    g_last_error.clear();
+    if (!plan || !out) return fail(FDA_EINVAL, "NULL argument");
+    *out = plan->m2l_cfg;
+    for (int l = 0; l < 24; ++l) out->width[l] = 0;
+    for (const auto &lh : plan->m2l_host) out->width[lh.level] = plan->m2l_cfg.width[lh.level];
+    return FDA_OK;
+}
+
+namespace {
+
+// Switch the plan to configuration c (rebuilding the merged list when the
+// order or a width changes); the device is idle on return.
+void apply_m2l_config(fda_plan *p, const fda_m2l_config &c) {
+    hip_check(hipDeviceSynchronize(), "sync");
+    const fda_m2l_config old = p->m2l_cfg;
+    bool rebuild = c.xcd_order != old.xcd_order;
+    for (const auto &lh : p->m2l_host) rebuild = rebuild || c.width[lh.level] != old.width[lh.level];
+    p->m2l_cfg.variant = c.variant;
+    p->m2l_cfg.xcd_order = c.xcd_order;
+    for (const auto &lh : p->m2l_host) p->m2l_cfg.width[lh.level] = c.width[lh.level];
+    if (rebuild) {
+        try {
+            build_m2l_merged(p);
+        } catch (...) {
+            p->m2l_cfg = old;
+            throw;
+        }
+    }
+    p->d.m2l_all.variant = p->m2l_cfg.variant;
+}
+
+}  // namespace
+
+int fda_m2l_set_config(fda_plan *plan, const fda_m2l_config *cfg) {
+    g_last_error.clear();
+    if (!plan || !cfg) return fail(FDA_EINVAL, "NULL argument");
+    if (cfg->variant < 0 || cfg->variant >= kM2LVariants) return fail(FDA_EINVAL, "variant out of range");
+    if (cfg->xcd_order != 0 && cfg->xcd_order != 1) return fail(FDA_EINVAL, "xcd_order must be 0 or 1");
+    for (const auto &lh : plan->m2l_host)
+        if (cfg->width[lh.level] != 16 && cfg->width[lh.level] != 32)
+            return fail(FDA_EINVAL, "width must be 16 or 32 on level " + std::to_string(lh.level));
+    try {
+        hip_check(hipSetDevice(plan->device), "hipSetDevice");
+        apply_m2l_config(plan, *cfg);
+    } catch (const BuildError &e) {
+        return fail(e.code, e.msg);
+    } catch (const HipError &e) {
+        return fail(FDA_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
+    }
+    return FDA_OK;
+}
+
+int fda_autotune(fda_plan *plan, int32_t reps, void *stream, fda_tune_result *out) {
+    g_last_error.clear();
+    if (!plan || !out) return fail(FDA_EINVAL, "NULL argument");
+    if (reps < 1 || reps > 1000) return fail(FDA_EINVAL, "reps out of range");
+    std::memset(out, 0, sizeof(*out));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = FDA_OK;
+    try {
+        hip_check(hipSetDevice(plan->device), "hipSetDevice");
+        hip_check(hipEventCreate(&e0), "event");
+        hip_check(hipEventCreate(&e1), "event");
+        hipStream_t st = as_stream(stream);
+        out->nlevels = (int32_t)plan->m2l_host.size();
+        if (plan->d.m2l_all.nwork > 0) {
+            ensure_capacity(plan, 1);
+            // current states everywhere: one product of the zero vector
+            hip_check(hipMemsetAsync(plan->xt, 0, sizeof(double2) * (size_t)plan->d.n, st), "memset");
+            hip_check(launch_matvec_tree(plan->d, plan->xt, plan->yt, 1, st, nullptr, nullptr), "matvec");
+            hip_check(hipStreamSynchronize(st), "sync");
+            // median of reps launches of the merged M2L (after one untimed)
+            auto time_m2l = [&]() {
+                hip_check(launch_m2l_merged(plan->d, 1, st), "M2L");
+                std::vector<float> t(reps);
+                for (int r = 0; r < reps; ++r) {
+                    hip_check(hipEventRecord(e0, st), "event");
+                    hip_check(launch_m2l_merged(plan->d, 1, st), "M2L");
+                    hip_check(hipEventRecord(e1, st), "event");
+                    hip_check(hipEventSynchronize(e1), "sync");
+                    hip_check(hipEventElapsedTime(&t[r], e0, e1), "elapsed");
+                }
+                std::sort(t.begin(), t.end());
+                ++out->candidates;
+                return (double)t[reps / 2];
+            };
+            fda_m2l_config cur = plan->m2l_cfg;
+            double best = time_m2l();
+            out->ms_before = best;
+            auto trial = [&](const fda_m2l_config &c) {
+                apply_m2l_config(plan, c);
+                const double t = time_m2l();
+                if (t < 0.99 * best) {
+                    best = t;
+                    cur = c;
+                } else {
+                    apply_m2l_config(plan, cur);
+                }
+            };
+            const int v0 = cur.variant;
+            for (int v = 0; v < kM2LVariants; ++v) {
+                if (v == v0) continue;
+                fda_m2l_config c = cur;
+                c.variant = v;
+                trial(c);
+            }
+            {
+                fda_m2l_config c = cur;
+                c.xcd_order = 1 - c.xcd_order;
+                trial(c);
+            }
+            for (const auto &lh : plan->m2l_host) {
+                fda_m2l_config c = cur;
+                c.width[lh.level] = c.width[lh.level] == 16 ? 32 : 16;
+                trial(c);
+            }
+            out->ms_after = time_m2l();
+            --out->candidates;  // the final timing repeats the chosen one
+        }
+        fda_m2l_get_config(plan, &out->best);
+    } catch (const HipError &e) {
+        rc = fail(FDA_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
+    } catch (const BuildError &e) {
+        rc = fail(e.code, e.msg);
+    }
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
     return rc;
 }
 

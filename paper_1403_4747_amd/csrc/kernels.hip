@@ -334,12 +334,29 @@ __global__ void k_s2m(const int64_t *leaf_off, const C *S, int ku, const double2
 #ifndef FDA_M2L_DIRECT32
 #define FDA_M2L_DIRECT32 0  // FP32 phase 1: staged through LDS
 #endif
-#ifndef M2L_P1D
-#define M2L_P1D 4  // phase-1 k-steps in flight per wave (direct form)
-#endif
-#ifndef M2L_PD
-#define M2L_PD 5  // phase-2 factor fragments in flight (k-steps of look-ahead + 1)
-#endif
+// Variants of the low-rank M2L kernel (chosen per plan, fda_autotune):
+// k-steps in flight in the register rings of phase 1 (direct form; waves
+// with two / one row tiles) and of phase 2.  Every variant runs at 4 FP64
+// waves per SIMD without spills and gives bit-identical results.
+template <int VAR>
+struct M2LVariant;
+template <>
+struct M2LVariant<0> {
+    static constexpr int p1d = 4, p1d1 = 4, pd = 5;
+};
+template <>
+struct M2LVariant<1> {
+    static constexpr int p1d = 2, p1d1 = 4, pd = 2;
+};
+template <>
+struct M2LVariant<2> {
+    static constexpr int p1d = 4, p1d1 = 6, pd = 6;
+};
+template <>
+struct M2LVariant<3> {
+    static constexpr int p1d = 3, p1d1 = 4, pd = 3;
+};
+static_assert(kM2LVariants == 4, "one M2LVariant per variant index");
 
 // Load up to GG_J x GG_NB gathered input values (zero padded) into LDS.
 template <class C>
@@ -677,7 +694,7 @@ __device__ __forceinline__ void m2l_p1_direct(CAcc<C, FDA_M2L_3M> *zacc, const C
 // work list, scratch layout and reduction as k_ggemm.  Phase 1 spreads its
 // (row tile, column tile) outputs over the 4 waves round-robin so that the
 // usual ranks (r <= 32, two column tiles: four tiles) keep every wave busy.
-template <class C, int NCT>
+template <class C, int NCT, int P1D, int P1D1, int PD>
 __device__ __forceinline__ void m2l_body(const int4 h, const int32_t *sidx, const C *Ut, const C *Vt, int r, int kd,
                                          int ku, int rmax, const C *Xr, C *Tr, C (*S)[GG_LD], C (*Vs)[LR_LD],
                                          C (*Z)[GG_LD]) {
@@ -702,7 +719,7 @@ __device__ __forceinline__ void m2l_body(const int4 h, const int32_t *sidx, cons
     for (int q = 0; q < ZQ; ++q) zacc[q].zero();
     if constexpr (M2LOcc<C>::direct) {
         // Every wave multiplies its own tiles with operands loaded straight from
-        // memory into MFMA registers, M2L_P1D k-steps ahead of their use: the
+        // memory into MFMA registers, P1D (P1D1) k-steps ahead of their use: the
         // V^ rows of its row tiles and the gathered state columns of its column
         // tile (all tiles of a wave share one column tile: the tile stride is 4
         // and NCT divides 4).  No LDS staging and no barriers in the k loop.
@@ -721,9 +738,9 @@ __device__ __forceinline__ void m2l_body(const int4 h, const int32_t *sidx, cons
 #pragma unroll
             for (int q = 0; q < ZQ; ++q) vrow[q] = Vt + min(((tbase + tstep * q) / NCT) * 16 + li, rmax - 1);
             if (tbase + tstep < ntz)
-                m2l_p1_direct<C, 2, M2L_P1D>(zacc, xcol, vrow, rmax, ku, 4 * kg, 4 * kg_n, lk);
+                m2l_p1_direct<C, 2, P1D>(zacc, xcol, vrow, rmax, ku, 4 * kg, 4 * kg_n, lk);
             else
-                m2l_p1_direct<C, 1, M2L_P1D>(zacc, xcol, vrow, rmax, ku, 4 * kg, 4 * kg_n, lk);
+                m2l_p1_direct<C, 1, P1D1>(zacc, xcol, vrow, rmax, ku, 4 * kg, 4 * kg_n, lk);
         }
     } else {
         // the next chunk is fetched into registers while the current one is
@@ -839,7 +856,6 @@ __device__ __forceinline__ void m2l_body(const int4 h, const int32_t *sidx, cons
         // unconditional: rows from kd on are clamped (they feed output rows
         // that are never stored) and so are columns from r on (prefetches
         // past the last step, never used).
-        constexpr int PD = M2L_PD;
         C af[PD][P2];
         const C *urow[P2];
 #pragma unroll
@@ -897,7 +913,7 @@ __device__ __forceinline__ void m2l_body(const int4 h, const int32_t *sidx, cons
 
 // One launch for the low-rank M2L of every level: the item's level slot
 // (h.w) selects its factors, states and scratch region.
-template <class C>
+template <class C, int VAR>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M2LOcc<C>::waves)))
 k_m2l_lowrank(const int4 *hdr, const int32_t *src, const M2LLevelArgs *args, C *T, int64_t tstride, int nwork) {
     // LDS: phase 1 stages S (LRJ x GG_LD) and V^ (LRJ x LR_LD); phase 2
@@ -924,10 +940,11 @@ k_m2l_lowrank(const int4 *hdr, const int32_t *src, const M2LLevelArgs *args, C *
     C *Tr = T + (int64_t)blockIdx.y * tstride + la.tbase + (int64_t)h.y * kd;
     const C *Vt = (const C *)la.V + (int64_t)op * rmax * ((ku + 3) & ~3);
     const C *Ut = (const C *)la.U + (int64_t)op * kd * rmax;
+    using V = M2LVariant<VAR>;
     if (h.z > 16)
-        m2l_body<C, 2>(h, sidx, Ut, Vt, r, kd, ku, rmax, Xr, Tr, S, Vs, Z);
+        m2l_body<C, 2, V::p1d, V::p1d1, V::pd>(h, sidx, Ut, Vt, r, kd, ku, rmax, Xr, Tr, S, Vs, Z);
     else
-        m2l_body<C, 1>(h, sidx, Ut, Vt, r, kd, ku, rmax, Xr, Tr, S, Vs, Z);
+        m2l_body<C, 1, V::p1d, V::p1d1, V::pd>(h, sidx, Ut, Vt, r, kd, ku, rmax, Xr, Tr, S, Vs, Z);
 }
 
 // c[dst] = sum of the M2L scratch columns listed for dst (every state of the
@@ -1328,6 +1345,38 @@ static hipError_t ggemm_t(const GWork &g, const void *A, int m, int kin, const v
     return hipSuccess;
 }
 
+// The merged low-rank M2L of all levels: the product kernel (variant
+// mm.variant; ev[0], ev[1] around it when given) and the reduction of its
+// scratch columns into the incoming states.
+template <class C>
+static hipError_t m2l_merged_t(const M2LMerged &mm, int nrhs, hipStream_t st, hipEvent_t *ev) {
+    const dim3 g2(mm.nwork, nrhs);  // grid ordered for XCD dispatch (or translation order)
+    if (ev) hipEventRecord(ev[0], st);
+    switch (mm.variant) {
+    case 1:
+        hipLaunchKernelGGL((k_m2l_lowrank<C, 1>), g2, dim3(256), 0, st, mm.hdr, mm.src, mm.args, (C *)mm.tmp,
+                           mm.nscratch, mm.nwork);
+        break;
+    case 2:
+        hipLaunchKernelGGL((k_m2l_lowrank<C, 2>), g2, dim3(256), 0, st, mm.hdr, mm.src, mm.args, (C *)mm.tmp,
+                           mm.nscratch, mm.nwork);
+        break;
+    case 3:
+        hipLaunchKernelGGL((k_m2l_lowrank<C, 3>), g2, dim3(256), 0, st, mm.hdr, mm.src, mm.args, (C *)mm.tmp,
+                           mm.nscratch, mm.nwork);
+        break;
+    default:
+        hipLaunchKernelGGL((k_m2l_lowrank<C, 0>), g2, dim3(256), 0, st, mm.hdr, mm.src, mm.args, (C *)mm.tmp,
+                           mm.nscratch, mm.nwork);
+    }
+    CHECK_LAUNCH();
+    if (ev) hipEventRecord(ev[1], st);
+    hipLaunchKernelGGL(k_gather_reduce_m2l<C>, dim3(mm.nred, nrhs), dim3(128), 0, st, mm.rd_dst, mm.rd_off,
+                       mm.rd_list, mm.rd_lev, mm.args, (const C *)mm.tmp, mm.nscratch);
+    CHECK_LAUNCH();
+    return hipSuccess;
+}
+
 #ifndef FDA_NEAR_FORK
 #define FDA_NEAR_FORK 1  // 0: the side-stream near field starts with the matvec; 1: with the M2L
 #endif
@@ -1391,17 +1440,9 @@ static hipError_t matvec_t(const DevPlan &d, const double2 *xt, double2 *yt, int
         const hipError_t e = near_side();
         if (e != hipSuccess) return e;
     }
-    const M2LMerged &mm = d.m2l_all;
-    if (mm.nwork > 0) {
-        const int grid = mm.nwork;  // a multiple of 8, ordered for XCD dispatch
-        if (lev) hipEventRecord(lev[2 * 24], st);
-        hipLaunchKernelGGL(k_m2l_lowrank<C>, dim3(grid, nrhs), dim3(256), 0, st, mm.hdr, mm.src, mm.args, (C *)mm.tmp,
-                           mm.nscratch, mm.nwork);
-        CHECK_LAUNCH();
-        if (lev) hipEventRecord(lev[2 * 24 + 1], st);
-        hipLaunchKernelGGL(k_gather_reduce_m2l<C>, dim3(mm.nred, nrhs), dim3(128), 0, st, mm.rd_dst, mm.rd_off,
-                           mm.rd_list, mm.rd_lev, mm.args, (const C *)mm.tmp, mm.nscratch);
-        CHECK_LAUNCH();
+    if (d.m2l_all.nwork > 0) {
+        const hipError_t e = m2l_merged_t<C>(d.m2l_all, nrhs, st, lev ? lev + 48 : nullptr);
+        if (e != hipSuccess) return e;
     }
     for (int l = top; l <= L; ++l) {
         const DevLevel &lv = d.lv[l];
@@ -1435,6 +1476,12 @@ hipError_t launch_matvec_tree(const DevPlan &d, const double2 *xt, double2 *yt, 
                               hipEvent_t *ev, hipEvent_t *lev) {
     if (d.prec == 1) return matvec_t<float2>(d, xt, yt, nrhs, st, ev, lev);
     return matvec_t<double2>(d, xt, yt, nrhs, st, ev, lev);
+}
+
+hipError_t launch_m2l_merged(const DevPlan &d, int nrhs, hipStream_t st) {
+    if (d.m2l_all.nwork == 0) return hipSuccess;
+    if (d.prec == 1) return m2l_merged_t<float2>(d.m2l_all, nrhs, st, nullptr);
+    return m2l_merged_t<double2>(d.m2l_all, nrhs, st, nullptr);
 }
 
 hipError_t launch_permute_in(const DevPlan &d, const double2 *x, int64_t ld, double2 *xt, int nrhs, hipStream_t st) {

@@ -36,8 +36,11 @@ struct M2LLevelArgs {
     int64_t tbase = 0;                      // first scratch element of the level
     int32_t kd = 0, ku = 0, rmax = 0, level = 0;
 };
+constexpr int kM2LVariants = 4;  // ring-depth variants of the low-rank M2L kernel
+
 struct M2LMerged {
     int nwork = 0, nred = 0, nlev = 0;
+    int variant = 0;                       // kernel variant, 0 .. kM2LVariants - 1
     int64_t nscratch = 0;                  // scratch elements per right-hand side
     int4 *hdr = nullptr;                   // (translation, level-local scratch column, columns, level slot)
     int32_t *src = nullptr;
@@ -110,6 +113,9 @@ hipError_t launch_to_f32(const double2 *in, void *out, int64_t n, hipStream_t st
 // product kernel, or null.
 hipError_t launch_matvec_tree(const DevPlan &d, const double2 *xt, double2 *yt, int nrhs, hipStream_t st,
                               hipEvent_t *ev, hipEvent_t *lev);
+// the merged low-rank M2L alone (product kernel and reduction); the
+// outgoing states of the merged levels must be current
+hipError_t launch_m2l_merged(const DevPlan &d, int nrhs, hipStream_t st);
 hipError_t launch_permute_in(const DevPlan &d, const double2 *x, int64_t ld, double2 *xt, int nrhs, hipStream_t st);
 hipError_t launch_permute_out(const DevPlan &d, const double2 *yt, double2 *y, int64_t ld, int nrhs, hipStream_t st);
 hipError_t launch_rhs_planewave(const DevPlan &d, const double *dirs_dev, int nrhs, double2 *b, int64_t ld,

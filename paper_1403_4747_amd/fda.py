@@ -81,6 +81,19 @@ class ProfileResult(ctypes.Structure):
     ]
 
 
+class M2LConfig(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int32), ("xcd_order", ctypes.c_int32), ("width", ctypes.c_int32 * 24)]
+
+    def to_dict(self) -> Dict:
+        return dict(variant=self.variant, xcd_order=self.xcd_order,
+                    width={l: w for l, w in enumerate(self.width) if w})
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("best", M2LConfig), ("ms_before", ctypes.c_double), ("ms_after", ctypes.c_double),
+                ("candidates", ctypes.c_int32), ("nlevels", ctypes.c_int32)]
+
+
 class SolveStats(ctypes.Structure):
     _fields_ = [
         ("iterations", ctypes.c_int32), ("restarts", ctypes.c_int32), ("rel_residual", ctypes.c_double),
@@ -139,6 +152,12 @@ def library():
         L.fda_mlp_samples.restype = ctypes.c_int
         L.fda_plan_leaves.argtypes = [vp, vp, i64, vp, i64]
         L.fda_plan_leaves.restype = ctypes.c_int
+        L.fda_m2l_get_config.argtypes = [vp, ctypes.POINTER(M2LConfig)]
+        L.fda_m2l_get_config.restype = ctypes.c_int
+        L.fda_m2l_set_config.argtypes = [vp, ctypes.POINTER(M2LConfig)]
+        L.fda_m2l_set_config.restype = ctypes.c_int
+        L.fda_autotune.argtypes = [vp, ctypes.c_int32, vp, ctypes.POINTER(TuneResult)]
+        L.fda_autotune.restype = ctypes.c_int
         L.fda_batch_create.argtypes = [vp, ctypes.c_int32, vp, vp, vp, ctypes.POINTER(vp)]
         L.fda_batch_create.restype = ctypes.c_int
         L.fda_batch_launch.argtypes = [vp, vp]
@@ -313,6 +332,36 @@ class Plan:
         st = Stats()
         _err(library().fda_plan_stats(self._h, ctypes.byref(st)))
         return st.to_dict()
+
+    def m2l_config(self) -> Dict:
+        """The merged M2L launch configuration (fda_m2l_get_config):
+        kernel variant, item order and pairs per work item per level."""
+        c = M2LConfig()
+        _err(library().fda_m2l_get_config(self._h, ctypes.byref(c)))
+        return c.to_dict()
+
+    def set_m2l_config(self, variant: Optional[int] = None, xcd_order: Optional[int] = None,
+                       width: Optional[Dict[int, int]] = None) -> Dict:
+        """Change the merged M2L launch configuration (fda_m2l_set_config);
+        unnamed fields keep their current value."""
+        c = M2LConfig()
+        _err(library().fda_m2l_get_config(self._h, ctypes.byref(c)))
+        if variant is not None:
+            c.variant = int(variant)
+        if xcd_order is not None:
+            c.xcd_order = int(xcd_order)
+        for l, w in (width or {}).items():
+            c.width[int(l)] = int(w)
+        _err(library().fda_m2l_set_config(self._h, ctypes.byref(c)))
+        return self.m2l_config()
+
+    def autotune(self, reps: int = 20) -> Dict:
+        """Time the merged M2L launch configurations and keep the fastest
+        (fda_autotune); returns the chosen configuration and the times."""
+        r = TuneResult()
+        _err(library().fda_autotune(self._h, int(reps), _stream(), ctypes.byref(r)))
+        return dict(best=r.best.to_dict(), ms_before=r.ms_before, ms_after=r.ms_after, candidates=r.candidates,
+                    nlevels=r.nlevels)
 
     def profile(self, x, reps: int = 10, out=None) -> Dict:
         """Per-stage HIP-event timings (ms) of fda_matvec, plus the merged
