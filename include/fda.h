@@ -349,7 +349,7 @@ int fda_m2l_set_config(fda_plan *plan, const fda_m2l_config *cfg);
  * configuration it times (HIP events on `stream`, median of `reps` launches
  * of the M2L product kernel plus its reduction, one right-hand side) every
  * kernel variant, then the other item order, then width 16 / 32 per level,
- * keeping a change when it is at least 1 % faster, and leaves the plan in the
+ * keeping a change when it is at least 3 % faster, and leaves the plan in the
  * best configuration found.  The plan's work buffers are overwritten.
  * Synchronous.  Errors: FDA_EINVAL (reps < 1 or > 1000), FDA_ENOMEM,
  * FDA_EHIP. */
