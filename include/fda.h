@@ -90,6 +90,8 @@ typedef struct fda_options {
     int32_t verbose;       /* print build statistics to stderr, default 0 */
     int32_t svd_method;    /* batched SVDs of the build (eqs. (eq_svdg), (eq_epsk)): 0 = bidiagonal QR
                               (rocSOLVER gesvd), 1 = one-sided Jacobi (gesvdj); default 0 */
+    double m2l_svd_eps;    /* truncation of the reduced M2L matrices alone (eq. (eq_epsk));
+                              0 = svd_eps */
 } fda_options;
 
 /* Plan statistics (filled by fda_inspect / fda_plan_stats). */

@@ -430,7 +430,7 @@ __global__ void k_pack_lowrank(const double2 *U, const double *S, const double2 
 // Truncated SVD factors of `count` column-major m x n matrices (stride m*n):
 // A = U^ V^ with U^ = U[:, :r] (m x rmax) and V^ = diag(s[:r]) V^H[:r, :]
 // (rmax x n, stored with n rounded up to a multiple of 4 and zero columns
-// there), r the number of singular values >= svd_eps * s_0, padded to a
+// there), r the number of singular values >= m2l_svd_eps * s_0, padded to a
 // multiple of 4.  rmax = 0 (nothing kept) when some rank exceeds max_rank or
 // 2 r >= min(m, n) (the factors would not pay; Section 4.2).
 LowRank factor_batch(const HostPlan &hp, rocblas_handle h, const double2 *mats, int m, int n, int count,
@@ -457,7 +457,7 @@ LowRank factor_batch(const HostPlan &hp, rocblas_handle h, const double2 *mats, 
         if (info[o] != 0) throw BuildError{FDA_EHIP, std::string("SVD did not converge: ") + what};
         const double *so = S.data() + (size_t)o * mn;
         int r = 0;
-        while (r < mn && so[r] >= hp.svd_eps * so[0] && so[0] > 0) ++r;
+        while (r < mn && so[r] >= hp.m2l_svd_eps * so[0] && so[0] > 0) ++r;
         r = std::max(r, 1);
         rsum += r;
         lr.rtrue[o] = r;

@@ -51,7 +51,7 @@ struct Level {
 
 struct HostPlan {
     int64_t n = 0;
-    double k = 0, eps = 0, svd_eps = 0;
+    double k = 0, eps = 0, svd_eps = 0, m2l_svd_eps = 0;
     cplx alpha;
     fda_options opt{};
     double h_max = 0;

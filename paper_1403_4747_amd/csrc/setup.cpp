@@ -151,6 +151,8 @@ void host_setup(const double *V, int64_t nv, const int32_t *T, int64_t nt, doubl
     if (!(eps > 0 && eps < 1)) throw BuildError{FDA_EINVAL, "eps must be in (0, 1)"};
     if (nt <= 0 || nv <= 0 || !V || !T) throw BuildError{FDA_EINVAL, "empty mesh"};
     if (opt.max_leaf < 1 || opt.max_leaf > 256) throw BuildError{FDA_EINVAL, "max_leaf must be in [1, 256]"};
+    if (!(opt.svd_eps >= 0 && opt.svd_eps < 1) || !(opt.m2l_svd_eps >= 0 && opt.m2l_svd_eps < 1))
+        throw BuildError{FDA_EINVAL, "svd_eps and m2l_svd_eps must be in [0, 1)"};
     for (int64_t i = 0; i < 3 * nv; ++i)
         if (!std::isfinite(V[i])) throw BuildError{FDA_EINVAL, "non-finite vertex coordinate"};
     hp.n = nt;
@@ -158,6 +160,7 @@ void host_setup(const double *V, int64_t nv, const int32_t *T, int64_t nt, doubl
     hp.eps = eps;
     hp.opt = opt;
     hp.svd_eps = opt.svd_eps > 0 ? opt.svd_eps : eps / 10.0;
+    hp.m2l_svd_eps = opt.m2l_svd_eps > 0 ? opt.m2l_svd_eps : hp.svd_eps;
     // i/k for the fluid-side normal, i.e. -i/k for the body-pointing normal n
     hp.alpha = (opt.alpha_re == 0 && opt.alpha_im == 0) ? cplx(0.0, -1.0 / k) : cplx(opt.alpha_re, opt.alpha_im);
     const double lambda = 2.0 * kPi / k;
