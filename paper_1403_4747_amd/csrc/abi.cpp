@@ -1076,7 +1076,7 @@ int bm_solve(fda_plan *plan, const void *b_dev, void *x_dev, int64_t nrhs, int64
     const int nr = (int)nrhs, m = restart;
     const int64_t N = plan->d.n;
     hipStream_t s = as_stream(stream);
-    std::vector<void *> tmp;
+    std::vector<void *> tmp, pinned;
     auto talloc = [&](size_t bytes) {
         void *q = nullptr;
         if (hipMalloc(&q, bytes) != hipSuccess) throw BuildError{FDA_ENOMEM, "GMRES workspace allocation failed"};
@@ -1100,6 +1100,20 @@ int bm_solve(fda_plan *plan, const void *b_dev, void *x_dev, int64_t nrhs, int64
         double2 *sc = (double2 *)talloc(sizeof(double2) * nr);
         int32_t *act_d = (int32_t *)talloc(sizeof(int32_t) * nr);
         std::vector<int32_t> act(nr, 1);
+        // pinned host copies of one Arnoldi step's inner products (the two
+        // Gram-Schmidt passes and the norm), read after a single sync
+        double2 *hpin[3];
+        for (auto &q : hpin) {
+            if (hipHostMalloc((void **)&q, sizeof(double2) * (m + 1) * nr, hipHostMallocDefault) != hipSuccess)
+                throw BuildError{FDA_ENOMEM, "GMRES pinned buffer allocation failed"};
+            pinned.push_back(q);
+        }
+        // inner products of Vb's mm columns with w into hd, copied to `pin`
+        // (stream-ordered: the next kernel that writes hd runs after the copy)
+        auto dots_async = [&](const double2 *Vb, int mm, const double2 *wv, double2 *pin) {
+            hip_check(launch_multidot(Vb, mm, nr, wv, N, partial, hd, s), "dots");
+            hip_check(hipMemcpyAsync(pin, hd, sizeof(double2) * mm * nr, hipMemcpyDeviceToHost, s), "d2h");
+        };
 
         auto dots = [&](const double2 *Vb, int mm, const double2 *wv, std::vector<cplx> &outv) {
             hip_check(launch_multidot(Vb, mm, nr, wv, N, partial, hd, s), "dots");
@@ -1210,24 +1224,29 @@ int bm_solve(fda_plan *plan, const void *b_dev, void *x_dev, int64_t nrhs, int64
                 apply_M(V + (size_t)j * N * nr, zj);
                 apply_A(zj, w);
                 ++iters;
-                // classical Gram-Schmidt, twice
-                std::vector<cplx> h1, h2v;
-                dots(V, j + 1, w, h1);
+                // classical Gram-Schmidt, twice, and the normalisation, all on
+                // the device; the host reads the step's inner products once
+                dots_async(V, j + 1, w, hpin[0]);
                 hip_check(launch_multi_axpy(V, j + 1, nr, hd, -1.0, w, N, nullptr, s), "cgs");
-                dots(V, j + 1, w, h2v);
+                dots_async(V, j + 1, w, hpin[1]);
                 hip_check(launch_multi_axpy(V, j + 1, nr, hd, -1.0, w, N, nullptr, s), "cgs");
-                std::vector<double> hn;
-                norms(w, hn);
-                for (int c = 0; c < nr; ++c) scl[c] = hn[c] > 0 ? 1.0 / hn[c] : 0.0;
-                hip_check(hipMemcpyAsync(sc, scl.data(), sizeof(double2) * nr, hipMemcpyHostToDevice, s), "h2d");
+                dots_async(w, 1, w, hpin[2]);
+                hip_check(launch_inv_norm(hd, sc, nr, s), "norm");
                 hip_check(launch_scale_cols(w, sc, V + (size_t)(j + 1) * N * nr, N, nr, s), "scale");
+                hip_check(hipStreamSynchronize(s), "sync");
+                const double2 *h1 = hpin[0], *h2v = hpin[1];
+                std::vector<double> hn(nr);
+                for (int c = 0; c < nr; ++c) hn[c] = std::sqrt(std::max(0.0, hpin[2][c].x));
                 bool all_ok = true;
                 for (int c = 0; c < nr; ++c) {
                     if (!act[c] || done[c]) continue;
                     coliters[c]++;
                     jcnt[c] = j + 1;
                     auto &Hc = H[c];
-                    for (int i = 0; i <= j; ++i) Hc[i + (size_t)j * (m + 1)] = h1[(size_t)c * (j + 1) + i] + h2v[(size_t)c * (j + 1) + i];
+                    for (int i = 0; i <= j; ++i) {
+                        const double2 a1 = h1[(size_t)c * (j + 1) + i], a2 = h2v[(size_t)c * (j + 1) + i];
+                        Hc[i + (size_t)j * (m + 1)] = cplx(a1.x, a1.y) + cplx(a2.x, a2.y);
+                    }
                     Hc[j + 1 + (size_t)j * (m + 1)] = hn[c];
                     for (int i = 0; i < j; ++i) {
                         cplx a = Hc[i + (size_t)j * (m + 1)], b = Hc[i + 1 + (size_t)j * (m + 1)];
@@ -1304,6 +1323,7 @@ int bm_solve(fda_plan *plan, const void *b_dev, void *x_dev, int64_t nrhs, int64
     }
     hipStreamSynchronize(s);
     for (void *q : tmp) hipFree(q);
+    for (void *q : pinned) hipHostFree(q);
     st.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (stp) *stp = st;
     if (rc == FDA_NOTCONV) g_last_error = "GMRES reached maxit before the tolerance";

@@ -1170,6 +1170,16 @@ __global__ void k_multi_axpy(const double2 *V, int m, int nrhs, const double2 *h
 }
 
 // out_c = in_c * scale[c]  (complex scale per column)
+// scale[c] = 1 / sqrt(Re d[c]) (0 for a zero column): reciprocal column
+// norms from the columns' inner products with themselves, on the device.
+__global__ void k_inv_norm(const double2 *d, double2 *scale, int n) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < n) {
+        const double r = d[c].x;
+        scale[c] = make_double2(r > 0 ? 1.0 / sqrt(r) : 0.0, 0.0);
+    }
+}
+
 __global__ void k_scale_cols(const double2 *in, const double2 *scale, double2 *out, int64_t N) {
     const int c = blockIdx.y;
     const double2 s = scale[c];
@@ -1515,6 +1525,11 @@ hipError_t launch_multidot(const double2 *V, int m, int nrhs, const double2 *w, 
 hipError_t launch_multi_axpy(const double2 *V, int m, int nrhs, const double2 *h, double sign, double2 *w, int64_t N,
                              const int32_t *active, hipStream_t st) {
     hipLaunchKernelGGL(k_multi_axpy, dim3(grid1(N), nrhs), dim3(256), 0, st, V, m, nrhs, h, sign, w, N, active);
+    CHECK_LAUNCH();
+    return hipSuccess;
+}
+hipError_t launch_inv_norm(const double2 *d, double2 *scale, int n, hipStream_t st) {
+    hipLaunchKernelGGL(k_inv_norm, dim3((n + 63) / 64), dim3(64), 0, st, d, scale, n);
     CHECK_LAUNCH();
     return hipSuccess;
 }

@@ -124,6 +124,7 @@ hipError_t launch_multidot(const double2 *V, int m, int nrhs, const double2 *w, 
                            double2 *out, hipStream_t st);
 hipError_t launch_multi_axpy(const double2 *V, int m, int nrhs, const double2 *h, double sign, double2 *w, int64_t N,
                              const int32_t *active, hipStream_t st);
+hipError_t launch_inv_norm(const double2 *d, double2 *scale, int n, hipStream_t st);
 hipError_t launch_scale_cols(const double2 *in, const double2 *scale, double2 *out, int64_t N, int nrhs,
                              hipStream_t st);
 hipError_t launch_sub(const double2 *b, const double2 *y, double2 *r, int64_t n, hipStream_t st);
