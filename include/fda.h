@@ -92,6 +92,8 @@ typedef struct fda_options {
                               (rocSOLVER gesvd), 1 = one-sided Jacobi (gesvdj); default 0 */
     double m2l_svd_eps;    /* truncation of the reduced M2L matrices alone (eq. (eq_epsk));
                               0 = svd_eps */
+    int32_t neumann_rhs;   /* also build the right-hand operator B of eq. (eq_bm) for Neumann data
+                              (bm_rhs_neumann): its near-field blocks and leaf S2M; default 0 */
 } fda_options;
 
 /* Plan statistics (filled by fda_inspect / fda_plan_stats). */
@@ -163,6 +165,16 @@ int fda_matvec(fda_plan *plan, const void *x_dev, void *y_dev, int64_t nrhs, int
  * complex128 device buffer, leading dimension ld.  Asynchronous.  Errors:
  * FDA_EINVAL, FDA_EHIP. */
 int bm_rhs_planewave(fda_plan *plan, const double *dirs, int64_t nrhs, void *b_dev, int64_t ld, void *stream);
+
+/* b = B g: the right-hand side of eq. (eq_bm) for Neumann data du/dn = g on
+ * the surface and no incident field (Section 2; the same fast directional
+ * algorithm with the source kernel G, Section 4), with
+ *   B_ij = -alpha/2 delta_ij + int_{D_j} [G + alpha dG/dn_x](c_i, y) dy.
+ * g_dev, b_dev: N x nrhs complex128 device buffers, leading dimension ld
+ * (elements), caller's element order; they must not overlap.  Asynchronous
+ * on stream.  Errors: FDA_EINVAL (plan built without opt.neumann_rhs, nrhs <
+ * 1 or > nrhs_max, ld < N, null pointers), FDA_EHIP. */
+int bm_rhs_neumann(fda_plan *plan, const void *g_dev, void *b_dev, int64_t nrhs, int64_t ld, void *stream);
 
 /* Per-solve results. */
 typedef struct bm_stats {

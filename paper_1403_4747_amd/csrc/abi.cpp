@@ -479,6 +479,7 @@ void upload_plan(fda_plan *p, const HostOps &ops, DevTranslations &tr) {
     d.lv.assign(L + 1, DevLevel());
     if (!d.has_far) return;
     d.S = to_storage(p, upload_cplx(p, ops.S), ops.S.size());
+    if (!ops.SB.empty()) d.rhs.S = to_storage(p, upload_cplx(p, ops.SB), ops.SB.size());
     d.T = to_storage(p, upload_cplx(p, ops.T), ops.T.size());
     for (int l = hp.top; l <= L; ++l) {
         const Level &lv = hp.lv[l];
@@ -722,7 +723,7 @@ int fda_build(const double *verts, int64_t nv, const int32_t *tris, int64_t nt, 
             if (p->d.prec == FDA_PREC_FP32) {
                 p->d.nf_vals = dalloc<float2>(p.get(), (size_t)p->hp.near_nnz, p->allocs);
                 p->d.nf_diag = dalloc<double2>(p.get(), (size_t)p->d.n, p->allocs);
-                hip_check(launch_near_split(p->d, v64, nullptr), "near-field split");
+                hip_check(launch_near_split(p->d, v64, p->d.nf_vals, p->d.nf_diag, nullptr), "near-field split");
                 hip_check(hipDeviceSynchronize(), "near split");
                 auto it = std::find(p->allocs.begin(), p->allocs.end(), (void *)v64);
                 hipFree(v64);
@@ -730,6 +731,26 @@ int fda_build(const double *verts, int64_t nv, const int32_t *tris, int64_t nt, 
                 p->device_bytes -= (int64_t)(sizeof(double2) * p->hp.near_nnz);
             } else {
                 p->d.nf_vals = v64;
+            }
+            if (p->hp.opt.neumann_rhs) {
+                // the right-hand operator B: its own near-field blocks (same
+                // pattern and quadrature), stored like A's
+                double2 *b64 = dalloc<double2>(p.get(), (size_t)p->hp.near_nnz, p->allocs);
+                hip_check(launch_near_blocks(p->d, b64, nullptr, 1), "near-field blocks of B");
+                if (p->d.prec == FDA_PREC_FP32) {
+                    p->d.rhs.nf_vals = dalloc<float2>(p.get(), (size_t)p->hp.near_nnz, p->allocs);
+                    p->d.rhs.nf_diag = dalloc<double2>(p.get(), (size_t)p->d.n, p->allocs);
+                    hip_check(launch_near_split(p->d, b64, p->d.rhs.nf_vals, p->d.rhs.nf_diag, nullptr),
+                              "near-field split of B");
+                    hip_check(hipDeviceSynchronize(), "near split");
+                    auto it = std::find(p->allocs.begin(), p->allocs.end(), (void *)b64);
+                    hipFree(b64);
+                    p->allocs.erase(it);
+                    p->device_bytes -= (int64_t)(sizeof(double2) * p->hp.near_nnz);
+                } else {
+                    p->d.rhs.nf_vals = b64;
+                }
+                p->d.has_rhs = true;
             }
         }
         hip_check(hipDeviceSynchronize(), "build synchronize");
@@ -835,6 +856,28 @@ int fda_matvec(fda_plan *plan, const void *x_dev, void *y_dev, int64_t nrhs, int
         hip_check(launch_permute_in(plan->d, (const double2 *)x_dev, ld, plan->xt, (int)nrhs, st), "permute");
         hip_check(launch_matvec_tree(plan->d, plan->xt, plan->yt, (int)nrhs, st, nullptr, nullptr), "matvec");
         hip_check(launch_permute_out(plan->d, plan->yt, (double2 *)y_dev, ld, (int)nrhs, st), "permute");
+    } catch (const BuildError &e) {
+        return fail(e.code, e.msg);
+    } catch (const HipError &e) {
+        return fail(FDA_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
+    }
+    return FDA_OK;
+}
+
+int bm_rhs_neumann(fda_plan *plan, const void *g_dev, void *b_dev, int64_t nrhs, int64_t ld, void *stream) {
+    g_last_error.clear();
+    if (!plan || !g_dev || !b_dev) return fail(FDA_EINVAL, "NULL argument");
+    if (!plan->d.has_rhs) return fail(FDA_EINVAL, "plan built without neumann_rhs (the operator B)");
+    if (nrhs < 1 || nrhs > plan->hp.opt.nrhs_max) return fail(FDA_EINVAL, "nrhs out of range");
+    if (ld < plan->d.n) return fail(FDA_EINVAL, "ld < N");
+    try {
+        hip_check(hipSetDevice(plan->device), "hipSetDevice");
+        ensure_capacity(plan, (int)nrhs);
+        hipStream_t st = as_stream(stream);
+        hip_check(launch_permute_in(plan->d, (const double2 *)g_dev, ld, plan->xt, (int)nrhs, st), "permute");
+        hip_check(launch_matvec_tree(plan->d, plan->xt, plan->yt, (int)nrhs, st, nullptr, nullptr, &plan->d.rhs),
+                  "B product");
+        hip_check(launch_permute_out(plan->d, plan->yt, (double2 *)b_dev, ld, (int)nrhs, st), "permute");
     } catch (const BuildError &e) {
         return fail(e.code, e.msg);
     } catch (const HipError &e) {

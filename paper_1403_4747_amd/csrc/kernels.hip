@@ -60,8 +60,22 @@ __device__ __forceinline__ double2 lhs_kernel(const double *x, const double *y, 
     return make_double2(d1.x + ad2.x, d1.y + ad2.y);
 }
 
-// Near-field entry A_ij (i != j): 7-point rule on 4^level midpoint
-// sub-triangles of triangle j.
+// [G + alpha dG/dn_x](x, y): the kernel of the right-hand operator B of
+// eq. (eq_bm), which acts on Neumann data (paper normal convention).
+__device__ __forceinline__ double2 rhs_kernel(const double *x, const double *y, const double *nx, double k,
+                                              double2 alpha) {
+    double r0 = x[0] - y[0], r1 = x[1] - y[1], r2 = x[2] - y[2];
+    double R = sqrt(r0 * r0 + r1 * r1 + r2 * r2);
+    double2 g, gp;
+    green_pair(k, R, g, gp);
+    double rnx = (r0 * nx[0] + r1 * nx[1] + r2 * nx[2]) / R;
+    const double2 d = cmul(alpha, make_double2(gp.x * rnx, gp.y * rnx));
+    return make_double2(g.x + d.x, g.y + d.y);
+}
+
+// Near-field entry A_ij (OP 0) or B_ij (OP 1), i != j: 7-point rule on
+// 4^level midpoint sub-triangles of triangle j.
+template <int OP>
 __device__ double2 near_entry(const double *tv, double area, const double *x, const double *nx, const double *ny,
                               double k, double2 alpha, int level) {
     double2 acc = make_double2(0.0, 0.0);
@@ -96,7 +110,7 @@ __device__ double2 near_entry(const double *tv, double area, const double *x, co
         for (int p = 0; p < 7; ++p) {
             double y[3];
             for (int q = 0; q < 3; ++q) y[q] = c_r7b[p][0] * a[q] + c_r7b[p][1] * b[q] + c_r7b[p][2] * c[q];
-            double2 v = lhs_kernel(x, y, nx, ny, k, alpha);
+            const double2 v = OP == 0 ? lhs_kernel(x, y, nx, ny, k, alpha) : rhs_kernel(x, y, nx, k, alpha);
             double w = c_r7w[p] * asub;
             acc.x += w * v.x;
             acc.y += w * v.y;
@@ -135,6 +149,37 @@ __device__ double2 self_entry(const double *tv, const double *x, double k, doubl
     return make_double2(0.5 + ah.x, ah.y);
 }
 
+// Diagonal entry of B: -alpha/2 + int G over the element's own flat
+// triangle at its centroid (the alpha dG/dn_x part vanishes there, r . n_x
+// = 0); in polar coordinates about the centroid
+// int G = (i / (4 pi k)) int_0^{2 pi} (1 - exp(ik R(theta))) dtheta, the
+// angular integral taken edge by edge with 32-point Gauss-Legendre.
+__device__ double2 self_entry_rhs(const double *tv, const double *x, double k, double2 alpha) {
+    double2 s = make_double2(0.0, 0.0);
+    for (int e = 0; e < 3; ++e) {
+        const double *p = tv + 3 * e, *q = tv + 3 * ((e + 1) % 3);
+        double ev[3] = {q[0] - p[0], q[1] - p[1], q[2] - p[2]};
+        double L = sqrt(ev[0] * ev[0] + ev[1] * ev[1] + ev[2] * ev[2]);
+        double eh[3] = {ev[0] / L, ev[1] / L, ev[2] / L};
+        double t = (x[0] - p[0]) * eh[0] + (x[1] - p[1]) * eh[1] + (x[2] - p[2]) * eh[2];
+        double f[3] = {p[0] + t * eh[0] - x[0], p[1] + t * eh[1] - x[1], p[2] + t * eh[2] - x[2]};
+        double d = sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+        double ph1 = atan2(-t, d), ph2 = atan2(L - t, d);
+        double half = 0.5 * (ph2 - ph1), mid = 0.5 * (ph2 + ph1);
+        for (int g = 0; g < 32; ++g) {
+            double R = d / cos(mid + half * c_glx[g]);
+            double sn, cs;
+            sincos(k * R, &sn, &cs);
+            double w = half * c_glw[g];
+            s.x += w * (1.0 - cs);
+            s.y -= w * sn;
+        }
+    }
+    const double c = 1.0 / (4.0 * 3.14159265358979323846 * k);  // i c s = (-c s.y, c s.x)
+    return make_double2(-c * s.y - 0.5 * alpha.x, c * s.x - 0.5 * alpha.y);
+}
+
+template <int OP>
 __global__ void k_near_blocks(const int64_t *leaf_off, const int64_t *col_off, const int32_t *cols,
                               const int64_t *blk_off, const double *tri, const double *cen, const double *nrm,
                               const double *area, double k, double2 alpha, double h, double2 *vals) {
@@ -150,13 +195,13 @@ __global__ void k_near_blocks(const int64_t *leaf_off, const int64_t *col_off, c
         const double *x = cen + 3 * ti;
         double2 v;
         if (ti == tj) {
-            v = self_entry(tri + 9 * tj, x, k, alpha);
+            v = OP == 0 ? self_entry(tri + 9 * tj, x, k, alpha) : self_entry_rhs(tri + 9 * tj, x, k, alpha);
         } else {
             const double *cj = cen + 3 * tj;
             double dd = sqrt((x[0] - cj[0]) * (x[0] - cj[0]) + (x[1] - cj[1]) * (x[1] - cj[1]) +
                              (x[2] - cj[2]) * (x[2] - cj[2]));
             int level = (dd < h) ? 3 : (dd < 1.75 * h) ? 2 : (dd < 2.5 * h) ? 1 : 0;
-            v = near_entry(tri + 9 * tj, area[tj], x, nrm + 3 * ti, nrm + 3 * tj, k, alpha, level);
+            v = near_entry<OP>(tri + 9 * tj, area[tj], x, nrm + 3 * ti, nrm + 3 * tj, k, alpha, level);
         }
         blk[idx] = v;
     }
@@ -1303,10 +1348,14 @@ hipError_t set_quadrature_constants(const double r7b[7][3], const double r7w[7],
     return hipMemcpyToSymbol(HIP_SYMBOL(c_glw), glw, sizeof(double) * 32);
 }
 
-hipError_t launch_near_blocks(const DevPlan &d, double2 *vals64, hipStream_t st) {
+hipError_t launch_near_blocks(const DevPlan &d, double2 *vals64, hipStream_t st, int op) {
     if (d.nleaf == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_near_blocks, dim3(d.nleaf), dim3(256), 0, st, d.leaf_off, d.nf_col_off, d.nf_cols,
-                       d.nf_blk_off, d.tri, d.cen, d.nrm, d.area, d.k, d.alpha, d.h_max, vals64);
+    if (op == 1)
+        hipLaunchKernelGGL(k_near_blocks<1>, dim3(d.nleaf), dim3(256), 0, st, d.leaf_off, d.nf_col_off, d.nf_cols,
+                           d.nf_blk_off, d.tri, d.cen, d.nrm, d.area, d.k, d.alpha, d.h_max, vals64);
+    else
+        hipLaunchKernelGGL(k_near_blocks<0>, dim3(d.nleaf), dim3(256), 0, st, d.leaf_off, d.nf_col_off, d.nf_cols,
+                           d.nf_blk_off, d.tri, d.cen, d.nrm, d.area, d.k, d.alpha, d.h_max, vals64);
     CHECK_LAUNCH();
     return hipSuccess;
 }
@@ -1323,9 +1372,9 @@ static int grid1(int64_t n) {
     return (int)std::min<int64_t>(std::max<int64_t>(g, 1), 4096);
 }
 
-hipError_t launch_near_split(const DevPlan &d, const double2 *vals64, hipStream_t st) {
+hipError_t launch_near_split(const DevPlan &d, const double2 *vals64, void *out32, double2 *diag, hipStream_t st) {
     hipLaunchKernelGGL(k_near_split, dim3(d.nleaf), dim3(256), 0, st, d.leaf_off, d.nf_blk_off, d.nf_self_col,
-                       d.nf_ncol, vals64, (float2 *)d.nf_vals, d.nf_diag);
+                       d.nf_ncol, vals64, (float2 *)out32, diag);
     CHECK_LAUNCH();
     return hipSuccess;
 }
@@ -1394,7 +1443,7 @@ static hipError_t m2l_merged_t(const M2LMerged &mm, int nrhs, hipStream_t st, hi
 // near, after S2M, after M2M, after M2L, after L2L, end).
 template <class C>
 static hipError_t matvec_t(const DevPlan &d, const double2 *xt, double2 *yt, int nrhs, hipStream_t st,
-                           hipEvent_t *ev, hipEvent_t *lev) {
+                           hipEvent_t *ev, hipEvent_t *lev, const NearFar &op) {
     const int64_t N = d.n;
     // The near field (HBM-bound) overlaps the far-field chain (matrix cores)
     // on the plan's side stream, unless stage timings are taken or the
@@ -1413,7 +1462,7 @@ static hipError_t matvec_t(const DevPlan &d, const double2 *xt, double2 *yt, int
         if (e == hipSuccess) e = hipStreamWaitEvent(d.side, d.fork, 0);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_p2p<C>, dim3(d.nleaf, nrhs), dim3(256), sizeof(C) * d.max_ncol, d.side, d.leaf_off,
-                           d.nf_list_off, d.nf_list, d.nf_blk_off, (const C *)d.nf_vals, (const double2 *)d.nf_diag,
+                           d.nf_list_off, d.nf_list, d.nf_blk_off, (const C *)op.nf_vals, (const double2 *)op.nf_diag,
                            xt, yt, N);
         e = hipGetLastError();
         if (e == hipSuccess) e = hipEventRecord(d.join, d.side);
@@ -1422,7 +1471,7 @@ static hipError_t matvec_t(const DevPlan &d, const double2 *xt, double2 *yt, int
     if (ev) hipEventRecord(ev[0], st);
     if (!overlap) {
         hipLaunchKernelGGL(k_p2p<C>, dim3(d.nleaf, nrhs), dim3(256), sizeof(C) * d.max_ncol, st, d.leaf_off,
-                           d.nf_list_off, d.nf_list, d.nf_blk_off, (const C *)d.nf_vals, (const double2 *)d.nf_diag,
+                           d.nf_list_off, d.nf_list, d.nf_blk_off, (const C *)op.nf_vals, (const double2 *)op.nf_diag,
                            xt, yt, N);
         CHECK_LAUNCH();
     } else if (FDA_NEAR_FORK == 0) {
@@ -1437,7 +1486,7 @@ static hipError_t matvec_t(const DevPlan &d, const double2 *xt, double2 *yt, int
     const int L = d.depth, top = d.top;
     const DevLevel &lf = d.lv[L];
     hipLaunchKernelGGL(k_s2m<C>, dim3(d.nleaf, nrhs), dim3(128), sizeof(C) * d.max_leaf, st, d.leaf_off,
-                       (const C *)d.S, lf.ku, xt, (C *)lf.s, N, lf.sstride);
+                       (const C *)op.S, lf.ku, xt, (C *)lf.s, N, lf.sstride);
     CHECK_LAUNCH();
     if (ev) hipEventRecord(ev[2], st);
     for (int l = L - 1; l >= top; --l) {
@@ -1483,9 +1532,14 @@ static hipError_t matvec_t(const DevPlan &d, const double2 *xt, double2 *yt, int
 }
 
 hipError_t launch_matvec_tree(const DevPlan &d, const double2 *xt, double2 *yt, int nrhs, hipStream_t st,
-                              hipEvent_t *ev, hipEvent_t *lev) {
-    if (d.prec == 1) return matvec_t<float2>(d, xt, yt, nrhs, st, ev, lev);
-    return matvec_t<double2>(d, xt, yt, nrhs, st, ev, lev);
+                              hipEvent_t *ev, hipEvent_t *lev, const NearFar *ops) {
+    NearFar a;
+    a.nf_vals = d.nf_vals;
+    a.nf_diag = d.nf_diag;
+    a.S = d.S;
+    const NearFar &op = ops ? *ops : a;
+    if (d.prec == 1) return matvec_t<float2>(d, xt, yt, nrhs, st, ev, lev, op);
+    return matvec_t<double2>(d, xt, yt, nrhs, st, ev, lev, op);
 }
 
 hipError_t launch_m2l_merged(const DevPlan &d, int nrhs, hipStream_t st) {

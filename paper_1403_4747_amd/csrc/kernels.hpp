@@ -69,6 +69,16 @@ struct DevLevel {
     GWork m2m, l2l;
 };
 
+// The operator-specific parts of the matvec: near-field blocks and leaf S2M
+// (the tree, translations and L2T are shared).  DevPlan holds the left-hand
+// operator A in its own fields; the right-hand operator B of eq. (eq_bm),
+// which acts on Neumann data, is built on request into DevPlan::rhs.
+struct NearFar {
+    void *nf_vals = nullptr;     // near-field blocks (FP32 plans: self terms zeroed)
+    double2 *nf_diag = nullptr;  // FP32 plans: FP64 self terms, tree order
+    void *S = nullptr;           // leaf S2M
+};
+
 struct DevPlan {
     int64_t n = 0;
     M2LMerged m2l_all;
@@ -101,18 +111,22 @@ struct DevPlan {
     // null: everything on the caller's stream.
     hipStream_t side = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
+    bool has_rhs = false;  // B built (fda_options.neumann_rhs)
+    NearFar rhs;
 };
 
 hipError_t set_quadrature_constants(const double r7b[7][3], const double r7w[7], const double glx[32],
                                     const double glw[32]);
-hipError_t launch_near_blocks(const DevPlan &d, double2 *vals64, hipStream_t st);
+// op 0: A's near-field blocks, op 1: B's
+hipError_t launch_near_blocks(const DevPlan &d, double2 *vals64, hipStream_t st, int op = 0);
 hipError_t launch_bj_invert(const DevPlan &d, const double2 *vals64, hipStream_t st);
-hipError_t launch_near_split(const DevPlan &d, const double2 *vals64, hipStream_t st);
+hipError_t launch_near_split(const DevPlan &d, const double2 *vals64, void *out32, double2 *diag, hipStream_t st);
 hipError_t launch_to_f32(const double2 *in, void *out, int64_t n, hipStream_t st);
 // ev: 7 stage events or null; lev: 2 events per level around its M2L
 // product kernel, or null.
+// ops: the operator's near field and S2M (null: A's)
 hipError_t launch_matvec_tree(const DevPlan &d, const double2 *xt, double2 *yt, int nrhs, hipStream_t st,
-                              hipEvent_t *ev, hipEvent_t *lev);
+                              hipEvent_t *ev, hipEvent_t *lev, const NearFar *ops = nullptr);
 // the merged low-rank M2L alone (product kernel and reduction); the
 // outgoing states of the merged levels must be current
 hipError_t launch_m2l_merged(const DevPlan &d, int nrhs, hipStream_t st);

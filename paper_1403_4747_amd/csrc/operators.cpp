@@ -1,7 +1,10 @@
 // Leaf operators of the fast directional algorithm formed on the host from
 // the SVD factors: compressed S2M and L2T matrices per leaf (Section 4.3),
 // which fold the 7-point element quadrature (S2M, eq. (eq_s2m)) and the
-// target operator [1 + alpha d/dn_x] (L2T, eq. (eq_l2t)).
+// target operator [1 + alpha d/dn_x] (L2T, eq. (eq_l2t)).  The left-hand
+// operator A has the source kernel dG/dn_y; the right-hand operator B of
+// eq. (eq_bm) (Neumann data) the source kernel G and the same target
+// operator, so only its S2M differs.
 #include <cmath>
 #include <cstring>
 
@@ -58,8 +61,10 @@ void form_operators(const HostPlan &hp, HostOps &ops) {
     double bary[7][3], w7[7];
     r7_rule(bary, w7);
     const int64_t nleaf = lf.nbox;
+    const bool rhsB = hp.opt.neumann_rhs != 0;
     ops.S.assign((size_t)lf.ku * hp.n, cplx(0));
     ops.T.assign((size_t)lf.kd * hp.n, cplx(0));
+    if (rhsB) ops.SB.assign((size_t)lf.ku * hp.n, cplx(0));
     std::vector<double> uc = scaled(lf.cube, kRout * lf.r), de = uc;
     parallel_for(nleaf, [&](int64_t b) {
         int64_t e0 = hp.leaf_off[b], e1 = hp.leaf_off[b + 1];
@@ -67,14 +72,14 @@ void form_operators(const HostPlan &hp, HostOps &ops) {
         double c[3];
         for (int q = 0; q < 3; ++q) c[q] = hp.origin[q] + (lf.key[3 * b + q] + 0.5) * lf.w;
         int nc = (int)uc.size() / 3;
-        Mat E(nc, nl), Ed(nl, nc);
+        Mat E(nc, nl), Ed(nl, nc), EB(rhsB ? nc : 0, rhsB ? nl : 0);
         for (int j = 0; j < nl; ++j) {
             int64_t e = e0 + j;
             const double *tv = &hp.tri[9 * e];
             const double *ny = &hp.nrm[3 * e];
             for (int i = 0; i < nc; ++i) {
                 double x[3] = {uc[3 * i] + c[0], uc[3 * i + 1] + c[1], uc[3 * i + 2] + c[2]};
-                cplx acc = 0;
+                cplx acc = 0, accB = 0;
                 for (int q = 0; q < 7; ++q) {
                     double y[3];
                     for (int a = 0; a < 3; ++a) y[a] = bary[q][0] * tv[a] + bary[q][1] * tv[3 + a] + bary[q][2] * tv[6 + a];
@@ -84,8 +89,10 @@ void form_operators(const HostPlan &hp, HostOps &ops) {
                     cplx gp = g * cplx(-1.0, k * R) / R;
                     double rny = (r[0] * ny[0] + r[1] * ny[1] + r[2] * ny[2]) / R;
                     acc += w7[q] * hp.area[e] * (-gp * rny);
+                    accB += w7[q] * hp.area[e] * g;
                 }
                 E(i, j) = acc;
+                if (rhsB) EB(i, j) = accB;
             }
             // target side: [G + alpha dG/dn_x](c_j, incoming equivalent point)
             const double *x = &hp.cen[3 * e];
@@ -111,6 +118,13 @@ void form_operators(const HostPlan &hp, HostOps &ops) {
         for (int j = 0; j < lf.kd; ++j)
             for (int i = 0; i < nl; ++i)
                 ops.T[(size_t)lf.kd * e0 + i + (size_t)j * nl] = (j < Tt.n) ? Tt(i, j) : cplx(0);
+        if (rhsB) {
+            Mat SBt = matmul(lf.Uu[0], 'C', EB, 'N');
+            scale_rows(SBt, lf.su[0]);
+            for (int j = 0; j < nl; ++j)
+                for (int i = 0; i < lf.ku; ++i)
+                    ops.SB[(size_t)lf.ku * e0 + i + (size_t)j * lf.ku] = (i < SBt.m) ? SBt(i, j) : cplx(0);
+        }
     });
 }
 

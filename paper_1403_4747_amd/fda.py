@@ -44,6 +44,7 @@ class Options(ctypes.Structure):
         ("hf_wavelengths", ctypes.c_double), ("rho_c", ctypes.c_double), ("leaf_min_h", ctypes.c_double),
         ("prec", ctypes.c_int32), ("nrhs_max", ctypes.c_int32), ("device", ctypes.c_int32),
         ("verbose", ctypes.c_int32), ("svd_method", ctypes.c_int32), ("m2l_svd_eps", ctypes.c_double),
+        ("neumann_rhs", ctypes.c_int32),
     ]
 
 
@@ -152,6 +153,8 @@ def library():
         L.fda_mlp_samples.restype = ctypes.c_int
         L.fda_plan_leaves.argtypes = [vp, vp, i64, vp, i64]
         L.fda_plan_leaves.restype = ctypes.c_int
+        L.bm_rhs_neumann.argtypes = [vp, vp, vp, i64, i64, vp]
+        L.bm_rhs_neumann.restype = ctypes.c_int
         L.fda_m2l_get_config.argtypes = [vp, ctypes.POINTER(M2LConfig)]
         L.fda_m2l_get_config.restype = ctypes.c_int
         L.fda_m2l_set_config.argtypes = [vp, ctypes.POINTER(M2LConfig)]
@@ -264,6 +267,17 @@ class Plan:
         rc = library().fda_matvec(self._h, x.data_ptr(), y.data_ptr(), nrhs, self.n, _stream())
         _err(rc)
         return y
+
+    def rhs_neumann(self, g, out=None):
+        """b = B g, the right-hand side for Neumann data du/dn = g
+        (bm_rhs_neumann; the plan must be built with neumann_rhs=1)."""
+        import torch
+
+        nrhs = self._check_vec(g, self.n)
+        b = torch.empty_like(g) if out is None else out
+        self._check_vec(b, self.n)
+        _err(library().bm_rhs_neumann(self._h, g.data_ptr(), b.data_ptr(), nrhs, self.n, _stream()))
+        return b
 
     def rhs_planewave(self, directions: Sequence) -> "torch.Tensor":
         """b = u_inc + alpha du_inc/dn for unit plane waves (bm_rhs_planewave)."""
