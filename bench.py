@@ -135,6 +135,111 @@ def uneven_batch_leg(nmesh, steps, log, tune=True):
     return out
 
 
+def large_case(args, log):
+    """The large one-GPU case: rigid prolate spheroid with semi-axes
+    (2.5, 0.5, 0.5) (D = 5) at kD = 1000, meshed uniformly with about 4 M
+    triangles (edges of about 0.0025, 12.6 per wavelength), unit plane wave at
+    30 degrees to the long axis, eps = 1e-4, leaves at least 2 longest edges
+    wide (depth 9: at most 46 elements per leaf).  Plain FP64 FDA against
+    the FP32 arm (FP64 self terms and Arnoldi) with block Jacobi and the
+    learned preconditioner; matvec rate, GMRES time to 1e-5, build time,
+    peak HBM and the error on oracle rows."""
+    import torch
+
+    import workloads as W
+    from paper_1403_4747_amd import Plan
+
+    V, T = W.spheroid_rings(0.0025)
+    n, kD = len(T), 1000.0
+    k = kD / 5.0
+    th = math.radians(30.0)
+    d = (math.cos(th), math.sin(th), 0.0)
+    log(f"[bench] large case: spheroid N={n} kD={kD}")
+    x = torch.from_numpy(W.complex_normal(n, 1, seed=0)).to("cuda")
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    free0 = torch.cuda.mem_get_info()[0]
+    arms, ys = {}, {}
+    for prec in ("fp64", "fp32"):
+        t0 = time.perf_counter()
+        p = Plan(V, T, k, 1e-4, prec=prec, leaf_min_h=2.0)
+        torch.cuda.synchronize()
+        arm = dict(build_seconds=round(time.perf_counter() - t0, 2))
+        st = p.stats()
+        arm.update(depth=st["depth"], leaves=st["nleaf"], max_leaf=st["max_leaf_count"], near_nnz=st["near_nnz"],
+                   plan_gib=round((free0 - torch.cuda.mem_get_info()[0]) / 2**30, 2))
+        if not args.no_tune:
+            arm["m2l_autotune"] = p.autotune(reps=5)["best"]
+        y = p.matvec(x)
+        for _ in range(2):
+            p.matvec(x, out=y)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(args.steps):
+            p.matvec(x, out=y)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        prof = p.profile(x, reps=3)
+        arm.update(ms_per_matvec=round(ms, 3), matvecs_per_s=round(1000.0 / ms, 3),
+                   stages_ms={q: round(v, 3) for q, v in prof.items() if q != "m2l_gemm"})
+        if prof["m2l_lowrank"] > 0:
+            a = st["m2l_flops"] / (prof["m2l_lowrank"] * 1e-3) / 1e12
+            peak = FP64_PEAK_TFLOPS if prec == "fp64" else FP32_PEAK_TFLOPS
+            arm["m2l_roofline"] = dict(achieved=round(a, 3), peak=peak, unit="TFLOP/s", frac=round(a / peak, 4),
+                                       flops_per_launch=st["m2l_flops"])
+        ys[prec] = y.cpu().numpy()
+        if not args.no_solve:
+            b = p.rhs_planewave(d)
+            pcs = ["none", "block_jacobi"]
+            if prec == "fp32" and os.path.exists(args.mlp_weights):
+                from paper_1403_4747_amd import train_mlp
+
+                p.set_mlp(train_mlp.load(args.mlp_weights))
+                pcs.append("mlp")
+            for pc in pcs:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, info = p.solve(b, tol=1e-5, restart=50, maxit=1000, precond=pc)
+                torch.cuda.synchronize()
+                arm["solve_" + pc] = dict(seconds=round(time.perf_counter() - t0, 3), iterations=info["iterations"],
+                                          converged=info["converged"], rel_residual=info["rel_residual"])
+                if pc == "mlp":
+                    arm["solve_mlp"].update(mlp_rejected=info["mlp_rejected"], mlp_fallbacks=info["mlp_fallbacks"])
+            p.set_mlp(None)
+        arm["peak_hbm_gib"] = round((free0 - torch.cuda.mem_get_info()[0]) / 2**30, 2)
+        log(f"[bench] large {prec}: {arm}")
+        arms[prec] = arm
+        p.close()
+        torch.cuda.empty_cache()
+    cpu = None
+    if not args.no_cpu:
+        cpu, err, rows, yr = cpu_baseline(V, T, k, W.complex_normal(n, 1, seed=0), ys["fp64"], 4096, args.cpu_seconds / 2)
+        arms["fp64"]["matvec_rel_err_vs_oracle_sampled"] = err
+        arms["fp32"]["matvec_rel_err_vs_oracle_sampled"] = float(np.linalg.norm(ys["fp32"][rows] - yr) / np.linalg.norm(yr))
+        log(f"[bench] large cpu baseline {cpu}")
+    f64 = arms["fp64"]
+    return {
+        "metric": "FDA matvecs/s + GMRES time-to-1e-5, large case (prolate spheroid 2.5 x 0.5 x 0.5, N~4M, kD=1000)",
+        "value": f64["matvecs_per_s"],
+        "unit": "matvecs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": 2,
+        "ms_per_step": f64["ms_per_matvec"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"spheroid{n}_kD1000", "N": n, "k": k, "kD": kD, "eps": 1e-4, "leaf_min_h": 2.0,
+                   "direction_deg_to_axis": 30.0, "arm": "plain FP64"},
+        "time_to_1e-5_s": f64.get("solve_none", {}).get("seconds"),
+        "arms": arms,
+        "cpu_baseline": cpu,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -156,6 +261,8 @@ def main():
     ap.add_argument("--mlp-weights", default=os.path.join(ROOT, "paper_1403_4747_amd", "weights",
                                                           "mlp_ellipsoid_s5_h256.npz"),
                     help="trained learned-preconditioner weights for the fast arm's solve")
+    ap.add_argument("--large", action="store_true",
+                    help="run only the large case (prolate spheroid, about 4 M triangles, kD = 1000) and print its line")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "m2l_lowrank_sphere81920_kD100_traffic.json"),
                     help="measured HBM traffic of the M2L kernel (written from rocprofv3 counter passes)")
     args = ap.parse_args()
@@ -171,6 +278,9 @@ def main():
 
     assert torch.cuda.is_available(), "needs a GPU"
     torch.cuda.set_device(0)
+    if args.large:
+        print(json.dumps(large_case(args, log)), flush=True)
+        return
     V, T, prm = W.workload(args.workload)
     n, k = len(T), prm["k"]
     log(f"[bench] workload {args.workload}: N={n} k={k}")

@@ -24,6 +24,7 @@ __all__ = [
     "icosphere",
     "octasphere",
     "ellipsoid",
+    "spheroid_rings",
     "fibonacci_directions",
     "complex_normal",
     "uneven_batch",
@@ -120,6 +121,51 @@ def ellipsoid(subdiv: int, semi_axes=(0.5, 0.5, 0.5)):
     scaling keeps the outward winding."""
     V, T = icosphere(subdiv, 1.0)
     return V * np.asarray(semi_axes, dtype=np.float64)[None, :], T
+
+
+def spheroid_rings(h: float, a: float = 2.5, b: float = 0.5):
+    """Near-uniform mesh of the prolate spheroid x^2/a^2 + (y^2 + z^2)/b^2 = 1
+    (long axis x) with edges of about h: rings of constant x spaced h apart
+    in arc length along the meridian, each with about 2 pi rho / h points
+    (alternate rings offset by half a step), consecutive rings zipped into
+    triangles in angular order, one vertex at each pole.  (A scaled sphere
+    mesh would stretch its elements a / b times along the axis.)"""
+    t = np.linspace(0.0, math.pi, 200001)
+    ds = np.hypot(a * np.sin(t), b * np.cos(t))
+    s = np.concatenate([[0.0], np.cumsum(0.5 * (ds[1:] + ds[:-1]) * (t[1] - t[0]))])
+    m = max(4, int(round(s[-1] / h)))
+    ti = np.interp(np.linspace(0.0, s[-1], m + 1), s, t)
+    verts = [np.array([[a, 0.0, 0.0]])]
+    rings = []  # (first vertex, count, angles)
+    nv = 1
+    for i in range(1, m):
+        rho, x = b * math.sin(ti[i]), a * math.cos(ti[i])
+        n = max(3, int(round(2.0 * math.pi * rho / h)))
+        ang = 2.0 * math.pi * (np.arange(n) + 0.5 * (i % 2)) / n
+        verts.append(np.stack([np.full(n, x), rho * np.cos(ang), rho * np.sin(ang)], axis=1))
+        rings.append((nv, n, ang))
+        nv += n
+    verts.append(np.array([[-a, 0.0, 0.0]]))
+    south = nv
+    V = np.concatenate(verts)
+    tris = []
+    f0, n0, _ = rings[0]
+    j = np.arange(n0)
+    tris.append(np.stack([np.zeros(n0, dtype=np.int64), f0 + j, f0 + (j + 1) % n0], axis=1))
+    for (fa, na, aa), (fb, nb, ab) in zip(rings[:-1], rings[1:]):
+        # walk both rings in angular order; each step advances one of them
+        ev = np.concatenate([aa[1:], [aa[0] + 2.0 * math.pi], ab[1:], [ab[0] + 2.0 * math.pi]])
+        typ = np.concatenate([np.zeros(na, dtype=np.int64), np.ones(nb, dtype=np.int64)])[np.argsort(ev, kind="stable")]
+        ia = np.cumsum(typ == 0) - (typ == 0)
+        jb = np.cumsum(typ == 1) - (typ == 1)
+        A0, A1 = fa + ia % na, fa + (ia + 1) % na
+        B0, B1 = fb + jb % nb, fb + (jb + 1) % nb
+        tris.append(np.where((typ == 0)[:, None], np.stack([A0, A1, B0], axis=1), np.stack([A0, B1, B0], axis=1)))
+    fl, nl, _ = rings[-1]
+    j = np.arange(nl)
+    tris.append(np.stack([np.full(nl, south), fl + (j + 1) % nl, fl + j], axis=1))
+    T = np.concatenate(tris).astype(np.int32)
+    return V, orient_outward(V, T)
 
 
 def fibonacci_directions(n: int) -> np.ndarray:
