@@ -53,6 +53,22 @@ def cpu_baseline(V, T, k, x, y_gpu, rows_sample, seconds_target=20.0):
     full = dt * n / m
     err = float(np.linalg.norm(y_gpu[rows] - yr) / np.linalg.norm(yr))
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    # the same oracle on one thread over a few rows, extrapolated to a full
+    # matvec (to set beside a one-core figure); the thread count is restored
+    one = None
+    try:
+        import ctypes
+
+        gomp = ctypes.CDLL("libgomp.so.1")
+        gomp.omp_set_num_threads(1)
+        r1 = rows[: max(8, min(len(rows), int(2.0 / max(per_row * threads, 1e-9))))]
+        t0 = time.perf_counter()
+        O.matvec(V, T, k, x, row_idx=r1)
+        one = dict(seconds_per_matvec=round((time.perf_counter() - t0) * n / len(r1), 1),
+                   sample=f"{len(r1)} rows on 1 thread, extrapolated to N")
+        gomp.omp_set_num_threads(threads)
+    except OSError:
+        pass
     model = ""
     try:
         with open("/proc/cpuinfo") as f:
@@ -62,7 +78,7 @@ def cpu_baseline(V, T, k, x, y_gpu, rows_sample, seconds_target=20.0):
     return dict(value=1.0 / full, unit="matvecs/s", cores=threads, kind="oracle", cpu_model=model,
                 nproc=os.cpu_count(),
                 sample=f"{m} of {n} rows of one FP64 dense matvec ({dt:.1f} s), scaled by N/{m}",
-                seconds_per_matvec=full), err, rows, yr
+                seconds_per_matvec=full, one_thread_extrapolated=one), err, rows, yr
 
 
 def uneven_batch_leg(nmesh, steps, log, tune=True):
