@@ -94,14 +94,22 @@ typedef struct fda_options {
                               0 = svd_eps */
     int32_t neumann_rhs;   /* also build the right-hand operator B of eq. (eq_bm) for Neumann data
                               (bm_rhs_neumann): its near-field blocks and leaf S2M; default 0 */
+    int32_t adaptive;      /* 0 (default): uniform tree, every leaf on the first level on which
+                              all boxes qualify as leaves; 1: adaptive tree (Section 3.2), each box
+                              a leaf as soon as it holds <= max_leaf elements (or its children
+                              would be narrower than leaf_min_h largest edges), so leaves sit on
+                              many levels.  Leaves are never directional: a directional box is
+                              always subdivided.  Leaf pairs whose boxes lie on different levels
+                              and are not separated by an interaction list (the U, W and X lists
+                              of adaptive FMMs) are evaluated directly in the near field. */
 } fda_options;
 
 /* Plan statistics (filled by fda_inspect / fda_plan_stats). */
 typedef struct fda_stats {
     int64_t n;                  /* triangles */
-    int32_t depth;              /* leaf level */
+    int32_t depth;              /* finest level (the leaf level of a uniform tree) */
     int32_t top_level;          /* coarsest level with interactions */
-    int64_t nleaf;              /* non-empty leaves */
+    int64_t nleaf;              /* non-empty leaves, all levels */
     int32_t max_leaf_count;     /* most elements in one leaf */
     int64_t near_nnz;           /* entries of the near-field block matrix */
     int64_t boxes[24];          /* non-empty boxes per level */
@@ -130,6 +138,16 @@ typedef struct fda_stats {
     double build_phase_seconds[8]; /* fda_build wall time by phase: tree and lists (host), factors of
                                       G_up / G_dn, translation matrices, low-rank M2L factors, leaf
                                       operators (host), upload, near-field quadrature; [7] unused */
+    int64_t leaves[24];         /* leaves per level */
+    int64_t u_pairs;            /* leaf pairs evaluated directly because the leaves touch (U lists) */
+    int64_t w_pairs;            /* leaf pairs below a touching box that the target leaf does not touch
+                                   (W lists; zero on uniform trees) */
+    int64_t x_pairs;            /* leaf pairs from a coarser source leaf that does not touch the target
+                                   (X lists; zero on uniform trees) */
+    int64_t far_elem_pairs;     /* element pairs covered by interaction lists (M2L); every ordered
+                                   element pair is covered once: near_nnz + far_elem_pairs = n^2 */
+    int64_t max_near_cols;      /* longest near-field row (source elements of one leaf); a build
+                                   refuses rows above 4,096 */
 } fda_stats;
 
 /* Fill *opt with the defaults listed above. */

@@ -396,7 +396,7 @@ void upload_plan(fda_plan *p, const HostOps &ops, DevTranslations &tr) {
     DevPlan &d = p->d;
     const int L = hp.depth;
     d.n = hp.n;
-    d.nleaf = (int)hp.lv[L].nbox;
+    d.nleaf = (int)hp.nleaf;
     d.depth = L;
     d.top = hp.top;
     d.max_leaf = hp.max_leaf_count;
@@ -439,7 +439,8 @@ void upload_plan(fda_plan *p, const HostOps &ops, DevTranslations &tr) {
         max_ncol = std::max(max_ncol, c);
     }
     if ((size_t)max_ncol * sizeof(double2) > 64 * 1024)
-        throw BuildError{FDA_EINVAL, "near-field row too long for one workgroup (lower max_leaf)"};
+        throw BuildError{FDA_EINVAL, "near-field row longer than 4,096 elements, too long for one workgroup "
+                                     "(lower max_leaf)"};
     d.max_ncol = max_ncol;
     d.nf_col_off = upload(p, col_off);
     d.nf_cols = upload(p, cols);
@@ -457,7 +458,7 @@ void upload_plan(fda_plan *p, const HostOps &ops, DevTranslations &tr) {
         const double lam = 2.0 * 3.14159265358979323846 / hp.k;
         std::vector<float> sc(2 * (size_t)d.nleaf);
         for (int b = 0; b < d.nleaf; ++b) {
-            sc[2 * b] = (float)(hp.lv[L].w / lam);
+            sc[2 * b] = (float)(hp.lv[hp.leaf_level[b]].w / lam);
             sc[2 * b + 1] = (float)(hp.h_max / lam);
         }
         d.leaf_scalars = upload(p, sc);
@@ -481,10 +482,19 @@ void upload_plan(fda_plan *p, const HostOps &ops, DevTranslations &tr) {
     d.S = to_storage(p, upload_cplx(p, ops.S), ops.S.size());
     if (!ops.SB.empty()) d.rhs.S = to_storage(p, upload_cplx(p, ops.SB), ops.SB.size());
     d.T = to_storage(p, upload_cplx(p, ops.T), ops.T.size());
+    d.leaf_sop = upload(p, ops.sop);
+    d.leaf_top = upload(p, ops.top);
     for (int l = hp.top; l <= L; ++l) {
         const Level &lv = hp.lv[l];
         DevLevel &dl = d.lv[l];
         dl.nbox = lv.nbox;
+        if (!lv.leaves.empty()) {
+            std::vector<int32_t> box;
+            for (int32_t t : lv.leaves) box.push_back(hp.leaf_box[t]);
+            dl.nleaves = (int)lv.leaves.size();
+            dl.leaf_ids = upload(p, lv.leaves);
+            dl.leaf_box = upload(p, box);
+        }
         dl.nslot = lv.nslot;
         dl.ku = lv.ku;
         dl.kd = lv.kd;

@@ -318,20 +318,21 @@ __global__ void k_p2p(const int64_t *leaf_off, const int32_t *nl_off, const int3
     }
 }
 
-// s_leaf = S~ x_leaf
+// s_leaf = S~ x_leaf, for the leaves of one level (ids: global leaf ids,
+// box: their boxes on the level, sop: offset of each leaf's S~)
 template <class C>
-__global__ void k_s2m(const int64_t *leaf_off, const C *S, int ku, const double2 *x, C *s, int64_t N,
-                      int64_t sstride) {
+__global__ void k_s2m(const int64_t *leaf_off, const int32_t *ids, const int32_t *box, const int64_t *sop,
+                      const C *S, int ku, const double2 *x, C *s, int64_t N, int64_t sstride) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C *xs = (C *)smem_raw;
-    const int b = blockIdx.x;
+    const int b = ids[blockIdx.x];
     const double2 *xr = x + (int64_t)blockIdx.y * N;
     const int64_t e0 = leaf_off[b];
     const int nl = (int)(leaf_off[b + 1] - e0);
     for (int i = threadIdx.x; i < nl; i += blockDim.x) xs[i] = cfrom<C>(xr[e0 + i]);
     __syncthreads();
-    const C *Sb = S + (int64_t)ku * e0;
-    C *sr = s + (int64_t)blockIdx.y * sstride + (int64_t)b * ku;
+    const C *Sb = S + sop[b];
+    C *sr = s + (int64_t)blockIdx.y * sstride + (int64_t)box[blockIdx.x] * ku;
     for (int r = threadIdx.x; r < ku; r += blockDim.x) {
         C acc = czero<C>();
         for (int j = 0; j < nl; ++j) cmac(acc, Sb[r + (int64_t)j * ku], xs[j]);
@@ -1051,13 +1052,14 @@ __global__ void k_gather_reduce(const int32_t *dst, const int32_t *off, const in
 // are split over 256 / npad thread groups, whose partial sums are added in a
 // fixed order (the product is bound by reading T~ from HBM).
 template <class C>
-__global__ void __launch_bounds__(256) k_l2t(const int64_t *leaf_off, const C *Tm, int kd, const C *c, double2 *y,
+__global__ void __launch_bounds__(256) k_l2t(const int64_t *leaf_off, const int32_t *ids, const int32_t *box,
+                                             const int64_t *top, const C *Tm, int kd, const C *c, double2 *y,
                                              int64_t N, int64_t cstride) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C *v = (C *)smem_raw;     // kd
     C *part = v + kd;         // 256
-    const int b = blockIdx.x, t = threadIdx.x;
-    const C *cr = c + (int64_t)blockIdx.y * cstride + (int64_t)b * kd;
+    const int b = ids[blockIdx.x], t = threadIdx.x;
+    const C *cr = c + (int64_t)blockIdx.y * cstride + (int64_t)box[blockIdx.x] * kd;
     for (int j = t; j < kd; j += blockDim.x) v[j] = cr[j];
     __syncthreads();
     const int64_t e0 = leaf_off[b];
@@ -1066,7 +1068,7 @@ __global__ void __launch_bounds__(256) k_l2t(const int64_t *leaf_off, const C *T
     while (npad < nl && npad < 256) npad <<= 1;
     const int G = 256 / npad;
     const int g = t / npad;
-    const C *Tb = Tm + (int64_t)kd * e0;
+    const C *Tb = Tm + top[b];
     double2 *yr = y + (int64_t)blockIdx.y * N;
     for (int i0 = 0; i0 < nl; i0 += npad) {
         const int i = i0 + (t % npad);
@@ -1484,10 +1486,16 @@ static hipError_t matvec_t(const DevPlan &d, const double2 *xt, double2 *yt, int
         return hipSuccess;
     }
     const int L = d.depth, top = d.top;
-    const DevLevel &lf = d.lv[L];
-    hipLaunchKernelGGL(k_s2m<C>, dim3(d.nleaf, nrhs), dim3(128), sizeof(C) * d.max_leaf, st, d.leaf_off,
-                       (const C *)op.S, lf.ku, xt, (C *)lf.s, N, lf.sstride);
-    CHECK_LAUNCH();
+    // S2M at the leaves of every level (a leaf's state is never written by
+    // M2M: only boxes with children are)
+    for (int l = L; l >= top; --l) {
+        const DevLevel &lf = d.lv[l];
+        if (lf.nleaves == 0) continue;
+        hipLaunchKernelGGL(k_s2m<C>, dim3(lf.nleaves, nrhs), dim3(128), sizeof(C) * d.max_leaf, st, d.leaf_off,
+                           lf.leaf_ids, lf.leaf_box, d.leaf_sop, (const C *)op.S, lf.ku, xt, (C *)lf.s, N,
+                           lf.sstride);
+        CHECK_LAUNCH();
+    }
     if (ev) hipEventRecord(ev[2], st);
     for (int l = L - 1; l >= top; --l) {
         const DevLevel &P = d.lv[l], &Cl = d.lv[l + 1];
@@ -1524,9 +1532,14 @@ static hipError_t matvec_t(const DevPlan &d, const double2 *xt, double2 *yt, int
         hipError_t e = hipStreamWaitEvent(st, d.join, 0);  // L2T adds to the near-field result
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_l2t<C>, dim3(d.nleaf, nrhs), dim3(256), sizeof(C) * (lf.kd + 256), st, d.leaf_off, (const C *)d.T,
-                       lf.kd, (const C *)lf.c, yt, N, lf.cstride);
-    CHECK_LAUNCH();
+    for (int l = top; l <= L; ++l) {
+        const DevLevel &lf = d.lv[l];
+        if (lf.nleaves == 0) continue;
+        hipLaunchKernelGGL(k_l2t<C>, dim3(lf.nleaves, nrhs), dim3(256), sizeof(C) * (lf.kd + 256), st, d.leaf_off,
+                           lf.leaf_ids, lf.leaf_box, d.leaf_top, (const C *)d.T, lf.kd, (const C *)lf.c, yt, N,
+                           lf.cstride);
+        CHECK_LAUNCH();
+    }
     if (ev) hipEventRecord(ev[6], st);
     return hipSuccess;
 }

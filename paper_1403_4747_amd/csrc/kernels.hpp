@@ -67,6 +67,9 @@ struct DevLevel {
     // parent-level operators towards level + 1 and their work lists
     void *M = nullptr, *Lo = nullptr;
     GWork m2m, l2l;
+    // the leaves of this level (S2M and L2T): global leaf ids and box indices
+    int nleaves = 0;
+    int32_t *leaf_ids = nullptr, *leaf_box = nullptr;
 };
 
 // The operator-specific parts of the matvec: near-field blocks and leaf S2M
@@ -95,6 +98,7 @@ struct DevPlan {
     void *nf_vals = nullptr;        // near-field blocks (FP32 plans: self terms zeroed)
     double2 *nf_diag = nullptr;     // FP32 plans: FP64 self terms, tree order
     void *S = nullptr, *T = nullptr;
+    int64_t *leaf_sop = nullptr, *leaf_top = nullptr;  // per leaf: offsets of its S~ and T~
     std::vector<DevLevel> lv;
     // block-Jacobi inverses of the leaf diagonal blocks
     int64_t *bj_off = nullptr;

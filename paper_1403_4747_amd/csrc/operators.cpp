@@ -56,18 +56,30 @@ void form_operators(const HostPlan &hp, HostOps &ops) {
         if (!hp.lv[l].offsets.empty()) any = true;
     if (!any) return;  // everything is near field
 
-    // leaf S2M and L2T per leaf (Section 4.3): S~ = S^-1 U^H E_up, T~ = E_dn V S^-1
-    const Level &lf = hp.lv[L];
+    // leaf S2M and L2T per leaf (Section 4.3): S~ = S^-1 U^H E_up, T~ = E_dn V S^-1,
+    // with the point sets and factors of the leaf's own level
     double bary[7][3], w7[7];
     r7_rule(bary, w7);
-    const int64_t nleaf = lf.nbox;
+    const int64_t nleaf = hp.nleaf;
     const bool rhsB = hp.opt.neumann_rhs != 0;
-    ops.S.assign((size_t)lf.ku * hp.n, cplx(0));
-    ops.T.assign((size_t)lf.kd * hp.n, cplx(0));
-    if (rhsB) ops.SB.assign((size_t)lf.ku * hp.n, cplx(0));
-    std::vector<double> uc = scaled(lf.cube, kRout * lf.r), de = uc;
-    parallel_for(nleaf, [&](int64_t b) {
-        int64_t e0 = hp.leaf_off[b], e1 = hp.leaf_off[b + 1];
+    auto has_far = [&](int64_t t) { return hp.leaf_level[t] >= hp.top; };
+    ops.sop.assign(nleaf + 1, 0);
+    ops.top.assign(nleaf + 1, 0);
+    for (int64_t t = 0; t < nleaf; ++t) {
+        const Level &lf = hp.lv[hp.leaf_level[t]];
+        const int64_t nl = hp.leaf_off[t + 1] - hp.leaf_off[t];
+        ops.sop[t + 1] = ops.sop[t] + (has_far(t) ? lf.ku * nl : 0);
+        ops.top[t + 1] = ops.top[t] + (has_far(t) ? lf.kd * nl : 0);
+    }
+    ops.S.assign((size_t)ops.sop[nleaf], cplx(0));
+    ops.T.assign((size_t)ops.top[nleaf], cplx(0));
+    if (rhsB) ops.SB.assign((size_t)ops.sop[nleaf], cplx(0));
+    parallel_for(nleaf, [&](int64_t t) {
+        if (!has_far(t)) return;
+        const Level &lf = hp.lv[hp.leaf_level[t]];
+        const int64_t b = hp.leaf_box[t];
+        const std::vector<double> uc = scaled(lf.cube, kRout * lf.r), &de = uc;
+        int64_t e0 = hp.leaf_off[t], e1 = hp.leaf_off[t + 1];
         int nl = (int)(e1 - e0);
         double c[3];
         for (int q = 0; q < 3; ++q) c[q] = hp.origin[q] + (lf.key[3 * b + q] + 0.5) * lf.w;
@@ -111,19 +123,20 @@ void form_operators(const HostPlan &hp, HostOps &ops) {
         scale_rows(St, lf.su[0]);
         Mat Tt = matmul(Ed, 'N', lf.Vd[0], 'N');
         scale_cols(Tt, lf.sd[0]);
-        // S~ stored ku x nl column-major at ku * e0; T~ stored nl x kd column-major at kd * e0
+        // S~ stored ku x nl column-major at sop[t]; T~ stored nl x kd column-major at top[t]
+        const size_t so = (size_t)ops.sop[t], to = (size_t)ops.top[t];
         for (int j = 0; j < nl; ++j)
             for (int i = 0; i < lf.ku; ++i)
-                ops.S[(size_t)lf.ku * e0 + i + (size_t)j * lf.ku] = (i < St.m) ? St(i, j) : cplx(0);
+                ops.S[so + i + (size_t)j * lf.ku] = (i < St.m) ? St(i, j) : cplx(0);
         for (int j = 0; j < lf.kd; ++j)
             for (int i = 0; i < nl; ++i)
-                ops.T[(size_t)lf.kd * e0 + i + (size_t)j * nl] = (j < Tt.n) ? Tt(i, j) : cplx(0);
+                ops.T[to + i + (size_t)j * nl] = (j < Tt.n) ? Tt(i, j) : cplx(0);
         if (rhsB) {
             Mat SBt = matmul(lf.Uu[0], 'C', EB, 'N');
             scale_rows(SBt, lf.su[0]);
             for (int j = 0; j < nl; ++j)
                 for (int i = 0; i < lf.ku; ++i)
-                    ops.SB[(size_t)lf.ku * e0 + i + (size_t)j * lf.ku] = (i < SBt.m) ? SBt(i, j) : cplx(0);
+                    ops.SB[so + i + (size_t)j * lf.ku] = (i < SBt.m) ? SBt(i, j) : cplx(0);
         }
     });
 }

@@ -25,7 +25,11 @@ struct Level {
     std::vector<int32_t> key;   // 3 per box, integer box coordinates
     std::vector<int32_t> parent, octant;  // parent box index and child octant (bit 2: x, 1: y, 0: z)
     std::vector<int32_t> child_begin;     // children of box b are [child_begin[b], child_begin[b+1]) at level+1
+    std::vector<int32_t> leaf;            // global leaf id of each box, -1 for a box that is subdivided
+    std::vector<int64_t> nelem;           // elements in each box
+    std::vector<int32_t> leaves;          // global ids of the leaves at this level, ascending
     std::vector<std::vector<int32_t>> near, il;  // near list and interaction list (sources) per box
+    std::vector<std::vector<int32_t>> near_up;   // coarser leaves adjacent to the box (global leaf ids)
     std::vector<int32_t> il_op;           // per (box, il entry) flattened: distinct-offset index
     std::vector<std::vector<int32_t>> il_ops;
     std::vector<std::array<int32_t, 3>> offsets;  // distinct offsets (target - source) of this level
@@ -57,15 +61,22 @@ struct HostPlan {
     double h_max = 0;
     double origin[3] = {0, 0, 0};
     double side = 0;
-    int depth = 0, top = 0;      // leaf level, coarsest level with interactions
+    int depth = 0, top = 0;      // finest level, coarsest level with interactions
     std::vector<Level> lv;
     // geometry in tree order
     std::vector<int32_t> perm;   // tree index -> caller index
     std::vector<double> tri;     // 9 doubles per element (vertices), tree order
     std::vector<double> cen, nrm, area;  // tree order
     std::vector<int64_t> leaf_off;       // element range of each leaf
+    int64_t nleaf = 0;                   // leaves at every level, in depth-first Morton order
+    std::vector<int32_t> leaf_level, leaf_box;  // level and box index of each leaf
     int max_leaf_count = 0;
-    // near field (leaf level): per target leaf, its near leaves
+    // adaptive trees: leaf pairs evaluated directly because one box of the
+    // pair is a leaf coarser than the other (U list across levels, W and X
+    // lists), and element pairs covered by interaction lists (all levels)
+    int64_t u_pairs = 0, w_pairs = 0, x_pairs = 0;
+    int64_t far_elem_pairs = 0;
+    // near field: per target leaf, the source leaves evaluated directly
     std::vector<int64_t> nf_list_off;    // nleaf + 1
     std::vector<int32_t> nf_list;        // near source leaves
     std::vector<int64_t> nf_blk_off;     // nleaf + 1: value offset of each target block

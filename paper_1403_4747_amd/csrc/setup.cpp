@@ -151,6 +151,7 @@ void host_setup(const double *V, int64_t nv, const int32_t *T, int64_t nt, doubl
     if (!(eps > 0 && eps < 1)) throw BuildError{FDA_EINVAL, "eps must be in (0, 1)"};
     if (nt <= 0 || nv <= 0 || !V || !T) throw BuildError{FDA_EINVAL, "empty mesh"};
     if (opt.max_leaf < 1 || opt.max_leaf > 256) throw BuildError{FDA_EINVAL, "max_leaf must be in [1, 256]"};
+    if (opt.adaptive != 0 && opt.adaptive != 1) throw BuildError{FDA_EINVAL, "adaptive must be 0 or 1"};
     if (!(opt.svd_eps >= 0 && opt.svd_eps < 1) || !(opt.m2l_svd_eps >= 0 && opt.m2l_svd_eps < 1))
         throw BuildError{FDA_EINVAL, "svd_eps and m2l_svd_eps must be in [0, 1)"};
     for (int64_t i = 0; i < 3 * nv; ++i)
@@ -166,7 +167,7 @@ void host_setup(const double *V, int64_t nv, const int32_t *T, int64_t nt, doubl
     const double lambda = 2.0 * kPi / k;
 
     // geometry (caller order)
-    std::vector<double> cen(3 * nt), nrm(3 * nt), area(nt);
+    std::vector<double> cen(3 * nt), nrm(3 * nt), area(nt), emax(nt);
     double h = 0;
     for (int64_t t = 0; t < nt; ++t) {
         for (int q = 0; q < 3; ++q)
@@ -186,9 +187,10 @@ void host_setup(const double *V, int64_t nv, const int32_t *T, int64_t nt, doubl
             nrm[3 * t + q] = -cr[q] / ln;
         }
         area[t] = 0.5 * ln;
-        h = std::max(h, std::sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]));
-        h = std::max(h, std::sqrt(e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2]));
-        h = std::max(h, std::sqrt(e3[0] * e3[0] + e3[1] * e3[1] + e3[2] * e3[2]));
+        emax[t] = std::max(std::sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]),
+                           std::max(std::sqrt(e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2]),
+                                    std::sqrt(e3[0] * e3[0] + e3[1] * e3[1] + e3[2] * e3[2])));
+        h = std::max(h, emax[t]);
     }
     hp.h_max = h;
 
@@ -213,47 +215,59 @@ void host_setup(const double *V, int64_t nv, const int32_t *T, int64_t nt, doubl
         }
     };
 
-    // depth: smallest L with every leaf <= max_leaf, but no leaf narrower
-    // than leaf_min_h * h_max (near-singular pairs must stay in the near field)
+    // Tree (Algorithm, Step 1.1).  A box is a leaf when it holds at most
+    // max_leaf elements or when its children would be narrower than
+    // leaf_min_h times the largest edge (near-singular pairs must stay in the
+    // near field).  Uniform trees put every leaf on one level: the first on
+    // which every box qualifies, with the largest edge of the mesh.  Adaptive
+    // trees (Section 3.2) stop subdividing each box as soon as it qualifies,
+    // with the largest edge among the box's own elements, so leaves sit on
+    // many levels and every box is still at least leaf_min_h of its own
+    // largest edges wide; a directional box is always subdivided (leaves are
+    // non-directional).
     const double tau = opt.leaf_min_h * h;
-    int L = 0;
-    for (;;) {
-        if (L >= 20) break;
-        double w = side / std::ldexp(1.0, L);
-        if (w * 0.5 < tau) break;
-        std::unordered_map<uint64_t, int> cnt;
-        int mx = 0;
-        for (int64_t e = 0; e < nt; ++e) {
-            int32_t kk[3];
-            keys_at(L, e, kk);
-            mx = std::max(mx, ++cnt[morton(kk[0], kk[1], kk[2])]);
+    auto width = [&](int l) { return side / std::ldexp(1.0, l); };
+    auto hf_width = [&](int l) { return l > 0 && width(l) >= opt.hf_wavelengths * lambda * (1.0 - 1e-9); };
+    const bool adaptive = opt.adaptive != 0;
+    int Lu = -1;
+    if (!adaptive) {
+        Lu = 0;
+        for (;;) {
+            if (Lu >= 20) break;
+            if (width(Lu) * 0.5 < tau) break;
+            std::unordered_map<uint64_t, int> cnt;
+            int mx = 0;
+            for (int64_t e = 0; e < nt; ++e) {
+                int32_t kk[3];
+                keys_at(Lu, e, kk);
+                mx = std::max(mx, ++cnt[morton(kk[0], kk[1], kk[2])]);
+            }
+            if (mx <= opt.max_leaf) break;
+            ++Lu;
         }
-        if (mx <= opt.max_leaf) break;
-        ++L;
     }
-    hp.depth = L;
-    hp.lv.assign(L + 1, Level());
-
-    // boxes per level, Morton ordered
-    std::vector<uint64_t> leafcode(nt);
-    for (int l = 0; l <= L; ++l) {
+    // boxes per level (Morton ordered): those holding an element that is not
+    // yet in a leaf
+    std::vector<int32_t> elev(nt, -1);  // leaf level of each element
+    hp.lv.clear();
+    for (int l = 0;; ++l) {
+        hp.lv.emplace_back();
         Level &lv = hp.lv[l];
-        lv.w = side / std::ldexp(1.0, l);
+        lv.w = width(l);
         lv.r = 0.5 * lv.w;
-        std::vector<uint64_t> codes(nt);
+        std::vector<uint64_t> codes(nt, ~0ULL), u;
         for (int64_t e = 0; e < nt; ++e) {
+            if (elev[e] >= 0) continue;
             int32_t kk[3];
             keys_at(l, e, kk);
             codes[e] = morton(kk[0], kk[1], kk[2]);
-            if (l == L) leafcode[e] = codes[e];
+            u.push_back(codes[e]);
         }
-        std::vector<uint64_t> u(codes);
         std::sort(u.begin(), u.end());
         u.erase(std::unique(u.begin(), u.end()), u.end());
         lv.nbox = (int64_t)u.size();
         lv.key.resize(3 * lv.nbox);
         for (int64_t b = 0; b < lv.nbox; ++b) {
-            // decode
             int32_t kk[3] = {0, 0, 0};
             for (int bit = 0; bit < 21; ++bit) {
                 kk[0] |= (int32_t)((u[b] >> (3 * bit + 2)) & 1) << bit;
@@ -262,7 +276,41 @@ void host_setup(const double *V, int64_t nv, const int32_t *T, int64_t nt, doubl
             }
             for (int q = 0; q < 3; ++q) lv.key[3 * b + q] = kk[q];
         }
+        std::vector<int32_t> ebox(nt, -1);
+        std::vector<double> hbox(lv.nbox, 0.0);
+        lv.nelem.assign(lv.nbox, 0);
+        for (int64_t e = 0; e < nt; ++e) {
+            if (codes[e] == ~0ULL) continue;
+            ebox[e] = (int32_t)(std::lower_bound(u.begin(), u.end(), codes[e]) - u.begin());
+            lv.nelem[ebox[e]]++;
+            hbox[ebox[e]] = std::max(hbox[ebox[e]], emax[e]);
+        }
+        lv.leaf.assign(lv.nbox, -1);
+        bool split = false;
+        for (int64_t b = 0; b < lv.nbox; ++b) {
+            bool leaf;
+            if (!adaptive) {
+                leaf = l == Lu;
+            } else {
+                // children would be too narrow
+                const bool cannot = lv.w * 0.5 < opt.leaf_min_h * hbox[b] || l >= 20;
+                leaf = lv.nelem[b] <= opt.max_leaf || cannot;
+                if (leaf && hf_width(l)) {
+                    if (cannot)
+                        throw BuildError{FDA_EINVAL, "leaf boxes are directional (too few elements per wavelength "
+                                                     "for max_leaf); raise max_leaf or hf_wavelengths"};
+                    leaf = false;
+                }
+            }
+            if (leaf) lv.leaf[b] = 0;  // marked; numbered below
+            else split = true;
+        }
+        for (int64_t e = 0; e < nt; ++e)
+            if (ebox[e] >= 0 && lv.leaf[ebox[e]] >= 0) elev[e] = l;
+        if (!split) break;
     }
+    const int L = (int)hp.lv.size() - 1;
+    hp.depth = L;
     // parents / children (Morton order keeps the children of a box contiguous)
     for (int l = 1; l <= L; ++l) {
         Level &lv = hp.lv[l], &pv = hp.lv[l - 1];
@@ -279,25 +327,60 @@ void host_setup(const double *V, int64_t nv, const int32_t *T, int64_t nt, doubl
         }
         for (int64_t b = 0; b < pv.nbox; ++b) pv.child_begin[b + 1] += pv.child_begin[b];
     }
+    hp.lv[L].child_begin.assign(hp.lv[L].nbox + 1, 0);
 
-    // element permutation: by leaf (Morton), then caller index
+    // leaves in depth-first Morton order: a box's code shifted to the finest
+    // level orders boxes of different levels, and the leaves below any box
+    // are a contiguous range
+    auto dfs_key = [&](int l, int64_t b) {
+        const int32_t *kk = &hp.lv[l].key[3 * b];
+        return morton(kk[0], kk[1], kk[2]) << (3 * (L - l));
+    };
+    std::vector<std::pair<uint64_t, std::pair<int32_t, int32_t>>> lk;
+    for (int l = 0; l <= L; ++l)
+        for (int64_t b = 0; b < hp.lv[l].nbox; ++b)
+            if (hp.lv[l].leaf[b] >= 0) lk.push_back({dfs_key(l, b), {l, (int32_t)b}});
+    std::sort(lk.begin(), lk.end());
+    hp.nleaf = (int64_t)lk.size();
+    hp.leaf_level.resize(hp.nleaf);
+    hp.leaf_box.resize(hp.nleaf);
+    std::vector<uint64_t> leaf_dfs(hp.nleaf);
+    for (int64_t t = 0; t < hp.nleaf; ++t) {
+        const int l = lk[t].second.first, b = lk[t].second.second;
+        hp.leaf_level[t] = l;
+        hp.leaf_box[t] = b;
+        hp.lv[l].leaf[b] = (int32_t)t;
+        hp.lv[l].leaves.push_back((int32_t)t);
+        leaf_dfs[t] = lk[t].first;
+    }
+    // leaves below box b of level l: [first, last)
+    auto subtree_leaves = [&](int l, int64_t b) {
+        const uint64_t lo = dfs_key(l, b), hi = lo + (1ULL << (3 * (L - l)));
+        return std::make_pair(std::lower_bound(leaf_dfs.begin(), leaf_dfs.end(), lo) - leaf_dfs.begin(),
+                              std::lower_bound(leaf_dfs.begin(), leaf_dfs.end(), hi) - leaf_dfs.begin());
+    };
+
+    // element permutation: by leaf, then caller index
+    std::vector<uint64_t> leafcode(nt);
+    for (int64_t e = 0; e < nt; ++e) {
+        int32_t kk[3];
+        keys_at(elev[e], e, kk);
+        leafcode[e] = morton(kk[0], kk[1], kk[2]) << (3 * (L - elev[e]));
+    }
     std::vector<int32_t> perm(nt);
     std::iota(perm.begin(), perm.end(), 0);
     std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) { return leafcode[a] < leafcode[b]; });
     hp.perm = perm;
     {
-        Level &lf = hp.lv[L];
-        hp.leaf_off.assign(lf.nbox + 1, 0);
+        hp.leaf_off.assign(hp.nleaf + 1, 0);
         int64_t b = 0;
         for (int64_t i = 0; i < nt; ++i) {
             uint64_t c = leafcode[perm[i]];
-            while (morton(lf.key[3 * b], lf.key[3 * b + 1], lf.key[3 * b + 2]) != c) {
-                hp.leaf_off[++b] = i;
-            }
+            while (leaf_dfs[b] != c) hp.leaf_off[++b] = i;
         }
-        while (b < lf.nbox) hp.leaf_off[++b] = nt;
+        while (b < hp.nleaf) hp.leaf_off[++b] = nt;
         hp.max_leaf_count = 0;
-        for (int64_t q = 0; q < lf.nbox; ++q)
+        for (int64_t q = 0; q < hp.nleaf; ++q)
             hp.max_leaf_count = std::max<int>(hp.max_leaf_count, (int)(hp.leaf_off[q + 1] - hp.leaf_off[q]));
         // leaves wider than leaf_min_h * h_max may hold more elements than
         // max_leaf on strongly graded meshes; the leaf kernels (block-Jacobi
@@ -332,8 +415,9 @@ void host_setup(const double *V, int64_t nv, const int32_t *T, int64_t nt, doubl
         lv.hf = lv.w >= opt.hf_wavelengths * lambda * (1.0 - 1e-9) && l > 0;
         if (lv.hf) finest_hf = l;
     }
-    if (finest_hf == L && L > 0)
-        throw BuildError{FDA_EINVAL, "leaf boxes are directional (too few elements per wavelength for max_leaf); "
+    for (int l = 0; l <= finest_hf; ++l)
+        if (hp.lv[l].hf && !hp.lv[l].leaves.empty())
+            throw BuildError{FDA_EINVAL, "leaf boxes are directional (too few elements per wavelength for max_leaf); "
                                      "raise max_leaf or hf_wavelengths"};
     if (finest_hf >= 0) {
         int n0 = std::max(1, (int)std::lround(hp.lv[finest_hf].w / lambda));
@@ -348,19 +432,44 @@ void host_setup(const double *V, int64_t nv, const int32_t *T, int64_t nt, doubl
         }
     }
 
-    // near and interaction lists, top-down (Algorithm, Step 1.2-1.5)
+    // near and interaction lists, top-down (Algorithm, Step 1.2-1.5).  On an
+    // adaptive tree a leaf in the near list of a box's parent is coarser than
+    // the box's children: it stays in their near lists (near_up) while it
+    // touches them, and otherwise its elements act on every leaf below the
+    // child directly (the X list of the child, evaluated in the near field).
+    // closed boxes b1 (level l1) and b2 (level l2 >= l1) meet
+    auto touches = [&](int l1, int64_t b1, int l2, int64_t b2) {
+        const int s = l2 - l1;
+        for (int q = 0; q < 3; ++q) {
+            const int64_t k1 = hp.lv[l1].key[3 * b1 + q], k2 = hp.lv[l2].key[3 * b2 + q];
+            if (k2 + 1 < (k1 << s) || k2 > ((k1 + 1) << s)) return false;
+        }
+        return true;
+    };
+    struct XEntry {
+        int l;
+        int32_t b, src;  // box of level l, source leaf
+    };
+    std::vector<XEntry> xlist;
     hp.lv[0].near.assign(1, std::vector<int32_t>{0});
     hp.lv[0].il.assign(1, {});
     hp.lv[0].il_ops.assign(1, {});
+    hp.lv[0].near_up.assign(1, {});
     for (int l = 1; l <= L; ++l) {
         Level &lv = hp.lv[l], &pv = hp.lv[l - 1];
         lv.near.assign(lv.nbox, {});
         lv.il.assign(lv.nbox, {});
         lv.il_ops.assign(lv.nbox, {});
+        lv.near_up.assign(lv.nbox, {});
         std::map<std::array<int32_t, 3>, int32_t> opidx;
         for (int64_t b = 0; b < lv.nbox; ++b) {
             int32_t P = lv.parent[b];
             for (int32_t pn : pv.near[P]) {
+                if (pv.leaf[pn] >= 0) {
+                    if (touches(l - 1, pn, l, b)) lv.near_up[b].push_back(pv.leaf[pn]);
+                    else xlist.push_back({l, (int32_t)b, pv.leaf[pn]});
+                    continue;
+                }
                 for (int32_t a = pv.child_begin[pn]; a < pv.child_begin[pn + 1]; ++a) {
                     int d[3] = {lv.key[3 * b] - lv.key[3 * a], lv.key[3 * b + 1] - lv.key[3 * a + 1],
                                 lv.key[3 * b + 2] - lv.key[3 * a + 2]};
@@ -388,6 +497,10 @@ void host_setup(const double *V, int64_t nv, const int32_t *T, int64_t nt, doubl
                     }
                 }
             }
+            for (int32_t c : pv.near_up[P]) {
+                if (touches(hp.leaf_level[c], hp.leaf_box[c], l, b)) lv.near_up[b].push_back(c);
+                else xlist.push_back({l, (int32_t)b, c});
+            }
         }
     }
     hp.top = L;
@@ -397,27 +510,79 @@ void host_setup(const double *V, int64_t nv, const int32_t *T, int64_t nt, doubl
             if (!x.empty()) { any = true; break; }
         if (any) { hp.top = l; break; }
     }
+    hp.far_elem_pairs = 0;
+    for (int l = 0; l <= L; ++l) {
+        const Level &lv = hp.lv[l];
+        for (int64_t b = 0; b < lv.nbox; ++b)
+            for (int32_t a : lv.il[b]) hp.far_elem_pairs += lv.nelem[b] * lv.nelem[a];
+    }
 
-    // near field at the leaves
+    // the source leaves each leaf evaluates directly: its U list (touching
+    // leaves of any level), its W list (boxes below a same-level neighbour
+    // that do not touch it but whose parents do: every leaf below them) and
+    // the X entries of its ancestors and itself
     {
-        Level &lf = hp.lv[L];
-        hp.nf_list_off.assign(lf.nbox + 1, 0);
-        hp.nf_blk_off.assign(lf.nbox + 1, 0);
-        hp.nf_ncol.assign(lf.nbox, 0);
+        std::vector<std::vector<int32_t>> nsrc(hp.nleaf);
+        hp.u_pairs = hp.w_pairs = hp.x_pairs = 0;
+        for (int64_t t = 0; t < hp.nleaf; ++t) {
+            const int l = hp.leaf_level[t];
+            const int32_t b = hp.leaf_box[t];
+            const Level &lv = hp.lv[l];
+            auto &out = nsrc[t];
+            for (int32_t c : lv.near_up[b]) out.push_back(c);
+            hp.u_pairs += (int64_t)lv.near_up[b].size();
+            std::vector<std::pair<int, int32_t>> stack;
+            for (int32_t a : lv.near[b]) {
+                if (lv.leaf[a] >= 0) {
+                    out.push_back(lv.leaf[a]);
+                    ++hp.u_pairs;
+                    continue;
+                }
+                stack.push_back({l, a});
+                while (!stack.empty()) {
+                    const auto [m, x] = stack.back();
+                    stack.pop_back();
+                    const Level &mv = hp.lv[m];
+                    for (int32_t y = mv.child_begin[x]; y < mv.child_begin[x + 1]; ++y) {
+                        if (!touches(l, b, m + 1, y)) {
+                            const auto r = subtree_leaves(m + 1, y);
+                            for (int64_t s = r.first; s < r.second; ++s) out.push_back((int32_t)s);
+                            hp.w_pairs += r.second - r.first;
+                        } else if (hp.lv[m + 1].leaf[y] >= 0) {
+                            out.push_back(hp.lv[m + 1].leaf[y]);
+                            ++hp.u_pairs;
+                        } else {
+                            stack.push_back({m + 1, y});
+                        }
+                    }
+                }
+            }
+        }
+        for (const XEntry &x : xlist) {
+            const auto r = subtree_leaves(x.l, x.b);
+            for (int64_t t = r.first; t < r.second; ++t) nsrc[t].push_back(x.src);
+            hp.x_pairs += r.second - r.first;
+        }
+        hp.nf_list_off.assign(hp.nleaf + 1, 0);
+        hp.nf_blk_off.assign(hp.nleaf + 1, 0);
+        hp.nf_ncol.assign(hp.nleaf, 0);
         hp.nf_list.clear();
-        for (int64_t b = 0; b < lf.nbox; ++b) {
-            auto nl = lf.near[b];
+        for (int64_t t = 0; t < hp.nleaf; ++t) {
+            auto &nl = nsrc[t];
             std::sort(nl.begin(), nl.end());
+            if (std::adjacent_find(nl.begin(), nl.end()) != nl.end())
+                throw BuildError{FDA_EINVAL, "internal: a leaf pair is listed twice"};
             int64_t ncol = 0;
             for (int32_t s : nl) {
                 hp.nf_list.push_back(s);
                 ncol += hp.leaf_off[s + 1] - hp.leaf_off[s];
             }
-            hp.nf_list_off[b + 1] = (int64_t)hp.nf_list.size();
-            hp.nf_ncol[b] = (int32_t)ncol;
-            hp.nf_blk_off[b + 1] = hp.nf_blk_off[b] + ncol * (hp.leaf_off[b + 1] - hp.leaf_off[b]);
+            hp.nf_list_off[t + 1] = (int64_t)hp.nf_list.size();
+            hp.nf_ncol[t] = (int32_t)ncol;
+            hp.nf_blk_off[t + 1] = hp.nf_blk_off[t] + ncol * (hp.leaf_off[t + 1] - hp.leaf_off[t]);
+            std::vector<int32_t>().swap(nl);
         }
-        hp.near_nnz = hp.nf_blk_off[lf.nbox];
+        hp.near_nnz = hp.nf_blk_off[hp.nleaf];
     }
 
     // active directions, top-down: those used by interaction lists, plus the
@@ -573,7 +738,10 @@ void host_setup(const double *V, int64_t nv, const int32_t *T, int64_t nt, doubl
                     lv.hf ? (int)lv.active.size() : 0, lv.ndir, lv.p, lv.ku, lv.theta, lv.tmin / lv.w, lv.far.size() / 3);
         }
         fprintf(stderr, "[fda] depth=%d top=%d leaves=%lld max_leaf=%d near_nnz=%lld h_max=%.4g\n", hp.depth, hp.top,
-                (long long)hp.lv[L].nbox, hp.max_leaf_count, (long long)hp.near_nnz, hp.h_max);
+                (long long)hp.nleaf, hp.max_leaf_count, (long long)hp.near_nnz, hp.h_max);
+        if (adaptive)
+            fprintf(stderr, "[fda] adaptive: U pairs=%lld W pairs=%lld X pairs=%lld\n", (long long)hp.u_pairs,
+                    (long long)hp.w_pairs, (long long)hp.x_pairs);
     }
 }
 
@@ -582,7 +750,12 @@ void fill_stats(const HostPlan &hp, fda_stats *st) {
     st->n = hp.n;
     st->depth = hp.depth;
     st->top_level = hp.top;
-    st->nleaf = hp.lv.empty() ? 0 : hp.lv[hp.depth].nbox;
+    st->nleaf = hp.nleaf;
+    st->u_pairs = hp.u_pairs;
+    st->w_pairs = hp.w_pairs;
+    st->x_pairs = hp.x_pairs;
+    st->far_elem_pairs = hp.far_elem_pairs;
+    for (int32_t c : hp.nf_ncol) st->max_near_cols = std::max<int64_t>(st->max_near_cols, c);
     st->max_leaf_count = hp.max_leaf_count;
     st->near_nnz = hp.near_nnz;
     st->h_max = hp.h_max;
@@ -591,6 +764,7 @@ void fill_stats(const HostPlan &hp, fda_stats *st) {
     for (int l = 0; l <= hp.depth && l < 24; ++l) {
         const Level &lv = hp.lv[l];
         st->boxes[l] = lv.nbox;
+        st->leaves[l] = (int64_t)lv.leaves.size();
         int64_t pairs = 0;
         for (auto &x : lv.il) pairs += (int64_t)x.size();
         st->m2l_pairs[l] = pairs;

@@ -44,7 +44,7 @@ class Options(ctypes.Structure):
         ("hf_wavelengths", ctypes.c_double), ("rho_c", ctypes.c_double), ("leaf_min_h", ctypes.c_double),
         ("prec", ctypes.c_int32), ("nrhs_max", ctypes.c_int32), ("device", ctypes.c_int32),
         ("verbose", ctypes.c_int32), ("svd_method", ctypes.c_int32), ("m2l_svd_eps", ctypes.c_double),
-        ("neumann_rhs", ctypes.c_int32),
+        ("neumann_rhs", ctypes.c_int32), ("adaptive", ctypes.c_int32),
     ]
 
 
@@ -59,7 +59,9 @@ class Stats(ctypes.Structure):
         ("m2l_level_flops", ctypes.c_double * 24), ("m2l_flops", ctypes.c_int64), ("m2l_bytes", ctypes.c_int64), ("h_max", ctypes.c_double),
         ("root_width", ctypes.c_double), ("build_seconds", ctypes.c_double), ("device_bytes", ctypes.c_int64),
         ("m2m_flops", ctypes.c_double), ("l2l_flops", ctypes.c_double), ("mlp_rows", ctypes.c_int64),
-        ("build_phase_seconds", ctypes.c_double * 8),
+        ("build_phase_seconds", ctypes.c_double * 8), ("leaves", ctypes.c_int64 * 24),
+        ("u_pairs", ctypes.c_int64), ("w_pairs", ctypes.c_int64), ("x_pairs", ctypes.c_int64),
+        ("far_elem_pairs", ctypes.c_int64), ("max_near_cols", ctypes.c_int64),
     ]
 
     def to_dict(self) -> Dict:

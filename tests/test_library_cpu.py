@@ -70,18 +70,21 @@ def test_inspect_directional_levels_at_kD100():
 
 
 def test_pair_coverage_counts():
-    """Every ordered pair of elements is either near (P2P) or reached by
-    exactly one interaction-list pair: near entries plus far pairs sum to
-    N^2.  Far element pairs are counted from the per-level pair lists with
-    box populations, which the stats do not carry, so this checks the weaker
-    identity near_nnz <= N^2 and a positive far count."""
+    """Every ordered pair of elements is either evaluated directly (near
+    field) or reached by exactly one interaction-list pair: near entries
+    plus the element pairs of all interaction-list pairs sum to N^2
+    (Algorithm, Step 1: the lists partition the far field)."""
     from paper_1403_4747_amd import inspect
 
-    V, T, prm = W.workload("sphere5120_kD20")
-    st = inspect(V, T, prm["k"], prm["eps"])
-    n = st["n"]
-    assert 0 < st["near_nnz"] < n * n
-    assert sum(st["m2l_pairs"]) > 0
+    for name in ("sphere5120_kD20", "sphere20480_kD100"):
+        V, T, prm = W.workload(name)
+        st = inspect(V, T, prm["k"], prm["eps"])
+        n = st["n"]
+        assert 0 < st["near_nnz"] < n * n
+        assert sum(st["m2l_pairs"]) > 0
+        assert st["near_nnz"] + st["far_elem_pairs"] == n * n, name
+        # a uniform tree: every leaf on the finest level, no W / X lists
+        assert st["leaves"][-1] == st["nleaf"] and st["w_pairs"] == st["x_pairs"] == 0
 
 
 @pytest.mark.parametrize("bad", ["index", "zero_area", "k", "eps"])
@@ -138,3 +141,8 @@ def test_inspect_rejects_leaves_above_256_elements():
     # with narrow leaves allowed the same mesh builds
     st = inspect(V, T, 5.0, 1e-4, leaf_min_h=0.01)
     assert st["max_leaf_count"] <= 64
+    # an adaptive tree sizes each box by its own largest edge, but here the
+    # root holds the large triangle and cannot be split either
+    with pytest.raises(FDAError) as e:
+        inspect(V, T, 5.0, 1e-4, adaptive=1)
+    assert e.value.code == -2 and "256" in str(e.value)
