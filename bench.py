@@ -256,6 +256,103 @@ def large_case(args, log):
     }
 
 
+def adaptive_case(args, log):
+    """Adaptive trees on a graded mesh: an icosphere of 20,480 triangles whose
+    cap above z = 0.3 r is refined once and above z = 0.7 r twice more
+    (79,106 triangles, 4.8:1 in edge length), radius 0.5, kD = 100, eps =
+    1e-4, plane wave along +z.  A uniform tree refuses the mesh (a leaf of
+    more than 256 elements); the adaptive tree puts leaves on three levels
+    and evaluates W and X pairs directly.  Arms: adaptive FP64, adaptive
+    FP32, and a uniform tree with leaves only 1.5 largest edges wide (the
+    widest setting that builds: near-singular pairs then reach the far
+    field).  Matvec rate, stage times, GMRES to 1e-5 and the error on oracle
+    rows of each arm."""
+    import torch
+
+    import workloads as W
+    from paper_1403_4747_amd import FDAError, Plan, inspect
+
+    V, T = W.graded_sphere(5)
+    n, k = len(T), 100.0
+    log(f"[bench] adaptive case: graded sphere N={n} kD={k:g}")
+    x = torch.from_numpy(W.complex_normal(n, 1, seed=0)).to("cuda")
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    try:
+        inspect(V, T, k, 1e-4)
+        uniform_refusal = None
+    except FDAError as e:
+        uniform_refusal = str(e)
+    arms, ys = {}, {}
+    for name, kw in (("adaptive_fp64", dict(adaptive=1)), ("adaptive_fp32", dict(adaptive=1, prec="fp32")),
+                     ("uniform_leaf1.5h_fp64", dict(leaf_min_h=1.5))):
+        t0 = time.perf_counter()
+        p = Plan(V, T, k, 1e-4, **kw)
+        torch.cuda.synchronize()
+        arm = dict(build_seconds=round(time.perf_counter() - t0, 2))
+        st = p.stats()
+        arm.update(depth=st["depth"], leaves_per_level=st["leaves"], leaves=st["nleaf"], max_leaf=st["max_leaf_count"],
+                   near_nnz=st["near_nnz"], near_from_w_x=st["wx_elem_pairs"], u_pairs=st["u_pairs"],
+                   w_pairs=st["w_pairs"], x_pairs=st["x_pairs"], m2l_flops=st["m2l_flops"])
+        if not args.no_tune:
+            arm["m2l_autotune"] = p.autotune(reps=5)["best"]
+        y = p.matvec(x)
+        for _ in range(2):
+            p.matvec(x, out=y)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(args.steps):
+            p.matvec(x, out=y)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        prof = p.profile(x, reps=3)
+        arm.update(ms_per_matvec=round(ms, 4), matvecs_per_s=round(1000.0 / ms, 2),
+                   stages_ms={q: round(v, 4) for q, v in prof.items() if q != "m2l_gemm"})
+        ys[name] = y.cpu().numpy()
+        if not args.no_solve:
+            b = p.rhs_planewave((0.0, 0.0, 1.0))
+            for pc in ("none", "block_jacobi"):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, info = p.solve(b, tol=1e-5, restart=50, maxit=1000, precond=pc)
+                torch.cuda.synchronize()
+                arm["solve_" + pc] = dict(seconds=round(time.perf_counter() - t0, 3), iterations=info["iterations"],
+                                          converged=info["converged"], rel_residual=info["rel_residual"])
+        log(f"[bench] adaptive case {name}: {arm}")
+        arms[name] = arm
+        p.close()
+        torch.cuda.empty_cache()
+    cpu = None
+    if not args.no_cpu:
+        cpu, err, rows, yr = cpu_baseline(V, T, k, W.complex_normal(n, 1, seed=0), ys["adaptive_fp64"], 4096,
+                                          args.cpu_seconds / 2)
+        for name in arms:
+            arms[name]["matvec_rel_err_vs_oracle_sampled"] = float(np.linalg.norm(ys[name][rows] - yr) /
+                                                                   np.linalg.norm(yr))
+        log(f"[bench] adaptive case cpu baseline {cpu}")
+    a64 = arms["adaptive_fp64"]
+    return {
+        "metric": "FDA matvecs/s, adaptive tree on a graded sphere (N=79,106, kD=100)",
+        "value": a64["matvecs_per_s"],
+        "unit": "matvecs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": 2,
+        "ms_per_step": a64["ms_per_matvec"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"graded_sphere{n}_kD100", "N": n, "k": k, "kD": k, "eps": 1e-4,
+                   "refinement": "icosphere s=5, +1 level above z=0.3r, +2 above z=0.7r", "arm": "adaptive FP64"},
+        "uniform_tree_refusal": uniform_refusal,
+        "arms": arms,
+        "cpu_baseline": cpu,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -279,6 +376,8 @@ def main():
                     help="trained learned-preconditioner weights for the fast arm's solve")
     ap.add_argument("--large", action="store_true",
                     help="run only the large case (prolate spheroid, about 4 M triangles, kD = 1000) and print its line")
+    ap.add_argument("--adaptive", action="store_true",
+                    help="run only the adaptive-tree case (graded sphere, 79,106 triangles, kD = 100) and print its line")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "m2l_lowrank_sphere81920_kD100_traffic.json"),
                     help="measured HBM traffic of the M2L kernel (written from rocprofv3 counter passes)")
     args = ap.parse_args()
@@ -296,6 +395,9 @@ def main():
     torch.cuda.set_device(0)
     if args.large:
         print(json.dumps(large_case(args, log)), flush=True)
+        return
+    if args.adaptive:
+        print(json.dumps(adaptive_case(args, log)), flush=True)
         return
     V, T, prm = W.workload(args.workload)
     n, k = len(T), prm["k"]

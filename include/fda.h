@@ -148,6 +148,7 @@ typedef struct fda_stats {
                                    element pair is covered once: near_nnz + far_elem_pairs = n^2 */
     int64_t max_near_cols;      /* longest near-field row (source elements of one leaf); a build
                                    refuses rows above 4,096 */
+    int64_t wx_elem_pairs;      /* entries of near_nnz that come from W and X pairs */
 } fda_stats;
 
 /* Fill *opt with the defaults listed above. */

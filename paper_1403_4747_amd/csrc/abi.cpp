@@ -442,6 +442,24 @@ void upload_plan(fda_plan *p, const HostOps &ops, DevTranslations &tr) {
         throw BuildError{FDA_EINVAL, "near-field row longer than 4,096 elements, too long for one workgroup "
                                      "(lower max_leaf)"};
     d.max_ncol = max_ncol;
+    {
+        // near-field work items: rows of one leaf, about kP2PItemEntries
+        // block entries each; short rows first
+        std::vector<int32_t> items[2];
+        int cols_short = 0;
+        for (int b = 0; b < d.nleaf; ++b) {
+            const int nc = hp.nf_ncol[b], nt = (int)(hp.leaf_off[b + 1] - hp.leaf_off[b]);
+            const int rows = std::max(4, kP2PItemEntries / std::max(nc, 1));
+            const int g = nc <= kP2PShortCols ? 0 : 1;
+            if (g == 0) cols_short = std::max(cols_short, nc);
+            for (int r0 = 0; r0 < nt; r0 += rows) items[g].insert(items[g].end(), {b, r0, std::min(nt, r0 + rows), 0});
+        }
+        d.p2p_nshort = (int)(items[0].size() / 4);
+        d.p2p_nitems = d.p2p_nshort + (int)(items[1].size() / 4);
+        d.p2p_cols_short = cols_short;
+        items[0].insert(items[0].end(), items[1].begin(), items[1].end());
+        d.p2p_items = (int4 *)upload(p, items[0]);
+    }
     d.nf_col_off = upload(p, col_off);
     d.nf_cols = upload(p, cols);
     d.nf_self_col = upload(p, self_col);

@@ -278,11 +278,13 @@ __device__ __forceinline__ void cmac(C &acc, C a, C b) {
 // y_tree[i] = sum over the near leaves of the block entries times x
 // (+ the FP64 self term diag[i] x[i] when the blocks are FP32).
 template <class C>
-__global__ void k_p2p(const int64_t *leaf_off, const int32_t *nl_off, const int32_t *nl, const int64_t *blk_off,
-                      const C *vals, const double2 *diag, const double2 *x, double2 *y, int64_t N) {
+__global__ void k_p2p(const int4 *items, const int64_t *leaf_off, const int32_t *nl_off, const int32_t *nl,
+                      const int64_t *blk_off, const C *vals, const double2 *diag, const double2 *x, double2 *y,
+                      int64_t N) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C *xs = (C *)smem_raw;
-    const int b = blockIdx.x;
+    const int4 it = items[blockIdx.x];  // (leaf, first row, end row, -)
+    const int b = it.x;
     const double2 *xr = x + (int64_t)blockIdx.y * N;
     double2 *yr = y + (int64_t)blockIdx.y * N;
     int nc = 0;
@@ -295,10 +297,9 @@ __global__ void k_p2p(const int64_t *leaf_off, const int32_t *nl_off, const int3
     }
     __syncthreads();
     const int64_t t0 = leaf_off[b];
-    const int nt = (int)(leaf_off[b + 1] - t0);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const C *blk = vals + blk_off[b];
-    for (int i = wv; i < nt; i += nw) {
+    for (int i = it.y + wv; i < it.z; i += nw) {
         C acc = czero<C>();
         const C *row = blk + (int64_t)i * nc;
         for (int c = lane; c < nc; c += 64) cmac(acc, row[c], xs[c]);
@@ -1438,6 +1439,29 @@ static hipError_t m2l_merged_t(const M2LMerged &mm, int nrhs, hipStream_t st, hi
     return hipSuccess;
 }
 
+// The near field: work items of at most about 24k block entries (rows of
+// one leaf), those with rows of <= kP2PShortCols columns first; the two
+// groups are launched with the LDS their longest row needs, so that a few
+// long rows neither serialise at the tail nor limit the occupancy of all.
+template <class C>
+static hipError_t launch_p2p_t(const DevPlan &d, const NearFar &op, const double2 *xt, double2 *yt, int nrhs,
+                               hipStream_t st) {
+    const int ns = d.p2p_nshort, nl = d.p2p_nitems - d.p2p_nshort;
+    if (ns > 0) {
+        hipLaunchKernelGGL(k_p2p<C>, dim3(ns, nrhs), dim3(256), sizeof(C) * d.p2p_cols_short, st, d.p2p_items,
+                           d.leaf_off, d.nf_list_off, d.nf_list, d.nf_blk_off, (const C *)op.nf_vals,
+                           (const double2 *)op.nf_diag, xt, yt, d.n);
+        CHECK_LAUNCH();
+    }
+    if (nl > 0) {
+        hipLaunchKernelGGL(k_p2p<C>, dim3(nl, nrhs), dim3(256), sizeof(C) * d.max_ncol, st, d.p2p_items + ns,
+                           d.leaf_off, d.nf_list_off, d.nf_list, d.nf_blk_off, (const C *)op.nf_vals,
+                           (const double2 *)op.nf_diag, xt, yt, d.n);
+        CHECK_LAUNCH();
+    }
+    return hipSuccess;
+}
+
 #ifndef FDA_NEAR_FORK
 #define FDA_NEAR_FORK 1  // 0: the side-stream near field starts with the matvec; 1: with the M2L
 #endif
@@ -1463,19 +1487,14 @@ static hipError_t matvec_t(const DevPlan &d, const double2 *xt, double2 *yt, int
         hipError_t e = hipEventRecord(d.fork, st);
         if (e == hipSuccess) e = hipStreamWaitEvent(d.side, d.fork, 0);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_p2p<C>, dim3(d.nleaf, nrhs), dim3(256), sizeof(C) * d.max_ncol, d.side, d.leaf_off,
-                           d.nf_list_off, d.nf_list, d.nf_blk_off, (const C *)op.nf_vals, (const double2 *)op.nf_diag,
-                           xt, yt, N);
-        e = hipGetLastError();
+        e = launch_p2p_t<C>(d, op, xt, yt, nrhs, d.side);
         if (e == hipSuccess) e = hipEventRecord(d.join, d.side);
         return e;
     };
     if (ev) hipEventRecord(ev[0], st);
     if (!overlap) {
-        hipLaunchKernelGGL(k_p2p<C>, dim3(d.nleaf, nrhs), dim3(256), sizeof(C) * d.max_ncol, st, d.leaf_off,
-                           d.nf_list_off, d.nf_list, d.nf_blk_off, (const C *)op.nf_vals, (const double2 *)op.nf_diag,
-                           xt, yt, N);
-        CHECK_LAUNCH();
+        const hipError_t e = launch_p2p_t<C>(d, op, xt, yt, nrhs, st);
+        if (e != hipSuccess) return e;
     } else if (FDA_NEAR_FORK == 0) {
         const hipError_t e = near_side();
         if (e != hipSuccess) return e;

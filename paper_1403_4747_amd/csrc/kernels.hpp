@@ -36,7 +36,9 @@ struct M2LLevelArgs {
     int64_t tbase = 0;                      // first scratch element of the level
     int32_t kd = 0, ku = 0, rmax = 0, level = 0;
 };
-constexpr int kM2LVariants = 4;  // ring-depth variants of the low-rank M2L kernel
+constexpr int kM2LVariants = 4;
+constexpr int kP2PShortCols = 1024;     // near-field rows up to this length share one launch
+constexpr int kP2PItemEntries = 24576;  // near-field block entries per work item (at least 4 rows)  // ring-depth variants of the low-rank M2L kernel
 
 struct M2LMerged {
     int nwork = 0, nred = 0, nlev = 0;
@@ -92,6 +94,11 @@ struct DevPlan {
     int32_t *perm = nullptr;
     double *tri = nullptr, *cen = nullptr, *nrm = nullptr, *area = nullptr;
     int64_t *leaf_off = nullptr;
+    // near-field work items (leaf, first row, end row, -): p2p_nshort items
+    // whose rows have <= kP2PShortCols columns (LDS for p2p_cols_short), then
+    // the rest (LDS for max_ncol)
+    int4 *p2p_items = nullptr;
+    int p2p_nitems = 0, p2p_nshort = 0, p2p_cols_short = 0;
     int32_t *nf_list_off = nullptr, *nf_list = nullptr, *nf_ncol = nullptr, *nf_self_col = nullptr, *nf_cols = nullptr;
     int64_t *nf_blk_off = nullptr, *nf_col_off = nullptr;
     int prec = 0;                   // 0: FP64 storage, 1: FP32 storage

@@ -76,6 +76,7 @@ struct HostPlan {
     // lists), and element pairs covered by interaction lists (all levels)
     int64_t u_pairs = 0, w_pairs = 0, x_pairs = 0;
     int64_t far_elem_pairs = 0;
+    int64_t wx_elem_pairs = 0;  // near-field entries that come from W and X pairs
     // near field: per target leaf, the source leaves evaluated directly
     std::vector<int64_t> nf_list_off;    // nleaf + 1
     std::vector<int32_t> nf_list;        // near source leaves

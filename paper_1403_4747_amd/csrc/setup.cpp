@@ -521,9 +521,10 @@ void host_setup(const double *V, int64_t nv, const int32_t *T, int64_t nt, doubl
     // leaves of any level), its W list (boxes below a same-level neighbour
     // that do not touch it but whose parents do: every leaf below them) and
     // the X entries of its ancestors and itself
+    int64_t wbox = 0, wbox_elems = 0, xbox_elems = 0;  // W entries and the elements below them
     {
         std::vector<std::vector<int32_t>> nsrc(hp.nleaf);
-        hp.u_pairs = hp.w_pairs = hp.x_pairs = 0;
+        hp.u_pairs = hp.w_pairs = hp.x_pairs = hp.wx_elem_pairs = 0;
         for (int64_t t = 0; t < hp.nleaf; ++t) {
             const int l = hp.leaf_level[t];
             const int32_t b = hp.leaf_box[t];
@@ -548,6 +549,10 @@ void host_setup(const double *V, int64_t nv, const int32_t *T, int64_t nt, doubl
                             const auto r = subtree_leaves(m + 1, y);
                             for (int64_t s = r.first; s < r.second; ++s) out.push_back((int32_t)s);
                             hp.w_pairs += r.second - r.first;
+                            hp.wx_elem_pairs += (hp.leaf_off[t + 1] - hp.leaf_off[t]) *
+                                                (hp.leaf_off[r.second] - hp.leaf_off[r.first]);
+                            ++wbox;
+                            wbox_elems += hp.leaf_off[r.second] - hp.leaf_off[r.first];
                         } else if (hp.lv[m + 1].leaf[y] >= 0) {
                             out.push_back(hp.lv[m + 1].leaf[y]);
                             ++hp.u_pairs;
@@ -562,6 +567,9 @@ void host_setup(const double *V, int64_t nv, const int32_t *T, int64_t nt, doubl
             const auto r = subtree_leaves(x.l, x.b);
             for (int64_t t = r.first; t < r.second; ++t) nsrc[t].push_back(x.src);
             hp.x_pairs += r.second - r.first;
+            hp.wx_elem_pairs += (hp.leaf_off[r.second] - hp.leaf_off[r.first]) *
+                                (hp.leaf_off[x.src + 1] - hp.leaf_off[x.src]);
+            xbox_elems += hp.leaf_off[r.second] - hp.leaf_off[r.first];
         }
         hp.nf_list_off.assign(hp.nleaf + 1, 0);
         hp.nf_blk_off.assign(hp.nleaf + 1, 0);
@@ -740,8 +748,12 @@ void host_setup(const double *V, int64_t nv, const int32_t *T, int64_t nt, doubl
         fprintf(stderr, "[fda] depth=%d top=%d leaves=%lld max_leaf=%d near_nnz=%lld h_max=%.4g\n", hp.depth, hp.top,
                 (long long)hp.nleaf, hp.max_leaf_count, (long long)hp.near_nnz, hp.h_max);
         if (adaptive)
-            fprintf(stderr, "[fda] adaptive: U pairs=%lld W pairs=%lld X pairs=%lld\n", (long long)hp.u_pairs,
-                    (long long)hp.w_pairs, (long long)hp.x_pairs);
+            fprintf(stderr,
+                    "[fda] adaptive: U leaf pairs=%lld, W boxes=%lld (%.1f elements each, %lld leaf pairs), "
+                    "X entries=%zu (%.1f elements below each box, %lld leaf pairs)\n",
+                    (long long)hp.u_pairs, (long long)wbox, wbox ? (double)wbox_elems / wbox : 0.0,
+                    (long long)hp.w_pairs, xlist.size(), xlist.empty() ? 0.0 : (double)xbox_elems / xlist.size(),
+                    (long long)hp.x_pairs);
     }
 }
 
@@ -755,6 +767,7 @@ void fill_stats(const HostPlan &hp, fda_stats *st) {
     st->w_pairs = hp.w_pairs;
     st->x_pairs = hp.x_pairs;
     st->far_elem_pairs = hp.far_elem_pairs;
+    st->wx_elem_pairs = hp.wx_elem_pairs;
     for (int32_t c : hp.nf_ncol) st->max_near_cols = std::max<int64_t>(st->max_near_cols, c);
     st->max_leaf_count = hp.max_leaf_count;
     st->near_nnz = hp.near_nnz;
