@@ -319,6 +319,45 @@ __global__ void k_p2p(const int4 *items, const int64_t *leaf_off, const int32_t 
     }
 }
 
+// The same product for long rows (more than kP2PShortCols columns): x is
+// read through the row's column list (cols, from col_off[leaf]) instead of
+// being staged in LDS, so these workgroups need no LDS and keep full
+// occupancy (x is small enough to stay in L2).  Same summation order as
+// k_p2p, so the same result bit for bit.
+template <class C>
+__global__ void k_p2p_direct(const int4 *items, const int64_t *leaf_off, const int64_t *col_off,
+                             const int32_t *cols, const int64_t *blk_off, const C *vals, const double2 *diag,
+                             const double2 *x, double2 *y, int64_t N) {
+    const int4 it = items[blockIdx.x];  // (leaf, first row, end row, -)
+    const int b = it.x;
+    const double2 *xr = x + (int64_t)blockIdx.y * N;
+    double2 *yr = y + (int64_t)blockIdx.y * N;
+    const int64_t c0 = col_off[b];
+    const int nc = (int)(col_off[b + 1] - c0);
+    const int32_t *cl = cols + c0;
+    const int64_t t0 = leaf_off[b];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const C *blk = vals + blk_off[b];
+    for (int i = it.y + wv; i < it.z; i += nw) {
+        C acc = czero<C>();
+        const C *row = blk + (int64_t)i * nc;
+        for (int c = lane; c < nc; c += 64) cmac(acc, row[c], cfrom<C>(xr[cl[c]]));
+        for (int o = 32; o > 0; o >>= 1) {
+            acc.x += __shfl_down(acc.x, o, 64);
+            acc.y += __shfl_down(acc.y, o, 64);
+        }
+        if (lane == 0) {
+            double2 out = make_double2((double)acc.x, (double)acc.y);
+            if (diag) {
+                const double2 d = diag[t0 + i], v = xr[t0 + i];
+                out.x += d.x * v.x - d.y * v.y;
+                out.y += d.x * v.y + d.y * v.x;
+            }
+            yr[t0 + i] = out;
+        }
+    }
+}
+
 // s_leaf = S~ x_leaf, for the leaves of one level (ids: global leaf ids,
 // box: their boxes on the level, sop: offset of each leaf's S~)
 template <class C>
@@ -1440,9 +1479,10 @@ static hipError_t m2l_merged_t(const M2LMerged &mm, int nrhs, hipStream_t st, hi
 }
 
 // The near field: work items of at most about 24k block entries (rows of
-// one leaf), those with rows of <= kP2PShortCols columns first; the two
-// groups are launched with the LDS their longest row needs, so that a few
-// long rows neither serialise at the tail nor limit the occupancy of all.
+// one leaf), those with rows of <= kP2PShortCols columns first (x staged in
+// LDS sized for their longest row), then the long rows (x read through the
+// column list, no LDS), so that a few long rows neither serialise at the
+// tail nor limit the occupancy of all.
 template <class C>
 static hipError_t launch_p2p_t(const DevPlan &d, const NearFar &op, const double2 *xt, double2 *yt, int nrhs,
                                hipStream_t st) {
@@ -1454,9 +1494,9 @@ static hipError_t launch_p2p_t(const DevPlan &d, const NearFar &op, const double
         CHECK_LAUNCH();
     }
     if (nl > 0) {
-        hipLaunchKernelGGL(k_p2p<C>, dim3(nl, nrhs), dim3(256), sizeof(C) * d.max_ncol, st, d.p2p_items + ns,
-                           d.leaf_off, d.nf_list_off, d.nf_list, d.nf_blk_off, (const C *)op.nf_vals,
-                           (const double2 *)op.nf_diag, xt, yt, d.n);
+        hipLaunchKernelGGL(k_p2p_direct<C>, dim3(nl, nrhs), dim3(256), 0, st, d.p2p_items + ns, d.leaf_off,
+                           d.nf_col_off, d.nf_cols, d.nf_blk_off, (const C *)op.nf_vals, (const double2 *)op.nf_diag,
+                           xt, yt, d.n);
         CHECK_LAUNCH();
     }
     return hipSuccess;
