@@ -143,3 +143,56 @@ def test_graded_sphere_neumann_rhs_matches_oracle():
     with _plan(V, T, k, neumann_rhs=1) as p:
         bg = p.rhs_neumann(_dev(g)).cpu().numpy()
     assert _rel(bg, O.neumann_rhs(V, T, k, g)) < 1e-4
+
+
+def test_adaptive_plans_in_a_batch_graph_and_a_torch_graph():
+    """Adaptive plans (several S2M / L2T launches, two near-field launches)
+    inside one captured HIP graph with a uniform plan (fda_batch), and a
+    matvec captured into a torch CUDA graph: every replay equals the eager
+    product, with eager work between the replays."""
+    from paper_1403_4747_amd import Batch, Plan
+
+    _say("[adaptive] batch graph: graded sphere FP64 + FP32 adaptive, uniform sphere")
+    Vg, Tg = W.graded_sphere(3)
+    Vu, Tu, pu = W.workload("sphere1280_kD10")
+    plans = [_plan(Vg, Tg, 10.0), _plan(Vg, Tg, 10.0, prec="fp32"), Plan(Vu, Tu, pu["k"], pu["eps"])]
+    xs, ys, want = [], [], []
+    for i, p in enumerate(plans):
+        x = torch.from_numpy(np.ascontiguousarray(W.complex_normal(p.n, 2, seed=70 + i).T)).to("cuda")
+        xs.append(x)
+        ys.append(torch.zeros_like(x))
+        want.append(p.matvec(x).cpu().numpy())
+    b = Batch(plans, xs, ys)
+    for rep in range(3):
+        for y in ys:
+            y.zero_()
+        b.launch()
+        torch.cuda.synchronize()
+        for i in range(len(plans)):
+            assert np.array_equal(ys[i].cpu().numpy(), want[i]), (rep, i)
+        z = plans[0].matvec(torch.ones_like(xs[0]))
+        torch.cuda.synchronize()
+        assert torch.isfinite(z.real).all()
+    b.close()
+    _say("[adaptive] torch CUDA graph of one adaptive matvec, 3 replays")
+    p = plans[0]
+    x = xs[0][0].contiguous()
+    y = torch.zeros_like(x)
+    w = p.matvec(x).cpu().numpy()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s, capture_error_mode="thread_local"):
+            p.matvec(x, out=y)
+    torch.cuda.current_stream().wait_stream(s)
+    for rep in range(3):
+        y.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(y.cpu().numpy(), w), rep
+        p.matvec(torch.ones_like(x))
+        torch.cuda.synchronize()
+    for q in plans:
+        q.close()
