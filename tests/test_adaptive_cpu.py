@@ -82,3 +82,102 @@ def test_adaptive_option_is_validated():
     with pytest.raises(FDAError) as e:
         _inspect(V, T, prm["k"], adaptive=2)
     assert e.value.code == -1
+
+
+# ---------------------------------------------------------------------------
+# An independent model of the adaptive tree and of which leaf pairs are
+# evaluated directly, written from the definitions (Section 3.2 and the
+# separation rules of Section 3), against the library's host phase.
+
+def _model_tree(V, T, k, max_leaf=64, leaf_min_h=2.5, hf_wavelengths=1.9, adaptive=True):
+    """Leaves of the adaptive (or uniform) tree as (level, integer key,
+    element count).  Uniform: every leaf on the first level whose boxes all
+    hold <= max_leaf elements or whose children would be narrower than
+    leaf_min_h largest edges of the whole mesh."""
+    a, b, c = V[T[:, 0]], V[T[:, 1]], V[T[:, 2]]
+    cen = (a + b + c) / 3.0
+    emax = np.maximum(np.linalg.norm(b - a, axis=1),
+                      np.maximum(np.linalg.norm(c - a, axis=1), np.linalg.norm(c - b, axis=1)))
+    lo, hi = V.min(axis=0), V.max(axis=0)
+    side = (hi - lo).max() * (1.0 + 1e-9)
+    origin = 0.5 * (lo + hi) - 0.5 * side
+    lam = 2.0 * math.pi / k
+    active = np.ones(len(T), dtype=bool)
+    leaves = []
+    Lu = None
+    if not adaptive:
+        Lu = 0
+        while Lu < 20 and side / 2.0**Lu * 0.5 >= leaf_min_h * emax.max():
+            key = np.clip(np.floor((cen - origin) / (side / 2.0**Lu)).astype(np.int64), 0, 2**Lu - 1)
+            if np.unique(key, axis=0, return_counts=True)[1].max() <= max_leaf:
+                break
+            Lu += 1
+    for l in range(21):
+        w = side / 2.0**l
+        hf = l > 0 and w >= hf_wavelengths * lam * (1.0 - 1e-9)
+        idx = np.nonzero(active)[0]
+        if len(idx) == 0:
+            break
+        key = np.clip(np.floor((cen[idx] - origin) / w).astype(np.int64), 0, 2**l - 1)
+        ukey, inv = np.unique(key, axis=0, return_inverse=True)
+        inv = inv.reshape(-1)
+        cnt = np.bincount(inv, minlength=len(ukey))
+        hbox = np.zeros(len(ukey))
+        np.maximum.at(hbox, inv, emax[idx])
+        cannot = (w * 0.5 < leaf_min_h * hbox) | (l >= 20)
+        if adaptive:
+            leaf = ((cnt <= max_leaf) | cannot) & (not hf)
+            assert not np.any(hf & cannot)
+        else:
+            leaf = np.full(len(ukey), l == Lu)
+        for j in np.nonzero(leaf)[0]:
+            leaves.append((l, ukey[j], int(cnt[j])))
+        active[idx[leaf[inv]]] = False
+    return leaves, side, lam
+
+
+def _model_near_entries(leaves, side, lam, hf_wavelengths=1.9, rho_c=1.0):
+    """Near-field entries: sum of n_t n_s over leaf pairs (t, s) none of whose
+    same-level ancestor pairs is well separated (not touching, and on a
+    directional level at least rho apart)."""
+    lev = np.array([t[0] for t in leaves])
+    key = np.array([t[1] for t in leaves])
+    n = np.array([t[2] for t in leaves], dtype=np.int64)
+    T_, S_ = np.meshgrid(np.arange(len(leaves)), np.arange(len(leaves)), indexing="ij")
+    T_, S_ = T_.ravel(), S_.ravel()
+    m = np.minimum(lev[T_], lev[S_])
+    separated = np.zeros(len(T_), dtype=bool)
+    for l in range(int(lev.max()) + 1):
+        sel = m >= l
+        kt = key[T_[sel]] >> (lev[T_[sel]] - l)[:, None]
+        ks = key[S_[sel]] >> (lev[S_[sel]] - l)[:, None]
+        d = kt - ks
+        sep = np.abs(d).max(axis=1) >= 2
+        w = side / 2.0**l
+        if l > 0 and w >= hf_wavelengths * lam * (1.0 - 1e-9):
+            rho = max(2.0 * w, rho_c * w * w / lam)
+            sep &= np.sqrt((d.astype(np.float64) ** 2).sum(axis=1)) * w >= rho * (1.0 - 1e-12)
+        separated[np.nonzero(sel)[0][sep]] = True
+    direct = ~separated
+    return int((n[T_[direct]] * n[S_[direct]]).sum())
+
+
+@pytest.mark.parametrize("case,adaptive", [("graded3_kD10", 1), ("graded4_kD60", 1), ("sphere20480_kD50", 1),
+                                           ("sphere20480_kD50", 0), ("sphere20480_kD100", 0)])
+def test_tree_and_direct_pairs_match_an_independent_model(case, adaptive):
+    if case.startswith("graded"):
+        s, k = (3, 10.0) if case == "graded3_kD10" else (4, 60.0)
+        V, T = W.graded_sphere(s)
+    else:
+        V, T, prm = W.workload(case)
+        k = prm["k"]
+    st = _inspect(V, T, k, adaptive=adaptive)
+    leaves, side, lam = _model_tree(V, T, k, adaptive=bool(adaptive))
+    per_level = [0] * (st["depth"] + 1)
+    for l, _, _ in leaves:
+        per_level[l] += 1
+    assert per_level == list(st["leaves"]), (per_level, st["leaves"])
+    assert max(c for _, _, c in leaves) == st["max_leaf_count"]
+    assert _model_near_entries(leaves, side, lam) == st["near_nnz"]
+    if case != "graded3_kD10":
+        assert any(st["hf"])  # directional levels above the leaves
