@@ -37,7 +37,10 @@ struct M2LLevelArgs {
     int32_t kd = 0, ku = 0, rmax = 0, level = 0;
 };
 constexpr int kM2LVariants = 4;
-constexpr int kP2PShortCols = 1024;     // near-field rows up to this length share one launch
+#ifndef FDA_P2P_SHORT_COLS
+#define FDA_P2P_SHORT_COLS 1024
+#endif
+constexpr int kP2PShortCols = FDA_P2P_SHORT_COLS;  // near-field rows up to this length: x staged in LDS
 constexpr int kP2PItemEntries = 24576;  // near-field block entries per work item (at least 4 rows)  // ring-depth variants of the low-rank M2L kernel
 
 struct M2LMerged {
