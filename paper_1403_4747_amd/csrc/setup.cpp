@@ -229,68 +229,68 @@ void host_setup(const double *V, int64_t nv, const int32_t *T, int64_t nt, doubl
     auto width = [&](int l) { return side / std::ldexp(1.0, l); };
     auto hf_width = [&](int l) { return l > 0 && width(l) >= opt.hf_wavelengths * lambda * (1.0 - 1e-9); };
     const bool adaptive = opt.adaptive != 0;
-    int Lu = -1;
-    if (!adaptive) {
-        Lu = 0;
-        for (;;) {
-            if (Lu >= 20) break;
-            if (width(Lu) * 0.5 < tau) break;
-            std::unordered_map<uint64_t, int> cnt;
-            int mx = 0;
-            for (int64_t e = 0; e < nt; ++e) {
-                int32_t kk[3];
-                keys_at(Lu, e, kk);
-                mx = std::max(mx, ++cnt[morton(kk[0], kk[1], kk[2])]);
-            }
-            if (mx <= opt.max_leaf) break;
-            ++Lu;
-        }
-    }
-    // boxes per level (Morton ordered): those holding an element that is not
-    // yet in a leaf
+    // boxes per level, Morton ordered: the occupied octants of the boxes of
+    // the level above that are subdivided, parent by parent (a child's
+    // Morton code is its parent's followed by the octant bits)
     std::vector<int32_t> elev(nt, -1);  // leaf level of each element
+    std::vector<int32_t> ebox(nt, 0);   // its box on the current level
+    std::vector<uint8_t> eoct(nt, 0);
     hp.lv.clear();
     for (int l = 0;; ++l) {
         hp.lv.emplace_back();
         Level &lv = hp.lv[l];
         lv.w = width(l);
         lv.r = 0.5 * lv.w;
-        std::vector<uint64_t> codes(nt, ~0ULL), u;
-        for (int64_t e = 0; e < nt; ++e) {
-            if (elev[e] >= 0) continue;
-            int32_t kk[3];
-            keys_at(l, e, kk);
-            codes[e] = morton(kk[0], kk[1], kk[2]);
-            u.push_back(codes[e]);
-        }
-        std::sort(u.begin(), u.end());
-        u.erase(std::unique(u.begin(), u.end()), u.end());
-        lv.nbox = (int64_t)u.size();
-        lv.key.resize(3 * lv.nbox);
-        for (int64_t b = 0; b < lv.nbox; ++b) {
-            int32_t kk[3] = {0, 0, 0};
-            for (int bit = 0; bit < 21; ++bit) {
-                kk[0] |= (int32_t)((u[b] >> (3 * bit + 2)) & 1) << bit;
-                kk[1] |= (int32_t)((u[b] >> (3 * bit + 1)) & 1) << bit;
-                kk[2] |= (int32_t)((u[b] >> (3 * bit)) & 1) << bit;
+        if (l == 0) {
+            lv.nbox = 1;
+            lv.key.assign(3, 0);
+        } else {
+            Level &pv = hp.lv[l - 1];
+            std::vector<int32_t> slot(8 * (size_t)pv.nbox, -1);
+            for (int64_t e = 0; e < nt; ++e) {
+                if (elev[e] >= 0) continue;
+                int32_t kk[3];
+                keys_at(l, e, kk);
+                for (int q = 0; q < 3; ++q)
+                    if ((kk[q] >> 1) != pv.key[3 * (size_t)ebox[e] + q])
+                        throw BuildError{FDA_EINVAL, "internal: element box is not inside its parent box"};
+                eoct[e] = (uint8_t)(((kk[0] & 1) << 2) | ((kk[1] & 1) << 1) | (kk[2] & 1));
+                slot[8 * (size_t)ebox[e] + eoct[e]] = 0;
             }
-            for (int q = 0; q < 3; ++q) lv.key[3 * b + q] = kk[q];
+            lv.nbox = 0;
+            pv.child_begin.assign(pv.nbox + 1, 0);
+            for (int64_t pb = 0; pb < pv.nbox; ++pb) {
+                for (int o = 0; o < 8; ++o) {
+                    int32_t &s = slot[8 * (size_t)pb + o];
+                    if (s < 0) continue;
+                    s = (int32_t)lv.nbox++;
+                    lv.parent.push_back((int32_t)pb);
+                    lv.octant.push_back(o);
+                    lv.key.push_back(2 * pv.key[3 * pb] + ((o >> 2) & 1));
+                    lv.key.push_back(2 * pv.key[3 * pb + 1] + ((o >> 1) & 1));
+                    lv.key.push_back(2 * pv.key[3 * pb + 2] + (o & 1));
+                }
+                pv.child_begin[pb + 1] = (int32_t)lv.nbox;
+            }
+            for (int64_t e = 0; e < nt; ++e)
+                if (elev[e] < 0) ebox[e] = slot[8 * (size_t)ebox[e] + eoct[e]];
         }
-        std::vector<int32_t> ebox(nt, -1);
         std::vector<double> hbox(lv.nbox, 0.0);
         lv.nelem.assign(lv.nbox, 0);
+        int64_t most = 0;
         for (int64_t e = 0; e < nt; ++e) {
-            if (codes[e] == ~0ULL) continue;
-            ebox[e] = (int32_t)(std::lower_bound(u.begin(), u.end(), codes[e]) - u.begin());
-            lv.nelem[ebox[e]]++;
+            if (elev[e] >= 0) continue;
+            most = std::max(most, ++lv.nelem[ebox[e]]);
             hbox[ebox[e]] = std::max(hbox[ebox[e]], emax[e]);
         }
+        // uniform: this is the leaf level when every box qualifies
+        const bool uniform_leaves = l >= 20 || lv.w * 0.5 < tau || most <= opt.max_leaf;
         lv.leaf.assign(lv.nbox, -1);
         bool split = false;
         for (int64_t b = 0; b < lv.nbox; ++b) {
             bool leaf;
             if (!adaptive) {
-                leaf = l == Lu;
+                leaf = uniform_leaves;
             } else {
                 // children would be too narrow
                 const bool cannot = lv.w * 0.5 < opt.leaf_min_h * hbox[b] || l >= 20;
@@ -306,27 +306,11 @@ void host_setup(const double *V, int64_t nv, const int32_t *T, int64_t nt, doubl
             else split = true;
         }
         for (int64_t e = 0; e < nt; ++e)
-            if (ebox[e] >= 0 && lv.leaf[ebox[e]] >= 0) elev[e] = l;
+            if (elev[e] < 0 && lv.leaf[ebox[e]] >= 0) elev[e] = l;
         if (!split) break;
     }
     const int L = (int)hp.lv.size() - 1;
     hp.depth = L;
-    // parents / children (Morton order keeps the children of a box contiguous)
-    for (int l = 1; l <= L; ++l) {
-        Level &lv = hp.lv[l], &pv = hp.lv[l - 1];
-        std::unordered_map<uint64_t, int32_t> pidx;
-        for (int64_t b = 0; b < pv.nbox; ++b) pidx[morton(pv.key[3 * b], pv.key[3 * b + 1], pv.key[3 * b + 2])] = (int32_t)b;
-        lv.parent.resize(lv.nbox);
-        lv.octant.resize(lv.nbox);
-        pv.child_begin.assign(pv.nbox + 1, 0);
-        for (int64_t b = 0; b < lv.nbox; ++b) {
-            const int32_t *kk = &lv.key[3 * b];
-            lv.parent[b] = pidx.at(morton(kk[0] >> 1, kk[1] >> 1, kk[2] >> 1));
-            lv.octant[b] = ((kk[0] & 1) << 2) | ((kk[1] & 1) << 1) | (kk[2] & 1);
-            pv.child_begin[lv.parent[b] + 1]++;
-        }
-        for (int64_t b = 0; b < pv.nbox; ++b) pv.child_begin[b + 1] += pv.child_begin[b];
-    }
     hp.lv[L].child_begin.assign(hp.lv[L].nbox + 1, 0);
 
     // leaves in depth-first Morton order: a box's code shifted to the finest
