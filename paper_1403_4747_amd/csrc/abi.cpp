@@ -104,7 +104,7 @@ void *to_storage(fda_plan *p, double2 *a64, size_t n) {
     hip_check(hipDeviceSynchronize(), "to f32");
     auto it = std::find(p->allocs.begin(), p->allocs.end(), (void *)a64);
     if (it != p->allocs.end()) {
-        hipFree(a64);
+        (void)hipFree(a64);
         p->allocs.erase(it);
         p->device_bytes -= (int64_t)(sizeof(double2) * n);
     }
@@ -162,7 +162,7 @@ GWork upload_gwork(fda_plan *p, const GWorkHost &g) {
 }
 
 void free_work(fda_plan *p) {
-    for (void *q : p->work) hipFree(q);
+    for (void *q : p->work) (void)hipFree(q);
     p->work.clear();
     p->cap_nrhs = 0;
     p->xt = p->yt = nullptr;
@@ -287,7 +287,7 @@ void build_m2l_merged(fda_plan *p) {
     try {
         build_m2l_list(p, nm, fresh);
     } catch (...) {
-        for (void *q : fresh) hipFree(q);
+        for (void *q : fresh) (void)hipFree(q);
         p->device_bytes = bytes0;
         throw;
     }

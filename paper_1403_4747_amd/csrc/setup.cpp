@@ -15,14 +15,10 @@ namespace fda {
 
 static const double kPi = 3.14159265358979323846;
 
-// Radial scale factors of the cube-surface point sets relative to the box
-// half width (non-directional levels): outgoing equivalent / incoming check
-// cube just encloses the box; outgoing check / incoming equivalent cube sits
-// just inside the nearest well-separated box (which starts at 3 half widths).
-static const double kRin = 1.05, kRout = 2.95;
-// A point set whose numerical rank exceeds this fraction of its size is
-// treated as under-resolved and p is raised.
-static const double kSat = 0.7;
+// Radial scale factor of the outgoing equivalent / incoming check cube
+// relative to the box half width: the cube just encloses the box (the far
+// point sets of directional levels start beyond it).
+static const double kRin = 1.05;
 static const int kShells = 6, kRings = 8;
 
 cplx green(const double *x, const double *y, double k) {
@@ -67,68 +63,6 @@ static void dir_vector(int id, int n, double *out) {
     d[(a + 2) % 3] = -1.0 + (2.0 * j + 1.0) / n;
     double l = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
     for (int q = 0; q < 3; ++q) out[q] = d[q] / l;
-}
-
-// Rotation taking +z to u (minimal rotation; 180 degrees about x for -z).
-static void rotation_to(const double *u, double R[9]) {
-    double c = u[2];
-    double v[3] = {-u[1], u[0], 0.0};  // z x u
-    double vn = std::sqrt(v[0] * v[0] + v[1] * v[1]);
-    if (vn < 1e-14) {
-        double s = c > 0 ? 1.0 : -1.0;
-        double I[9] = {1, 0, 0, 0, s, 0, 0, 0, s};
-        std::copy(I, I + 9, R);
-        return;
-    }
-    double V[9] = {0, -v[2], v[1], v[2], 0, -v[0], -v[1], v[0], 0};
-    double V2[9];
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) {
-            double s = 0;
-            for (int q = 0; q < 3; ++q) s += V[3 * i + q] * V[3 * q + j];
-            V2[3 * i + j] = s;
-        }
-    for (int i = 0; i < 9; ++i) R[i] = (i % 4 == 0 ? 1.0 : 0.0) + V[i] + V2[i] / (1.0 + c);
-}
-
-static std::vector<double> cube_points(int p) {
-    std::vector<double> out;
-    for (int i = 0; i < p; ++i)
-        for (int j = 0; j < p; ++j)
-            for (int k = 0; k < p; ++k) {
-                if (i == 0 || j == 0 || k == 0 || i == p - 1 || j == p - 1 || k == p - 1) {
-                    out.push_back(-1.0 + 2.0 * i / (p - 1));
-                    out.push_back(-1.0 + 2.0 * j / (p - 1));
-                    out.push_back(-1.0 + 2.0 * k / (p - 1));
-                }
-            }
-    return out;
-}
-
-// G between point sets: M[i, j] = G(X_i + tx, Y_j).
-static Mat green_matrix(const std::vector<double> &X, const double *tx, const std::vector<double> &Y, double k) {
-    int m = (int)X.size() / 3, n = (int)Y.size() / 3;
-    Mat M(m, n);
-    for (int j = 0; j < n; ++j)
-        for (int i = 0; i < m; ++i) {
-            double x[3] = {X[3 * i] + tx[0], X[3 * i + 1] + tx[1], X[3 * i + 2] + tx[2]};
-            M(i, j) = green(x, &Y[3 * j], k);
-        }
-    return M;
-}
-
-static std::vector<double> scaled(const std::vector<double> &P, double s) {
-    std::vector<double> o(P);
-    for (auto &v : o) v *= s;
-    return o;
-}
-
-static std::vector<double> rotated(const std::vector<double> &P, const double R[9], double sign = 1.0) {
-    std::vector<double> o(P.size());
-    for (size_t i = 0; i < P.size() / 3; ++i)
-        for (int a = 0; a < 3; ++a)
-            o[3 * i + a] = sign * (R[3 * a] * P[3 * i] + R[3 * a + 1] * P[3 * i + 1] + R[3 * a + 2] * P[3 * i + 2]);
-    return o;
 }
 
 // Well-separation test at a level for an integer offset (target - source):
