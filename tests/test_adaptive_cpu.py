@@ -104,6 +104,7 @@ def _model_tree(V, T, k, max_leaf=64, leaf_min_h=2.5, hf_wavelengths=1.9, adapti
     lam = 2.0 * math.pi / k
     active = np.ones(len(T), dtype=bool)
     leaves = []
+    boxes = _model_tree.boxes = []  # integer keys of every box, per level
     Lu = None
     if not adaptive:
         Lu = 0
@@ -132,8 +133,35 @@ def _model_tree(V, T, k, max_leaf=64, leaf_min_h=2.5, hf_wavelengths=1.9, adapti
             leaf = np.full(len(ukey), l == Lu)
         for j in np.nonzero(leaf)[0]:
             leaves.append((l, ukey[j], int(cnt[j])))
+        boxes.append(ukey)
         active[idx[leaf[inv]]] = False
     return leaves, side, lam
+
+
+def _separated(d, l, side, lam, hf_wavelengths=1.9, rho_c=1.0):
+    """Well separated on level l for integer offsets d (rows): not touching,
+    and on a directional level at least rho apart (Section 3)."""
+    sep = np.abs(d).max(axis=1) >= 2
+    w = side / 2.0**l
+    if l > 0 and w >= hf_wavelengths * lam * (1.0 - 1e-9):
+        rho = max(2.0 * w, rho_c * w * w / lam)
+        sep &= np.sqrt((d.astype(np.float64) ** 2).sum(axis=1)) * w >= rho * (1.0 - 1e-12)
+    return sep
+
+
+def _model_v_pairs(boxes, side, lam):
+    """Interaction-list pairs per level: ordered pairs of boxes of the same
+    level that are well separated there and on no coarser level (their
+    ancestors were all near each other)."""
+    out = []
+    for l, keys in enumerate(boxes):
+        i, j = np.meshgrid(np.arange(len(keys)), np.arange(len(keys)), indexing="ij")
+        i, j = i.ravel(), j.ravel()
+        far = _separated(keys[i] - keys[j], l, side, lam)
+        for m in range(l):
+            far &= ~_separated((keys[i] >> (l - m)) - (keys[j] >> (l - m)), m, side, lam)
+        out.append(int(far.sum()))
+    return out
 
 
 def _model_near_entries(leaves, side, lam, hf_wavelengths=1.9, rho_c=1.0):
@@ -179,5 +207,6 @@ def test_tree_and_direct_pairs_match_an_independent_model(case, adaptive):
     assert per_level == list(st["leaves"]), (per_level, st["leaves"])
     assert max(c for _, _, c in leaves) == st["max_leaf_count"]
     assert _model_near_entries(leaves, side, lam) == st["near_nnz"]
+    assert _model_v_pairs(_model_tree.boxes, side, lam) == list(st["m2l_pairs"])
     if case != "graded3_kD10":
         assert any(st["hf"])  # directional levels above the leaves
