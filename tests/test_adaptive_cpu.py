@@ -187,6 +187,14 @@ def _model_near_entries(leaves, side, lam, hf_wavelengths=1.9, rho_c=1.0):
             sep &= np.sqrt((d.astype(np.float64) ** 2).sum(axis=1)) * w >= rho * (1.0 - 1e-12)
         separated[np.nonzero(sel)[0][sep]] = True
     direct = ~separated
+    # classify the direct pairs: U (the two leaves touch), W (they do not
+    # and the source is finer), X (they do not and the source is coarser)
+    lt, ls = lev[T_[direct]], lev[S_[direct]]
+    coarse_k = np.where((lt <= ls)[:, None], key[T_[direct]], key[S_[direct]])
+    fine_k = np.where((lt <= ls)[:, None], key[S_[direct]], key[T_[direct]])
+    sh = np.abs(lt - ls)[:, None]  # closed boxes meet: compare on the finer level
+    touch = np.all((fine_k + 1 >= coarse_k << sh) & (fine_k <= (coarse_k + 1) << sh), axis=1)
+    _model_near_entries.uwx = (int(touch.sum()), int((~touch & (ls > lt)).sum()), int((~touch & (ls < lt)).sum()))
     return int((n[T_[direct]] * n[S_[direct]]).sum())
 
 
@@ -207,6 +215,7 @@ def test_tree_and_direct_pairs_match_an_independent_model(case, adaptive):
     assert per_level == list(st["leaves"]), (per_level, st["leaves"])
     assert max(c for _, _, c in leaves) == st["max_leaf_count"]
     assert _model_near_entries(leaves, side, lam) == st["near_nnz"]
+    assert _model_near_entries.uwx == (st["u_pairs"], st["w_pairs"], st["x_pairs"])
     assert _model_v_pairs(_model_tree.boxes, side, lam) == list(st["m2l_pairs"])
     if case != "graded3_kD10":
         assert any(st["hf"])  # directional levels above the leaves
