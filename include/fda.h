@@ -303,8 +303,10 @@ int fda_mlp_samples(fda_plan *plan, const void *r_dev, const void *e_dev, int64_
 /* The plan's element order: perm (host, N entries) receives, for each tree
  * position, the caller's element index; leaf_off (host, nleaf + 1 entries)
  * the tree-position range of each leaf (leaf L holds positions
- * leaf_off[L] .. leaf_off[L+1]-1).  Either pointer may be NULL.  Errors:
- * FDA_EINVAL (length mismatch). */
+ * leaf_off[L] .. leaf_off[L+1]-1).  Leaves are in depth-first Morton order
+ * (on adaptive trees they sit on several levels, and the leaves below any
+ * box are consecutive).  Either pointer may be NULL.  Errors: FDA_EINVAL
+ * (length mismatch). */
 int fda_plan_leaves(const fda_plan *plan, int32_t *perm, int64_t n, int64_t *leaf_off, int64_t nleaf);
 
 /* Attach a network to a plan for FDA_PRECOND_MLP (NULL detaches).  The plan
