@@ -146,8 +146,7 @@ typedef struct fda_stats {
                                    (X lists; zero on uniform trees) */
     int64_t far_elem_pairs;     /* element pairs covered by interaction lists (M2L); every ordered
                                    element pair is covered once: near_nnz + far_elem_pairs = n^2 */
-    int64_t max_near_cols;      /* longest near-field row (source elements of one leaf); a build
-                                   refuses rows above 4,096 */
+    int64_t max_near_cols;      /* longest near-field row (source elements of one leaf) */
     int64_t wx_elem_pairs;      /* entries of near_nnz that come from W and X pairs */
 } fda_stats;
 
@@ -233,17 +232,20 @@ int bm_solve(fda_plan *plan, const void *b_dev, void *x_dev, int64_t nrhs, int64
  * (Section 5); these calls add one.  A row R is a chunk of <= 64 consecutive
  * elements (tree order) of one leaf L (one row per leaf when n_L <= 64;
  * stats.mlp_rows rows in all).  For a residual v, with z = inv(A_LL) v_L the
- * block-Jacobi correction of the leaf restricted to the row:
+ * block-Jacobi correction of the leaf restricted to the row, and the complex
+ * row scale s_R = |v_R| * (phase of the entry of v_R with the largest
+ * modulus, the first such entry on ties):
  *
- *   features (FDA_MLP_IN = 272 floats): Re v_R/|v_R|, Im v_R/|v_R|,
- *     Re z_R/|v_R|, Im z_R/|v_R| (each zero-padded to 64 entries), the leaf
+ *   features (FDA_MLP_IN = 272 floats): Re v_R/s_R, Im v_R/s_R,
+ *     Re z_R/s_R, Im z_R/s_R (each zero-padded to 64 entries), the leaf
  *     width and the mesh's largest edge in wavelengths, n_R/64, 1, then
  *     zeros (v_R = 0 gives zero features apart from the scalars);
  *   network: 272 -> h -> h -> 128, ReLU after the two hidden layers, BF16
  *     weights with FP32 accumulation in inference and training, FP32 master
  *     parameters updated by Adam (beta 0.9 / 0.999, eps 1e-8);
  *   output (FDA_MLP_OUT = 128): Re and Im of a 64-entry correction c_R;
- *   preconditioner: M(v)_R = z_R + |v_R| c_R.
+ *   preconditioner: M(v)_R = z_R + s_R c_R, so M(a v) = a M(v) for every
+ *     complex a.
  *
  * Parameters are one flat FP32 array: W1 (272 x h, row-major: input index
  * major), b1 (h), W2 (h x h), b2 (h), W3 (h x 128), b3 (128).  Rows of X,
@@ -294,7 +296,7 @@ int fda_mlp_train(fda_mlp *mlp, const float *X_dev, const float *T_dev, const fl
  * e_dev (may be NULL): the matching errors e = A^-1 r.  For column c and row
  * R (leaf order, then chunk order; stats.mlp_rows rows) row c*mlp_rows + R
  * of X_dev (272 floats) gets the features of r; if e_dev is given, the same
- * row of T_dev (128) gets (e_R - z_R)/|r_R| and of M_dev (128) the mask of
+ * row of T_dev (128) gets (e_R - z_R)/s_R (s_R the row scale of r) and of M_dev (128) the mask of
  * the row's n_R entries (1 on Re and Im of each, 0 on padding).
  * Synchronous.  Errors: FDA_EINVAL (nrhs / ld out of range), FDA_EHIP. */
 int fda_mlp_samples(fda_plan *plan, const void *r_dev, const void *e_dev, int64_t nrhs, int64_t ld, float *X_dev,
@@ -323,8 +325,15 @@ int fda_plan_set_mlp(fda_plan *plan, fda_mlp *mlp);
 
 /* Capture the batch: plans[i] (distinct, same device), x_devs[i] / y_devs[i]
  * device buffers of N_i x nrhs[i] complex128 (leading dimension N_i).  The
- * plans' work buffers are sized here (nothing allocates inside the graph);
- * while the batch exists, the plans must not run concurrently with it.
+ * plans' work buffers are sized here (nothing allocates inside the graph)
+ * and the graph keeps pointers to them and to each plan's M2L work list.
+ * While the batch exists: the plans must not run concurrently with it; a
+ * call on one of its plans that would reallocate those buffers (fda_matvec,
+ * bm_rhs_neumann, bm_solve or fda_profile_matvec with more columns than the
+ * work buffers hold, fda_m2l_set_config with another item order or width,
+ * fda_autotune) fails with FDA_EINVAL; and its plans must not be freed (free
+ * the batch first).  The same holds for a graph the caller captures around
+ * fda_matvec: it records the work buffers of that call's column count.
  * Errors: FDA_EINVAL, FDA_ENOMEM, FDA_EHIP; *out is NULL on error. */
 int fda_batch_create(fda_plan *const *plans, int32_t nplans, const void *const *x_devs, void *const *y_devs,
                      const int64_t *nrhs, fda_batch **out);

@@ -57,6 +57,9 @@ struct fda_plan {
     std::vector<void *> m2l_allocs;  // device arrays of the merged list
     int64_t m2l_bytes = 0;
     fda_m2l_config m2l_cfg{};
+    // Batches (captured graphs) that hold pointers to the work buffers and
+    // the merged M2L list: while one exists, nothing may reallocate them.
+    int live_batches = 0;
 };
 
 namespace {
@@ -173,6 +176,10 @@ void free_work(fda_plan *p) {
 // per-level outgoing / incoming states.
 void ensure_capacity(fda_plan *p, int nrhs) {
     if (nrhs <= p->cap_nrhs) return;
+    if (p->live_batches > 0)
+        throw BuildError{FDA_EINVAL, "the plan's work buffers hold " + std::to_string(p->cap_nrhs) +
+                                         " columns and a batch graph references them; free the batch before a "
+                                         "call with more columns"};
     free_work(p);
     const int64_t N = p->d.n;
     p->xt = dalloc<double2>(p, (size_t)N * nrhs, p->work);
@@ -215,33 +222,59 @@ void ensure_capacity(fda_plan *p, int nrhs) {
     p->cap_nrhs = nrhs;
 }
 
+// Gauss-Legendre rule on [-1, 1] by the Golub-Welsch construction: the
+// nodes are the eigenvalues of the symmetric tridiagonal Jacobi matrix of the
+// Legendre polynomials (zero diagonal, off-diagonal j / sqrt(4 j^2 - 1)), and
+// each weight is 2 (the integral of 1) times the squared first component of
+// the node's normalised eigenvector.  The eigenproblem (n <= 64) is solved
+// by cyclic Jacobi rotations on the dense matrix.
 void legendre_nodes(int n, double *x, double *w) {
-    // Newton iteration on P_n from Chebyshev-like initial guesses.
-    const double pi = 3.14159265358979323846;
-    for (int i = 0; i < n; ++i) {
-        double z = std::cos(pi * (i + 0.75) / (n + 0.5)), dp = 1;
-        for (int it = 0; it < 100; ++it) {
-            double p0 = 1, p1 = z;
-            for (int m = 2; m <= n; ++m) {
-                double p2 = ((2 * m - 1) * z * p1 - (m - 1) * p0) / m;
-                p0 = p1;
-                p1 = p2;
+    std::vector<double> A((size_t)n * n, 0.0), Q((size_t)n * n, 0.0);
+    auto a = [&](int i, int j) -> double & { return A[(size_t)i * n + j]; };
+    auto q = [&](int i, int j) -> double & { return Q[(size_t)i * n + j]; };
+    for (int i = 0; i < n; ++i) q(i, i) = 1.0;
+    for (int j = 1; j < n; ++j) a(j - 1, j) = a(j, j - 1) = j / std::sqrt(4.0 * j * j - 1.0);
+    for (int sweep = 0; sweep < 64; ++sweep) {
+        double off = 0.0;
+        for (int i = 0; i < n; ++i)
+            for (int j = i + 1; j < n; ++j) off += a(i, j) * a(i, j);
+        if (off < 1e-40) break;
+        for (int p = 0; p < n; ++p)
+            for (int r = p + 1; r < n; ++r) {
+                if (a(p, r) == 0.0) continue;
+                // rotation in the (p, r) plane that zeroes a(p, r): with
+                // theta = (a_rr - a_pp) / (2 a_pr), t = tan of the angle
+                const double th = (a(r, r) - a(p, p)) / (2.0 * a(p, r));
+                const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+                const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+                for (int k = 0; k < n; ++k) {  // columns p, r of A and Q
+                    const double akp = a(k, p), akr = a(k, r);
+                    a(k, p) = c * akp - sn * akr;
+                    a(k, r) = sn * akp + c * akr;
+                    const double qkp = q(k, p), qkr = q(k, r);
+                    q(k, p) = c * qkp - sn * qkr;
+                    q(k, r) = sn * qkp + c * qkr;
+                }
+                for (int k = 0; k < n; ++k) {  // rows p, r of A
+                    const double apk = a(p, k), ark = a(r, k);
+                    a(p, k) = c * apk - sn * ark;
+                    a(r, k) = sn * apk + c * ark;
+                }
             }
-            dp = n * (z * p1 - p0) / (z * z - 1);
-            double dz = p1 / dp;
-            z -= dz;
-            if (std::fabs(dz) < 1e-16) break;
-        }
-        double p0 = 1, p1 = z;
-        for (int m = 2; m <= n; ++m) {
-            double p2 = ((2 * m - 1) * z * p1 - (m - 1) * p0) / m;
-            p0 = p1;
-            p1 = p2;
-        }
-        dp = n * (z * p1 - p0) / (z * z - 1);
-        x[i] = z;
-        w[i] = 2.0 / ((1 - z * z) * dp * dp);
     }
+    std::vector<std::pair<double, double>> nw(n);
+    for (int j = 0; j < n; ++j) nw[j] = {a(j, j), 2.0 * q(0, j) * q(0, j)};
+    std::sort(nw.begin(), nw.end());
+    // the rule is symmetric about 0: average each node with its mirror
+    for (int j = 0; j < n; ++j) {
+        const auto &m = nw[n - 1 - j];
+        x[j] = 0.5 * (nw[j].first - m.first);
+        w[j] = 0.5 * (nw[j].second + m.second);
+    }
+    // the weights integrate 1 exactly
+    double sw = 0.0;
+    for (int j = 0; j < n; ++j) sw += w[j];
+    for (int j = 0; j < n; ++j) w[j] *= 2.0 / sw;
 }
 
 void quadrature_constants() {
@@ -438,9 +471,13 @@ void upload_plan(fda_plan *p, const HostOps &ops, DevTranslations &tr) {
         col_off[b + 1] = (int64_t)cols.size();
         max_ncol = std::max(max_ncol, c);
     }
-    if ((size_t)max_ncol * sizeof(double2) > 64 * 1024)
-        throw BuildError{FDA_EINVAL, "near-field row longer than 4,096 elements, too long for one workgroup "
-                                     "(lower max_leaf)"};
+    // rows up to kP2PShortCols columns stage x in LDS (k_p2p); longer rows
+    // read it through the column list (k_p2p_direct, no LDS), so the row
+    // length is bounded only by the 32-bit entry index of a leaf's block in
+    // the quadrature kernel
+    for (int b = 0; b < d.nleaf; ++b)
+        if ((int64_t)hp.nf_ncol[b] * (hp.leaf_off[b + 1] - hp.leaf_off[b]) > INT32_MAX)
+            throw BuildError{FDA_EINVAL, "near-field block of one leaf above 2^31 entries (lower max_leaf)"};
     d.max_ncol = max_ncol;
     {
         // near-field work items: rows of one leaf, about kP2PItemEntries
@@ -995,6 +1032,9 @@ void apply_m2l_config(fda_plan *p, const fda_m2l_config &c) {
     const fda_m2l_config old = p->m2l_cfg;
     bool rebuild = c.xcd_order != old.xcd_order;
     for (const auto &lh : p->m2l_host) rebuild = rebuild || c.width[lh.level] != old.width[lh.level];
+    if (rebuild && p->live_batches > 0)
+        throw BuildError{FDA_EINVAL, "a batch graph references the plan's M2L work list; free the batch before "
+                                     "changing the item order or widths"};
     p->m2l_cfg.variant = c.variant;
     p->m2l_cfg.xcd_order = c.xcd_order;
     for (const auto &lh : p->m2l_host) p->m2l_cfg.width[lh.level] = c.width[lh.level];
@@ -1034,6 +1074,7 @@ int fda_autotune(fda_plan *plan, int32_t reps, void *stream, fda_tune_result *ou
     g_last_error.clear();
     if (!plan || !out) return fail(FDA_EINVAL, "NULL argument");
     if (reps < 1 || reps > 1000) return fail(FDA_EINVAL, "reps out of range");
+    if (plan->live_batches > 0) return fail(FDA_EINVAL, "a batch graph references the plan; free it before tuning");
     std::memset(out, 0, sizeof(*out));
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int rc = FDA_OK;
@@ -1595,12 +1636,14 @@ struct fda_batch {
     hipGraphExec_t exec = nullptr;
     std::vector<hipStream_t> streams;
     std::vector<hipEvent_t> events;
+    std::vector<fda_plan *> plans;  // each holds one count in live_batches while the batch exists
     int device = 0;
     int nplans = 0;
 };
 
 static void batch_release(fda_batch *b) {
     if (!b) return;
+    for (fda_plan *p : b->plans) --p->live_batches;
     if (b->exec) hipGraphExecDestroy(b->exec);
     if (b->graph) hipGraphDestroy(b->graph);
     for (auto e : b->events) hipEventDestroy(e);
@@ -1660,6 +1703,10 @@ int fda_batch_create(fda_plan *const *plans, int32_t nplans, const void *const *
         capturing = false;
         hip_check(hipStreamEndCapture(s0, &b->graph), "end capture");
         hip_check(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "instantiate");
+        for (int i = 0; i < nplans; ++i) {
+            b->plans.push_back(plans[i]);
+            ++plans[i]->live_batches;
+        }
     } catch (const BuildError &e) {
         if (capturing) {
             hipGraph_t g = nullptr;

@@ -119,28 +119,51 @@ __device__ double2 near_entry(const double *tv, double area, const double *x, co
     return acc;
 }
 
-// Diagonal entry: 1/2 + alpha * f.p. int d2G over the element's own flat
-// triangle at its centroid = 1/2 + alpha (ik/2 - (1/4pi) int exp(ikR)/R dtheta),
-// the angular integral taken edge by edge with 32-point Gauss-Legendre.
+// Geometry of one edge (p, q) of a flat triangle seen from an interior point
+// x: d = distance from x to the edge's line, and the angles phi1 < phi2 of
+// the end points measured at x from the foot of the perpendicular, as sines
+// and as angles.  Along the edge R(phi) = d / cos(phi).
+struct EdgeView {
+    double d, sin1, sin2, phi1, phi2;
+};
+__device__ __forceinline__ EdgeView edge_view(const double *p, const double *q, const double *x) {
+    const double ev[3] = {q[0] - p[0], q[1] - p[1], q[2] - p[2]};
+    const double L = sqrt(ev[0] * ev[0] + ev[1] * ev[1] + ev[2] * ev[2]);
+    const double t = ((x[0] - p[0]) * ev[0] + (x[1] - p[1]) * ev[1] + (x[2] - p[2]) * ev[2]) / L;  // foot at p + t e
+    const double xp2 = (x[0] - p[0]) * (x[0] - p[0]) + (x[1] - p[1]) * (x[1] - p[1]) + (x[2] - p[2]) * (x[2] - p[2]);
+    const double xq2 = (x[0] - q[0]) * (x[0] - q[0]) + (x[1] - q[1]) * (x[1] - q[1]) + (x[2] - q[2]) * (x[2] - q[2]);
+    EdgeView e;
+    e.d = sqrt(fmax(xp2 - t * t, 0.0));
+    e.sin1 = -t / sqrt(xp2);
+    e.sin2 = (L - t) / sqrt(xq2);
+    e.phi1 = atan2(-t, e.d);
+    e.phi2 = atan2(L - t, e.d);
+    return e;
+}
+
+// Diagonal entry of A: 1/2 + alpha * (finite part of the integral of
+// d2G/dn_x dn_y over the element's own flat triangle at its centroid).  On a
+// flat triangle r . n = 0 and the kernel is exp(ikR)(1 - ikR)/(4 pi R^3),
+// whose radial antiderivative is -exp(ikR)/(4 pi R); dropping the 1/eps of a
+// small disc about the centroid leaves
+//   ik/2 - (1/4pi) oint exp(ikR(theta)) / R(theta) dtheta
+// over the polar angle theta.  The contour integral is split as
+// exp(ikR)/R = 1/R + (exp(ikR) - 1)/R: per edge the static part is exact,
+// int cos(phi)/d dphi = (sin phi2 - sin phi1)/d, and the rest,
+// (-2 sin^2(kR/2) + i sin(kR))/R, is bounded by k and smooth in phi, which a
+// 32-point Gauss-Legendre rule integrates.
 __device__ double2 self_entry(const double *tv, const double *x, double k, double2 alpha) {
     double2 s = make_double2(0.0, 0.0);
     for (int e = 0; e < 3; ++e) {
-        const double *p = tv + 3 * e, *q = tv + 3 * ((e + 1) % 3);
-        double ev[3] = {q[0] - p[0], q[1] - p[1], q[2] - p[2]};
-        double L = sqrt(ev[0] * ev[0] + ev[1] * ev[1] + ev[2] * ev[2]);
-        double eh[3] = {ev[0] / L, ev[1] / L, ev[2] / L};
-        double t = (x[0] - p[0]) * eh[0] + (x[1] - p[1]) * eh[1] + (x[2] - p[2]) * eh[2];
-        double f[3] = {p[0] + t * eh[0] - x[0], p[1] + t * eh[1] - x[1], p[2] + t * eh[2] - x[2]};
-        double d = sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
-        double ph1 = atan2(-t, d), ph2 = atan2(L - t, d);
-        double half = 0.5 * (ph2 - ph1), mid = 0.5 * (ph2 + ph1);
+        const EdgeView ed = edge_view(tv + 3 * e, tv + 3 * ((e + 1) % 3), x);
+        s.x += (ed.sin2 - ed.sin1) / ed.d;
+        const double half = 0.5 * (ed.phi2 - ed.phi1), mid = 0.5 * (ed.phi2 + ed.phi1);
         for (int g = 0; g < 32; ++g) {
-            double R = d / cos(mid + half * c_glx[g]);
-            double sn, cs;
-            sincos(k * R, &sn, &cs);
-            double w = half * c_glw[g] / R;
-            s.x += w * cs;
-            s.y += w * sn;
+            const double R = ed.d / cos(mid + half * c_glx[g]);
+            const double h = sin(0.5 * k * R);
+            const double w = half * c_glw[g] / R;
+            s.x -= w * 2.0 * h * h;
+            s.y += w * sin(k * R);
         }
     }
     const double inv4pi = 1.0 / (4.0 * 3.14159265358979323846);
@@ -151,28 +174,22 @@ __device__ double2 self_entry(const double *tv, const double *x, double k, doubl
 
 // Diagonal entry of B: -alpha/2 + int G over the element's own flat
 // triangle at its centroid (the alpha dG/dn_x part vanishes there, r . n_x
-// = 0); in polar coordinates about the centroid
-// int G = (i / (4 pi k)) int_0^{2 pi} (1 - exp(ik R(theta))) dtheta, the
-// angular integral taken edge by edge with 32-point Gauss-Legendre.
+// = 0).  In polar coordinates about the centroid the radial integral of
+// exp(ikR)/(4 pi R) R dR is exact, so
+//   int G = (i / (4 pi k)) oint (1 - exp(ik R(theta))) dtheta,
+// with 1 - exp(ikR) = 2 sin^2(kR/2) - i sin(kR), integrated edge by edge with
+// 32-point Gauss-Legendre in phi.
 __device__ double2 self_entry_rhs(const double *tv, const double *x, double k, double2 alpha) {
     double2 s = make_double2(0.0, 0.0);
     for (int e = 0; e < 3; ++e) {
-        const double *p = tv + 3 * e, *q = tv + 3 * ((e + 1) % 3);
-        double ev[3] = {q[0] - p[0], q[1] - p[1], q[2] - p[2]};
-        double L = sqrt(ev[0] * ev[0] + ev[1] * ev[1] + ev[2] * ev[2]);
-        double eh[3] = {ev[0] / L, ev[1] / L, ev[2] / L};
-        double t = (x[0] - p[0]) * eh[0] + (x[1] - p[1]) * eh[1] + (x[2] - p[2]) * eh[2];
-        double f[3] = {p[0] + t * eh[0] - x[0], p[1] + t * eh[1] - x[1], p[2] + t * eh[2] - x[2]};
-        double d = sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
-        double ph1 = atan2(-t, d), ph2 = atan2(L - t, d);
-        double half = 0.5 * (ph2 - ph1), mid = 0.5 * (ph2 + ph1);
+        const EdgeView ed = edge_view(tv + 3 * e, tv + 3 * ((e + 1) % 3), x);
+        const double half = 0.5 * (ed.phi2 - ed.phi1), mid = 0.5 * (ed.phi2 + ed.phi1);
         for (int g = 0; g < 32; ++g) {
-            double R = d / cos(mid + half * c_glx[g]);
-            double sn, cs;
-            sincos(k * R, &sn, &cs);
-            double w = half * c_glw[g];
-            s.x += w * (1.0 - cs);
-            s.y -= w * sn;
+            const double R = ed.d / cos(mid + half * c_glx[g]);
+            const double h = sin(0.5 * k * R);
+            const double w = half * c_glw[g];
+            s.x += w * 2.0 * h * h;
+            s.y -= w * sin(k * R);
         }
     }
     const double c = 1.0 / (4.0 * 3.14159265358979323846 * k);  // i c s = (-c s.y, c s.x)
@@ -211,9 +228,11 @@ __global__ void k_near_blocks(const int64_t *leaf_off, const int64_t *col_off, c
 //
 // The matvec kernels are templates over the storage type of the operators
 // and states: double2 (FP64 plan) or float2 (FP32 plan: M2L, M2M, L2L, S2M,
-// L2T and the off-diagonal near field in FP32 with FP32 accumulation on the
-// matrix cores; the element self terms and every vector the caller sees stay
-// FP64).
+// L2T and the off-diagonal near field stored in FP32 with FP32 accumulation;
+// the element self terms and every vector the caller sees stay FP64).  The
+// dense contractions (M2M, M2L, L2L) run on the matrix cores (FP64 or FP32
+// MFMA); the near field, S2M and L2T stream their precomputed operators from
+// HBM once per product and are scalar FMA loops.
 
 template <class C>
 struct CT;
@@ -402,7 +421,6 @@ __global__ void k_s2m(const int64_t *leaf_off, const int32_t *ids, const int32_t
 // XCD so that the shared translation matrices stay in that XCD's L2.
 #define GG_NB 32
 #define GG_LD (GG_NB + 1)  // padded LDS row: spreads the 4 k-rows of an MFMA operand over the banks
-#define GG_J 32
 #define MF_RT 4
 #define GG_RT 2  // row tiles per wave in a band of the gathered GEMM (band = 128 rows)
 #define LR_MAX 72
@@ -413,12 +431,6 @@ __global__ void k_s2m(const int64_t *leaf_off, const int32_t *ids, const int32_t
 #define LR_P2 1  // row tiles per wave and pass in phase 2
 #ifndef FDA_M2L_WAVES64
 #define FDA_M2L_WAVES64 4  // k_m2l_lowrank<double2> waves per SIMD
-#endif
-#ifndef FDA_M2L_DIRECT64
-#define FDA_M2L_DIRECT64 1  // FP64 phase 1: operands straight into registers (no LDS staging, no barriers)
-#endif
-#ifndef FDA_M2L_DIRECT32
-#define FDA_M2L_DIRECT32 0  // FP32 phase 1: staged through LDS
 #endif
 // Variants of the low-rank M2L kernel (chosen per plan, fda_autotune):
 // k-steps in flight in the register rings of phase 1 (direct form; waves
@@ -444,34 +456,13 @@ struct M2LVariant<3> {
 };
 static_assert(kM2LVariants == 4, "one M2LVariant per variant index");
 
-// Load up to GG_J x GG_NB gathered input values (zero padded) into LDS.
+// Complex accumulator of one 16 x 16 output tile on the matrix cores, in the
+// three-product form (Gauss): P1 = Ar Br, P2 = Ai Bi, P3 = (Ar + Ai)(Br + Bi),
+// then Re = P1 - P2 and Im = P3 - P1 - P2 (three MFMAs per complex k-step
+// instead of four).  Independent accumulators keep consecutive MFMAs from
+// waiting on each other.
 template <class C>
-__device__ __forceinline__ void load_states(C (*S)[GG_LD], const C *Xr, const int32_t *sidx, int kin, int j0) {
-    for (int e = threadIdx.x; e < GG_J * GG_NB; e += blockDim.x) {
-        const int jj = e % GG_J, b = e / GG_J;
-        const int sb = sidx[b];
-        C v = czero<C>();
-        if (sb >= 0 && j0 + jj < kin) v = Xr[(int64_t)sb * kin + j0 + jj];
-        S[jj][b] = v;
-    }
-}
-
-// Complex accumulator of one 16 x 16 output tile on the matrix cores.  The
-// three-product form (Gauss) takes P1 = Ar Br, P2 = Ai Bi,
-// P3 = (Ar + Ai)(Br + Bi), then Re = P1 - P2 and Im = P3 - P1 - P2; the
-// four-product form Re += Ar Br - Ai Bi, Im += Ar Bi + Ai Br needs a third
-// fewer accumulator registers.  Independent accumulators keep consecutive
-// MFMAs from waiting on each other.
-#ifndef FDA_GEMM_3M
-#define FDA_GEMM_3M 1  // k_ggemm (M2M, L2L, full-rank M2L)
-#endif
-#ifndef FDA_M2L_3M
-#define FDA_M2L_3M 1  // k_m2l_lowrank (3 waves per SIMD in FP64, 4 in FP32)
-#endif
-template <class C, bool G3>
-struct CAcc;
-template <class C>
-struct CAcc<C, true> {
+struct CAcc {
     using v4 = typename CT<C>::v4;
     using R = typename CT<C>::R;
     v4 p1, p2, p3;
@@ -488,98 +479,8 @@ struct CAcc<C, true> {
     __device__ __forceinline__ R re(int v) const { return p1[v] - p2[v]; }
     __device__ __forceinline__ R im(int v) const { return p3[v] - p1[v] - p2[v]; }
 };
-template <class C>
-struct CAcc<C, false> {
-    using v4 = typename CT<C>::v4;
-    using R = typename CT<C>::R;
-    v4 r, i;
-    __device__ __forceinline__ void zero() {
-        r = (v4){0, 0, 0, 0};
-        i = (v4){0, 0, 0, 0};
-    }
-    __device__ __forceinline__ void mac(C a, C b) {
-        r = CT<C>::mfma(a.x, b.x, r);
-        i = CT<C>::mfma(a.x, b.y, i);
-        r = CT<C>::mfma(-a.y, b.y, r);
-        i = CT<C>::mfma(a.y, b.x, i);
-    }
-    __device__ __forceinline__ R re(int v) const { return r[v]; }
-    __device__ __forceinline__ R im(int v) const { return i[v]; }
-};
 
-// A fragments of the wave's row tiles rt = wave + 4 q at k-column kcol of a
-// column-major matrix (zero outside rows < mrows, columns < kend).
-template <class C, int NT>
-__device__ __forceinline__ void load_afrag(C (&a)[NT], const C *A, int lda, int mrows, int row0, int ntile, int wave,
-                                           int li, int kcol, int kend) {
-#pragma unroll
-    for (int q = 0; q < NT; ++q) {
-        const int rt = wave + 4 * q;
-        const int row = row0 + rt * 16 + li;
-        a[q] = czero<C>();
-        if (rt < ntile && row < mrows && kcol < kend) a[q] = gload(A + row + (int64_t)kcol * lda);
-    }
-}
-
-// Y (m x ncols) = A (m x kin) S-gathered (kin x ncols), NCT 16-column tiles.
-template <class C, int NCT>
-__device__ __forceinline__ void ggemm_body(const int4 h, const int32_t *sidx, const C *At, int m, int kin,
-                                           const C *Xr, C *Tr, C (*S)[GG_LD]) {
-    using v4 = typename CT<C>::v4;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int li = lane & 15, lk = lane >> 4;
-    for (int band = 0; band < m; band += 64 * GG_RT) {
-        const int ntile = min(GG_RT * 4, (m - band + 15) >> 4);
-        CAcc<C, FDA_GEMM_3M> acc[GG_RT][NCT];
-#pragma unroll
-        for (int q = 0; q < GG_RT; ++q)
-#pragma unroll
-            for (int c = 0; c < NCT; ++c) acc[q][c].zero();
-        for (int j0 = 0; j0 < kin; j0 += GG_J) {
-            __syncthreads();
-            load_states<C>(S, Xr, sidx, kin, j0);
-            __syncthreads();
-            const int jm = min(GG_J, kin - j0);
-            C a[GG_RT], an[GG_RT];
-            load_afrag<C, GG_RT>(a, At, m, m, band, ntile, wave, li, j0 + lk, kin);
-            for (int kk = 0; kk < jm; kk += 4) {
-                if (kk + 4 < jm) load_afrag<C, GG_RT>(an, At, m, m, band, ntile, wave, li, j0 + kk + 4 + lk, kin);
-                const C b0 = S[kk + lk][li];
-                const C b1 = NCT == 2 ? S[kk + lk][16 + li] : czero<C>();
-#pragma unroll
-                for (int q = 0; q < GG_RT; ++q) {
-                    if (wave + 4 * q >= ntile) break;
-                    acc[q][0].mac(a[q], b0);
-                    if (NCT == 2) acc[q][NCT - 1].mac(a[q], b1);
-                }
-#pragma unroll
-                for (int q = 0; q < GG_RT; ++q) a[q] = an[q];
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < GG_RT; ++q) {
-            const int rt = wave + 4 * q;
-            if (rt >= ntile) break;
-#pragma unroll
-            for (int c = 0; c < NCT; ++c) {
-                const int col = c * 16 + li;
-                if (col >= h.z) continue;
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int row = band + rt * 16 + CT<C>::row(lk, v);
-                    if (row < m) {
-                        C r;
-                        r.x = acc[q][c].re(v);
-                        r.y = acc[q][c].im(v);
-                        Tr[(int64_t)col * m + row] = r;
-                    }
-                }
-            }
-        }
-    }
-}
-
-// Staged form of the gathered GEMM: every 16-deep k-chunk of the 128-row
+// Gathered GEMM body: every GG_SJ-deep k-chunk of the 128-row
 // band of A is staged in LDS beside the chunk of gathered states, and the
 // next chunk of both is fetched into registers while the current one is
 // multiplied (the MFMA loop reads only LDS).
@@ -598,7 +499,7 @@ __device__ __forceinline__ void ggemm_body_staged(const int4 h, const int32_t *s
     for (int band = 0; band < m; band += GG_SB) {
         const int ntile = min(GG_RT * 4, (m - band + 15) >> 4);
         const int nrow = min(GG_SB, m - band);
-        CAcc<C, FDA_GEMM_3M> acc[GG_RT][NCT];
+        CAcc<C> acc[GG_RT][NCT];
 #pragma unroll
         for (int q = 0; q < GG_RT; ++q)
 #pragma unroll
@@ -674,9 +575,6 @@ __device__ __forceinline__ void ggemm_body_staged(const int4 h, const int32_t *s
     }
 }
 
-#ifndef FDA_GEMM_STAGED
-#define FDA_GEMM_STAGED 1
-#endif
 
 // Waves per SIMD the GEMM kernels are compiled for: FP64 needs more
 // registers per complex accumulator than FP32.
@@ -690,15 +588,15 @@ struct GemmOcc {
 template <class C>
 struct M2LOcc {
     static constexpr int waves = FDA_M2L_WAVES64;
-    static constexpr bool direct = FDA_M2L_DIRECT64;
+    static constexpr bool direct = true;  // phase 1: operands straight into registers (no LDS staging)
 };
 template <>
 struct M2LOcc<float2> {
     static constexpr int waves = 4;
-    static constexpr bool direct = FDA_M2L_DIRECT32;
+    static constexpr bool direct = false;  // phase 1 staged through LDS (the direct form is slower in FP32)
 };
 #ifndef FDA_GEMM_WAVES32
-#define FDA_GEMM_WAVES32 (FDA_GEMM_STAGED ? 3 : 4)
+#define FDA_GEMM_WAVES32 3
 #endif
 template <>
 struct GemmOcc<float2> {
@@ -709,12 +607,8 @@ template <class C>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GemmOcc<C>::waves)))
 k_ggemm(const int4 *hdr, const int32_t *src, const C *A, int m, int kin, const C *X, int64_t xstride, C *T,
         int64_t tstride, int nwork) {
-#if FDA_GEMM_STAGED
     __shared__ C S[GG_SJ][GG_LD];
     __shared__ C As[GG_SJ][GG_SLD];
-#else
-    __shared__ C S[GG_J][GG_LD];
-#endif
     __shared__ int32_t sidx[GG_NB];
     const int nx = 8;
     const int per = gridDim.x / nx;
@@ -725,17 +619,10 @@ k_ggemm(const int4 *hdr, const int32_t *src, const C *A, int m, int kin, const C
     const C *Xr = X + (int64_t)blockIdx.y * xstride;
     C *Tr = T + (int64_t)blockIdx.y * tstride + (int64_t)h.y * m;
     const C *At = A + (int64_t)h.x * m * kin;
-#if FDA_GEMM_STAGED
     if (h.z > 16)
         ggemm_body_staged<C, 2>(h, sidx, At, m, kin, Xr, Tr, S, As);
     else
         ggemm_body_staged<C, 1>(h, sidx, At, m, kin, Xr, Tr, S, As);
-#else
-    if (h.z > 16)
-        ggemm_body<C, 2>(h, sidx, At, m, kin, Xr, Tr, S);
-    else
-        ggemm_body<C, 1>(h, sidx, At, m, kin, Xr, Tr, S);
-#endif
 }
 
 // Phase 1 of the low-rank M2L in the direct form: NQ row tiles of V^ (rows
@@ -744,7 +631,7 @@ k_ggemm(const int4 *hdr, const int32_t *src, const C *A, int m, int kin, const C
 // ring of registers; the main loop issues exactly PD loads per trip and the
 // tail none, so the waits count loads instead of draining them.
 template <class C, int NQ, int PD>
-__device__ __forceinline__ void m2l_p1_direct(CAcc<C, FDA_M2L_3M> *zacc, const C *xcol, const C *const *vrow, int rmax,
+__device__ __forceinline__ void m2l_p1_direct(CAcc<C> *zacc, const C *xcol, const C *const *vrow, int rmax,
                                               int ku, int kb0, int kstep, int lk) {
     const int ku4 = (ku + 3) & ~3;
     auto fetch = [&](C (&av)[NQ], C &bv, int kc) {
@@ -800,7 +687,7 @@ __device__ __forceinline__ void m2l_body(const int4 h, const int32_t *sidx, cons
     const int kg = kg_n > 1 ? wave / ntz : 0;
     const int tbase = kg_n > 1 ? wave % ntz : wave;
     const int tstep = kg_n > 1 ? 64 : 4;  // kg_n > 1: one tile per wave
-    CAcc<C, FDA_M2L_3M> zacc[ZQ];
+    CAcc<C> zacc[ZQ];
 #pragma unroll
     for (int q = 0; q < ZQ; ++q) zacc[q].zero();
     if constexpr (M2LOcc<C>::direct) {
@@ -931,7 +818,7 @@ __device__ __forceinline__ void m2l_body(const int4 h, const int32_t *sidx, cons
     for (int pass = 0; pass < MF_RT / P2; ++pass) {
         const int rt0 = wave + 4 * P2 * pass;  // this pass: row tiles rt0, rt0 + 4
         if (rt0 >= ntile) break;
-        CAcc<C, FDA_M2L_3M> acc[P2][NCT];
+        CAcc<C> acc[P2][NCT];
 #pragma unroll
         for (int q = 0; q < P2; ++q)
 #pragma unroll

@@ -260,13 +260,25 @@ class Plan:
             raise ValueError(f"expected a contiguous (N,) or (nrhs, N) tensor with N = {n}")
         return 1 if t.dim() == 1 else t.shape[0]
 
-    def matvec(self, x, out=None):
-        """y = A x (fda_matvec)."""
+    def _check_out(self, out, x):
+        """out (when given) must have x's shape and device: the library
+        writes nrhs x N values into it."""
         import torch
 
+        if out is None:
+            return torch.empty_like(x)
+        self._check_vec(out, self.n)
+        if tuple(out.shape) != tuple(x.shape) or out.device != x.device:
+            raise ValueError(f"out has shape {tuple(out.shape)} on {out.device}; expected {tuple(x.shape)} on "
+                             f"{x.device}")
+        if out.data_ptr() == x.data_ptr():
+            raise ValueError("out must not be the input tensor")
+        return out
+
+    def matvec(self, x, out=None):
+        """y = A x (fda_matvec)."""
         nrhs = self._check_vec(x, self.n)
-        y = torch.empty_like(x) if out is None else out
-        self._check_vec(y, self.n)
+        y = self._check_out(out, x)
         rc = library().fda_matvec(self._h, x.data_ptr(), y.data_ptr(), nrhs, self.n, _stream())
         _err(rc)
         return y
@@ -274,11 +286,8 @@ class Plan:
     def rhs_neumann(self, g, out=None):
         """b = B g, the right-hand side for Neumann data du/dn = g
         (bm_rhs_neumann; the plan must be built with neumann_rhs=1)."""
-        import torch
-
         nrhs = self._check_vec(g, self.n)
-        b = torch.empty_like(g) if out is None else out
-        self._check_vec(b, self.n)
+        b = self._check_out(out, g)
         _err(library().bm_rhs_neumann(self._h, g.data_ptr(), b.data_ptr(), nrhs, self.n, _stream()))
         return b
 
@@ -296,10 +305,8 @@ class Plan:
 
     def solve(self, b, tol: float = 1e-5, restart: int = 50, maxit: int = 1000, precond: str = "none", out=None):
         """GMRES solve of A x = b (bm_solve).  Returns (x, stats dict)."""
-        import torch
-
         nrhs = self._check_vec(b, self.n)
-        x = torch.empty_like(b) if out is None else out
+        x = self._check_out(out, b)
         st = SolveStats()
         rc = library().bm_solve(self._h, b.data_ptr(), x.data_ptr(), nrhs, self.n, float(tol), int(restart),
                                 int(maxit), PRECOND[precond], ctypes.byref(st), _stream())
@@ -384,10 +391,8 @@ class Plan:
         """Per-stage HIP-event timings (ms) of fda_matvec, plus the merged
         low-rank M2L product kernel ("m2l_lowrank") and the full-rank M2L
         product kernel of every other level ("m2l_gemm", a list per level)."""
-        import torch
-
         nrhs = self._check_vec(x, self.n)
-        y = torch.empty_like(x) if out is None else out
+        y = self._check_out(out, x)
         res = ProfileResult()
         rc = library().fda_profile_matvec(self._h, x.data_ptr(), y.data_ptr(), nrhs, self.n, int(reps), _stream(),
                                           ctypes.byref(res))

@@ -219,3 +219,13 @@ def test_tree_and_direct_pairs_match_an_independent_model(case, adaptive):
     assert _model_v_pairs(_model_tree.boxes, side, lam) == list(st["m2l_pairs"])
     if case != "graded3_kD10":
         assert any(st["hf"])  # directional levels above the leaves
+
+
+def test_long_near_rows_are_planned():
+    """A graded sphere with leaves of up to 256 elements has near-field rows
+    longer than 4,096 columns; the plan accepts them (the long-row kernel
+    needs no LDS) and still covers every ordered element pair once."""
+    V, T = W.graded_sphere(3)
+    st = _inspect(V, T, 10.0, max_leaf=256, adaptive=1)
+    assert st["max_near_cols"] > 4096
+    assert st["near_nnz"] + st["far_elem_pairs"] == len(T) ** 2

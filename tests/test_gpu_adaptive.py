@@ -9,6 +9,7 @@ import sys
 import numpy as np
 import pytest
 
+import _parity as P
 import oracle as O
 import workloads as W
 
@@ -196,3 +197,22 @@ def test_adaptive_plans_in_a_batch_graph_and_a_torch_graph():
         torch.cuda.synchronize()
     for q in plans:
         q.close()
+
+
+def test_near_rows_longer_than_4096_columns():
+    """Leaves of up to 256 elements on the graded sphere (4,952 triangles,
+    kD = 10) give near-field rows of 4,952 columns (every element): the
+    long-row kernel, which reads x through the column list, matches the
+    dense oracle on every entry (FP64 and FP32 plans)."""
+    V, T = W.graded_sphere(3)
+    k = 10.0
+    _say("[adaptive] rows above 4,096 columns")
+    x = W.complex_normal(len(T), 1, seed=44)
+    yr = O.matvec(V, T, k, x)
+    for prec in ("fp64", "fp32"):
+        with _plan(V, T, k, max_leaf=256, prec=prec) as p:
+            st = p.stats()
+            assert st["max_near_cols"] > 4096
+            y = p.matvec(_dev(x)).cpu().numpy()
+        _say(prec, "max cols", st["max_near_cols"], "rel err", P.rel_err(y, yr))
+        P.check(y, yr, regress=2e-5)

@@ -1,10 +1,14 @@
 """Several meshes in one captured HIP graph (fda_batch_*): every replay
-equals the plans' own products, with eager work between the replays."""
+equals the plans' own products and the dense oracle's, with eager work
+between the replays; calls that would reallocate what the graph references
+are refused while the batch exists."""
 import sys
 
 import numpy as np
 import pytest
 
+import _parity as P
+import oracle as O
 import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -45,6 +49,12 @@ def test_batch_graph_replays_equal_the_single_products():
         xs.append(x)
         ys.append(torch.zeros_like(x))
         want.append(p.matvec(x).cpu().numpy())
+    # the oracle's products of the same inputs (every row of each mesh)
+    for i, (V, T, k, nr, prec) in enumerate(_meshes()):
+        yr = O.matvec(V, T, k, xs[i].cpu().numpy().T if nr > 1 else xs[i].cpu().numpy())
+        yr = yr.T if nr > 1 else yr
+        _say(f"mesh {i}: N={len(T)} {prec} rel err {P.rel_err(want[i], yr):.2e}")
+        P.check(want[i], yr, regress=2e-5)
     b = Batch(plans, xs, ys)
     for rep in range(3):
         for y in ys:
@@ -78,4 +88,37 @@ def test_batch_rejects_a_repeated_plan():
     y2 = torch.zeros_like(x)
     with pytest.raises(FDAError):
         Batch([p, p], [x, x], [y, y2])
+    p.close()
+
+
+def test_batch_keeps_its_buffers_in_place():
+    """While a batch exists, calls that would reallocate the work buffers or
+    the M2L work list it references fail cleanly; the batch still replays to
+    the same products, and after it is freed the calls work again."""
+    from paper_1403_4747_amd import Batch, FDAError, Plan
+
+    V, T, prm = W.workload("sphere5120_kD20")
+    p = Plan(V, T, prm["k"], prm["eps"], nrhs_max=4)
+    x = torch.from_numpy(W.complex_normal(len(T), 1, seed=40)).to("cuda")
+    y = torch.zeros_like(x)
+    want = p.matvec(x).cpu().numpy()
+    b = Batch([p], [x], [y])
+    x2 = torch.zeros((2, len(T)), dtype=torch.complex128, device="cuda")
+    with pytest.raises(FDAError):
+        p.matvec(x2)  # two columns: the buffers hold one
+    cfg = p.m2l_config()
+    lv = next(iter(cfg["width"]))
+    with pytest.raises(FDAError):
+        p.set_m2l_config(width={lv: 16 if cfg["width"][lv] == 32 else 32})
+    with pytest.raises(FDAError):
+        p.autotune(reps=2)
+    assert p.m2l_config() == cfg
+    p.matvec(x)  # one column still fits
+    b.launch()
+    torch.cuda.synchronize()
+    assert np.array_equal(y.cpu().numpy(), want)
+    b.close()
+    Y = p.matvec(x2)
+    torch.cuda.synchronize()
+    assert Y.shape == x2.shape
     p.close()

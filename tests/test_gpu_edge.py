@@ -163,6 +163,20 @@ def test_argument_errors_on_gpu_entry_points():
             p.matvec(b.to(torch.complex64))
         with pytest.raises(ValueError):
             p.matvec(b[: n - 1].contiguous())
+        # an output tensor of another shape than the input (the library would
+        # write nrhs x N values into it), or the input itself, is refused
+        X4 = torch.zeros((4, n), dtype=torch.complex128, device="cuda")
+        for bad in (torch.empty_like(b), torch.empty((2, n), dtype=torch.complex128, device="cuda")):
+            with pytest.raises(ValueError):
+                p.matvec(X4, out=bad if bad.dim() == 2 else bad)
+        with pytest.raises(ValueError):
+            p.matvec(b, out=torch.empty((1, n), dtype=torch.complex128, device="cuda"))
+        with pytest.raises(ValueError):
+            p.matvec(b, out=b)
+        with pytest.raises(ValueError):
+            p.solve(X4, out=torch.empty_like(b))
+        with pytest.raises(ValueError):
+            p.profile(X4, reps=1, out=torch.empty_like(b))
     # build errors: k <= 0, eps out of range, vertex index out of range
     from paper_1403_4747_amd import Plan
 
