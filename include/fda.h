@@ -102,6 +102,10 @@ typedef struct fda_options {
                               always subdivided.  Leaf pairs whose boxes lie on different levels
                               and are not separated by an interaction list (the U, W and X lists
                               of adaptive FMMs) are evaluated directly in the near field. */
+    int32_t p_fixed;       /* 0 (default): p starts at p_min (or ceil(log10(1/eps)) + p0) and is raised
+                              per level until the numerical rank of G_up uses at most 70 % of the
+                              cube points; 1: that starting p on every level (Section 5.1's
+                              p = log(1/eps) + p0 as printed) */
 } fda_options;
 
 /* Plan statistics (filled by fda_inspect / fda_plan_stats). */

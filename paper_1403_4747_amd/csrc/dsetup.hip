@@ -242,7 +242,7 @@ void device_factors(HostPlan &hp, rocblas_handle h) {
             svd_batched(h, hp.opt.svd_method, G.as<double2>(), m, nc, 1, S, U, Vh);
             int r = trunc_rank(S.data(), nc, hp.svd_eps);
             lv.cube = cube;
-            if ((double)r <= kSat * nc || p >= 14) break;
+            if (hp.opt.p_fixed || (double)r <= kSat * nc || p >= 14) break;
         }
         lv.p = p;
         const int nc = (int)lv.cube.size() / 3;

@@ -44,7 +44,7 @@ class Options(ctypes.Structure):
         ("hf_wavelengths", ctypes.c_double), ("rho_c", ctypes.c_double), ("leaf_min_h", ctypes.c_double),
         ("prec", ctypes.c_int32), ("nrhs_max", ctypes.c_int32), ("device", ctypes.c_int32),
         ("verbose", ctypes.c_int32), ("svd_method", ctypes.c_int32), ("m2l_svd_eps", ctypes.c_double),
-        ("neumann_rhs", ctypes.c_int32), ("adaptive", ctypes.c_int32),
+        ("neumann_rhs", ctypes.c_int32), ("adaptive", ctypes.c_int32), ("p_fixed", ctypes.c_int32),
     ]
 
 
