@@ -280,6 +280,21 @@ int fda_mlp_set_params(fda_mlp *mlp, const float *params, int64_t n);
  * FDA_EINVAL, FDA_EHIP. */
 int fda_mlp_forward(fda_mlp *mlp, const float *X_dev, int64_t rows, float *Y_dev, void *stream);
 
+/* fda_mlp_forward for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and the same result, bit for bit, but the two hidden
+ * activations (rows x hidden floats each) live in a statically allocated
+ * device array of 8,388,608 floats (32 MiB), which each GPU the library runs
+ * on holds until the process ends; the call allocates nothing (no hipMalloc,
+ * no library allocation) and does not synchronise.  Limit: 2 x rows x hidden
+ * <= 8,388,608, i.e. rows <= 16,384 at width 256.  Every call on one GPU
+ * shares that GPU's array: calls that overlap in time on one GPU (different
+ * streams, or different networks) race and must be serialised by the caller.
+ * The caller owns X_dev (rows x 272) and Y_dev (rows x 128), as for
+ * fda_mlp_forward.  Asynchronous on `stream`.  Errors: FDA_EINVAL (NULL
+ * argument, rows < 1 or above the limit; nothing is launched), FDA_EHIP. */
+int fda_mlp_forward_noalloc(fda_mlp *mlp, const float *X_dev, int64_t rows, float *Y_dev, void *stream);
+
 /* Gradient of the masked mean squared error
  *   L = sum (mask * (network(X) - T))^2 / (rows * 128)
  * with respect to every parameter (layout as above) into grad_dev (device,

@@ -1532,6 +1532,22 @@ int fda_mlp_forward(fda_mlp *mlp, const float *X_dev, int64_t rows, float *Y_dev
     return FDA_OK;
 }
 
+int fda_mlp_forward_noalloc(fda_mlp *mlp, const float *X_dev, int64_t rows, float *Y_dev, void *stream) {
+    g_last_error.clear();
+    if (!mlp || !mlp->m || !X_dev || !Y_dev) return fail(FDA_EINVAL, "NULL argument");
+    const int64_t cap = mlp_noalloc_max_rows(mlp->m->hidden);
+    if (rows < 1 || rows > cap)
+        return fail(FDA_EINVAL, "rows must be in [1, " + std::to_string(cap) +
+                                    "]: the static scratch holds 2 x rows x hidden <= " +
+                                    std::to_string(kMlpNoAllocFloats) + " floats");
+    MLP_GUARD({
+        hip_check(hipSetDevice(mlp->device), "hipSetDevice");
+        mlp->m->forward_noalloc(X_dev, rows, Y_dev, mlp->device, as_stream(stream));
+        hip_check(hipGetLastError(), "forward");
+    })
+    return FDA_OK;
+}
+
 int fda_mlp_gradient(fda_mlp *mlp, const float *X_dev, const float *T_dev, const float *M_dev, int64_t rows,
                      float *grad_dev, double *loss, void *stream) {
     g_last_error.clear();

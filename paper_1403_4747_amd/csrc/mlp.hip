@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <random>
 #include <string>
 #include <vector>
@@ -361,14 +362,55 @@ void Mlp::ensure_rows(int64_t rows) {
     cap_rows = rows;
 }
 
-// Y (rows x 128) = MLP(X (rows x 272)) with the BF16 weights.
-void Mlp::forward(const float *X, int64_t rows, float *Y, hipStream_t st) {
-    ensure_rows(rows);
+// Y (rows x 128) = MLP(X (rows x 272)) with the BF16 weights; the hidden
+// activations go to a1 and a2 (rows x hidden floats each).
+void Mlp::forward_into(const float *X, int64_t rows, float *Y, float *a1, float *a2, hipStream_t st) const {
     size_t w1, b1, w2, b2, w3, b3;
     offsets(w1, b1, w2, b2, w3, b3);
-    gemm<uint16_t>((int)rows, hidden, kMlpIn, X, kMlpIn, 0, wb + w1, hidden, 0, h1, hidden, w + b1, 1, 0, st);
-    gemm<uint16_t>((int)rows, hidden, hidden, h1, hidden, 0, wb + w2, hidden, 0, h2, hidden, w + b2, 1, 0, st);
-    gemm<uint16_t>((int)rows, kMlpOut, hidden, h2, hidden, 0, wb + w3, kMlpOut, 0, Y, kMlpOut, w + b3, 0, 0, st);
+    gemm<uint16_t>((int)rows, hidden, kMlpIn, X, kMlpIn, 0, wb + w1, hidden, 0, a1, hidden, w + b1, 1, 0, st);
+    gemm<uint16_t>((int)rows, hidden, hidden, a1, hidden, 0, wb + w2, hidden, 0, a2, hidden, w + b2, 1, 0, st);
+    gemm<uint16_t>((int)rows, kMlpOut, hidden, a2, hidden, 0, wb + w3, kMlpOut, 0, Y, kMlpOut, w + b3, 0, 0, st);
+}
+
+void Mlp::forward(const float *X, int64_t rows, float *Y, hipStream_t st) {
+    ensure_rows(rows);
+    forward_into(X, rows, Y, h1, h2, st);
+}
+
+// ------------------------------------------------------------------ allocation-free forward pass
+// For callers that cannot allocate device memory: the hidden activations
+// live in one statically allocated array per device, so the pass needs no
+// hipMalloc.  Every call on a device shares its array (concurrent calls on
+// one device race); it is never cleared, since the first layer overwrites
+// every activation it later reads.
+static __device__ __align__(256) float scratch[kMlpNoAllocFloats];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float *g_scratch_dev[kMaxDevices] = {};  // device address of `scratch`, per device ordinal
+}  // namespace
+
+int64_t mlp_noalloc_max_rows(int hidden) { return kMlpNoAllocFloats / (2 * (int64_t)hidden); }
+
+// Device address of `scratch` on `device`, which must be the current device;
+// looked up once per device (the array's name is only a host-side stand-in).
+static float *noalloc_scratch(int device) {
+    if (device < 0 || device >= kMaxDevices) throw MlpError{"device ordinal out of range for the static scratch"};
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[device]) {
+        void *ptr = nullptr;
+        chk(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        if (!ptr) throw MlpError{"hipGetSymbolAddress(scratch) returned a null address"};
+        g_scratch_dev[device] = (float *)ptr;
+    }
+    return g_scratch_dev[device];
+}
+
+void Mlp::forward_noalloc(const float *X, int64_t rows, float *Y, int device, hipStream_t st) const {
+    if (rows > mlp_noalloc_max_rows(hidden)) throw MlpError{"rows exceed the static scratch"};
+    float *ws = noalloc_scratch(device);
+    forward_into(X, rows, Y, ws, ws + rows * (int64_t)hidden, st);
 }
 
 // Gradient of the masked MSE (mean over rows x 128 outputs) of one batch

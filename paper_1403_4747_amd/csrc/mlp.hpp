@@ -14,6 +14,9 @@ namespace fda {
 constexpr int kMlpIn = 272;   // features per leaf
 constexpr int kMlpOut = 128;  // Re / Im of a 64-element correction
 constexpr int kMlpLeaf = 64;  // largest leaf the features cover
+// Floats of the static per-device scratch of the allocation-free forward
+// pass (32 MiB): both hidden activations, rows x hidden each.
+constexpr int64_t kMlpNoAllocFloats = (int64_t)8 << 20;
 
 struct MlpError {
     std::string msg;
@@ -31,7 +34,14 @@ struct Mlp {
     void sync_bf16(hipStream_t st);
     void ensure_rows(int64_t rows);
     void forward(const float *X, int64_t rows, float *Y, hipStream_t st);
+    void forward_into(const float *X, int64_t rows, float *Y, float *a1, float *a2, hipStream_t st) const;
+    // the forward pass with its activations in the static scratch of
+    // `device` (the current device); rows <= mlp_noalloc_max_rows(hidden)
+    void forward_noalloc(const float *X, int64_t rows, float *Y, int device, hipStream_t st) const;
 };
+
+// Largest row count of the allocation-free forward pass at width `hidden`.
+int64_t mlp_noalloc_max_rows(int hidden);
 
 // Scratch for one gradient evaluation of up to `batch` rows.
 struct MlpGradWork {

@@ -147,6 +147,8 @@ def library():
         L.fda_mlp_set_params.restype = ctypes.c_int
         L.fda_mlp_forward.argtypes = [vp, vp, i64, vp, vp]
         L.fda_mlp_forward.restype = ctypes.c_int
+        L.fda_mlp_forward_noalloc.argtypes = [vp, vp, i64, vp, vp]
+        L.fda_mlp_forward_noalloc.restype = ctypes.c_int
         L.fda_mlp_gradient.argtypes = [vp, vp, vp, vp, i64, vp, ctypes.POINTER(dbl), vp]
         L.fda_mlp_gradient.restype = ctypes.c_int
         L.fda_mlp_train.argtypes = [vp, vp, vp, vp, i64, ctypes.c_int32, ctypes.c_int32, ctypes.c_float,
@@ -466,6 +468,15 @@ class Mlp:
         Y = torch.empty((rows, MLP_OUT), dtype=torch.float32, device=X.device)
         _err(library().fda_mlp_forward(self._h, X.data_ptr(), rows, Y.data_ptr(), _stream()))
         return Y
+
+    def forward_noalloc(self, X, out):
+        """forward() into the caller's `out` (rows x 128 float32) through the
+        allocation-free entry point: the library allocates nothing."""
+        rows = _f32_dev(X, MLP_IN, "X")
+        if _f32_dev(out, MLP_OUT, "out") != rows:
+            raise ValueError("X and out differ in rows")
+        _err(library().fda_mlp_forward_noalloc(self._h, X.data_ptr(), rows, out.data_ptr(), _stream()))
+        return out
 
     def gradient(self, X, T, M):
         """(loss, flat gradient as a float32 device tensor)."""
