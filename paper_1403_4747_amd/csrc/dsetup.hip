@@ -124,17 +124,6 @@ std::vector<double> rotated(const std::vector<double> &P, const double *u, doubl
     return o;
 }
 
-// Outgoing check points of a level / slot, relative to the box centre.
-std::vector<double> out_check(const Level &lv, int slot) {
-    if (!lv.hf) return scaled(lv.cube, kRout * lv.r);
-    return rotated(lv.far, &lv.dirvec[3 * lv.active[slot]], 1.0);
-}
-// Incoming equivalent points.
-std::vector<double> in_equiv(const Level &lv, int slot) {
-    if (!lv.hf) return scaled(lv.cube, kRout * lv.r);
-    return rotated(lv.far, &lv.dirvec[3 * lv.active[slot]], -1.0);
-}
-
 std::vector<double> cube_points(int p) {
     std::vector<double> out;
     for (int i = 0; i < p; ++i)
@@ -219,6 +208,17 @@ Mat padded(const Mat &M, int padc, const std::vector<double> *inv_scale) {
 }
 
 }  // namespace
+
+// Outgoing check points of a level / slot, relative to the box centre.
+std::vector<double> out_check(const Level &lv, int slot) {
+    if (!lv.hf) return scaled(lv.cube, kRout * lv.r);
+    return rotated(lv.far, &lv.dirvec[3 * lv.active[slot]], 1.0);
+}
+// Incoming equivalent points.
+std::vector<double> in_equiv(const Level &lv, int slot) {
+    if (!lv.hf) return scaled(lv.cube, kRout * lv.r);
+    return rotated(lv.far, &lv.dirvec[3 * lv.active[slot]], -1.0);
+}
 
 void device_factors(HostPlan &hp, rocblas_handle h) {
     const int L = hp.depth;

@@ -974,47 +974,53 @@ __global__ void k_gather_reduce(const int32_t *dst, const int32_t *off, const in
     }
 }
 
-// y_leaf += T~ c_leaf (T~: n_L x kd, column-major per leaf).  256 threads
-// per leaf: rows are padded to a power of two npad <= 256 and the kd columns
-// are split over 256 / npad thread groups, whose partial sums are added in a
-// fixed order (the product is bound by reading T~ from HBM).
+// y_leaf += T~ c_leaf (T~: n_L x kd, column-major per leaf; on a
+// directional level kd counts every slot's columns, c_leaf being the box's
+// [slot][rank] states).  256 threads per leaf: rows are padded to a power of
+// two npad <= 256 and the kd columns are split over 256 / npad thread
+// groups, whose partial sums are added in a fixed order (the product is
+// bound by reading T~ from HBM).  c_leaf is staged in LDS in chunks of
+// kL2TChunk entries; a chunk is a multiple of the group count, so every
+// thread meets its columns in increasing order whatever the chunking.
 template <class C>
 __global__ void __launch_bounds__(256) k_l2t(const int64_t *leaf_off, const int32_t *ids, const int32_t *box,
                                              const int64_t *top, const C *Tm, int kd, const C *c, double2 *y,
                                              int64_t N, int64_t cstride) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    C *v = (C *)smem_raw;     // kd
-    C *part = v + kd;         // 256
+    const int kc = min(kd, kL2TChunk);
+    C *v = (C *)smem_raw;     // kc
+    C *part = v + kc;         // 256
     const int b = ids[blockIdx.x], t = threadIdx.x;
     const C *cr = c + (int64_t)blockIdx.y * cstride + (int64_t)box[blockIdx.x] * kd;
-    for (int j = t; j < kd; j += blockDim.x) v[j] = cr[j];
-    __syncthreads();
     const int64_t e0 = leaf_off[b];
-    const int nl = (int)(leaf_off[b + 1] - e0);
+    const int nl = (int)(leaf_off[b + 1] - e0);  // <= 256
     int npad = 1;
     while (npad < nl && npad < 256) npad <<= 1;
     const int G = 256 / npad;
     const int g = t / npad;
+    const int i = t % npad;
     const C *Tb = Tm + top[b];
     double2 *yr = y + (int64_t)blockIdx.y * N;
-    for (int i0 = 0; i0 < nl; i0 += npad) {
-        const int i = i0 + (t % npad);
-        C acc = czero<C>();
+    C acc = czero<C>();
+    for (int r0 = 0; r0 < kd; r0 += kc) {
+        const int r1 = min(kd, r0 + kc);
+        __syncthreads();  // the previous chunk is consumed
+        for (int j = r0 + t; j < r1; j += blockDim.x) v[j - r0] = cr[j];
+        __syncthreads();
         if (i < nl)
-            for (int r = g; r < kd; r += G) cmac(acc, Tb[i + (int64_t)r * nl], v[r]);
-        part[t] = acc;
-        __syncthreads();
-        if (t < npad && i < nl) {
-            C s = part[t];
-            for (int q = 1; q < G; ++q) {
-                const C u = part[t + q * npad];
-                s.x += u.x;
-                s.y += u.y;
-            }
-            double2 o = yr[e0 + i];
-            yr[e0 + i] = make_double2(o.x + (double)s.x, o.y + (double)s.y);
+            for (int r = r0 + g; r < r1; r += G) cmac(acc, Tb[i + (int64_t)r * nl], v[r - r0]);
+    }
+    part[t] = acc;
+    __syncthreads();
+    if (t < npad && i < nl) {
+        C s = part[t];
+        for (int q = 1; q < G; ++q) {
+            const C u = part[t + q * npad];
+            s.x += u.x;
+            s.y += u.y;
         }
-        __syncthreads();
+        double2 o = yr[e0 + i];
+        yr[e0 + i] = make_double2(o.x + (double)s.x, o.y + (double)s.y);
     }
 }
 
@@ -1437,9 +1443,10 @@ static hipError_t matvec_t(const DevPlan &d, const double2 *xt, double2 *yt, int
     for (int l = L; l >= top; --l) {
         const DevLevel &lf = d.lv[l];
         if (lf.nleaves == 0) continue;
+        // a leaf's states are [slot][rank]: one vector of nslot ku entries
         hipLaunchKernelGGL(k_s2m<C>, dim3(lf.nleaves, nrhs), dim3(128), sizeof(C) * d.max_leaf, st, d.leaf_off,
-                           lf.leaf_ids, lf.leaf_box, d.leaf_sop, (const C *)op.S, lf.ku, xt, (C *)lf.s, N,
-                           lf.sstride);
+                           lf.leaf_ids, lf.leaf_box, d.leaf_sop, (const C *)op.S, lf.nslot * lf.ku, xt, (C *)lf.s,
+                           N, lf.sstride);
         CHECK_LAUNCH();
     }
     if (ev) hipEventRecord(ev[2], st);
@@ -1481,9 +1488,10 @@ static hipError_t matvec_t(const DevPlan &d, const double2 *xt, double2 *yt, int
     for (int l = top; l <= L; ++l) {
         const DevLevel &lf = d.lv[l];
         if (lf.nleaves == 0) continue;
-        hipLaunchKernelGGL(k_l2t<C>, dim3(lf.nleaves, nrhs), dim3(256), sizeof(C) * (lf.kd + 256), st, d.leaf_off,
-                           lf.leaf_ids, lf.leaf_box, d.leaf_top, (const C *)d.T, lf.kd, (const C *)lf.c, yt, N,
-                           lf.cstride);
+        const int kd = lf.nslot * lf.kd;
+        hipLaunchKernelGGL(k_l2t<C>, dim3(lf.nleaves, nrhs), dim3(256), sizeof(C) * (std::min(kd, kL2TChunk) + 256),
+                           st, d.leaf_off, lf.leaf_ids, lf.leaf_box, d.leaf_top, (const C *)d.T, kd, (const C *)lf.c,
+                           yt, N, lf.cstride);
         CHECK_LAUNCH();
     }
     if (ev) hipEventRecord(ev[6], st);

@@ -157,8 +157,14 @@ void host_setup(const double *V, int64_t nv, const int32_t *T, int64_t nt, doubl
     // trees (Section 3.2) stop subdividing each box as soon as it qualifies,
     // with the largest edge among the box's own elements, so leaves sit on
     // many levels and every box is still at least leaf_min_h of its own
-    // largest edges wide; a directional box is always subdivided (leaves are
-    // non-directional).
+    // largest edges wide.  A leaf may sit on a directional level (Section
+    // 3.2, completely adaptive trees): its outgoing and incoming states are
+    // then kept per direction slot like those of any box of that level.  A
+    // directional box that can still be subdivided is subdivided, even when
+    // it holds few elements, since a directional leaf carries one S2M and
+    // one L2T operator per slot; it becomes a leaf when its children would
+    // be too narrow (coarse meshes at high frequency), and on a uniform tree
+    // whose leaf level is directional.
     const double tau = opt.leaf_min_h * h;
     auto width = [&](int l) { return side / std::ldexp(1.0, l); };
     auto hf_width = [&](int l) { return l > 0 && width(l) >= opt.hf_wavelengths * lambda * (1.0 - 1e-9); };
@@ -228,13 +234,7 @@ void host_setup(const double *V, int64_t nv, const int32_t *T, int64_t nt, doubl
             } else {
                 // children would be too narrow
                 const bool cannot = lv.w * 0.5 < opt.leaf_min_h * hbox[b] || l >= 20;
-                leaf = lv.nelem[b] <= opt.max_leaf || cannot;
-                if (leaf && hf_width(l)) {
-                    if (cannot)
-                        throw BuildError{FDA_EINVAL, "leaf boxes are directional (too few elements per wavelength "
-                                                     "for max_leaf); raise max_leaf or hf_wavelengths"};
-                    leaf = false;
-                }
+                leaf = cannot || (lv.nelem[b] <= opt.max_leaf && !hf_width(l));
             }
             if (leaf) lv.leaf[b] = 0;  // marked; numbered below
             else split = true;
@@ -333,10 +333,6 @@ void host_setup(const double *V, int64_t nv, const int32_t *T, int64_t nt, doubl
         lv.hf = lv.w >= opt.hf_wavelengths * lambda * (1.0 - 1e-9) && l > 0;
         if (lv.hf) finest_hf = l;
     }
-    for (int l = 0; l <= finest_hf; ++l)
-        if (hp.lv[l].hf && !hp.lv[l].leaves.empty())
-            throw BuildError{FDA_EINVAL, "leaf boxes are directional (too few elements per wavelength for max_leaf); "
-                                     "raise max_leaf or hf_wavelengths"};
     if (finest_hf >= 0) {
         int n0 = std::max(1, (int)std::lround(hp.lv[finest_hf].w / lambda));
         for (int l = 0; l <= finest_hf; ++l) {

@@ -127,8 +127,9 @@ def _model_tree(V, T, k, max_leaf=64, leaf_min_h=2.5, hf_wavelengths=1.9, adapti
         np.maximum.at(hbox, inv, emax[idx])
         cannot = (w * 0.5 < leaf_min_h * hbox) | (l >= 20)
         if adaptive:
-            leaf = ((cnt <= max_leaf) | cannot) & (not hf)
-            assert not np.any(hf & cannot)
+            # a directional box is subdivided unless its children would be
+            # too narrow (then it is a directional leaf)
+            leaf = ((cnt <= max_leaf) & (not hf)) | cannot
         else:
             leaf = np.full(len(ukey), l == Lu)
         for j in np.nonzero(leaf)[0]:
@@ -198,12 +199,24 @@ def _model_near_entries(leaves, side, lam, hf_wavelengths=1.9, rho_c=1.0):
     return int((n[T_[direct]] * n[S_[direct]]).sum())
 
 
+def _coarse_ellipsoid(i):
+    """Meshes of the seeded uneven batch whose leaves must sit on a
+    directional level: 5,120 triangles at kD 90 (i = 20) and 97 (i = 25),
+    about two elements per wavelength."""
+    V, T, k, info = W.uneven_batch(32)[i]
+    assert info["n"] == 5120 and info["kD"] > 90
+    return V, T, k
+
+
 @pytest.mark.parametrize("case,adaptive", [("graded3_kD10", 1), ("graded4_kD60", 1), ("sphere20480_kD50", 1),
-                                           ("sphere20480_kD50", 0), ("sphere20480_kD100", 0)])
+                                           ("sphere20480_kD50", 0), ("sphere20480_kD100", 0),
+                                           ("batch25", 0), ("batch25", 1), ("batch20", 1)])
 def test_tree_and_direct_pairs_match_an_independent_model(case, adaptive):
     if case.startswith("graded"):
         s, k = (3, 10.0) if case == "graded3_kD10" else (4, 60.0)
         V, T = W.graded_sphere(s)
+    elif case.startswith("batch"):
+        V, T, k = _coarse_ellipsoid(int(case[5:]))
     else:
         V, T, prm = W.workload(case)
         k = prm["k"]
@@ -228,4 +241,17 @@ def test_long_near_rows_are_planned():
     V, T = W.graded_sphere(3)
     st = _inspect(V, T, 10.0, max_leaf=256, adaptive=1)
     assert st["max_near_cols"] > 4096
+    assert st["near_nnz"] + st["far_elem_pairs"] == len(T) ** 2
+
+
+@pytest.mark.parametrize("i,adaptive", [(25, 0), (25, 1)])
+def test_directional_leaves_are_planned(i, adaptive):
+    """Coarse meshes at high frequency (Section 3.2): leaves on a
+    directional level, which keep one state per direction slot; every
+    ordered element pair is still reached exactly once."""
+    V, T, k = _coarse_ellipsoid(i)
+    st = _inspect(V, T, k, adaptive=adaptive)
+    hf_leaves = [l for l in range(st["depth"] + 1) if st["hf"][l] and st["leaves"][l] > 0]
+    assert hf_leaves, (st["hf"], st["leaves"])
+    assert all(st["active_dirs"][l] > 1 for l in hf_leaves)
     assert st["near_nnz"] + st["far_elem_pairs"] == len(T) ** 2
