@@ -294,63 +294,115 @@ __device__ __forceinline__ void cmac(C &acc, C a, C b) {
     acc.y = fma(a.x, b.y, fma(a.y, b.x, acc.y));
 }
 
-// y_tree[i] = sum over the near leaves of the block entries times x
-// (+ the FP64 self term diag[i] x[i] when the blocks are FP32).
+// Block order of a product over nrhs right-hand sides (a 1-D grid of
+// rhs_grid(n, nrhs) workgroups for n work items): workgroup b runs on XCD
+// b % 8 (round-robin dispatch), and the blocks of one work item for every
+// right-hand side follow each other on that XCD, so the item's operator is
+// read from HBM once and from the XCD's L2 for the other columns.  Items
+// t * 8 + x go to XCD x; with one right-hand side block b takes item b.
+struct RhsBlock {
+    int item, rhs;
+};
+__device__ __forceinline__ RhsBlock rhs_block(int nrhs) {
+    const int b = blockIdx.x, x = b & 7, j = b >> 3;
+    const int t = j / nrhs;
+    return {t * 8 + x, j - t * nrhs};
+}
+// The same order for work lists cut into one contiguous chunk of `per`
+// items per XCD (item x * per + t on XCD x).
+__device__ __forceinline__ RhsBlock rhs_block_chunked(int nrhs, int per) {
+    const int b = blockIdx.x, x = b & 7, j = b >> 3;
+    const int t = j / nrhs;
+    return {x * per + t, j - t * nrhs};
+}
+static inline dim3 rhs_grid(int64_t n, int nrhs) { return dim3((unsigned)(((n + 7) / 8) * 8 * nrhs)); }
+
+// Near field, S2M and L2T take R right-hand sides per workgroup (the
+// columns r0 .. r0 + R - 1 of group g = r0 / R): every operator entry is
+// read once and applied to the group's columns, which are staged in LDS as
+// R rows (no bank conflicts between lanes of one column index).  Each
+// column is summed in the same order whatever R, so a product of several
+// columns equals the single-column products bit for bit.
+
+// Row sum of a wave's partial products (lane 0 ends with the total).
 template <class C>
-__global__ void k_p2p(const int4 *items, const int64_t *leaf_off, const int32_t *nl_off, const int32_t *nl,
-                      const int64_t *blk_off, const C *vals, const double2 *diag, const double2 *x, double2 *y,
-                      int64_t N) {
+__device__ __forceinline__ C wave_sum(C acc) {
+    for (int o = 32; o > 0; o >>= 1) {
+        acc.x += __shfl_down(acc.x, o, 64);
+        acc.y += __shfl_down(acc.y, o, 64);
+    }
+    return acc;
+}
+
+// y_tree[i] = sum over the near leaves of the block entries times x
+// (+ the FP64 self term diag[i] x[i] when the blocks are FP32).  x of the
+// block's columns (listed in cols from col_off[leaf], the near leaves'
+// elements in order) is gathered into LDS in one parallel pass.
+template <class C, int R>
+__global__ void __launch_bounds__(256) k_p2p(const int4 *items, const int64_t *leaf_off, const int64_t *col_off,
+                                             const int32_t *cols, const int64_t *blk_off, const C *vals,
+                                             const double2 *diag, const double2 *x, double2 *y, int64_t N,
+                                             int nitems, int ngroups, int nrhs) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    C *xs = (C *)smem_raw;
-    const int4 it = items[blockIdx.x];  // (leaf, first row, end row, -)
+    C *xs = (C *)smem_raw;  // R x nc
+    const RhsBlock rb = rhs_block(ngroups);
+    if (rb.item >= nitems) return;
+    const int r0 = rb.rhs * R, nr = min(R, nrhs - r0);
+    const int4 it = items[rb.item];  // (leaf, first row, end row, -)
     const int b = it.x;
-    const double2 *xr = x + (int64_t)blockIdx.y * N;
-    double2 *yr = y + (int64_t)blockIdx.y * N;
-    int nc = 0;
-    for (int q = nl_off[b]; q < nl_off[b + 1]; ++q) {
-        int s = nl[q];
-        int64_t s0 = leaf_off[s];
-        int ns = (int)(leaf_off[s + 1] - s0);
-        for (int i = threadIdx.x; i < ns; i += blockDim.x) xs[nc + i] = cfrom<C>(xr[s0 + i]);
-        nc += ns;
+    const int64_t c0 = col_off[b];
+    const int nc = (int)(col_off[b + 1] - c0);
+    const int32_t *cl = cols + c0;
+    for (int e = threadIdx.x; e < R * nc; e += blockDim.x) {
+        const int r = e / nc, c = e - r * nc;
+        xs[e] = r < nr ? cfrom<C>(x[(int64_t)(r0 + r) * N + cl[c]]) : czero<C>();
     }
     __syncthreads();
     const int64_t t0 = leaf_off[b];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const C *blk = vals + blk_off[b];
     for (int i = it.y + wv; i < it.z; i += nw) {
-        C acc = czero<C>();
+        C acc[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] = czero<C>();
         const C *row = blk + (int64_t)i * nc;
-        for (int c = lane; c < nc; c += 64) cmac(acc, row[c], xs[c]);
-        for (int o = 32; o > 0; o >>= 1) {
-            acc.x += __shfl_down(acc.x, o, 64);
-            acc.y += __shfl_down(acc.y, o, 64);
+        for (int c = lane; c < nc; c += 64) {
+            const C v = row[c];
+#pragma unroll
+            for (int r = 0; r < R; ++r) cmac(acc[r], v, xs[r * nc + c]);
         }
-        if (lane == 0) {
-            double2 out = make_double2((double)acc.x, (double)acc.y);
-            if (diag) {
-                const double2 d = diag[t0 + i], v = xr[t0 + i];
-                out.x += d.x * v.x - d.y * v.y;
-                out.y += d.x * v.y + d.y * v.x;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            acc[r] = wave_sum(acc[r]);
+            if (lane == 0 && r < nr) {
+                double2 out = make_double2((double)acc[r].x, (double)acc[r].y);
+                if (diag) {
+                    const double2 d = diag[t0 + i], v = x[(int64_t)(r0 + r) * N + t0 + i];
+                    out.x += d.x * v.x - d.y * v.y;
+                    out.y += d.x * v.y + d.y * v.x;
+                }
+                y[(int64_t)(r0 + r) * N + t0 + i] = out;
             }
-            yr[t0 + i] = out;
         }
     }
 }
 
 // The same product for long rows (more than kP2PShortCols columns): x is
-// read through the row's column list (cols, from col_off[leaf]) instead of
-// being staged in LDS, so these workgroups need no LDS and keep full
-// occupancy (x is small enough to stay in L2).  Same summation order as
-// k_p2p, so the same result bit for bit.
-template <class C>
-__global__ void k_p2p_direct(const int4 *items, const int64_t *leaf_off, const int64_t *col_off,
-                             const int32_t *cols, const int64_t *blk_off, const C *vals, const double2 *diag,
-                             const double2 *x, double2 *y, int64_t N) {
-    const int4 it = items[blockIdx.x];  // (leaf, first row, end row, -)
+// read through the row's column list instead of being staged in LDS, so
+// these workgroups need no LDS and keep full occupancy (x is small enough
+// to stay in L2).  Same summation order as k_p2p, so the same result bit
+// for bit.
+template <class C, int R>
+__global__ void __launch_bounds__(256) k_p2p_direct(const int4 *items, const int64_t *leaf_off,
+                                                    const int64_t *col_off, const int32_t *cols,
+                                                    const int64_t *blk_off, const C *vals, const double2 *diag,
+                                                    const double2 *x, double2 *y, int64_t N, int nitems,
+                                                    int ngroups, int nrhs) {
+    const RhsBlock rb = rhs_block(ngroups);
+    if (rb.item >= nitems) return;
+    const int r0 = rb.rhs * R, nr = min(R, nrhs - r0);
+    const int4 it = items[rb.item];  // (leaf, first row, end row, -)
     const int b = it.x;
-    const double2 *xr = x + (int64_t)blockIdx.y * N;
-    double2 *yr = y + (int64_t)blockIdx.y * N;
     const int64_t c0 = col_off[b];
     const int nc = (int)(col_off[b + 1] - c0);
     const int32_t *cl = cols + c0;
@@ -358,44 +410,67 @@ __global__ void k_p2p_direct(const int4 *items, const int64_t *leaf_off, const i
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const C *blk = vals + blk_off[b];
     for (int i = it.y + wv; i < it.z; i += nw) {
-        C acc = czero<C>();
+        C acc[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] = czero<C>();
         const C *row = blk + (int64_t)i * nc;
-        for (int c = lane; c < nc; c += 64) cmac(acc, row[c], cfrom<C>(xr[cl[c]]));
-        for (int o = 32; o > 0; o >>= 1) {
-            acc.x += __shfl_down(acc.x, o, 64);
-            acc.y += __shfl_down(acc.y, o, 64);
+        for (int c = lane; c < nc; c += 64) {
+            const C v = row[c];
+            const int64_t j = cl[c];
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                cmac(acc[r], v, r < nr ? cfrom<C>(x[(int64_t)(r0 + r) * N + j]) : czero<C>());
         }
-        if (lane == 0) {
-            double2 out = make_double2((double)acc.x, (double)acc.y);
-            if (diag) {
-                const double2 d = diag[t0 + i], v = xr[t0 + i];
-                out.x += d.x * v.x - d.y * v.y;
-                out.y += d.x * v.y + d.y * v.x;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            acc[r] = wave_sum(acc[r]);
+            if (lane == 0 && r < nr) {
+                double2 out = make_double2((double)acc[r].x, (double)acc[r].y);
+                if (diag) {
+                    const double2 d = diag[t0 + i], v = x[(int64_t)(r0 + r) * N + t0 + i];
+                    out.x += d.x * v.x - d.y * v.y;
+                    out.y += d.x * v.y + d.y * v.x;
+                }
+                y[(int64_t)(r0 + r) * N + t0 + i] = out;
             }
-            yr[t0 + i] = out;
         }
     }
 }
 
 // s_leaf = S~ x_leaf, for the leaves of one level (ids: global leaf ids,
-// box: their boxes on the level, sop: offset of each leaf's S~)
-template <class C>
+// box: their boxes on the level, sop: offset of each leaf's S~), R
+// right-hand sides per workgroup.
+template <class C, int R>
 __global__ void k_s2m(const int64_t *leaf_off, const int32_t *ids, const int32_t *box, const int64_t *sop,
-                      const C *S, int ku, const double2 *x, C *s, int64_t N, int64_t sstride) {
+                      const C *S, int ku, const double2 *x, C *s, int64_t N, int64_t sstride, int nleaves,
+                      int ngroups, int nrhs) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    C *xs = (C *)smem_raw;
-    const int b = ids[blockIdx.x];
-    const double2 *xr = x + (int64_t)blockIdx.y * N;
+    C *xs = (C *)smem_raw;  // R x nl
+    const RhsBlock rb = rhs_block(ngroups);
+    if (rb.item >= nleaves) return;
+    const int r0 = rb.rhs * R, nr = min(R, nrhs - r0);
+    const int b = ids[rb.item];
     const int64_t e0 = leaf_off[b];
     const int nl = (int)(leaf_off[b + 1] - e0);
-    for (int i = threadIdx.x; i < nl; i += blockDim.x) xs[i] = cfrom<C>(xr[e0 + i]);
+    for (int e = threadIdx.x; e < R * nl; e += blockDim.x) {
+        const int r = e / nl, j = e - r * nl;
+        xs[e] = r < nr ? cfrom<C>(x[(int64_t)(r0 + r) * N + e0 + j]) : czero<C>();
+    }
     __syncthreads();
     const C *Sb = S + sop[b];
-    C *sr = s + (int64_t)blockIdx.y * sstride + (int64_t)box[blockIdx.x] * ku;
-    for (int r = threadIdx.x; r < ku; r += blockDim.x) {
-        C acc = czero<C>();
-        for (int j = 0; j < nl; ++j) cmac(acc, Sb[r + (int64_t)j * ku], xs[j]);
-        sr[r] = acc;
+    const int64_t so = (int64_t)box[rb.item] * ku;
+    for (int row = threadIdx.x; row < ku; row += blockDim.x) {
+        C acc[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] = czero<C>();
+        for (int j = 0; j < nl; ++j) {
+            const C v = Sb[row + (int64_t)j * ku];
+#pragma unroll
+            for (int r = 0; r < R; ++r) cmac(acc[r], v, xs[r * nl + j]);
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (r < nr) s[(int64_t)(r0 + r) * sstride + so + row] = acc[r];
     }
 }
 
@@ -606,18 +681,19 @@ struct GemmOcc<float2> {
 template <class C>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GemmOcc<C>::waves)))
 k_ggemm(const int4 *hdr, const int32_t *src, const C *A, int m, int kin, const C *X, int64_t xstride, C *T,
-        int64_t tstride, int nwork) {
+        int64_t tstride, int nwork, int nrhs) {
     __shared__ C S[GG_SJ][GG_LD];
     __shared__ C As[GG_SJ][GG_SLD];
     __shared__ int32_t sidx[GG_NB];
-    const int nx = 8;
-    const int per = gridDim.x / nx;
-    const int w = (blockIdx.x % nx) * per + blockIdx.x / nx;
+    // one contiguous chunk of the work list per XCD (consecutive items
+    // share their translation matrix)
+    const RhsBlock rb = rhs_block_chunked(nrhs, (nwork + 7) / 8);
+    const int w = rb.item;
     if (w >= nwork) return;
     const int4 h = hdr[w];  // (matrix, first scratch column, column count, 0)
     if (threadIdx.x < GG_NB) sidx[threadIdx.x] = src[(int64_t)w * GG_NB + threadIdx.x];
-    const C *Xr = X + (int64_t)blockIdx.y * xstride;
-    C *Tr = T + (int64_t)blockIdx.y * tstride + (int64_t)h.y * m;
+    const C *Xr = X + (int64_t)rb.rhs * xstride;
+    C *Tr = T + (int64_t)rb.rhs * tstride + (int64_t)h.y * m;
     const C *At = A + (int64_t)h.x * m * kin;
     if (h.z > 16)
         ggemm_body_staged<C, 2>(h, sidx, At, m, kin, Xr, Tr, S, As);
@@ -888,7 +964,8 @@ __device__ __forceinline__ void m2l_body(const int4 h, const int32_t *sidx, cons
 // (h.w) selects its factors, states and scratch region.
 template <class C, int VAR>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M2LOcc<C>::waves)))
-k_m2l_lowrank(const int4 *hdr, const int32_t *src, const M2LLevelArgs *args, C *T, int64_t tstride, int nwork) {
+k_m2l_lowrank(const int4 *hdr, const int32_t *src, const M2LLevelArgs *args, C *T, int64_t tstride, int nwork,
+              int nrhs) {
     // LDS: phase 1 stages S (LRJ x GG_LD) and V^ (LRJ x LR_LD); phase 2
     // reuses the same bytes for Z (LR_MAX x GG_LD) once phase 1 is done
     constexpr int kStage = M2LOcc<C>::direct ? 0 : LRJ * GG_LD + LRJ * LR_LD;
@@ -898,9 +975,10 @@ k_m2l_lowrank(const int4 *hdr, const int32_t *src, const M2LLevelArgs *args, C *
     C(*S)[GG_LD] = (C(*)[GG_LD])smem;
     C(*Vs)[LR_LD] = (C(*)[LR_LD])(smem + LRJ * GG_LD);
     C(*Z)[GG_LD] = (C(*)[GG_LD])smem;
-    // the host ordered the items for round-robin XCD dispatch (block b on
-    // XCD b % 8); empty items pad the queues
-    const int w = blockIdx.x;
+    // the host ordered the items for round-robin XCD dispatch (item t * 8 + x
+    // on XCD x); empty items pad the queues
+    const RhsBlock rb = rhs_block(nrhs);
+    const int w = rb.item;
     if (w >= nwork) return;
     const int4 h = hdr[w];
     if (h.z == 0) return;
@@ -909,8 +987,8 @@ k_m2l_lowrank(const int4 *hdr, const int32_t *src, const M2LLevelArgs *args, C *
     const int op = h.x;
     const int r = la.rank[op];
     if (threadIdx.x < GG_NB) sidx[threadIdx.x] = src[(int64_t)w * GG_NB + threadIdx.x];
-    const C *Xr = (const C *)la.X + (int64_t)blockIdx.y * la.xstride;
-    C *Tr = T + (int64_t)blockIdx.y * tstride + la.tbase + (int64_t)h.y * kd;
+    const C *Xr = (const C *)la.X + (int64_t)rb.rhs * la.xstride;
+    C *Tr = T + (int64_t)rb.rhs * tstride + la.tbase + (int64_t)h.y * kd;
     const C *Vt = (const C *)la.V + (int64_t)op * rmax * ((ku + 3) & ~3);
     const C *Ut = (const C *)la.U + (int64_t)op * kd * rmax;
     using V = M2LVariant<VAR>;
@@ -976,22 +1054,26 @@ __global__ void k_gather_reduce(const int32_t *dst, const int32_t *off, const in
 
 // y_leaf += T~ c_leaf (T~: n_L x kd, column-major per leaf; on a
 // directional level kd counts every slot's columns, c_leaf being the box's
-// [slot][rank] states).  256 threads per leaf: rows are padded to a power of
-// two npad <= 256 and the kd columns are split over 256 / npad thread
-// groups, whose partial sums are added in a fixed order (the product is
-// bound by reading T~ from HBM).  c_leaf is staged in LDS in chunks of
-// kL2TChunk entries; a chunk is a multiple of the group count, so every
-// thread meets its columns in increasing order whatever the chunking.
-template <class C>
+// [slot][rank] states), R right-hand sides per workgroup.  256 threads per
+// leaf: rows are padded to a power of two npad <= 256 and the kd columns
+// are split over 256 / npad thread groups, whose partial sums are added in
+// a fixed order (the product is bound by reading T~ from HBM).  c_leaf is
+// staged in LDS in chunks of kL2TChunk / R entries per column; a chunk is a
+// multiple of the group count, so every thread meets its columns in
+// increasing order whatever the chunking.
+template <class C, int R>
 __global__ void __launch_bounds__(256) k_l2t(const int64_t *leaf_off, const int32_t *ids, const int32_t *box,
                                              const int64_t *top, const C *Tm, int kd, const C *c, double2 *y,
-                                             int64_t N, int64_t cstride) {
+                                             int64_t N, int64_t cstride, int nleaves, int ngroups, int nrhs) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int kc = min(kd, kL2TChunk);
-    C *v = (C *)smem_raw;     // kc
-    C *part = v + kc;         // 256
-    const int b = ids[blockIdx.x], t = threadIdx.x;
-    const C *cr = c + (int64_t)blockIdx.y * cstride + (int64_t)box[blockIdx.x] * kd;
+    const int kc = min(kd, kL2TChunk / R);
+    C *v = (C *)smem_raw;     // R x kc
+    C *part = v + R * kc;     // R x 256
+    const RhsBlock rb = rhs_block(ngroups);
+    if (rb.item >= nleaves) return;
+    const int r0 = rb.rhs * R, nr = min(R, nrhs - r0);
+    const int b = ids[rb.item], t = threadIdx.x;
+    const int64_t co = (int64_t)box[rb.item] * kd;
     const int64_t e0 = leaf_off[b];
     const int nl = (int)(leaf_off[b + 1] - e0);  // <= 256
     int npad = 1;
@@ -1000,27 +1082,41 @@ __global__ void __launch_bounds__(256) k_l2t(const int64_t *leaf_off, const int3
     const int g = t / npad;
     const int i = t % npad;
     const C *Tb = Tm + top[b];
-    double2 *yr = y + (int64_t)blockIdx.y * N;
-    C acc = czero<C>();
-    for (int r0 = 0; r0 < kd; r0 += kc) {
-        const int r1 = min(kd, r0 + kc);
+    C acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = czero<C>();
+    for (int q0 = 0; q0 < kd; q0 += kc) {
+        const int q1 = min(kd, q0 + kc), nq = q1 - q0;
         __syncthreads();  // the previous chunk is consumed
-        for (int j = r0 + t; j < r1; j += blockDim.x) v[j - r0] = cr[j];
+        for (int e = t; e < R * nq; e += blockDim.x) {
+            const int r = e / nq, j = e - r * nq;
+            v[r * kc + j] = r < nr ? c[(int64_t)(r0 + r) * cstride + co + q0 + j] : czero<C>();
+        }
         __syncthreads();
         if (i < nl)
-            for (int r = r0 + g; r < r1; r += G) cmac(acc, Tb[i + (int64_t)r * nl], v[r - r0]);
+            for (int q = q0 + g; q < q1; q += G) {
+                const C m = Tb[i + (int64_t)q * nl];
+#pragma unroll
+                for (int r = 0; r < R; ++r) cmac(acc[r], m, v[r * kc + q - q0]);
+            }
     }
-    part[t] = acc;
+#pragma unroll
+    for (int r = 0; r < R; ++r) part[r * 256 + t] = acc[r];
     __syncthreads();
     if (t < npad && i < nl) {
-        C s = part[t];
-        for (int q = 1; q < G; ++q) {
-            const C u = part[t + q * npad];
-            s.x += u.x;
-            s.y += u.y;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (r >= nr) break;
+            C s = part[r * 256 + t];
+            for (int q = 1; q < G; ++q) {
+                const C u = part[r * 256 + t + q * npad];
+                s.x += u.x;
+                s.y += u.y;
+            }
+            double2 *yr = y + (int64_t)(r0 + r) * N;
+            double2 o = yr[e0 + i];
+            yr[e0 + i] = make_double2(o.x + (double)s.x, o.y + (double)s.y);
         }
-        double2 o = yr[e0 + i];
-        yr[e0 + i] = make_double2(o.x + (double)s.x, o.y + (double)s.y);
     }
 }
 
@@ -1329,8 +1425,8 @@ static hipError_t ggemm_t(const GWork &g, const void *A, int m, int kin, const v
     const int grid = (g.nwork + 7) / 8 * 8;
     const int64_t tstride = g.ncol * m;
     if (ev) hipEventRecord(ev[0], st);
-    hipLaunchKernelGGL(k_ggemm<C>, dim3(grid, nrhs), dim3(256), 0, st, g.hdr, g.src, (const C *)A, m, kin,
-                       (const C *)X, xstride, (C *)g.tmp, tstride, g.nwork);
+    hipLaunchKernelGGL(k_ggemm<C>, rhs_grid(grid, nrhs), dim3(256), 0, st, g.hdr, g.src, (const C *)A, m, kin,
+                       (const C *)X, xstride, (C *)g.tmp, tstride, g.nwork, nrhs);
     CHECK_LAUNCH();
     if (ev) hipEventRecord(ev[1], st);
     hipLaunchKernelGGL(k_gather_reduce<C>, dim3(g.nred, nrhs), dim3(std::min(256, ((m + 63) / 64) * 64)), 0, st,
@@ -1344,24 +1440,24 @@ static hipError_t ggemm_t(const GWork &g, const void *A, int m, int kin, const v
 // scratch columns into the incoming states.
 template <class C>
 static hipError_t m2l_merged_t(const M2LMerged &mm, int nrhs, hipStream_t st, hipEvent_t *ev) {
-    const dim3 g2(mm.nwork, nrhs);  // grid ordered for XCD dispatch (or translation order)
+    const dim3 g2 = rhs_grid(mm.nwork, nrhs);  // items ordered for XCD dispatch (or in translation order)
     if (ev) hipEventRecord(ev[0], st);
     switch (mm.variant) {
     case 1:
         hipLaunchKernelGGL((k_m2l_lowrank<C, 1>), g2, dim3(256), 0, st, mm.hdr, mm.src, mm.args, (C *)mm.tmp,
-                           mm.nscratch, mm.nwork);
+                           mm.nscratch, mm.nwork, nrhs);
         break;
     case 2:
         hipLaunchKernelGGL((k_m2l_lowrank<C, 2>), g2, dim3(256), 0, st, mm.hdr, mm.src, mm.args, (C *)mm.tmp,
-                           mm.nscratch, mm.nwork);
+                           mm.nscratch, mm.nwork, nrhs);
         break;
     case 3:
         hipLaunchKernelGGL((k_m2l_lowrank<C, 3>), g2, dim3(256), 0, st, mm.hdr, mm.src, mm.args, (C *)mm.tmp,
-                           mm.nscratch, mm.nwork);
+                           mm.nscratch, mm.nwork, nrhs);
         break;
     default:
         hipLaunchKernelGGL((k_m2l_lowrank<C, 0>), g2, dim3(256), 0, st, mm.hdr, mm.src, mm.args, (C *)mm.tmp,
-                           mm.nscratch, mm.nwork);
+                           mm.nscratch, mm.nwork, nrhs);
     }
     CHECK_LAUNCH();
     if (ev) hipEventRecord(ev[1], st);
@@ -1380,19 +1476,80 @@ template <class C>
 static hipError_t launch_p2p_t(const DevPlan &d, const NearFar &op, const double2 *xt, double2 *yt, int nrhs,
                                hipStream_t st) {
     const int ns = d.p2p_nshort, nl = d.p2p_nitems - d.p2p_nshort;
-    if (ns > 0) {
-        hipLaunchKernelGGL(k_p2p<C>, dim3(ns, nrhs), dim3(256), sizeof(C) * d.p2p_cols_short, st, d.p2p_items,
-                           d.leaf_off, d.nf_list_off, d.nf_list, d.nf_blk_off, (const C *)op.nf_vals,
-                           (const double2 *)op.nf_diag, xt, yt, d.n);
-        CHECK_LAUNCH();
+    // right-hand sides per workgroup: up to 8, with x of the short rows'
+    // columns for all of them in at most 64 KiB of LDS
+    int R = 1;
+    while (R < 8 && 2 * R <= nrhs && (size_t)2 * R * d.p2p_cols_short * sizeof(C) <= 65536) R *= 2;
+    const int ng = (nrhs + R - 1) / R;
+    auto go = [&](auto rc) -> hipError_t {
+        constexpr int RR = decltype(rc)::value;
+        if (ns > 0) {
+            hipLaunchKernelGGL((k_p2p<C, RR>), rhs_grid(ns, ng), dim3(256), sizeof(C) * RR * d.p2p_cols_short, st,
+                               d.p2p_items, d.leaf_off, d.nf_col_off, d.nf_cols, d.nf_blk_off, (const C *)op.nf_vals,
+                               (const double2 *)op.nf_diag, xt, yt, d.n, ns, ng, nrhs);
+            CHECK_LAUNCH();
+        }
+        if (nl > 0) {
+            hipLaunchKernelGGL((k_p2p_direct<C, RR>), rhs_grid(nl, ng), dim3(256), 0, st, d.p2p_items + ns,
+                               d.leaf_off, d.nf_col_off, d.nf_cols, d.nf_blk_off, (const C *)op.nf_vals,
+                               (const double2 *)op.nf_diag, xt, yt, d.n, nl, ng, nrhs);
+            CHECK_LAUNCH();
+        }
+        return hipSuccess;
+    };
+    switch (R) {
+    case 8: return go(std::integral_constant<int, 8>{});
+    case 4: return go(std::integral_constant<int, 4>{});
+    case 2: return go(std::integral_constant<int, 2>{});
+    default: return go(std::integral_constant<int, 1>{});
     }
-    if (nl > 0) {
-        hipLaunchKernelGGL(k_p2p_direct<C>, dim3(nl, nrhs), dim3(256), 0, st, d.p2p_items + ns, d.leaf_off,
-                           d.nf_col_off, d.nf_cols, d.nf_blk_off, (const C *)op.nf_vals, (const double2 *)op.nf_diag,
-                           xt, yt, d.n);
+}
+
+// Leaf S2M and L2T of one level for nrhs columns, up to 8 per workgroup.
+template <class C>
+static hipError_t launch_s2m_t(const DevPlan &d, const DevLevel &lf, const void *S, const double2 *xt, int nrhs,
+                               hipStream_t st) {
+    const int R = nrhs >= 8 ? 8 : nrhs >= 4 ? 4 : nrhs >= 2 ? 2 : 1;
+    const int ng = (nrhs + R - 1) / R;
+    const int ku = lf.nslot * lf.ku;  // a leaf's states are [slot][rank]: one vector of nslot ku entries
+    auto go = [&](auto rc) -> hipError_t {
+        constexpr int RR = decltype(rc)::value;
+        hipLaunchKernelGGL((k_s2m<C, RR>), rhs_grid(lf.nleaves, ng), dim3(128), sizeof(C) * RR * d.max_leaf, st,
+                           d.leaf_off, lf.leaf_ids, lf.leaf_box, d.leaf_sop, (const C *)S, ku, xt, (C *)lf.s, d.n,
+                           lf.sstride, lf.nleaves, ng, nrhs);
         CHECK_LAUNCH();
+        return hipSuccess;
+    };
+    switch (R) {
+    case 8: return go(std::integral_constant<int, 8>{});
+    case 4: return go(std::integral_constant<int, 4>{});
+    case 2: return go(std::integral_constant<int, 2>{});
+    default: return go(std::integral_constant<int, 1>{});
     }
-    return hipSuccess;
+}
+
+template <class C>
+static hipError_t launch_l2t_t(const DevPlan &d, const DevLevel &lf, const double2 *dummy, double2 *yt, int nrhs,
+                               hipStream_t st) {
+    (void)dummy;
+    const int R = nrhs >= 8 ? 8 : nrhs >= 4 ? 4 : nrhs >= 2 ? 2 : 1;
+    const int ng = (nrhs + R - 1) / R;
+    const int kd = lf.nslot * lf.kd;
+    auto go = [&](auto rc) -> hipError_t {
+        constexpr int RR = decltype(rc)::value;
+        const size_t lds = sizeof(C) * RR * (std::min(kd, kL2TChunk / RR) + 256);
+        hipLaunchKernelGGL((k_l2t<C, RR>), rhs_grid(lf.nleaves, ng), dim3(256), lds, st, d.leaf_off, lf.leaf_ids,
+                           lf.leaf_box, d.leaf_top, (const C *)d.T, kd, (const C *)lf.c, yt, d.n, lf.cstride,
+                           lf.nleaves, ng, nrhs);
+        CHECK_LAUNCH();
+        return hipSuccess;
+    };
+    switch (R) {
+    case 8: return go(std::integral_constant<int, 8>{});
+    case 4: return go(std::integral_constant<int, 4>{});
+    case 2: return go(std::integral_constant<int, 2>{});
+    default: return go(std::integral_constant<int, 1>{});
+    }
 }
 
 #ifndef FDA_NEAR_FORK
@@ -1443,11 +1600,8 @@ static hipError_t matvec_t(const DevPlan &d, const double2 *xt, double2 *yt, int
     for (int l = L; l >= top; --l) {
         const DevLevel &lf = d.lv[l];
         if (lf.nleaves == 0) continue;
-        // a leaf's states are [slot][rank]: one vector of nslot ku entries
-        hipLaunchKernelGGL(k_s2m<C>, dim3(lf.nleaves, nrhs), dim3(128), sizeof(C) * d.max_leaf, st, d.leaf_off,
-                           lf.leaf_ids, lf.leaf_box, d.leaf_sop, (const C *)op.S, lf.nslot * lf.ku, xt, (C *)lf.s,
-                           N, lf.sstride);
-        CHECK_LAUNCH();
+        const hipError_t e = launch_s2m_t<C>(d, lf, op.S, xt, nrhs, st);
+        if (e != hipSuccess) return e;
     }
     if (ev) hipEventRecord(ev[2], st);
     for (int l = L - 1; l >= top; --l) {
@@ -1488,11 +1642,8 @@ static hipError_t matvec_t(const DevPlan &d, const double2 *xt, double2 *yt, int
     for (int l = top; l <= L; ++l) {
         const DevLevel &lf = d.lv[l];
         if (lf.nleaves == 0) continue;
-        const int kd = lf.nslot * lf.kd;
-        hipLaunchKernelGGL(k_l2t<C>, dim3(lf.nleaves, nrhs), dim3(256), sizeof(C) * (std::min(kd, kL2TChunk) + 256),
-                           st, d.leaf_off, lf.leaf_ids, lf.leaf_box, d.leaf_top, (const C *)d.T, kd, (const C *)lf.c,
-                           yt, N, lf.cstride);
-        CHECK_LAUNCH();
+        const hipError_t e = launch_l2t_t<C>(d, lf, xt, yt, nrhs, st);
+        if (e != hipSuccess) return e;
     }
     if (ev) hipEventRecord(ev[6], st);
     return hipSuccess;
