@@ -363,13 +363,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fast", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the M2L launch autotuner (fda_autotune) after the build")
-    ap.add_argument("--no-paper-threshold", action="store_true",
-                    help="skip the FP64 arm with the reduced M2L matrices truncated at eps (eq. (eq_epsk))")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run one plain device copy of this many MiB (calibrates HBM counters)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--nrhs-multi", type=int, default=64, help="also time products of this many columns (0: skip)")
-    ap.add_argument("--batch", type=int, default=0,
+    ap.add_argument("--batch", type=int, default=32,
                     help="also time the uneven multi-mesh batch of this many meshes in one graph (0: skip)")
     ap.add_argument("--mlp-weights", default=os.path.join(ROOT, "paper_1403_4747_amd", "weights",
                                                           "mlp_ellipsoid_s5_h256.npz"),
@@ -403,7 +401,8 @@ def main():
     n, k = len(T), prm["k"]
     log(f"[bench] workload {args.workload}: N={n} k={k}")
     t0 = time.perf_counter()
-    plan = Plan(V, T, k, prm["eps"])
+    popt = prm.get("plan", {})  # build options of the workload's configuration
+    plan = Plan(V, T, k, prm["eps"], **popt)
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
     st = plan.stats()
@@ -460,6 +459,24 @@ def main():
                      col0_rel_diff_vs_single=float(torch.linalg.norm(ym[0] - y0) / torch.linalg.norm(y0)))
         log(f"[bench] nrhs={args.nrhs_multi}: {multi}")
         del xm, ym
+        if not args.no_solve:
+            # plane waves from nrhs_multi directions on a Fibonacci sphere,
+            # solved together (one product of all unconverged columns per
+            # GMRES step; each column stops on its own residual)
+            dirs = W.fibonacci_directions(args.nrhs_multi)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            bm = plan.rhs_planewave(dirs)
+            um, info = plan.solve(bm, tol=1e-5, restart=50, maxit=2000)
+            torch.cuda.synchronize()
+            multi["solve"] = dict(directions=args.nrhs_multi, seconds=round(time.perf_counter() - t0, 4),
+                                  products=info["iterations"], converged=info["converged"],
+                                  rel_residual_max=info["rel_residual"],
+                                  column_iterations_max=max(info["col_iterations"]),
+                                  column_iterations_mean=round(float(np.mean(info["col_iterations"])), 2))
+            log(f"[bench] {args.nrhs_multi}-direction solve: {multi['solve']}")
+            del bm, um
+            torch.cuda.empty_cache()
 
     if args.calib_copy_mb > 0:
         # one elementwise kernel that reads and writes calib_copy_mb MiB each
@@ -530,7 +547,7 @@ def main():
     # fast arm: FP32 storage and FP32 matrix cores, FP64 self terms and Arnoldi
     fast = {}
     if not args.no_fast:
-        plan32 = Plan(V, T, k, prm["eps"], prec="fp32")
+        plan32 = Plan(V, T, k, prm["eps"], prec="fp32", **popt)
         tune32 = None if args.no_tune else plan32.autotune(reps=20)
         y32 = torch.empty_like(x)
         for _ in range(args.warmup):
@@ -575,44 +592,6 @@ def main():
         plan32.close()
         log("[bench] fast arm: " + str({q: v for q, v in fast.items() if q != 'y32'}))
 
-    # the same FP64 plan with the reduced M2L matrices truncated at eps, the
-    # paper's threshold (the default plans truncate every SVD at eps / 10)
-    paper = {}
-    if not args.no_paper_threshold:
-        planp = Plan(V, T, k, prm["eps"], m2l_svd_eps=prm["eps"])
-        stp = planp.stats()
-        if not args.no_tune:
-            planp.autotune(reps=20)
-        yp = torch.empty_like(x)
-        for _ in range(args.warmup):
-            planp.matvec(x, out=yp)
-        torch.cuda.synchronize()
-        e0.record(stream)
-        for _ in range(args.steps):
-            planp.matvec(x, out=yp)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        msp = e0.elapsed_time(e1) / args.steps
-        profp = planp.profile(x, reps=max(3, min(20, args.steps)), out=yp)
-        paper = dict(m2l_svd_eps=prm["eps"], matvecs_per_s=round(1000.0 / msp, 3), ms_per_matvec=round(msp, 4),
-                     m2l_flops_per_matvec=stp["m2l_flops"], m2l_rank_mean=[round(v, 1) for v in stp["m2l_rank_mean"]],
-                     m2l_lowrank_ms=round(profp["m2l_lowrank"], 4))
-        if profp["m2l_lowrank"] > 0:
-            ap_ = stp["m2l_flops"] / (profp["m2l_lowrank"] * 1e-3) / 1e12
-            paper["m2l_roofline"] = dict(achieved=round(ap_, 3), peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
-                                         frac=round(ap_ / FP64_PEAK_TFLOPS, 4))
-        if not args.no_solve:
-            bp = planp.rhs_planewave(prm["direction"])
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            _, info = planp.solve(bp, tol=1e-5, restart=50, maxit=2000)
-            torch.cuda.synchronize()
-            paper["solve_none"] = dict(seconds=round(time.perf_counter() - t0, 4), iterations=info["iterations"],
-                                       converged=info["converged"])
-        paper["y"] = yp.cpu().numpy()
-        planp.close()
-        log("[bench] paper M2L threshold arm: " + str({q: v for q, v in paper.items() if q != "y"}))
-
     batch = {}
     if args.batch > 0:
         batch = uneven_batch_leg(args.batch, args.steps, log, tune=not args.no_tune)
@@ -623,10 +602,7 @@ def main():
         log(f"[bench] cpu baseline {cpu}, sampled-row rel err {err:.3e}")
         if "y32" in fast:
             fast["matvec_rel_err_vs_oracle_sampled"] = float(np.linalg.norm(fast["y32"][rows] - yr) / np.linalg.norm(yr))
-        if "y" in paper:
-            paper["matvec_rel_err_vs_oracle_sampled"] = float(np.linalg.norm(paper["y"][rows] - yr) / np.linalg.norm(yr))
     fast.pop("y32", None)
-    paper.pop("y", None)
 
     out = {
         "metric": "FDA matvecs/s (N=81,920, kD=100); GMRES time-to-1e-5 reported alongside",
@@ -642,7 +618,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "N": n, "k": k, "kD": k * 2 * prm["radius"],
-                   "eps": prm["eps"], "nrhs": 1, "arm": "plain FP64"},
+                   "eps": prm["eps"], "svd_eps": popt.get("svd_eps", prm["eps"] / 10),
+                   "nrhs": 1, "arm": "plain FP64"},
         "build_seconds": round(build_s, 3),
         "m2l_autotune": tune,
         "build_phase_seconds": [round(v, 3) for v in st["build_phase_seconds"][:7]],
@@ -656,7 +633,6 @@ def main():
         "solve": solve,
         "matvec_rel_err_vs_oracle_sampled": err,
         "fast_arm_fp32": fast or None,
-        "fp64_paper_m2l_threshold": paper or None,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -7,6 +7,13 @@ import numpy as np
 # rows can hide: every entry within 1e-3 of the largest oracle entry.
 MATVEC_TOL = 1e-4
 ROW_TOL = 1e-3
+# Regression bounds: a few times the measured error, so that a loss of
+# accuracy well inside the specification still fails.  Default plans (SVD
+# truncation at eps / 10): 2e-6 to 5e-6 on the 1,280- to 81,920-triangle
+# spheres; plans truncated at the paper's eps (eqs. (eq_epsg), (eq_epsk)),
+# the benchmark's headline configuration: 1.6e-5 to 2.8e-5.
+REGRESS = 2e-5
+REGRESS_EPS = 6e-5
 
 
 def rel_err(y, yr):

@@ -215,4 +215,4 @@ def test_near_rows_longer_than_4096_columns():
             assert st["max_near_cols"] > 4096
             y = p.matvec(_dev(x)).cpu().numpy()
         _say(prec, "max cols", st["max_near_cols"], "rel err", P.rel_err(y, yr))
-        P.check(y, yr, regress=2e-5)
+        P.check(y, yr, regress=P.REGRESS)

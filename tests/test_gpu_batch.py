@@ -54,7 +54,7 @@ def test_batch_graph_replays_equal_the_single_products():
         yr = O.matvec(V, T, k, xs[i].cpu().numpy().T if nr > 1 else xs[i].cpu().numpy())
         yr = yr.T if nr > 1 else yr
         _say(f"mesh {i}: N={len(T)} {prec} rel err {P.rel_err(want[i], yr):.2e}")
-        P.check(want[i], yr, regress=2e-5)
+        P.check(want[i], yr, regress=P.REGRESS)
     b = Batch(plans, xs, ys)
     for rep in range(3):
         for y in ys:

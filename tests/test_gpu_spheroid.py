@@ -52,5 +52,5 @@ def test_spheroid_kD250_matches_oracle_and_solves(prec):
         _ORACLE["yr"] = O.matvec(V, T, k, x, row_idx=rows)
     yr = _ORACLE["yr"]
     _say("rel err", P.rel_err(y[rows], yr), "row err", P.row_err(y[rows], yr), "its", info["iterations"])
-    P.check(y[rows], yr, regress=2e-5)
+    P.check(y[rows], yr, regress=P.REGRESS)
     assert info["converged"] and info["iterations"] < 100

@@ -214,7 +214,10 @@ def complex_normal(n: int, nrhs: int = 1, seed: int = 0) -> np.ndarray:
 # GMRES(50) to a relative residual of 1e-5.
 WORKLOADS = {
     "sphere1280_kD10": dict(subdiv=3, radius=0.5, k=10.0, eps=1e-4, direction=(0.0, 0.0, 1.0)),
-    "sphere81920_kD100": dict(subdiv=6, radius=0.5, k=100.0, eps=1e-4, direction=(0.0, 0.0, 1.0)),
+    # the headline configuration: every SVD truncated at the paper's eps
+    # (eqs. (eq_epsg), (eq_epsk)) instead of the library's default eps / 10
+    "sphere81920_kD100": dict(subdiv=6, radius=0.5, k=100.0, eps=1e-4, direction=(0.0, 0.0, 1.0),
+                              plan=dict(svd_eps=1e-4)),
     "sphere5120_kD20": dict(subdiv=4, radius=0.5, k=20.0, eps=1e-4, direction=(0.0, 0.0, 1.0)),
     "sphere20480_kD50": dict(subdiv=5, radius=0.5, k=50.0, eps=1e-4, direction=(0.0, 0.0, 1.0)),
     "sphere20480_kD100": dict(subdiv=5, radius=0.5, k=100.0, eps=1e-4, direction=(0.0, 0.0, 1.0)),
