@@ -571,7 +571,7 @@ void upload_plan(fda_plan *p, const HostOps &ops, DevTranslations &tr) {
             for (int64_t b = 0; b < lv.nbox; ++b)
                 for (size_t q = 0; q < lv.il[b].size(); ++q) {
                     int op = lv.il_ops[b][q];
-                    int sl = lv.hf ? lv.slot_of_dir[lv.offset_dir[op]] : 0;
+                    int sl = lv.il_slots[b][q];
                     by_op[op].push_back({(int32_t)(lv.il[b][q] * lv.nslot + sl), (int32_t)(b * lv.nslot + sl)});
                 }
             // the low-rank kernel holds at most 8 phase-1 tiles per item:

@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <unordered_map>
 
 #include "dsetup.hpp"
 
@@ -209,15 +210,51 @@ Mat padded(const Mat &M, int padc, const std::vector<double> *inv_scale) {
 
 }  // namespace
 
-// Outgoing check points of a level / slot, relative to the box centre.
+// Outgoing check points of a level / slot, relative to the box centre: on a
+// directional level the cone far set turned to the slot's orbit
+// representative, then carried onto the slot by its cube symmetry.
+static std::vector<double> cone_points(const Level &lv, int slot, double sign) {
+    const int r = lv.rep_slot.empty() ? slot : lv.rep_slot[slot];
+    const int g = lv.sym.empty() ? 0 : lv.sym[slot];
+    std::vector<double> X = rotated(lv.far, &lv.dirvec[3 * lv.active[r]], sign);
+    for (size_t i = 0; i < X.size() / 3; ++i) {
+        double w[3];
+        cube_sym_apply(g, &X[3 * i], w);
+        for (int a = 0; a < 3; ++a) X[3 * i + a] = w[a];
+    }
+    return X;
+}
 std::vector<double> out_check(const Level &lv, int slot) {
     if (!lv.hf) return scaled(lv.cube, kRout * lv.r);
-    return rotated(lv.far, &lv.dirvec[3 * lv.active[slot]], 1.0);
+    return cone_points(lv, slot, 1.0);
 }
-// Incoming equivalent points.
+// Incoming equivalent points: the outgoing check points reflected through
+// the centre.
 std::vector<double> in_equiv(const Level &lv, int slot) {
     if (!lv.hf) return scaled(lv.cube, kRout * lv.r);
-    return rotated(lv.far, &lv.dirvec[3 * lv.active[slot]], -1.0);
+    return cone_points(lv, slot, -1.0);
+}
+
+// Permutation of the cube-surface points (p per edge) under cube symmetry
+// g: point k goes to point perm[k].
+static std::vector<int> cube_perm(const std::vector<double> &cube, int p, int g) {
+    const int n = (int)cube.size() / 3;
+    auto key = [&](const double *x) {
+        int64_t k = 0;
+        for (int a = 0; a < 3; ++a) k = k * 4096 + (int64_t)std::lround((x[a] + 1.0) * 0.5 * (p - 1));
+        return k;
+    };
+    std::unordered_map<int64_t, int> idx;
+    for (int k = 0; k < n; ++k) idx[key(&cube[3 * k])] = k;
+    std::vector<int> perm(n);
+    for (int k = 0; k < n; ++k) {
+        double w[3];
+        cube_sym_apply(g, &cube[3 * k], w);
+        auto it = idx.find(key(w));
+        if (it == idx.end()) throw BuildError{FDA_EINVAL, "internal: cube points not symmetric"};
+        perm[k] = it->second;
+    }
+    return perm;
 }
 
 void device_factors(HostPlan &hp, rocblas_handle h) {
@@ -248,18 +285,26 @@ void device_factors(HostPlan &hp, rocblas_handle h) {
         const int nc = (int)lv.cube.size() / 3;
         std::vector<int> negp(nc);
         for (int i = 0; i < nc; ++i) negp[i] = nc - 1 - i;
-        // G_up for every slot, batched
-        std::vector<double> X0 = out_check(lv, 0);
+        // G_up for every orbit representative slot, batched; the other slots
+        // take their representative's factors carried over by their cube
+        // symmetry g: their check points are g X_rep, so G_up,s = G_up,rep
+        // with its columns (equivalent points) permuted, and V_up,s is
+        // V_up,rep with its rows permuted the same way
+        std::vector<int> reps;
+        for (int s = 0; s < lv.nslot; ++s)
+            if (lv.rep_slot.empty() || lv.rep_slot[s] == s) reps.push_back(s);
+        const int nrep = (int)reps.size();
+        std::vector<double> X0 = out_check(lv, reps[0]);
         const int m = (int)X0.size() / 3;
         DBuf dY = to_dev(scaled(lv.cube, kRin * lv.r));
-        DBuf G(sizeof(double2) * (size_t)lv.nslot * m * nc);
-        for (int s = 0; s < lv.nslot; ++s) {
-            DBuf dX = to_dev(out_check(lv, s));
-            green_batched(dX, m, dY, nc, {0.0, 0.0, 0.0}, k, G.as<double2>() + (size_t)s * m * nc);
+        DBuf G(sizeof(double2) * (size_t)nrep * m * nc);
+        for (int i = 0; i < nrep; ++i) {
+            DBuf dX = to_dev(out_check(lv, reps[i]));
+            green_batched(dX, m, dY, nc, {0.0, 0.0, 0.0}, k, G.as<double2>() + (size_t)i * m * nc);
         }
         std::vector<double> S;
         std::vector<cplx> U, Vh;
-        svd_batched(h, hp.opt.svd_method, G.as<double2>(), m, nc, lv.nslot, S, U, Vh);
+        svd_batched(h, hp.opt.svd_method, G.as<double2>(), m, nc, nrep, S, U, Vh);
         lv.Uu.assign(lv.nslot, Mat());
         lv.Vu.assign(lv.nslot, Mat());
         lv.Ud.assign(lv.nslot, Mat());
@@ -268,28 +313,51 @@ void device_factors(HostPlan &hp, rocblas_handle h) {
         lv.sd.assign(lv.nslot, {});
         lv.ku_s.assign(lv.nslot, 0);
         lv.kd_s.assign(lv.nslot, 0);
-        for (int s = 0; s < lv.nslot; ++s) {
-            const double *Ss = S.data() + (size_t)s * nc;
-            int r = trunc_rank(Ss, nc, hp.svd_eps);
-            Mat Uu(m, r), Vu(nc, r), Ud(nc, r), Vd(m, r);
-            const cplx *Us = U.data() + (size_t)s * m * nc;
-            const cplx *Vs = Vh.data() + (size_t)s * nc * nc;  // V^H, n x n column-major
+        // G_dn = Pi G_up^T: U_dn = Pi conj(V_up), V_dn = conj(U_up)
+        auto set_dn = [&](int s) {
+            const int r = lv.Uu[s].n;
+            Mat Ud(nc, r), Vd(m, r);
             for (int j = 0; j < r; ++j) {
-                for (int i = 0; i < m; ++i) Uu(i, j) = Us[i + (size_t)j * m];
-                for (int i = 0; i < nc; ++i) Vu(i, j) = std::conj(Vs[j + (size_t)i * nc]);
+                for (int i = 0; i < nc; ++i) Ud(i, j) = std::conj(lv.Vu[s](lv.hf ? negp[i] : i, j));
+                for (int i = 0; i < m; ++i) Vd(i, j) = std::conj(lv.Uu[s](i, j));
             }
-            // G_dn = Pi G_up^T: U_dn = Pi conj(V_up), V_dn = conj(U_up)
+            lv.Ud[s] = std::move(Ud);
+            lv.Vd[s] = std::move(Vd);
+        };
+        for (int i = 0; i < nrep; ++i) {
+            const int s = reps[i];
+            const double *Ss = S.data() + (size_t)i * nc;
+            int r = trunc_rank(Ss, nc, hp.svd_eps);
+            Mat Uu(m, r), Vu(nc, r);
+            const cplx *Us = U.data() + (size_t)i * m * nc;
+            const cplx *Vs = Vh.data() + (size_t)i * nc * nc;  // V^H, n x n column-major
             for (int j = 0; j < r; ++j) {
-                for (int i = 0; i < nc; ++i) Ud(i, j) = std::conj(Vu(lv.hf ? negp[i] : i, j));
-                for (int i = 0; i < m; ++i) Vd(i, j) = std::conj(Uu(i, j));
+                for (int q = 0; q < m; ++q) Uu(q, j) = Us[q + (size_t)j * m];
+                for (int q = 0; q < nc; ++q) Vu(q, j) = std::conj(Vs[j + (size_t)q * nc]);
             }
             lv.Uu[s] = std::move(Uu);
             lv.Vu[s] = std::move(Vu);
-            lv.Ud[s] = std::move(Ud);
-            lv.Vd[s] = std::move(Vd);
             lv.su[s].assign(Ss, Ss + r);
             lv.sd[s] = lv.su[s];
             lv.ku_s[s] = lv.kd_s[s] = r;
+            set_dn(s);
+        }
+        for (int s = 0; s < lv.nslot; ++s) {
+            if (lv.rep_slot.empty() || lv.rep_slot[s] == s) continue;
+            const int rs = lv.rep_slot[s];
+            // G(g X, Y_j) = G(X, g^-1 Y_j): column j of G_up,s is column
+            // perm^-1(j) of G_up,rep, where g Y_k = Y_perm(k)
+            const std::vector<int> perm = cube_perm(lv.cube, lv.p, lv.sym[s]);
+            const Mat &Vr = lv.Vu[rs];
+            Mat Vu(nc, Vr.n);
+            for (int j = 0; j < Vr.n; ++j)
+                for (int q = 0; q < nc; ++q) Vu(perm[q], j) = Vr(q, j);
+            lv.Uu[s] = lv.Uu[rs];
+            lv.Vu[s] = std::move(Vu);
+            lv.su[s] = lv.su[rs];
+            lv.sd[s] = lv.sd[rs];
+            lv.ku_s[s] = lv.kd_s[s] = lv.ku_s[rs];
+            set_dn(s);
         }
         lv.ku = *std::max_element(lv.ku_s.begin(), lv.ku_s.end());
         lv.kd = lv.ku;

@@ -31,7 +31,8 @@ struct Level {
     std::vector<std::vector<int32_t>> near, il;  // near list and interaction list (sources) per box
     std::vector<std::vector<int32_t>> near_up;   // coarser leaves adjacent to the box (global leaf ids)
     std::vector<int32_t> il_op;           // per (box, il entry) flattened: distinct-offset index
-    std::vector<std::vector<int32_t>> il_ops;
+    std::vector<std::vector<int32_t>> il_ops;  // per (box, il entry): translation index
+    std::vector<std::vector<int32_t>> il_slots;  // per (box, il entry): direction slot of the pair
     std::vector<std::array<int32_t, 3>> offsets;  // distinct offsets (target - source) of this level
     std::vector<int32_t> offset_dir;      // direction of each distinct offset (-1 when non-directional)
     // directional bookkeeping
@@ -51,7 +52,28 @@ struct Level {
     std::vector<int> ku_s, kd_s;
     // towards level + 1: child slot of each slot, and the slots feeding each child slot
     std::vector<int32_t> cslot, l2l_off, l2l_src;
+    // directional levels: the slots fall into orbits of the cube's symmetry
+    // group; each slot's check set, SVD factors and translations are those
+    // of its orbit's representative slot carried over by one symmetry
+    // (Section 3.1, rotational invariance): rep_slot[s] and sym[s] with
+    // cube_sym(sym[s]) mapping the representative's direction to slot s's
+    std::vector<int32_t> rep_slot, sym;
 };
+
+// The 48 symmetries of the cube (signed permutations of the axes): symmetry
+// g = 8 q + b takes v to w with w[a] = (bit a of b ? -1 : 1) v[perm_q[a]].
+constexpr int kCubeSyms = 48;
+inline void cube_sym_apply(int g, const double *v, double *w) {
+    static const int perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+    const int *pq = perm[g / 8];
+    for (int a = 0; a < 3; ++a) w[a] = ((g >> a) & 1 ? -1.0 : 1.0) * v[pq[a]];
+}
+// the inverse (transpose) of cube_sym_apply(g)
+inline void cube_sym_apply_inv(int g, const double *w, double *v) {
+    static const int perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+    const int *pq = perm[g / 8];
+    for (int a = 0; a < 3; ++a) v[pq[a]] = ((g >> a) & 1 ? -1.0 : 1.0) * w[a];
+}
 
 struct HostPlan {
     int64_t n = 0;

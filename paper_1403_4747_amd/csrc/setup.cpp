@@ -534,6 +534,32 @@ void host_setup(const double *V, int64_t nv, const int32_t *T, int64_t nt, doubl
         if (lv.active.empty()) lv.active = {0}, lv.slot_of_dir[0] = 0;
     }
 
+    // orbits of the active directions under the cube's symmetries (Section
+    // 3.1: the directional point sets and translations are rotations of one
+    // another).  The directions are the cell centres of an n x n grid on
+    // each cube face, a set the 48 symmetries permute; each orbit's
+    // representative is its first active direction, and every slot keeps
+    // the symmetry that carries the representative's direction onto its own.
+    for (int l = 0; l <= L; ++l) {
+        Level &lv = hp.lv[l];
+        lv.rep_slot.assign(lv.nslot, 0);
+        lv.sym.assign(lv.nslot, 0);
+        if (!lv.hf) continue;
+        for (int s = 0; s < lv.nslot; ++s) {
+            lv.rep_slot[s] = s;
+            const double *u = &lv.dirvec[3 * lv.active[s]];
+            for (int g = 0; g < kCubeSyms && lv.rep_slot[s] == s; ++g) {
+                double w[3];
+                cube_sym_apply_inv(g, u, w);  // a direction that g carries onto u
+                const int r = lv.slot_of_dir[dir_index(w, lv.nface)];
+                if (r >= 0 && r < s && lv.rep_slot[r] == r) {
+                    lv.rep_slot[s] = r;
+                    lv.sym[s] = g;
+                }
+            }
+        }
+    }
+
     // far point sets of the directional levels (top-down), Section 3.1:
     // a circular cone around +z whose half angle covers every possible
     // interaction-list target box and the parent's cone, from the nearest
@@ -628,6 +654,54 @@ void host_setup(const double *V, int64_t nv, const int32_t *T, int64_t nt, doubl
         lv.offset_dir.swap(odir);
         for (auto &ops : lv.il_ops)
             for (auto &o : ops) o = newidx[o];
+    }
+
+    // translations shared by symmetry: on a directional level the reduced
+    // M2L matrix of offset t in slot s equals that of offset g^-1 t in the
+    // representative slot (g = sym[s]), since both the point sets and the
+    // SVD factors of slot s are the representative's carried over by g; the
+    // level keeps one translation per distinct (g^-1 t, representative),
+    // numbered representative by representative
+    for (int l = 0; l <= L; ++l) {
+        Level &lv = hp.lv[l];
+        lv.il_slots.assign(lv.nbox, {});
+        for (int64_t b = 0; b < lv.nbox; ++b)
+            for (int32_t op : lv.il_ops[b]) lv.il_slots[b].push_back(lv.hf ? lv.slot_of_dir[lv.offset_dir[op]] : 0);
+        if (!lv.hf || lv.offsets.empty()) continue;
+        const size_t no = lv.offsets.size();
+        std::map<std::pair<int32_t, std::array<int32_t, 3>>, int32_t> canon;
+        std::vector<std::pair<int32_t, std::array<int32_t, 3>>> keys;
+        std::vector<int32_t> cidx(no);
+        for (size_t o = 0; o < no; ++o) {
+            const int s = lv.slot_of_dir[lv.offset_dir[o]];
+            const double t[3] = {(double)lv.offsets[o][0], (double)lv.offsets[o][1], (double)lv.offsets[o][2]};
+            double tc[3];
+            cube_sym_apply_inv(lv.sym[s], t, tc);
+            const std::pair<int32_t, std::array<int32_t, 3>> key = {
+                lv.rep_slot[s], {(int32_t)std::lround(tc[0]), (int32_t)std::lround(tc[1]), (int32_t)std::lround(tc[2])}};
+            auto it = canon.find(key);
+            if (it == canon.end()) {
+                it = canon.emplace(key, (int32_t)keys.size()).first;
+                keys.push_back(key);
+            }
+            cidx[o] = it->second;
+        }
+        // number the distinct translations by representative slot
+        std::vector<int32_t> ord(keys.size());
+        std::iota(ord.begin(), ord.end(), 0);
+        std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) { return keys[a].first < keys[b].first; });
+        std::vector<int32_t> pos(keys.size());
+        std::vector<std::array<int32_t, 3>> offs(keys.size());
+        std::vector<int32_t> odir(keys.size());
+        for (size_t q = 0; q < ord.size(); ++q) {
+            pos[ord[q]] = (int32_t)q;
+            offs[q] = keys[ord[q]].second;
+            odir[q] = lv.active[keys[ord[q]].first];
+        }
+        lv.offsets.swap(offs);
+        lv.offset_dir.swap(odir);
+        for (auto &ops : lv.il_ops)
+            for (auto &o : ops) o = pos[cidx[o]];
     }
 
     // child slot of every slot (M2M source, L2L target) and its inverse
