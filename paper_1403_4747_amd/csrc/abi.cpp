@@ -400,6 +400,14 @@ void build_m2l_list(fda_plan *p, M2LMerged &mm, std::vector<void *> &fresh) {
     mm.nwork = (int)(hdr.size() / 4);
     mm.nred = (int)dst.size();
     mm.nlev = (int)args.size();
+    // reduction blocks per level: kRedRows (state, row) entries each
+    std::vector<int32_t> rblock{0}, rstate{0};
+    for (size_t q = 0; q < args.size(); ++q) {
+        const int64_t ns = p->m2l_host[q].nstates, entries = ns * args[q].kd;
+        rblock.push_back(rblock.back() + (int32_t)((entries + kRedRows - 1) / kRedRows));
+        rstate.push_back(rstate.back() + (int32_t)ns);
+    }
+    mm.nredblocks = rblock.back();
     mm.nscratch = nscratch;
     mm.hargs = args;
     mm.variant = p->m2l_cfg.variant;
@@ -410,6 +418,8 @@ void build_m2l_list(fda_plan *p, M2LMerged &mm, std::vector<void *> &fresh) {
         mm.rd_off = upload_to(p, off, fresh);
         mm.rd_list = upload_to(p, list, fresh);
         mm.rd_lev = upload_to(p, lev, fresh);
+        mm.rd_block = upload_to(p, rblock, fresh);
+        mm.rd_state = upload_to(p, rstate, fresh);
         mm.args = dalloc<M2LLevelArgs>(p, args.size(), fresh);
         if (p->cap_nrhs > 0) {
             // work buffers exist: point the level table at them

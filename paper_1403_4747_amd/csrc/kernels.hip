@@ -1000,38 +1000,47 @@ k_m2l_lowrank(const int4 *hdr, const int32_t *src, const M2LLevelArgs *args, C *
 
 // c[dst] = sum of the M2L scratch columns listed for dst (every state of the
 // merged levels has an entry; an empty list writes zero), in list order.
+// The (state, row) entries of a level are spread over the threads, kRedRows
+// per block, so that every lane has a row whatever the rank.
 template <class C>
-__global__ void k_gather_reduce_m2l(const int32_t *dst, const int32_t *off, const int32_t *list, const int32_t *lev,
-                                    const M2LLevelArgs *args, const C *T, int64_t tstride) {
-    const int t = blockIdx.x;
-    const M2LLevelArgs &la = args[lev[t]];
+__global__ void __launch_bounds__(kRedRows) k_gather_reduce_m2l(const int32_t *dst, const int32_t *off,
+                                                                const int32_t *list, const int32_t *rd_block,
+                                                                const int32_t *rd_state, int nlev,
+                                                                const M2LLevelArgs *args, const C *T,
+                                                                int64_t tstride) {
+    int q = 0;
+    while (q + 1 < nlev && (int)blockIdx.x >= rd_block[q + 1]) ++q;
+    const M2LLevelArgs &la = args[q];
     const int m = la.kd;
+    const int64_t e = (int64_t)(blockIdx.x - rd_block[q]) * kRedRows + threadIdx.x;
+    const int64_t sl = e / m;
+    const int r = (int)(e - sl * m);
+    const int64_t t = rd_state[q] + sl;
+    if (t >= rd_state[q + 1]) return;
     const C *Tr = T + (int64_t)blockIdx.y * tstride + la.tbase;
     C *out = (C *)la.Y + (int64_t)blockIdx.y * la.ystride + (int64_t)dst[t] * m;
+    // four independent loads in flight per step; the sum keeps list order
+    C acc = czero<C>();
     const int q0 = off[t], q1 = off[t + 1];
-    for (int r = threadIdx.x; r < m; r += blockDim.x) {
-        // four independent loads in flight per step; the sum keeps list order
-        C acc = czero<C>();
-        int q = q0;
-        for (; q + 4 <= q1; q += 4) {
-            const C v0 = Tr[(int64_t)list[q] * m + r], v1 = Tr[(int64_t)list[q + 1] * m + r];
-            const C v2 = Tr[(int64_t)list[q + 2] * m + r], v3 = Tr[(int64_t)list[q + 3] * m + r];
-            acc.x += v0.x;
-            acc.y += v0.y;
-            acc.x += v1.x;
-            acc.y += v1.y;
-            acc.x += v2.x;
-            acc.y += v2.y;
-            acc.x += v3.x;
-            acc.y += v3.y;
-        }
-        for (; q < q1; ++q) {
-            const C v = Tr[(int64_t)list[q] * m + r];
-            acc.x += v.x;
-            acc.y += v.y;
-        }
-        out[r] = acc;
+    int k = q0;
+    for (; k + 4 <= q1; k += 4) {
+        const C v0 = Tr[(int64_t)list[k] * m + r], v1 = Tr[(int64_t)list[k + 1] * m + r];
+        const C v2 = Tr[(int64_t)list[k + 2] * m + r], v3 = Tr[(int64_t)list[k + 3] * m + r];
+        acc.x += v0.x;
+        acc.y += v0.y;
+        acc.x += v1.x;
+        acc.y += v1.y;
+        acc.x += v2.x;
+        acc.y += v2.y;
+        acc.x += v3.x;
+        acc.y += v3.y;
     }
+    for (; k < q1; ++k) {
+        const C v = Tr[(int64_t)list[k] * m + r];
+        acc.x += v.x;
+        acc.y += v.y;
+    }
+    out[r] = acc;
 }
 
 // Y[dst] (+)= sum of the scratch columns listed for dst, in list order.
@@ -1461,8 +1470,9 @@ static hipError_t m2l_merged_t(const M2LMerged &mm, int nrhs, hipStream_t st, hi
     }
     CHECK_LAUNCH();
     if (ev) hipEventRecord(ev[1], st);
-    hipLaunchKernelGGL(k_gather_reduce_m2l<C>, dim3(mm.nred, nrhs), dim3(128), 0, st, mm.rd_dst, mm.rd_off,
-                       mm.rd_list, mm.rd_lev, mm.args, (const C *)mm.tmp, mm.nscratch);
+    hipLaunchKernelGGL(k_gather_reduce_m2l<C>, dim3(mm.nredblocks, nrhs), dim3(kRedRows), 0, st, mm.rd_dst,
+                       mm.rd_off, mm.rd_list, mm.rd_block, mm.rd_state, mm.nlev, mm.args, (const C *)mm.tmp,
+                       mm.nscratch);
     CHECK_LAUNCH();
     return hipSuccess;
 }

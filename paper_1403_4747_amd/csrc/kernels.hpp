@@ -51,6 +51,10 @@ struct M2LMerged {
     int4 *hdr = nullptr;                   // (translation, level-local scratch column, columns, level slot)
     int32_t *src = nullptr;
     int32_t *rd_dst = nullptr, *rd_off = nullptr, *rd_list = nullptr, *rd_lev = nullptr;
+    // reduction blocks: level slot q covers blocks rd_block[q] .. rd_block[q + 1]
+    // (kRedRows (state, row) entries each) and states rd_state[q] ..
+    int32_t *rd_block = nullptr, *rd_state = nullptr;
+    int nredblocks = 0;
     M2LLevelArgs *args = nullptr;          // device table, refreshed with the work buffers
     std::vector<M2LLevelArgs> hargs;
     void *tmp = nullptr;
@@ -161,6 +165,9 @@ hipError_t launch_bj_apply(const DevPlan &d, const double2 *r, double2 *z, int n
                            hipStream_t st);
 hipError_t launch_fill_zero(double2 *p, int64_t n, hipStream_t st);
 constexpr int kLowRankMax = 72;  // largest rank the low-rank M2L kernel holds in LDS
+
+// (state, row) entries per block of the merged M2L reduction.
+constexpr int kRedRows = 256;
 
 // Blocks used by the two-pass reductions.
 constexpr int kRedBlocks = 240;
