@@ -23,8 +23,9 @@ masked mean squared error between c_R and the normalised correction
 
 Parameters are one flat array: W1 (272 x h, input-major), b1 (h), W2
 (h x h), b2 (h), W3 (h x 128), b3 (128).  Inference uses bfloat16 copies of
-W1, W2, W3 (round to nearest, ties to even) with wider accumulation; the
-biases keep full precision.
+W1, W2, W3 (round to nearest, ties to even) and rounds each layer's input
+the same way (a bfloat16 product), with wider accumulation; the biases and
+the ReLU keep full precision.
 
 Pins (tests/test_oracle_pins_mlp.py): the backward pass against central
 differences of the loss, bfloat16 rounding against exactly representable
@@ -130,12 +131,16 @@ def _weights(p, h, bf16):
 
 
 def forward(p: np.ndarray, X: np.ndarray, h: int, bf16: bool = True):
-    """Y (rows x 128) and the hidden activations (H1, H2)."""
+    """Y (rows x 128) and the hidden activations (H1, H2).  With bf16 each
+    layer is a bfloat16 product: its input (X, H1, H2) and its weights are
+    rounded to bfloat16 and multiplied exactly (wider accumulation); the
+    bias, the ReLU and the returned H1, H2 stay unrounded."""
     W1, b1, W2, b2, W3, b3 = _weights(p, h, bf16)
     X = np.asarray(X, dtype=np.float64)
-    H1 = np.maximum(X @ W1 + b1, 0.0)
-    H2 = np.maximum(H1 @ W2 + b2, 0.0)
-    return H2 @ W3 + b3, H1, H2
+    rnd = (lambda A: bf16_round(A).astype(np.float64)) if bf16 else (lambda A: A)
+    H1 = np.maximum(rnd(X) @ W1 + b1, 0.0)
+    H2 = np.maximum(rnd(H1) @ W2 + b2, 0.0)
+    return rnd(H2) @ W3 + b3, H1, H2
 
 
 def loss_and_gradient(p: np.ndarray, X, T, M, h: int, bf16: bool = True):

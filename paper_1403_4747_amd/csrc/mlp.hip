@@ -115,6 +115,66 @@ static void gemm(int M, int N, int K, const float *A, int lda, int transA, const
                        relu, accumulate);
 }
 
+// Forward-pass product on the matrix cores: C[M x N] = act(bf16(A) W + bias)
+// with v_mfma_f32_16x16x16bf16_1k (BF16 operands, FP32 accumulation).  The
+// FP32 activations A (row-major, lda) are rounded to bfloat16 as they are
+// loaded; W is the BF16 weight copy (row-major K x N, ldw).  A workgroup of
+// four waves computes a 64 x 64 tile: wave w rows 16 w .. 16 w + 15, four
+// 16-column tiles.  Operand layout per lane l: A row l % 16 and B column
+// l % 16, k-slots 4 (l / 16) .. 4 (l / 16) + 3; result column l % 16, rows
+// 4 (l / 16) .. + 3.
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+__global__ void __launch_bounds__(256) k_gemm_bf16(int M, int N, int K, const float *A, int lda, const uint16_t *W,
+                                                   int ldw, float *C, int ldc, const float *bias, int relu) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int m0 = blockIdx.y * 64 + wave * 16, n0 = blockIdx.x * 64;
+    const int arow = m0 + li;
+    f32x4 acc[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[c] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        bf16x4 a;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int k = k0 + 4 * lk + j;
+            const float v = (arow < M && k < K) ? A[(int64_t)arow * lda + k] : 0.f;
+            a[j] = (short)f32_to_bf16(v);
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int n = n0 + 16 * c + li;
+            bf16x4 b;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int k = k0 + 4 * lk + j;
+                b[j] = (short)((k < K && n < N) ? W[(int64_t)k * ldw + n] : 0);
+            }
+            acc[c] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[c], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int n = n0 + 16 * c + li;
+        if (n >= N) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = m0 + 4 * lk + v;
+            if (r >= M) continue;
+            float o = acc[c][v] + (bias ? bias[n] : 0.f);
+            if (relu) o = fmaxf(o, 0.f);
+            C[(int64_t)r * ldc + n] = o;
+        }
+    }
+}
+
+static void gemm_bf16(int M, int N, int K, const float *A, int lda, const uint16_t *W, int ldw, float *C, int ldc,
+                      const float *bias, int relu, hipStream_t st) {
+    dim3 grid((N + 63) / 64, (M + 63) / 64);
+    hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, st, M, N, K, A, lda, W, ldw, C, ldc, bias, relu);
+}
+
 // ------------------------------------------------------------------ training pieces
 
 // dY = 2 mask (Y - T) / count; partial sums of mask (Y - T)^2 per block.
@@ -362,14 +422,16 @@ void Mlp::ensure_rows(int64_t rows) {
     cap_rows = rows;
 }
 
-// Y (rows x 128) = MLP(X (rows x 272)) with the BF16 weights; the hidden
-// activations go to a1 and a2 (rows x hidden floats each).
+// Y (rows x 128) = MLP(X (rows x 272)): each layer a BF16 product on the
+// matrix cores (layer input and weights in bfloat16, FP32 accumulation,
+// bias and ReLU in FP32); the hidden activations go to a1 and a2 (rows x
+// hidden floats each, before rounding).
 void Mlp::forward_into(const float *X, int64_t rows, float *Y, float *a1, float *a2, hipStream_t st) const {
     size_t w1, b1, w2, b2, w3, b3;
     offsets(w1, b1, w2, b2, w3, b3);
-    gemm<uint16_t>((int)rows, hidden, kMlpIn, X, kMlpIn, 0, wb + w1, hidden, 0, a1, hidden, w + b1, 1, 0, st);
-    gemm<uint16_t>((int)rows, hidden, hidden, a1, hidden, 0, wb + w2, hidden, 0, a2, hidden, w + b2, 1, 0, st);
-    gemm<uint16_t>((int)rows, kMlpOut, hidden, a2, hidden, 0, wb + w3, kMlpOut, 0, Y, kMlpOut, w + b3, 0, 0, st);
+    gemm_bf16((int)rows, hidden, kMlpIn, X, kMlpIn, wb + w1, hidden, a1, hidden, w + b1, 1, st);
+    gemm_bf16((int)rows, hidden, hidden, a1, hidden, wb + w2, hidden, a2, hidden, w + b2, 1, st);
+    gemm_bf16((int)rows, kMlpOut, hidden, a2, hidden, wb + w3, kMlpOut, Y, kMlpOut, w + b3, 0, st);
 }
 
 void Mlp::forward(const float *X, int64_t rows, float *Y, hipStream_t st) {

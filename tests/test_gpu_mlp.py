@@ -55,9 +55,25 @@ def test_mlp_forward_matches_oracle(rows):
     net = Mlp(hidden=256, seed=7)
     X, _, _ = _rand_rows(rows, 1)
     Y = net.forward(_dev(X)).cpu().numpy()
-    Yr, _, _ = R.forward(net.get_params(), X, 256, bf16=True)
-    # FP32 accumulation over at most 272 products of bfloat16 weights
-    assert np.max(np.abs(Y - Yr)) <= 2e-5 * max(1.0, np.max(np.abs(Yr)))
+    prm = net.get_params()
+    Yr, H1, H2 = R.forward(prm, X, 256, bf16=True)
+    # bfloat16 products with FP32 accumulation (at most 256 terms).  The device
+    # rounds each hidden activation to bfloat16 from an FP32 sum, the oracle
+    # from an FP64 one, so an activation that lies within the accumulation
+    # error of a rounding boundary may round to the neighbouring bfloat16 value
+    # (measured: about one row in 300).  Rows without such a flip agree to the
+    # accumulation error; every row stays within what flips of all its hidden
+    # activations by one bfloat16 step (2^-7 relative) can change, to first
+    # order, plus that error.
+    W1, b1, W2, b2, W3, b3 = R.split(prm, 256)
+    aW2 = np.abs(R.bf16_round(W2).astype(np.float64))
+    aW3 = np.abs(R.bf16_round(W3).astype(np.float64))
+    flip = 2.0 ** -7 * ((np.abs(H1) @ aW2) @ aW3 + np.abs(H2) @ aW3)
+    scale = max(1.0, np.max(np.abs(Yr)))
+    d = np.abs(Y - Yr)
+    tight = np.all(d <= 2e-5 * scale, axis=1)
+    assert np.mean(tight) >= 0.97, f"{np.sum(~tight)} of {rows} rows differ beyond the accumulation error"
+    assert np.all(d <= flip + 2e-5 * scale)
 
 
 def test_mlp_gradient_matches_oracle():

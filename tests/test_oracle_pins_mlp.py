@@ -48,6 +48,31 @@ def test_forward_hand_evaluated_width2():
     assert np.count_nonzero(Y[1]) == 1 and Y[1, 7] == pytest.approx(0.125)
 
 
+def test_forward_bf16_rounds_layer_inputs_hand_evaluated():
+    """The width-2 network of the test above with bfloat16 layer inputs:
+    x = 1 + 3 / 512 rounds to 1 + 1 / 128 (bfloat16 keeps 7 fraction bits,
+    ties to even), and the hidden values then stay exactly representable."""
+    h = 2
+    p = np.zeros(R.num_params(h), dtype=np.float32)
+    W1, b1, W2, b2, W3, b3 = R.split(p, h)
+    W1[0, 0], W1[1, 1] = 1.0, -1.0
+    b1[:] = [0.5, 0.25]
+    W2[0, 0], W2[1, 0], W2[1, 1] = 2.0, 1.0, 1.0
+    b2[:] = [0.0, -1.0]
+    W3[0, 0], W3[1, 5] = 1.0, 3.0
+    X = np.zeros((1, R.MLP_IN))
+    X[0, 0], X[0, 1] = 1.0 + 3.0 / 512, -2.0
+    # bf16(x0) = 1 + 1/128: H1 = [1.5 + 1/128, 2.25]; H2 = [5.25 + 1/64, 1.25];
+    # the last layer's input 5.265625 = 1.01010001b x 4 lies halfway between
+    # two bfloat16 values and rounds to the even one, 5.25
+    Y, H1, H2 = R.forward(p, X, h, bf16=True)
+    assert H1[0, 0] == 1.5 + 1.0 / 128 and H1[0, 1] == 2.25
+    assert H2[0, 0] == 5.25 + 1.0 / 64 and H2[0, 1] == 1.25
+    assert Y[0, 0] == 5.25 and Y[0, 5] == 3.75
+    Yf, _, _ = R.forward(p, X, h, bf16=False)
+    assert Yf[0, 0] == pytest.approx(5.25 + 6.0 / 512)
+
+
 @pytest.mark.parametrize("bf16", [False, True])
 def test_gradient_matches_central_differences(bf16):
     rng = np.random.default_rng(1)
