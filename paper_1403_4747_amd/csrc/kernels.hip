@@ -334,15 +334,32 @@ __device__ __forceinline__ C wave_sum(C acc) {
     return acc;
 }
 
+// Sum over the kP2PGroup lanes of a row group (the group's first lane ends
+// with the total); every lane of the wave takes part.
+template <class C>
+__device__ __forceinline__ C group_sum(C acc) {
+    for (int o = kP2PGroup / 2; o > 0; o >>= 1) {
+        acc.x += __shfl_down(acc.x, o, kP2PGroup);
+        acc.y += __shfl_down(acc.y, o, kP2PGroup);
+    }
+    return acc;
+}
+
 // y_tree[i] = sum over the near leaves of the block entries times x
 // (+ the FP64 self term diag[i] x[i] when the blocks are FP32).  x of the
 // block's columns (listed in cols from col_off[leaf], the near leaves'
-// elements in order) is gathered into LDS in one parallel pass.
+// elements in order) is gathered into LDS in one parallel pass.  A row is
+// taken by a group of kP2PGroup lanes (four rows per wave, sixteen per
+// workgroup), each lane summing the columns lane, lane + kP2PGroup, ... in
+// order, with four row loads in flight: rows are a few hundred columns
+// long, so full-wave rows would leave lanes idle in their last chunk and
+// wait on one load at a time.
 template <class C, int R>
 __global__ void __launch_bounds__(256) k_p2p(const int4 *items, const int64_t *leaf_off, const int64_t *col_off,
                                              const int32_t *cols, const int64_t *blk_off, const C *vals,
                                              const double2 *diag, const double2 *x, double2 *y, int64_t N,
                                              int nitems, int ngroups, int nrhs) {
+    constexpr int G = kP2PGroup;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C *xs = (C *)smem_raw;  // R x nc
     const RhsBlock rb = rhs_block(ngroups);
@@ -359,22 +376,37 @@ __global__ void __launch_bounds__(256) k_p2p(const int4 *items, const int64_t *l
     }
     __syncthreads();
     const int64_t t0 = leaf_off[b];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int lane = threadIdx.x & (G - 1), grp = threadIdx.x / G, ngrp = blockDim.x / G;
     const C *blk = vals + blk_off[b];
-    for (int i = it.y + wv; i < it.z; i += nw) {
+    for (int i0 = it.y; i0 < it.z; i0 += ngrp) {  // the same trip count for every lane
+        const int i = i0 + grp;
         C acc[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) acc[r] = czero<C>();
-        const C *row = blk + (int64_t)i * nc;
-        for (int c = lane; c < nc; c += 64) {
-            const C v = row[c];
+        if (i < it.z) {
+            const C *row = blk + (int64_t)i * nc;
+            int c = lane;
+            for (; c + 3 * G < nc; c += 4 * G) {
+                const C v0 = row[c], v1 = row[c + G], v2 = row[c + 2 * G], v3 = row[c + 3 * G];
 #pragma unroll
-            for (int r = 0; r < R; ++r) cmac(acc[r], v, xs[r * nc + c]);
+                for (int r = 0; r < R; ++r) {
+                    const C *xr = xs + r * nc + c;
+                    cmac(acc[r], v0, xr[0]);
+                    cmac(acc[r], v1, xr[G]);
+                    cmac(acc[r], v2, xr[2 * G]);
+                    cmac(acc[r], v3, xr[3 * G]);
+                }
+            }
+            for (; c < nc; c += G) {
+                const C v = row[c];
+#pragma unroll
+                for (int r = 0; r < R; ++r) cmac(acc[r], v, xs[r * nc + c]);
+            }
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            acc[r] = wave_sum(acc[r]);
-            if (lane == 0 && r < nr) {
+            acc[r] = group_sum(acc[r]);
+            if (i < it.z && lane == 0 && r < nr) {
                 double2 out = make_double2((double)acc[r].x, (double)acc[r].y);
                 if (diag) {
                     const double2 d = diag[t0 + i], v = x[(int64_t)(r0 + r) * N + t0 + i];
@@ -390,8 +422,7 @@ __global__ void __launch_bounds__(256) k_p2p(const int4 *items, const int64_t *l
 // The same product for long rows (more than kP2PShortCols columns): x is
 // read through the row's column list instead of being staged in LDS, so
 // these workgroups need no LDS and keep full occupancy (x is small enough
-// to stay in L2).  Same summation order as k_p2p, so the same result bit
-// for bit.
+// to stay in L2); a full wave per row.
 template <class C, int R>
 __global__ void __launch_bounds__(256) k_p2p_direct(const int4 *items, const int64_t *leaf_off,
                                                     const int64_t *col_off, const int32_t *cols,
@@ -497,7 +528,9 @@ __global__ void k_s2m(const int64_t *leaf_off, const int32_t *ids, const int32_t
 #define GG_NB 32
 #define GG_LD (GG_NB + 1)  // padded LDS row: spreads the 4 k-rows of an MFMA operand over the banks
 #define MF_RT 4
-#define GG_RT 2  // row tiles per wave in a band of the gathered GEMM (band = 128 rows)
+#ifndef GG_RT
+#define GG_RT 2  // row tiles per wave in a band of the gathered GEMM (band = 64 * GG_RT rows)
+#endif
 #define LR_MAX 72
 #define LR_LD (LR_MAX + 1)
 #ifndef LRJ

@@ -15,6 +15,7 @@ Every step runs in libfda; this module only draws the seeded cases and moves
 tensors.  Usage:
 
     python -m paper_1403_4747_amd.train_mlp --train 64 --eval 16 --out weights.npz
+    python -m paper_1403_4747_amd.train_mlp --eval-only weights.npz --eval 100
 """
 from __future__ import annotations
 
@@ -50,18 +51,24 @@ def ellipsoid_case(seed: int, subdiv: int = 5, axes=(0.3, 0.7), kD=(20.0, 60.0))
     return V, T, kd / D, d, dict(seed=seed, semi_axes=a.tolist(), kD=kd, n=len(T))
 
 
-def case_samples(plan, direction, tol_star: float = 1e-10, snapshots: Sequence[int] = SNAPSHOTS, n_random: int = 4,
-                 seed: int = 0):
+def case_samples(plan, direction, tol_star: float = 1e-6, snapshots: Sequence[int] = SNAPSHOTS, n_random: int = 4,
+                 seed: int = 0, maxit_star: int = 400):
     """(X, T, M) rows of one case: the GMRES iterates of the plane-wave
     solve, plus `n_random` complex-normal residuals r with e = A^-1 r (their
     leaf components are independent, so the rows also carry the local part
-    of A^-1 that GMRES residuals, dominated by a few global modes, hide)."""
+    of A^-1 that GMRES residuals, dominated by a few global modes, hide).
+
+    x* and A^-1 r are solved to `tol_star`: GMRES over the FP32 plan's
+    products stalls near a relative residual of 2e-7 (the products' own
+    rounding), so a tighter tolerance only spends iterations; the targets
+    e_m = x* - x_m stay accurate to tol_star / |r_m|, at most 1e-3 relative
+    for the iterates kept."""
     import torch
 
     import workloads as W
 
     b = plan.rhs_planewave(direction)
-    xs, info = plan.solve(b, tol=tol_star, restart=50, maxit=2000)
+    xs, info = plan.solve(b, tol=tol_star, restart=50, maxit=maxit_star)
     rs, es = [], []
     for m in snapshots:
         if m == 0:
@@ -72,30 +79,41 @@ def case_samples(plan, direction, tol_star: float = 1e-10, snapshots: Sequence[i
         es.append(xs - xm)
     if n_random > 0:
         R = torch.from_numpy(np.ascontiguousarray(W.complex_normal(plan.n, n_random, seed=seed).T)).to(b.device)
-        E, _ = plan.solve(R, tol=tol_star, restart=50, maxit=2000)
+        E, _ = plan.solve(R, tol=tol_star, restart=50, maxit=maxit_star)
         rs.extend(R)
         es.extend(E)
     return plan.mlp_samples(torch.stack(rs), torch.stack(es)), info
 
 
-def generate(seeds: Sequence[int], eps: float = 1e-4, prec: str = "fp32", log=print, n_random: int = 4, **case_kw):
-    """Concatenated training rows of the given seeds (device tensors)."""
+def generate(seeds: Sequence[int], eps: float = 1e-4, prec: str = "fp32", log=print, n_random: int = 4,
+             max_seconds: float = None, **case_kw):
+    """Concatenated training rows of the given seeds (device tensors); with
+    `max_seconds`, generation stops after the case that crosses it."""
     import torch
 
     from .fda import Plan
 
+    t_all = time.perf_counter()
     Xs, Ts, Ms, meta = [], [], [], []
     for s in seeds:
         t0 = time.perf_counter()
         V, T, k, d, info = ellipsoid_case(s, **case_kw)
         with Plan(V, T, k, eps, prec=prec) as p:
+            tb = time.perf_counter() - t0
+            phases = [round(v, 2) for v in p.stats()["build_phase_seconds"][:7]]
             (X, Tg, M), sinfo = case_samples(p, d, n_random=n_random, seed=s)
         Xs.append(X)
         Ts.append(Tg)
         Ms.append(M)
-        info.update(rows=int(X.shape[0]), its_star=sinfo["iterations"], seconds=round(time.perf_counter() - t0, 2))
+        info.update(rows=int(X.shape[0]), its_star=sinfo["iterations"], res_star=sinfo["rel_residual"],
+                    build_seconds=round(tb, 2), build_phase_seconds=phases,
+                    seconds=round(time.perf_counter() - t0, 2))
         meta.append(info)
-        log(f"[train_mlp] case {s}: N={info['n']} kD={info['kD']:.1f} rows={info['rows']} ({info['seconds']} s)")
+        log(f"[train_mlp] case {s}: N={info['n']} kD={info['kD']:.1f} rows={info['rows']} x* in "
+            f"{info['its_star']} its ({info['seconds']} s, build {info['build_seconds']} s {phases})")
+        if max_seconds is not None and time.perf_counter() - t_all > max_seconds:
+            log(f"[train_mlp] generation stopped after {len(meta)} solves ({max_seconds} s budget)")
+            break
     return torch.cat(Xs), torch.cat(Ts), torch.cat(Ms), meta
 
 
@@ -149,6 +167,21 @@ def load(path: str, device: int = 0):
     return net
 
 
+def summarize(ev: List[Dict]) -> Dict:
+    """Means over held-out cases: iterations and seconds per preconditioner,
+    how often the network needed fewer iterations than block Jacobi, and how
+    often the solver's judge rejected it."""
+    pcs = ("none", "block_jacobi", "mlp")
+    return dict(
+        eval_solves=len(ev),
+        mean_iterations={pc: float(np.mean([r[pc]["iterations"] for r in ev])) for pc in pcs},
+        mean_seconds={pc: float(np.mean([r[pc]["seconds"] for r in ev])) for pc in pcs},
+        mlp_fewer_iterations_than_bj=int(sum(r["mlp"]["iterations"] < r["block_jacobi"]["iterations"] for r in ev)),
+        judge_rejected=int(sum(r["mlp"]["mlp_rejected"] for r in ev)),
+        all_converged=bool(all(r[pc]["converged"] for r in ev for pc in pcs)),
+    )
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--train", type=int, default=64, help="training solves (seeds 0 ..)")
@@ -163,6 +196,10 @@ def main(argv=None):
     ap.add_argument("--out", default="mlp_weights.npz")
     ap.add_argument("--random", type=int, default=4, help="random residuals per training solve")
     ap.add_argument("--report", default=None, help="write a JSON report here")
+    ap.add_argument("--max-generate-seconds", type=float, default=None,
+                    help="stop drawing training solves after this many seconds")
+    ap.add_argument("--eval-only", default=None, metavar="WEIGHTS",
+                    help="skip training: evaluate the network stored in WEIGHTS on the held-out seeds")
     args = ap.parse_args(argv)
 
     import torch
@@ -171,8 +208,19 @@ def main(argv=None):
 
     log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
     torch.cuda.set_device(0)
+    held_out = range(100000, 100000 + args.eval)
+    if args.eval_only:
+        net = load(args.eval_only)
+        ev = evaluate(net, held_out, prec=args.prec, log=log, subdiv=args.subdiv)
+        summary = dict(weights=os.path.basename(args.eval_only), subdiv=args.subdiv, prec=args.prec, **summarize(ev))
+        if args.report:
+            with open(args.report, "w") as f:
+                json.dump(dict(summary=summary, eval=ev), f, indent=1)
+        print(json.dumps(summary), flush=True)
+        return
     t0 = time.perf_counter()
-    X, Tg, M, meta = generate(range(args.train), prec=args.prec, log=log, n_random=args.random, subdiv=args.subdiv)
+    X, Tg, M, meta = generate(range(args.train), prec=args.prec, log=log, n_random=args.random, subdiv=args.subdiv,
+                              max_seconds=args.max_generate_seconds)
     gen_s = time.perf_counter() - t0
     log(f"[train_mlp] {X.shape[0]} rows from {args.train} solves in {gen_s:.1f} s")
     net = Mlp(hidden=args.hidden, seed=args.seed)
@@ -180,17 +228,17 @@ def main(argv=None):
     losses = net.train(X, Tg, M, epochs=args.epochs, batch=args.batch, lr=args.lr, seed=args.seed)
     train_s = time.perf_counter() - t0
     log(f"[train_mlp] trained {args.epochs} epochs in {train_s:.1f} s; loss {losses[0]:.4e} -> {losses[-1]:.4e}")
+    rows = int(X.shape[0])
     del X, Tg, M
-    ev = evaluate(net, range(100000, 100000 + args.eval), prec=args.prec, log=log, subdiv=args.subdiv)
     summary = dict(
-        train_solves=args.train, eval_solves=args.eval, subdiv=args.subdiv, hidden=args.hidden, epochs=args.epochs,
+        train_solves=len(meta), train_rows=rows, subdiv=args.subdiv, hidden=args.hidden, epochs=args.epochs,
         batch=args.batch, lr=args.lr, prec=args.prec, generate_seconds=round(gen_s, 2),
-        train_seconds=round(train_s, 2), loss_first=float(losses[0]), loss_last=float(losses[-1]),
-        mean_iterations={pc: float(np.mean([r[pc]["iterations"] for r in ev])) for pc in ("none", "block_jacobi", "mlp")},
-        mean_seconds={pc: float(np.mean([r[pc]["seconds"] for r in ev])) for pc in ("none", "block_jacobi", "mlp")},
-        judge_rejected=int(sum(r["mlp"]["mlp_rejected"] for r in ev)),
-    )
+        train_seconds=round(train_s, 2), loss_first=float(losses[0]), loss_last=float(losses[-1]))
     save(net, args.out, dict(summary=summary, losses=[float(v) for v in losses]))
+    ev = []
+    if args.eval > 0:
+        ev = evaluate(net, held_out, prec=args.prec, log=log, subdiv=args.subdiv)
+        summary.update(summarize(ev))
     if args.report:
         with open(args.report, "w") as f:
             json.dump(dict(summary=summary, losses=[float(v) for v in losses], train_cases=meta, eval=ev), f, indent=1)
