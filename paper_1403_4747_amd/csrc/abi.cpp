@@ -116,7 +116,7 @@ void *to_storage(fda_plan *p, double2 *a64, size_t n) {
 
 // Host-side builder of a gathered-GEMM work list (kernels.hpp, GWork).
 struct GWorkHost {
-    std::vector<int32_t> hdr, src;
+    std::vector<int32_t> hdr, src, dstcol;
     int64_t ncol = 0;
     std::vector<std::vector<int32_t>> parts;  // per destination: scratch columns
     std::vector<int32_t> dest;                // destination state of each entry of parts
@@ -128,7 +128,10 @@ struct GWorkHost {
         hdr.push_back((int32_t)ncol);
         hdr.push_back((int32_t)srcs.size());
         hdr.push_back(0);
-        for (int b = 0; b < kGemmCols; ++b) src.push_back(b < (int)srcs.size() ? srcs[b] : -1);
+        for (int b = 0; b < kGemmCols; ++b) {
+            src.push_back(b < (int)srcs.size() ? srcs[b] : -1);
+            dstcol.push_back(b < (int)dsts.size() ? dsts[b] : -1);
+        }
         for (size_t b = 0; b < dsts.size(); ++b) {
             auto it = dest_index.find(dsts[b]);
             int32_t di;
@@ -150,14 +153,20 @@ GWork upload_gwork(fda_plan *p, const GWorkHost &g) {
     GWork w;
     w.nwork = (int)(g.hdr.size() / 4);
     w.ncol = g.ncol;
+    w.hdr = (int4 *)upload(p, g.hdr);
+    w.src = upload(p, g.src);
+    bool single = true;
+    for (const auto &pl : g.parts) single = single && pl.size() == 1;
+    if (single) {  // one product per destination: written in place
+        w.dst = upload(p, g.dstcol);
+        return w;
+    }
     w.nred = (int)g.dest.size();
     std::vector<int32_t> off{0}, list;
     for (const auto &pl : g.parts) {
         list.insert(list.end(), pl.begin(), pl.end());
         off.push_back((int32_t)list.size());
     }
-    w.hdr = (int4 *)upload(p, g.hdr);
-    w.src = upload(p, g.src);
     w.rd_dst = upload(p, g.dest);
     w.rd_off = upload(p, off);
     w.rd_list = upload(p, list);

@@ -517,20 +517,20 @@ __global__ void k_s2m(const int64_t *leaf_off, const int32_t *ids, const int32_t
 //   L2L: one matrix per (child octant, parent direction), columns = the
 //        children in that octant.
 // A second kernel sums the scratch columns of every destination state in a
-// fixed order (deterministic results).
+// fixed order (deterministic results).  Where every destination receives a
+// single product (L2L between non-directional levels: one parent each), the
+// product is added to it in place and the scratch and the second kernel
+// are skipped.
 // MFMA operand layout per wave (16x16x4, FP64 and FP32): A (16 x 4) lane l
 // holds row l % 16, column l / 16; B (4 x 16) lane l holds row l / 16, column
 // l % 16; the 16 x 16 result of lane l is column l % 16, rows CT<C>::row.  A
-// complex product is four real products: Re += Ar Br - Ai Bi,
-// Im += Ar Bi + Ai Br.  The 4 waves of a block take row tiles w, w + 4, ...
-// of a 256-row band.  Work items of consecutive index are mapped to the same
-// XCD so that the shared translation matrices stay in that XCD's L2.
+// complex product is taken as three real products (CAcc).  The 4 waves of a
+// block take row tiles w, w + 4, ... of a band of 64 or 128 rows
+// (GemmShape).  Work items of consecutive index are mapped to the same XCD
+// so that the shared translation matrices stay in that XCD's L2.
 #define GG_NB 32
 #define GG_LD (GG_NB + 1)  // padded LDS row: spreads the 4 k-rows of an MFMA operand over the banks
 #define MF_RT 4
-#ifndef GG_RT
-#define GG_RT 2  // row tiles per wave in a band of the gathered GEMM (band = 64 * GG_RT rows)
-#endif
 #define LR_MAX 72
 #define LR_LD (LR_MAX + 1)
 #ifndef LRJ
@@ -588,28 +588,33 @@ struct CAcc {
     __device__ __forceinline__ R im(int v) const { return p3[v] - p1[v] - p2[v]; }
 };
 
-// Gathered GEMM body: every GG_SJ-deep k-chunk of the 128-row
-// band of A is staged in LDS beside the chunk of gathered states, and the
-// next chunk of both is fetched into registers while the current one is
-// multiplied (the MFMA loop reads only LDS).
+// Gathered GEMM body: every GG_SJ-deep k-chunk of a band of 64 RT rows of A
+// is staged in LDS beside the chunk of the NB gathered states, and the next
+// chunk of both is fetched into registers while the current one is
+// multiplied (the MFMA loop reads only LDS).  NCT column tiles of 16 are
+// live (the item's column count rounded up).  Column col of the product
+// goes to scratch column col (Tr, m rows per column) or, when the item
+// lists destination states (sdst), is written (accumulate: added) to state
+// sdst[col] of Yr, the only contribution that state receives.
 #ifndef GG_SJ
 #define GG_SJ 8  // k-chunk of the staged form
 #endif
-#define GG_SB (64 * GG_RT)            // rows per band
-#define GG_SLD (GG_SB + 1)            // padded LDS row of the staged A chunk
-template <class C, int NCT>
-__device__ __forceinline__ void ggemm_body_staged(const int4 h, const int32_t *sidx, const C *At, int m, int kin,
-                                                  const C *Xr, C *Tr, C (*S)[GG_LD], C (*As)[GG_SLD]) {
+template <class C, int NCT, int RT>
+__device__ __forceinline__ void ggemm_body_staged(const int4 h, const int32_t *sidx, const int32_t *sdst,
+                                                  const C *At, int m, int kin, const C *Xr, C *Tr, C *Yr,
+                                                  int accumulate, int band0, int band1, C (*S)[GG_LD],
+                                                  C (*As)[64 * RT + 1]) {
+    constexpr int SB = 64 * RT;  // rows per band
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lk = lane >> 4;
     constexpr int SPT = GG_SJ * GG_NB / 256;
-    constexpr int APT = GG_SB * GG_SJ / 256;
-    for (int band = 0; band < m; band += GG_SB) {
-        const int ntile = min(GG_RT * 4, (m - band + 15) >> 4);
-        const int nrow = min(GG_SB, m - band);
-        CAcc<C> acc[GG_RT][NCT];
+    constexpr int APT = SB * GG_SJ / 256;
+    for (int band = band0; band < band1; band += SB) {
+        const int ntile = min(RT * 4, (m - band + 15) >> 4);
+        const int nrow = min(SB, m - band);
+        CAcc<C> acc[RT][NCT];
 #pragma unroll
-        for (int q = 0; q < GG_RT; ++q)
+        for (int q = 0; q < RT; ++q)
 #pragma unroll
             for (int c = 0; c < NCT; ++c) acc[q][c].zero();
         C sreg[SPT], areg[APT];
@@ -625,7 +630,7 @@ __device__ __forceinline__ void ggemm_body_staged(const int4 h, const int32_t *s
 #pragma unroll
             for (int i = 0; i < APT; ++i) {
                 const int e = threadIdx.x + 256 * i;
-                const int row = e % GG_SB, kc = e / GG_SB;
+                const int row = e % SB, kc = e / SB;
                 areg[i] = czero<C>();
                 if (row < nrow && j0 + kc < kin) areg[i] = At[band + row + (int64_t)(j0 + kc) * m];
             }
@@ -642,32 +647,34 @@ __device__ __forceinline__ void ggemm_body_staged(const int4 h, const int32_t *s
 #pragma unroll
             for (int i = 0; i < APT; ++i) {
                 const int e = threadIdx.x + 256 * i;
-                As[e / GG_SB][e % GG_SB] = areg[i];
+                As[e / SB][e % SB] = areg[i];
             }
             __syncthreads();
             if (j0 + GG_SJ < kin) fetch(j0 + GG_SJ);
             const int jm = min(GG_SJ, kin - j0);
             for (int kk = 0; kk < jm; kk += 4) {
-                const C b0 = S[kk + lk][li];
-                const C b1 = NCT == 2 ? S[kk + lk][16 + li] : czero<C>();
+                C bv[NCT];
 #pragma unroll
-                for (int q = 0; q < GG_RT; ++q) {
+                for (int c = 0; c < NCT; ++c) bv[c] = S[kk + lk][c * 16 + li];
+#pragma unroll
+                for (int q = 0; q < RT; ++q) {
                     const int rt = wave + 4 * q;
                     if (rt >= ntile) break;
                     const C av = As[kk + lk][rt * 16 + li];
-                    acc[q][0].mac(av, b0);
-                    if (NCT == 2) acc[q][NCT - 1].mac(av, b1);
+#pragma unroll
+                    for (int c = 0; c < NCT; ++c) acc[q][c].mac(av, bv[c]);
                 }
             }
         }
 #pragma unroll
-        for (int q = 0; q < GG_RT; ++q) {
+        for (int q = 0; q < RT; ++q) {
             const int rt = wave + 4 * q;
             if (rt >= ntile) break;
 #pragma unroll
             for (int c = 0; c < NCT; ++c) {
                 const int col = c * 16 + li;
                 if (col >= h.z) continue;
+                C *o = sdst ? Yr + (int64_t)sdst[col] * m : Tr + (int64_t)col * m;
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int row = band + rt * 16 + CT<C>::row(lk, v);
@@ -675,7 +682,12 @@ __device__ __forceinline__ void ggemm_body_staged(const int4 h, const int32_t *s
                         C r;
                         r.x = acc[q][c].re(v);
                         r.y = acc[q][c].im(v);
-                        Tr[(int64_t)col * m + row] = r;
+                        if (sdst && accumulate) {
+                            const C old = o[row];
+                            r.x = old.x + r.x;
+                            r.y = old.y + r.y;
+                        }
+                        o[row] = r;
                     }
                 }
             }
@@ -711,27 +723,58 @@ struct GemmOcc<float2> {
     static constexpr int waves = FDA_GEMM_WAVES32;
 };
 
+// Shape of the gathered GEMM per storage type.  FP64 accumulators take
+// twice the registers of FP32 ones, so an FP64 wave keeps one 16-row tile
+// (64-row bands) and every band of an item is a workgroup of its own (more
+// workgroups for the few, tall items of the upper levels; measured at
+// N = 81,920, kD = 100: M2M 0.242 -> 0.225 ms, L2L 0.272 -> 0.252 ms); an
+// FP32 wave keeps two tiles (128-row bands) and a workgroup loops over the
+// bands of its item (splitting was slower there: L2L 0.181 -> 0.213 ms).
+template <class C>
+struct GemmShape {
+    static constexpr int rt = 1;
+    static constexpr bool band_split = true;
+};
+template <>
+struct GemmShape<float2> {
+    static constexpr int rt = 2;
+    static constexpr bool band_split = false;
+};
+
+// One work item per workgroup (or one band of 64 RT rows of an item):
+// matrix hdr.x times the item's gathered states, into scratch columns
+// hdr.y .. or, with dst, straight into the listed destination states of Y.
 template <class C>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GemmOcc<C>::waves)))
-k_ggemm(const int4 *hdr, const int32_t *src, const C *A, int m, int kin, const C *X, int64_t xstride, C *T,
-        int64_t tstride, int nwork, int nrhs) {
+k_ggemm(const int4 *hdr, const int32_t *src, const int32_t *dst, const C *A, int m, int kin, const C *X,
+        int64_t xstride, C *T, int64_t tstride, C *Y, int64_t ystride, int accumulate, int nwork, int nband,
+        int nrhs) {
+    constexpr int RT = GemmShape<C>::rt;
+    constexpr int SB = 64 * RT;
     __shared__ C S[GG_SJ][GG_LD];
-    __shared__ C As[GG_SJ][GG_SLD];
-    __shared__ int32_t sidx[GG_NB];
+    __shared__ C As[GG_SJ][SB + 1];
+    __shared__ int32_t sidx[GG_NB], sdst[GG_NB];
     // one contiguous chunk of the work list per XCD (consecutive items
-    // share their translation matrix)
-    const RhsBlock rb = rhs_block_chunked(nrhs, (nwork + 7) / 8);
-    const int w = rb.item;
-    if (w >= nwork) return;
+    // share their translation matrix; the bands of an item are consecutive)
+    const int nunit = nwork * nband;
+    const RhsBlock rb = rhs_block_chunked(nrhs, (nunit + 7) / 8);
+    if (rb.item >= nunit) return;
+    const int w = rb.item / nband, bnd = rb.item - w * nband;
+    const int band0 = nband == 1 ? 0 : bnd * SB, band1 = nband == 1 ? m : min(m, band0 + SB);
     const int4 h = hdr[w];  // (matrix, first scratch column, column count, 0)
-    if (threadIdx.x < GG_NB) sidx[threadIdx.x] = src[(int64_t)w * GG_NB + threadIdx.x];
+    if (threadIdx.x < GG_NB) {
+        sidx[threadIdx.x] = src[(int64_t)w * GG_NB + threadIdx.x];
+        if (dst) sdst[threadIdx.x] = dst[(int64_t)w * GG_NB + threadIdx.x];
+    }
     const C *Xr = X + (int64_t)rb.rhs * xstride;
-    C *Tr = T + (int64_t)rb.rhs * tstride + (int64_t)h.y * m;
+    C *Tr = dst ? nullptr : T + (int64_t)rb.rhs * tstride + (int64_t)h.y * m;
+    C *Yr = dst ? Y + (int64_t)rb.rhs * ystride : nullptr;
+    const int32_t *sd = dst ? sdst : nullptr;
     const C *At = A + (int64_t)h.x * m * kin;
     if (h.z > 16)
-        ggemm_body_staged<C, 2>(h, sidx, At, m, kin, Xr, Tr, S, As);
+        ggemm_body_staged<C, 2, RT>(h, sidx, sd, At, m, kin, Xr, Tr, Yr, accumulate, band0, band1, S, As);
     else
-        ggemm_body_staged<C, 1>(h, sidx, At, m, kin, Xr, Tr, S, As);
+        ggemm_body_staged<C, 1, RT>(h, sidx, sd, At, m, kin, Xr, Tr, Yr, accumulate, band0, band1, S, As);
 }
 
 // Phase 1 of the low-rank M2L in the direct form: NQ row tiles of V^ (rows
@@ -1463,14 +1506,18 @@ template <class C>
 static hipError_t ggemm_t(const GWork &g, const void *A, int m, int kin, const void *X, int64_t xstride, void *Y,
                           int64_t ystride, int accumulate, int nrhs, hipStream_t st, hipEvent_t *ev) {
     if (g.nwork == 0) return hipSuccess;
+    constexpr int SB = 64 * GemmShape<C>::rt;
+    const int nband = GemmShape<C>::band_split ? (m + SB - 1) / SB : 1;
     // a multiple of 8 workgroups so every XCD runs the same share
-    const int grid = (g.nwork + 7) / 8 * 8;
+    const int grid = (g.nwork * nband + 7) / 8 * 8;
     const int64_t tstride = g.ncol * m;
     if (ev) hipEventRecord(ev[0], st);
-    hipLaunchKernelGGL(k_ggemm<C>, rhs_grid(grid, nrhs), dim3(256), 0, st, g.hdr, g.src, (const C *)A, m, kin,
-                       (const C *)X, xstride, (C *)g.tmp, tstride, g.nwork, nrhs);
+    hipLaunchKernelGGL(k_ggemm<C>, rhs_grid(grid, nrhs), dim3(256), 0, st, g.hdr, g.src, g.dst, (const C *)A, m,
+                       kin, (const C *)X, xstride, (C *)g.tmp, tstride, (C *)Y, ystride, accumulate, g.nwork, nband,
+                       nrhs);
     CHECK_LAUNCH();
     if (ev) hipEventRecord(ev[1], st);
+    if (g.dst) return hipSuccess;  // every destination had one product, written in place
     hipLaunchKernelGGL(k_gather_reduce<C>, dim3(g.nred, nrhs), dim3(std::min(256, ((m + 63) / 64) * 64)), 0, st,
                        g.rd_dst, g.rd_off, g.rd_list, m, (const C *)g.tmp, tstride, (C *)Y, ystride, accumulate);
     CHECK_LAUNCH();

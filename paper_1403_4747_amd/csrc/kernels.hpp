@@ -12,11 +12,14 @@ namespace fda {
 // per work item (matrix, first scratch column, column count, 0) and
 // kGemmCols source states; per destination state the scratch columns summed
 // into it.  tmp holds ncol scratch columns of length m per right-hand side.
+// When every destination receives exactly one product, dst lists each
+// item's destination states (kGemmCols per item) and the products are
+// written to them directly (no scratch, no reduction).
 struct GWork {
     int nwork = 0, nred = 0;
     int64_t ncol = 0;
     int4 *hdr = nullptr;
-    int32_t *src = nullptr, *rd_dst = nullptr, *rd_off = nullptr, *rd_list = nullptr;
+    int32_t *src = nullptr, *dst = nullptr, *rd_dst = nullptr, *rd_off = nullptr, *rd_list = nullptr;
     void *tmp = nullptr;  // storage type of the plan (double2 or float2)
 };
 
