@@ -81,6 +81,23 @@ def cpu_baseline(V, T, k, x, y_gpu, rows_sample, seconds_target=20.0):
                 seconds_per_matvec=full, one_thread_extrapolated=one), err, rows, yr
 
 
+def mlp_held_out(weights_path):
+    """The network's training size and held-out evaluation, as stored beside
+    its weights by the training driver (its report), or None."""
+    rep = os.path.splitext(weights_path)[0] + ".json"
+    if not os.path.exists(rep):
+        return None
+    with open(rep) as f:
+        sm = json.load(f).get("summary", {})
+    tr, ev = sm.get("train", {}), sm.get("eval", {})
+    if not ev:
+        return None
+    return dict(train_solves=tr.get("train_solves"), eval_solves=ev.get("eval_solves"),
+                mean_iterations=ev.get("mean_iterations"), judge_rejected=ev.get("judge_rejected"),
+                fewer_iterations_than_block_jacobi=ev.get("mlp_fewer_iterations_than_bj"),
+                beats_block_jacobi=bool(ev["mean_iterations"]["mlp"] < ev["mean_iterations"]["block_jacobi"]))
+
+
 def uneven_batch_leg(nmesh, steps, log, tune=True):
     """The seeded uneven batch (spheres and ellipsoids, N 5,120-81,920,
     kD 20-100): every plan's product run one after another on one stream,
@@ -584,10 +601,27 @@ def main():
                                            rel_residual=info["rel_residual"], converged=info["converged"])
                 if pc == "mlp":
                     fast["solve_mlp"].update(mlp_rejected=info["mlp_rejected"], mlp_fallbacks=info["mlp_fallbacks"],
-                                             weights=os.path.relpath(args.mlp_weights, ROOT))
+                                             weights=os.path.relpath(args.mlp_weights, ROOT),
+                                             held_out=mlp_held_out(args.mlp_weights))
             # difference of the two arms' solutions (surface field)
             u64, _ = plan.solve(b, tol=1e-5, restart=50, maxit=2000)
             fast["solution_rel_diff_vs_fp64_arm"] = float(torch.linalg.norm(u32 - u64) / torch.linalg.norm(u64))
+        if args.nrhs_multi > 1:
+            # the same many-column product on the FP32 plan
+            xm = torch.from_numpy(np.ascontiguousarray(W.complex_normal(n, args.nrhs_multi, seed=1).T)).to("cuda")
+            ym = torch.empty_like(xm)
+            plan32.matvec(xm, out=ym)
+            torch.cuda.synchronize()
+            reps = max(3, args.steps // 10)
+            e0.record(stream)
+            for _ in range(reps):
+                plan32.matvec(xm, out=ym)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            msm = e0.elapsed_time(e1) / reps
+            fast["multi_rhs"] = dict(nrhs=args.nrhs_multi, ms_per_matvec=round(msm, 4),
+                                     columns_per_s=round(args.nrhs_multi * 1000.0 / msm, 2))
+            del xm, ym
         fast["y32"] = y32.cpu().numpy()
         plan32.close()
         log("[bench] fast arm: " + str({q: v for q, v in fast.items() if q != 'y32'}))

@@ -351,9 +351,9 @@ __device__ __forceinline__ C group_sum(C acc) {
 // elements in order) is gathered into LDS in one parallel pass.  A row is
 // taken by a group of kP2PGroup lanes (four rows per wave, sixteen per
 // workgroup), each lane summing the columns lane, lane + kP2PGroup, ... in
-// order, with four row loads in flight: rows are a few hundred columns
-// long, so full-wave rows would leave lanes idle in their last chunk and
-// wait on one load at a time.
+// order, with kP2PUnroll row loads in flight: rows are a few hundred
+// columns long, so full-wave rows would leave lanes idle in their last
+// chunk and wait on one load at a time.
 template <class C, int R>
 __global__ void __launch_bounds__(256) k_p2p(const int4 *items, const int64_t *leaf_off, const int64_t *col_off,
                                              const int32_t *cols, const int64_t *blk_off, const C *vals,
@@ -386,15 +386,16 @@ __global__ void __launch_bounds__(256) k_p2p(const int4 *items, const int64_t *l
         if (i < it.z) {
             const C *row = blk + (int64_t)i * nc;
             int c = lane;
-            for (; c + 3 * G < nc; c += 4 * G) {
-                const C v0 = row[c], v1 = row[c + G], v2 = row[c + 2 * G], v3 = row[c + 3 * G];
+            constexpr int U = kP2PUnroll;
+            for (; c + (U - 1) * G < nc; c += U * G) {
+                C v[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) v[u] = row[c + u * G];
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     const C *xr = xs + r * nc + c;
-                    cmac(acc[r], v0, xr[0]);
-                    cmac(acc[r], v1, xr[G]);
-                    cmac(acc[r], v2, xr[2 * G]);
-                    cmac(acc[r], v3, xr[3 * G]);
+#pragma unroll
+                    for (int u = 0; u < U; ++u) cmac(acc[r], v[u], xr[u * G]);
                 }
             }
             for (; c < nc; c += G) {

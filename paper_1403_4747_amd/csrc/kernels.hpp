@@ -46,6 +46,7 @@ constexpr int kM2LVariants = 4;
 constexpr int kL2TChunk = 2048;  // incoming-state entries of a leaf staged in LDS at a time by L2T
 constexpr int kP2PShortCols = FDA_P2P_SHORT_COLS;  // near-field rows up to this length: x staged in LDS
 constexpr int kP2PGroup = 16;  // lanes per near-field row in k_p2p
+constexpr int kP2PUnroll = 8;  // row loads in flight per lane in k_p2p (4: 0.077 ms, 8: 0.075 ms FP64 at N = 81,920)
 constexpr int kP2PItemEntries = 24576;  // near-field block entries per work item (at least 4 rows)  // ring-depth variants of the low-rank M2L kernel
 
 struct M2LMerged {
