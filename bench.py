@@ -529,7 +529,10 @@ def main():
                         frac=round(achieved / FP64_PEAK_TFLOPS, 4), traffic=None,
                         kernel=f"k_m2l_lowrank<double2> (M2L, levels {lowr} in one launch)", launches_per_matvec=1,
                         flops_per_launch=lr_flops, avg_launch_ms=round(lr_ms, 5),
-                        full_rank_levels=full)
+                        full_rank_levels=full,
+                        # every distinct factor once, every outgoing state
+                        # read once, every incoming state written once
+                        algorithmic_bytes=int(st["m2l_factor_bytes"] + st["m2l_state_bytes"]))
     else:
         ms_f = sum(prof["m2l_gemm"][l] for l in full)
         fl_f = sum(float(st["m2l_level_flops"][l]) for l in full)

@@ -152,6 +152,11 @@ typedef struct fda_stats {
                                    element pair is covered once: near_nnz + far_elem_pairs = n^2 */
     int64_t max_near_cols;      /* longest near-field row (source elements of one leaf) */
     int64_t wx_elem_pairs;      /* entries of near_nnz that come from W and X pairs */
+    int64_t m2l_factor_bytes;   /* low-rank M2L levels: bytes of the distinct factors U^ (kd x r) and
+                                   V^ (r x ku) at the unpadded SVD ranks, in the plan's storage type */
+    int64_t m2l_state_bytes;    /* low-rank M2L levels: bytes of the outgoing states read and the
+                                   incoming states written by one pass, per right-hand side; with
+                                   m2l_factor_bytes the pass's algorithmic traffic */
 } fda_stats;
 
 /* Fill *opt with the defaults listed above. */

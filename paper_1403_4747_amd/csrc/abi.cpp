@@ -866,12 +866,15 @@ int fda_build(const double *verts, int64_t nv, const int32_t *tris, int64_t nt, 
         // translation (before the kernel pads it to a multiple of 4); full
         // levels 8 kd ku
         int64_t tot = 0;
+        const int64_t es = p->d.prec == FDA_PREC_FP32 ? 8 : 16;  // bytes per complex entry
         for (int l = 0; l <= p->hp.depth && l < 24; ++l) {
             const Level &lv = p->hp.lv[l];
             double f = 0;
             if (!lr_rank_host.empty() && !lr_rank_host[l].empty()) {
                 for (const auto &ops : lv.il_ops)
                     for (int op : ops) f += 8.0 * lr_rank_host[l][op] * (lv.kd + lv.ku);
+                for (int r : lr_rank_host[l]) p->stats.m2l_factor_bytes += es * r * (int64_t)(lv.kd + lv.ku);
+                p->stats.m2l_state_bytes += es * lv.nbox * (int64_t)lv.nslot * (lv.kd + lv.ku);
                 p->stats.m2l_rank_max[l] = tr_rmax[l];
             } else {
                 int64_t pairs = 0;

@@ -62,7 +62,7 @@ class Stats(ctypes.Structure):
         ("build_phase_seconds", ctypes.c_double * 8), ("leaves", ctypes.c_int64 * 24),
         ("u_pairs", ctypes.c_int64), ("w_pairs", ctypes.c_int64), ("x_pairs", ctypes.c_int64),
         ("far_elem_pairs", ctypes.c_int64), ("max_near_cols", ctypes.c_int64),
-        ("wx_elem_pairs", ctypes.c_int64),
+        ("wx_elem_pairs", ctypes.c_int64), ("m2l_factor_bytes", ctypes.c_int64), ("m2l_state_bytes", ctypes.c_int64),
     ]
 
     def to_dict(self) -> Dict:
