@@ -367,8 +367,9 @@ void build_m2l_list(fda_plan *p, M2LMerged &mm, std::vector<void *> &fresh) {
         const int slot = (int)args.size();
         M2LLevelArgs la = lh.la;
         la.tbase = nscratch;
+        la.ldt = (la.kd + 3) & ~3;
         args.push_back(la);
-        nscratch += g.ncol * (int64_t)la.kd;
+        nscratch += g.ncol * (int64_t)la.ldt;
         // XCD order: each level's items are split into 8 contiguous chunks,
         // one per XCD queue, so every XCD gets the same share of every level
         // (and consecutive items of a translation share an L2)

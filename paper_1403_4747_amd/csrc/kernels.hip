@@ -822,8 +822,8 @@ __device__ __forceinline__ void m2l_p1_direct(CAcc<C> *zacc, const C *xcol, cons
 // usual ranks (r <= 32, two column tiles: four tiles) keep every wave busy.
 template <class C, int NCT, int P1D, int P1D1, int PD>
 __device__ __forceinline__ void m2l_body(const int4 h, const int32_t *sidx, const C *Ut, const C *Vt, int r, int kd,
-                                         int ku, int rmax, const C *Xr, C *Tr, C (*S)[GG_LD], C (*Vs)[LR_LD],
-                                         C (*Z)[GG_LD]) {
+                                         int ku, int rmax, const C *Xr, C *Tr, int ldt, C (*S)[GG_LD],
+                                         C (*Vs)[LR_LD], C (*Z)[GG_LD]) {
     using v4 = typename CT<C>::v4;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lk = lane >> 4;
@@ -1029,7 +1029,7 @@ __device__ __forceinline__ void m2l_body(const int4 h, const int32_t *sidx, cons
                         C o;
                         o.x = acc[q][c].re(v);
                         o.y = acc[q][c].im(v);
-                        Tr[(int64_t)col * kd + row] = o;
+                        Tr[(int64_t)col * ldt + row] = o;
                     }
                 }
             }
@@ -1065,14 +1065,14 @@ k_m2l_lowrank(const int4 *hdr, const int32_t *src, const M2LLevelArgs *args, C *
     const int r = la.rank[op];
     if (threadIdx.x < GG_NB) sidx[threadIdx.x] = src[(int64_t)w * GG_NB + threadIdx.x];
     const C *Xr = (const C *)la.X + (int64_t)rb.rhs * la.xstride;
-    C *Tr = T + (int64_t)rb.rhs * tstride + la.tbase + (int64_t)h.y * kd;
+    C *Tr = T + (int64_t)rb.rhs * tstride + la.tbase + (int64_t)h.y * la.ldt;
     const C *Vt = (const C *)la.V + (int64_t)op * rmax * ((ku + 3) & ~3);
     const C *Ut = (const C *)la.U + (int64_t)op * kd * rmax;
     using V = M2LVariant<VAR>;
     if (h.z > 16)
-        m2l_body<C, 2, V::p1d, V::p1d1, V::pd>(h, sidx, Ut, Vt, r, kd, ku, rmax, Xr, Tr, S, Vs, Z);
+        m2l_body<C, 2, V::p1d, V::p1d1, V::pd>(h, sidx, Ut, Vt, r, kd, ku, rmax, Xr, Tr, la.ldt, S, Vs, Z);
     else
-        m2l_body<C, 1, V::p1d, V::p1d1, V::pd>(h, sidx, Ut, Vt, r, kd, ku, rmax, Xr, Tr, S, Vs, Z);
+        m2l_body<C, 1, V::p1d, V::p1d1, V::pd>(h, sidx, Ut, Vt, r, kd, ku, rmax, Xr, Tr, la.ldt, S, Vs, Z);
 }
 
 // c[dst] = sum of the M2L scratch columns listed for dst (every state of the
@@ -1089,6 +1089,7 @@ __global__ void __launch_bounds__(kRedRows) k_gather_reduce_m2l(const int32_t *d
     while (q + 1 < nlev && (int)blockIdx.x >= rd_block[q + 1]) ++q;
     const M2LLevelArgs &la = args[q];
     const int m = la.kd;
+    const int64_t ld = la.ldt;  // scratch column stride
     const int64_t e = (int64_t)(blockIdx.x - rd_block[q]) * kRedRows + threadIdx.x;
     const int64_t sl = e / m;
     const int r = (int)(e - sl * m);
@@ -1101,8 +1102,8 @@ __global__ void __launch_bounds__(kRedRows) k_gather_reduce_m2l(const int32_t *d
     const int q0 = off[t], q1 = off[t + 1];
     int k = q0;
     for (; k + 4 <= q1; k += 4) {
-        const C v0 = Tr[(int64_t)list[k] * m + r], v1 = Tr[(int64_t)list[k + 1] * m + r];
-        const C v2 = Tr[(int64_t)list[k + 2] * m + r], v3 = Tr[(int64_t)list[k + 3] * m + r];
+        const C v0 = Tr[(int64_t)list[k] * ld + r], v1 = Tr[(int64_t)list[k + 1] * ld + r];
+        const C v2 = Tr[(int64_t)list[k + 2] * ld + r], v3 = Tr[(int64_t)list[k + 3] * ld + r];
         acc.x += v0.x;
         acc.y += v0.y;
         acc.x += v1.x;
@@ -1113,7 +1114,7 @@ __global__ void __launch_bounds__(kRedRows) k_gather_reduce_m2l(const int32_t *d
         acc.y += v3.y;
     }
     for (; k < q1; ++k) {
-        const C v = Tr[(int64_t)list[k] * m + r];
+        const C v = Tr[(int64_t)list[k] * ld + r];
         acc.x += v.x;
         acc.y += v.y;
     }

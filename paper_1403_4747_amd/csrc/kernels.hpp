@@ -38,6 +38,8 @@ struct M2LLevelArgs {
     int64_t xstride = 0, ystride = 0;       // elements per right-hand side
     int64_t tbase = 0;                      // first scratch element of the level
     int32_t kd = 0, ku = 0, rmax = 0, level = 0;
+    int32_t ldt = 0;                        // scratch column stride: kd rounded up to a multiple of 4
+                                            // (FP64 columns start on 64-byte boundaries)
 };
 constexpr int kM2LVariants = 4;
 #ifndef FDA_P2P_SHORT_COLS
