@@ -1085,12 +1085,17 @@ __global__ void __launch_bounds__(kRedRows) k_gather_reduce_m2l(const int32_t *d
                                                                 const int32_t *rd_state, int nlev,
                                                                 const M2LLevelArgs *args, const C *T,
                                                                 int64_t tstride) {
+    // blocks run from the last level slot to the first: the finest levels'
+    // states have the longest lists (about 45 scratch columns each against
+    // 10 at the directional levels), and starting them first keeps them from
+    // forming the launch's tail (0.158 -> 0.128 ms at N = 81,920, kD = 100)
+    const int bx = (int)(gridDim.x - 1 - blockIdx.x);
     int q = 0;
-    while (q + 1 < nlev && (int)blockIdx.x >= rd_block[q + 1]) ++q;
+    while (q + 1 < nlev && bx >= rd_block[q + 1]) ++q;
     const M2LLevelArgs &la = args[q];
     const int m = la.kd;
     const int64_t ld = la.ldt;  // scratch column stride
-    const int64_t e = (int64_t)(blockIdx.x - rd_block[q]) * kRedRows + threadIdx.x;
+    const int64_t e = (int64_t)(bx - rd_block[q]) * kRedRows + threadIdx.x;
     const int64_t sl = e / m;
     const int r = (int)(e - sl * m);
     const int64_t t = rd_state[q] + sl;
