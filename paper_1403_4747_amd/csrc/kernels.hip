@@ -1185,12 +1185,27 @@ __global__ void __launch_bounds__(256) k_l2t(const int64_t *leaf_off, const int3
             v[r * kc + j] = r < nr ? c[(int64_t)(r0 + r) * cstride + co + q0 + j] : czero<C>();
         }
         __syncthreads();
-        if (i < nl)
-            for (int q = q0 + g; q < q1; q += G) {
+        if (i < nl) {
+            // four operator loads in flight (a group's column loop is only
+            // about ten steps long; one load at a time left it waiting:
+            // 0.034 -> 0.028 ms FP64 at N = 81,920); columns summed in
+            // increasing order
+            int q = q0 + g;
+            for (; q + 3 * G < q1; q += 4 * G) {
+                C m[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) m[u] = Tb[i + (int64_t)(q + u * G) * nl];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int r = 0; r < R; ++r) cmac(acc[r], m[u], v[r * kc + q + u * G - q0]);
+            }
+            for (; q < q1; q += G) {
                 const C m = Tb[i + (int64_t)q * nl];
 #pragma unroll
                 for (int r = 0; r < R; ++r) cmac(acc[r], m, v[r * kc + q - q0]);
             }
+        }
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) part[r * 256 + t] = acc[r];
@@ -1649,9 +1664,6 @@ static hipError_t launch_l2t_t(const DevPlan &d, const DevLevel &lf, const doubl
     }
 }
 
-#ifndef FDA_NEAR_FORK
-#define FDA_NEAR_FORK 1  // 0: the side-stream near field starts with the matvec; 1: with the M2L
-#endif
 // Stage timings are recorded when ev != nullptr (7 events: start, after
 // near, after S2M, after M2M, after M2L, after L2L, end).
 template <class C>
@@ -1682,7 +1694,7 @@ static hipError_t matvec_t(const DevPlan &d, const double2 *xt, double2 *yt, int
     if (!overlap) {
         const hipError_t e = launch_p2p_t<C>(d, op, xt, yt, nrhs, st);
         if (e != hipSuccess) return e;
-    } else if (FDA_NEAR_FORK == 0) {
+    } else {  // the side stream starts with the matvec (beside S2M, M2M and M2L)
         const hipError_t e = near_side();
         if (e != hipSuccess) return e;
     }
@@ -1707,10 +1719,6 @@ static hipError_t matvec_t(const DevPlan &d, const double2 *xt, double2 *yt, int
         if (e != hipSuccess) return e;
     }
     if (ev) hipEventRecord(ev[3], st);
-    if (overlap && FDA_NEAR_FORK == 1) {
-        const hipError_t e = near_side();
-        if (e != hipSuccess) return e;
-    }
     if (d.m2l_all.nwork > 0) {
         const hipError_t e = m2l_merged_t<C>(d.m2l_all, nrhs, st, lev ? lev + 48 : nullptr);
         if (e != hipSuccess) return e;
