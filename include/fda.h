@@ -89,7 +89,8 @@ typedef struct fda_options {
     int32_t device;        /* HIP device ordinal, default 0 */
     int32_t verbose;       /* print build statistics to stderr, default 0 */
     int32_t svd_method;    /* batched SVDs of the build (eqs. (eq_svdg), (eq_epsk)): 0 = bidiagonal QR
-                              (rocSOLVER gesvd), 1 = one-sided Jacobi (gesvdj); default 0 */
+                              (rocSOLVER gesvd), 1 = one-sided Jacobi (gesvdj); default 1 (the
+                              same ranks, a faster build) */
     double m2l_svd_eps;    /* truncation of the reduced M2L matrices alone (eq. (eq_epsk));
                               0 = svd_eps */
     int32_t neumann_rhs;   /* also build the right-hand operator B of eq. (eq_bm) for Neumann data

@@ -714,7 +714,7 @@ void fda_default_options(fda_options *o) {
     o->nrhs_max = 64;
     o->device = 0;
     o->verbose = 0;
-    o->svd_method = 0;
+    o->svd_method = 1;
 }
 
 const char *fda_last_error(void) { return g_last_error.c_str(); }

@@ -98,6 +98,32 @@ def test_leaf_capacity_variants_match_oracle(name, max_leaf):
     assert float(torch.linalg.norm(u1 - u0) / torch.linalg.norm(u0)) <= 1e-4
 
 
+def test_both_svd_methods_match_oracle():
+    """The build's batched SVDs by one-sided Jacobi (svd_method 1, the
+    default) and by bidiagonalisation + QR (0) truncate to the same ranks,
+    and both products meet the oracle on the 5,120-triangle sphere at
+    kD = 20 (their difference is a rotation inside the kept subspaces,
+    orders below the matvec bound)."""
+    _say("[edge] svd_method 0 and 1")
+    V, T, prm = W.workload("sphere5120_kD20")
+    k = prm["k"]
+    x = W.complex_normal(len(T), 1, seed=6)
+    ys, ranks = [], []
+    for meth in (0, 1):
+        with _plan(V, T, k, prm["eps"], svd_method=meth) as p:
+            st = p.stats()
+            ranks.append((st["rank_up"], st["rank_dn"], st["m2l_rank_max"]))
+            ys.append(p.matvec(_dev(x)).cpu().numpy())
+    yr = O.matvec(V, T, k, x)
+    # a singular value within rounding of the truncation threshold could be
+    # kept by one method and dropped by the other: ranks agree to one
+    for a0, a1 in zip(ranks[0], ranks[1]):
+        assert all(abs(int(u) - int(v)) <= 1 for u, v in zip(a0, a1)), ranks
+    for y in ys:
+        assert _rel(y, yr) <= 1e-4
+    assert _rel(ys[1], ys[0]) <= 5e-5
+
+
 def test_padded_leading_dimension_through_the_c_abi():
     """x and y with leading dimension ld = N + 7 (column-major N x nrhs):
     the product equals the contiguous one and the padding is untouched."""
