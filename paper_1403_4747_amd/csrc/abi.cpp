@@ -344,9 +344,10 @@ void build_m2l_merged(fda_plan *p) {
 
 void build_m2l_list(fda_plan *p, M2LMerged &mm, std::vector<void *> &fresh) {
     std::vector<int32_t> hdr, src, dst, off{0}, list, lev;
+    std::vector<int32_t> ent, nst;  // many-column form: per list entry and per state
     std::vector<std::vector<int32_t>> queue[8];  // per XCD queue (or queue 0 only): header + sources of each item
     std::vector<M2LLevelArgs> args;
-    int64_t nscratch = 0;
+    int64_t nscratch = 0, nz = 0;
     const bool xcd = p->m2l_cfg.xcd_order != 0;
     for (const auto &lh : p->m2l_host) {
         const size_t width = p->m2l_cfg.width[lh.level] == 16 ? 16 : kGemmCols;
@@ -368,8 +369,13 @@ void build_m2l_list(fda_plan *p, M2LMerged &mm, std::vector<void *> &fresh) {
         M2LLevelArgs la = lh.la;
         la.tbase = nscratch;
         la.ldt = (la.kd + 3) & ~3;
+        la.zbase = nz;
         args.push_back(la);
         nscratch += g.ncol * (int64_t)la.ldt;
+        nz += g.ncol * (int64_t)la.rmax;
+        std::vector<int32_t> col_op(g.ncol, 0);  // translation of each pair column
+        for (size_t i = 0; i < g.hdr.size() / 4; ++i)
+            for (int32_t b = 0; b < g.hdr[4 * i + 2]; ++b) col_op[g.hdr[4 * i + 1] + b] = g.hdr[4 * i];
         // XCD order: each level's items are split into 8 contiguous chunks,
         // one per XCD queue, so every XCD gets the same share of every level
         // (and consecutive items of a translation share an L2)
@@ -384,11 +390,18 @@ void build_m2l_list(fda_plan *p, M2LMerged &mm, std::vector<void *> &fresh) {
             dst.push_back((int32_t)s);
             lev.push_back(slot);
             auto it = g.dest_index.find((int32_t)s);
+            int32_t steps = 0;
             if (it != g.dest_index.end()) {
                 const auto &pl = g.parts[it->second];
                 list.insert(list.end(), pl.begin(), pl.end());
+                for (int32_t c : pl) {
+                    const int32_t op = col_op[c], ks = lh.prank[op] / 4;
+                    ent.insert(ent.end(), {c, op, ks, 0});
+                    steps += ks;
+                }
             }
             off.push_back((int32_t)list.size());
+            nst.push_back(steps);
         }
     }
     // launch order: XCD order has block b run on XCD b % 8 (round-robin
@@ -418,6 +431,17 @@ void build_m2l_list(fda_plan *p, M2LMerged &mm, std::vector<void *> &fresh) {
         rstate.push_back(rstate.back() + (int32_t)ns);
     }
     mm.nredblocks = rblock.back();
+    // destination-major units of the many-column form, the last level slot
+    // (the longest lists) first; the form needs its Z (rmax rows per pair)
+    // to fit in the scratch of the kd-row columns
+    std::vector<int32_t> units;
+    if (nz <= nscratch)
+        for (int q = (int)args.size() - 1; q >= 0; --q) {
+            const int nt = (args[q].kd + 15) / 16;
+            for (int64_t s = 0; s < p->m2l_host[q].nstates; ++s)
+                for (int rt = 0; rt < nt; rt += 4) units.insert(units.end(), {rstate[q] + (int32_t)s, rt, q, 0});
+        }
+    mm.nzunits = (int)(units.size() / 4);
     mm.nscratch = nscratch;
     mm.hargs = args;
     mm.variant = p->m2l_cfg.variant;
@@ -430,6 +454,11 @@ void build_m2l_list(fda_plan *p, M2LMerged &mm, std::vector<void *> &fresh) {
         mm.rd_lev = upload_to(p, lev, fresh);
         mm.rd_block = upload_to(p, rblock, fresh);
         mm.rd_state = upload_to(p, rstate, fresh);
+        if (mm.nzunits > 0) {
+            mm.rd_ent = (int4 *)upload_to(p, ent, fresh);
+            mm.rd_nst = upload_to(p, nst, fresh);
+            mm.zunits = (int4 *)upload_to(p, units, fresh);
+        }
         mm.args = dalloc<M2LLevelArgs>(p, args.size(), fresh);
         if (p->cap_nrhs > 0) {
             // work buffers exist: point the level table at them

@@ -820,7 +820,10 @@ __device__ __forceinline__ void m2l_p1_direct(CAcc<C> *zacc, const C *xcol, cons
 // work list, scratch layout and reduction as k_ggemm.  Phase 1 spreads its
 // (row tile, column tile) outputs over the 4 waves round-robin so that the
 // usual ranks (r <= 32, two column tiles: four tiles) keep every wave busy.
-template <class C, int NCT, int P1D, int P1D1, int PD>
+//
+// ZOUT (the many-column form): the item stores rows 0 .. r - 1 of Z, column
+// col at Tr + col * ldt, and skips phase 2.
+template <class C, int NCT, int P1D, int P1D1, int PD, bool ZOUT>
 __device__ __forceinline__ void m2l_body(const int4 h, const int32_t *sidx, const C *Ut, const C *Vt, int r, int kd,
                                          int ku, int rmax, const C *Xr, C *Tr, int ldt, C (*S)[GG_LD],
                                          C (*Vs)[LR_LD], C (*Z)[GG_LD]) {
@@ -964,6 +967,13 @@ __device__ __forceinline__ void m2l_body(const int4 h, const int32_t *sidx, cons
         }
         __syncthreads();
     }
+    if constexpr (ZOUT) {
+        for (int e = threadIdx.x; e < h.z * r; e += blockDim.x) {
+            const int col = e / r, row = e - col * r;
+            Tr[(int64_t)col * ldt + row] = Z[row][col];
+        }
+        return;
+    }
     // phase 2: Y = U^[:, 0:r] Z (kd <= 256: 16 row tiles, 4 per wave, taken
     // two at a time to keep the accumulators small)
     const int ntile = (kd + 15) >> 4;
@@ -1038,8 +1048,10 @@ __device__ __forceinline__ void m2l_body(const int4 h, const int32_t *sidx, cons
 }
 
 // One launch for the low-rank M2L of every level: the item's level slot
-// (h.w) selects its factors, states and scratch region.
-template <class C, int VAR>
+// (h.w) selects its factors, states and scratch region.  ZOUT: phase 1
+// only, Z of pair column c (level-local) and right-hand side j stored at
+// T + zbase nrhs + (c nrhs + j) rmax.
+template <class C, int VAR, bool ZOUT = false>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M2LOcc<C>::waves)))
 k_m2l_lowrank(const int4 *hdr, const int32_t *src, const M2LLevelArgs *args, C *T, int64_t tstride, int nwork,
               int nrhs) {
@@ -1065,14 +1077,122 @@ k_m2l_lowrank(const int4 *hdr, const int32_t *src, const M2LLevelArgs *args, C *
     const int r = la.rank[op];
     if (threadIdx.x < GG_NB) sidx[threadIdx.x] = src[(int64_t)w * GG_NB + threadIdx.x];
     const C *Xr = (const C *)la.X + (int64_t)rb.rhs * la.xstride;
-    C *Tr = T + (int64_t)rb.rhs * tstride + la.tbase + (int64_t)h.y * la.ldt;
+    C *Tr = ZOUT ? T + la.zbase * nrhs + ((int64_t)h.y * nrhs + rb.rhs) * rmax
+                 : T + (int64_t)rb.rhs * tstride + la.tbase + (int64_t)h.y * la.ldt;
+    const int ldt = ZOUT ? nrhs * rmax : la.ldt;
     const C *Vt = (const C *)la.V + (int64_t)op * rmax * ((ku + 3) & ~3);
     const C *Ut = (const C *)la.U + (int64_t)op * kd * rmax;
     using V = M2LVariant<VAR>;
     if (h.z > 16)
-        m2l_body<C, 2, V::p1d, V::p1d1, V::pd>(h, sidx, Ut, Vt, r, kd, ku, rmax, Xr, Tr, la.ldt, S, Vs, Z);
+        m2l_body<C, 2, V::p1d, V::p1d1, V::pd, ZOUT>(h, sidx, Ut, Vt, r, kd, ku, rmax, Xr, Tr, ldt, S, Vs, Z);
     else
-        m2l_body<C, 1, V::p1d, V::p1d1, V::pd>(h, sidx, Ut, Vt, r, kd, ku, rmax, Xr, Tr, la.ldt, S, Vs, Z);
+        m2l_body<C, 1, V::p1d, V::p1d1, V::pd, ZOUT>(h, sidx, Ut, Vt, r, kd, ku, rmax, Xr, Tr, ldt, S, Vs, Z);
+}
+
+// The many-column form's second phase: c_t = sum over the interaction list
+// of state t of U^_p Z_p (U^_p: kd x r_p, Z_p: the pair's phase-1 product,
+// r_p x nrhs), accumulated on the matrix cores across the list and written
+// once; with many columns every U^ fragment meets 16 NCT of them, so the
+// destination-major order is dense.  Wave w of a workgroup owns row tile
+// units.y + w of the state (exiting when it lies past kd) and columns
+// 16 NCT blockIdx.y ..; its k loop runs over the list's pairs in list
+// order, rank by rank, with the U^ and Z fragments loaded PD k-steps ahead
+// (a fetch cursor walks the entries; past the last step it re-reads that
+// step, never used).  No LDS, no barriers.
+#ifndef FDA_M2L_DEST_PD
+#define FDA_M2L_DEST_PD 4
+#endif
+template <class C>
+struct M2LDestOcc {
+    static constexpr int waves = 2;  // FP64: 96 accumulator registers at 64 columns
+};
+template <>
+struct M2LDestOcc<float2> {
+    static constexpr int waves = 4;
+};
+template <class C, int NCT, int PD>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M2LDestOcc<C>::waves))) k_m2l_dest(const int4 *units, const int4 *ent, const int32_t *off,
+                                                  const int32_t *nst, const int32_t *dst, const M2LLevelArgs *args,
+                                                  const C *Zs, int nrhs) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int li = lane & 15, lk = lane >> 4;
+    const int4 un = units[blockIdx.x];  // (state, first row tile, level slot, 0)
+    const M2LLevelArgs &la = args[un.z];
+    const int kd = la.kd, rmax = la.rmax;
+    const int rt = un.y + wave;
+    if (rt * 16 >= kd) return;
+    const int t = un.x;
+    const int c0 = (int)blockIdx.y * 16 * NCT;
+    const int64_t zp = (int64_t)nrhs * rmax;  // Z elements per pair
+    const C *Zl = Zs + la.zbase * nrhs;
+    const C *U = (const C *)la.U;
+    const int64_t ukd = (int64_t)kd * rmax;  // U^ elements per translation
+    const int arow = min(rt * 16 + li, kd - 1);
+    int64_t bo[NCT];
+#pragma unroll
+    for (int c = 0; c < NCT; ++c) bo[c] = (int64_t)min(c0 + c * 16 + li, nrhs - 1) * rmax + lk;
+    CAcc<C> acc[NCT];
+#pragma unroll
+    for (int c = 0; c < NCT; ++c) acc[c].zero();
+    const int ns = nst[t];
+    if (ns > 0) {
+        int fe = off[t];
+        const int last = off[t + 1] - 1;
+        int4 en = ent[fe];  // (pair, translation, rank / 4, 0)
+        int fk = 0;
+        const C *fa = U + en.y * ukd + arow + (int64_t)lk * kd;
+        const C *fb = Zl + en.x * zp;
+        auto fetch = [&](C &a, C (&b)[NCT]) {
+            a = gload(fa + (int64_t)(4 * fk) * kd);
+#pragma unroll
+            for (int c = 0; c < NCT; ++c) b[c] = gload(fb + bo[c] + 4 * fk);
+            if (++fk == en.z) {
+                if (fe < last) {
+                    en = ent[++fe];
+                    fk = 0;
+                    fa = U + en.y * ukd + arow + (int64_t)lk * kd;
+                    fb = Zl + en.x * zp;
+                } else {
+                    fk = en.z - 1;
+                }
+            }
+        };
+        C ar[PD], br[PD][NCT];
+#pragma unroll
+        for (int d = 0; d < PD; ++d) fetch(ar[d], br[d]);
+        int s = 0;
+        for (; s + PD <= ns; s += PD) {
+#pragma unroll
+            for (int d = 0; d < PD; ++d) {
+#pragma unroll
+                for (int c = 0; c < NCT; ++c) acc[c].mac(ar[d], br[d][c]);
+                fetch(ar[d], br[d]);
+            }
+        }
+#pragma unroll
+        for (int d = 0; d < PD; ++d)
+            if (s + d < ns) {
+#pragma unroll
+                for (int c = 0; c < NCT; ++c) acc[c].mac(ar[d], br[d][c]);
+            }
+    }
+    C *Y = (C *)la.Y + (int64_t)dst[t] * kd;
+#pragma unroll
+    for (int c = 0; c < NCT; ++c) {
+        const int col = c0 + c * 16 + li;
+        if (col >= nrhs) continue;
+        C *o = Y + (int64_t)col * la.ystride;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = rt * 16 + CT<C>::row(lk, v);
+            if (row < kd) {
+                C y;
+                y.x = acc[c].re(v);
+                y.y = acc[c].im(v);
+                o[row] = y;
+            }
+        }
+    }
 }
 
 // c[dst] = sum of the M2L scratch columns listed for dst (every state of the
@@ -1553,6 +1673,25 @@ template <class C>
 static hipError_t m2l_merged_t(const M2LMerged &mm, int nrhs, hipStream_t st, hipEvent_t *ev) {
     const dim3 g2 = rhs_grid(mm.nwork, nrhs);  // items ordered for XCD dispatch (or in translation order)
     if (ev) hipEventRecord(ev[0], st);
+    if (nrhs >= kM2LManyCols && mm.nzunits > 0) {
+        // many-column form: Z per pair, then the destination-major U^ Z
+        hipLaunchKernelGGL((k_m2l_lowrank<C, 0, true>), g2, dim3(256), 0, st, mm.hdr, mm.src, mm.args, (C *)mm.tmp,
+                           mm.nscratch, mm.nwork, nrhs);
+        CHECK_LAUNCH();
+        if (ev) hipEventRecord(ev[1], st);
+        constexpr int PD = FDA_M2L_DEST_PD;
+        auto go = [&](auto nc) -> hipError_t {
+            constexpr int NCT = decltype(nc)::value;
+            const dim3 g((unsigned)mm.nzunits, (unsigned)((nrhs + 16 * NCT - 1) / (16 * NCT)));
+            hipLaunchKernelGGL((k_m2l_dest<C, NCT, PD>), g, dim3(256), 0, st, mm.zunits, mm.rd_ent, mm.rd_off,
+                               mm.rd_nst, mm.rd_dst, mm.args, (const C *)mm.tmp, nrhs);
+            CHECK_LAUNCH();
+            return hipSuccess;
+        };
+        if (nrhs >= 64) return go(std::integral_constant<int, 4>{});
+        if (nrhs >= 32) return go(std::integral_constant<int, 2>{});
+        return go(std::integral_constant<int, 1>{});
+    }
     switch (mm.variant) {
     case 1:
         hipLaunchKernelGGL((k_m2l_lowrank<C, 1>), g2, dim3(256), 0, st, mm.hdr, mm.src, mm.args, (C *)mm.tmp,

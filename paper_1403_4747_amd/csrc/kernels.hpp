@@ -40,8 +40,18 @@ struct M2LLevelArgs {
     int32_t kd = 0, ku = 0, rmax = 0, level = 0;
     int32_t ldt = 0;                        // scratch column stride: kd rounded up to a multiple of 4
                                             // (FP64 columns start on 64-byte boundaries)
+    int64_t zbase = 0;                      // many-column form: first Z element of the level per
+                                            // right-hand side (rmax rows per pair and column)
 };
-constexpr int kM2LVariants = 4;
+// Right-hand sides from which the merged M2L runs in its many-column form:
+// phase 1 stores Z = V^ S per pair, and a destination-major kernel sums
+// U^ Z over each incoming state's list on the matrix cores (the columns
+// make that product dense), so no kd-row scratch column is written per pair.
+#ifndef FDA_M2L_MANY_COLS
+#define FDA_M2L_MANY_COLS 16
+#endif
+constexpr int kM2LManyCols = FDA_M2L_MANY_COLS;
+constexpr int kM2LVariants = 4;  // ring-depth variants of the low-rank M2L kernel
 #ifndef FDA_P2P_SHORT_COLS
 #define FDA_P2P_SHORT_COLS 1024
 #endif
@@ -49,7 +59,7 @@ constexpr int kL2TChunk = 2048;  // incoming-state entries of a leaf staged in L
 constexpr int kP2PShortCols = FDA_P2P_SHORT_COLS;  // near-field rows up to this length: x staged in LDS
 constexpr int kP2PGroup = 16;  // lanes per near-field row in k_p2p
 constexpr int kP2PUnroll = 8;  // row loads in flight per lane in k_p2p (4: 0.077 ms, 8: 0.075 ms FP64 at N = 81,920)
-constexpr int kP2PItemEntries = 24576;  // near-field block entries per work item (at least 4 rows)  // ring-depth variants of the low-rank M2L kernel
+constexpr int kP2PItemEntries = 24576;  // near-field block entries per work item (at least 4 rows)
 
 struct M2LMerged {
     int nwork = 0, nred = 0, nlev = 0;
@@ -62,6 +72,14 @@ struct M2LMerged {
     // (kRedRows (state, row) entries each) and states rd_state[q] ..
     int32_t *rd_block = nullptr, *rd_state = nullptr;
     int nredblocks = 0;
+    // many-column form: per reduction-list entry (pair, translation, rank / 4,
+    // 0), per state the sum of its entries' rank / 4, and the units of the
+    // destination-major kernel (state, first of 4 row tiles, level slot, 0);
+    // nzunits = 0 when the form is not available
+    int4 *rd_ent = nullptr;
+    int32_t *rd_nst = nullptr;
+    int4 *zunits = nullptr;
+    int nzunits = 0;
     M2LLevelArgs *args = nullptr;          // device table, refreshed with the work buffers
     std::vector<M2LLevelArgs> hargs;
     void *tmp = nullptr;
