@@ -439,7 +439,7 @@ void build_m2l_list(fda_plan *p, M2LMerged &mm, std::vector<void *> &fresh) {
         for (int q = (int)args.size() - 1; q >= 0; --q) {
             const int nt = (args[q].kd + 15) / 16;
             for (int64_t s = 0; s < p->m2l_host[q].nstates; ++s)
-                for (int rt = 0; rt < nt; rt += 4) units.insert(units.end(), {rstate[q] + (int32_t)s, rt, q, 0});
+                for (int rt = 0; rt < nt; ++rt) units.insert(units.end(), {rstate[q] + (int32_t)s, rt, q, 0});
         }
     mm.nzunits = (int)(units.size() / 4);
     mm.nscratch = nscratch;

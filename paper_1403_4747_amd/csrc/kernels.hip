@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "kernels.hpp"
 
@@ -314,6 +315,17 @@ __device__ __forceinline__ RhsBlock rhs_block_chunked(int nrhs, int per) {
     const int b = blockIdx.x, x = b & 7, j = b >> 3;
     const int t = j / nrhs;
     return {x * per + t, j - t * nrhs};
+}
+// The same grid taken in groups of G right-hand sides: every item of the
+// XCD's queue (nq items) for the group's columns, then the next group, so
+// that the states gathered for one group's columns stay in the caches
+// while the group runs (G >= nrhs: the order of rhs_block).
+__device__ __forceinline__ RhsBlock rhs_block_grouped(int nrhs, int nq, int G) {
+    const int b = blockIdx.x, x = b & 7, j = b >> 3;
+    const int g = j / (nq * G), rem = j - g * nq * G;
+    const int gg = min(G, nrhs - g * G);
+    const int t = rem / gg;
+    return {t * 8 + x, g * G + (rem - t * gg)};
 }
 static inline dim3 rhs_grid(int64_t n, int nrhs) { return dim3((unsigned)(((n + 7) / 8) * 8 * nrhs)); }
 
@@ -1047,6 +1059,12 @@ __device__ __forceinline__ void m2l_body(const int4 h, const int32_t *sidx, cons
     }
 }
 
+#ifndef FDA_M2L_ZGROUP
+// right-hand sides per group of the many-column phase 1 (rhs_block_grouped);
+// 64 columns at N = 81,920, kD = 100 (FP64 phase 1): groups of 64 (item
+// after item, every column) 11.7 ms, 16: 10.4, 4: 8.7, 1: 9.2
+#define FDA_M2L_ZGROUP 4
+#endif
 // One launch for the low-rank M2L of every level: the item's level slot
 // (h.w) selects its factors, states and scratch region.  ZOUT: phase 1
 // only, Z of pair column c (level-local) and right-hand side j stored at
@@ -1066,7 +1084,7 @@ k_m2l_lowrank(const int4 *hdr, const int32_t *src, const M2LLevelArgs *args, C *
     C(*Z)[GG_LD] = (C(*)[GG_LD])smem;
     // the host ordered the items for round-robin XCD dispatch (item t * 8 + x
     // on XCD x); empty items pad the queues
-    const RhsBlock rb = rhs_block(nrhs);
+    const RhsBlock rb = ZOUT ? rhs_block_grouped(nrhs, (nwork + 7) >> 3, FDA_M2L_ZGROUP) : rhs_block(nrhs);
     const int w = rb.item;
     if (w >= nwork) return;
     const int4 h = hdr[w];
@@ -1093,14 +1111,19 @@ k_m2l_lowrank(const int4 *hdr, const int32_t *src, const M2LLevelArgs *args, C *
 // of state t of U^_p Z_p (U^_p: kd x r_p, Z_p: the pair's phase-1 product,
 // r_p x nrhs), accumulated on the matrix cores across the list and written
 // once; with many columns every U^ fragment meets 16 NCT of them, so the
-// destination-major order is dense.  Wave w of a workgroup owns row tile
-// units.y + w of the state (exiting when it lies past kd) and columns
+// destination-major order is dense.  Wave w of workgroup b owns unit
+// 4 b + w, one (state, row tile) of the list (consecutive units share their
+// state, so the waves of a workgroup mostly read the same Z), and columns
 // 16 NCT blockIdx.y ..; its k loop runs over the list's pairs in list
 // order, rank by rank, with the U^ and Z fragments loaded PD k-steps ahead
-// (a fetch cursor walks the entries; past the last step it re-reads that
-// step, never used).  No LDS, no barriers.
+// (a fetch cursor walks the entries, the next entry's scalar load issued one
+// pair ahead; past the last step it re-reads that step, never used).  No
+// LDS, no barriers.
 #ifndef FDA_M2L_DEST_PD
 #define FDA_M2L_DEST_PD 4
+#endif
+#ifndef FDA_M2L_DEST_NCT
+#define FDA_M2L_DEST_NCT 4  // largest column-tile count per wave
 #endif
 template <class C>
 struct M2LDestOcc {
@@ -1111,16 +1134,17 @@ struct M2LDestOcc<float2> {
     static constexpr int waves = 4;
 };
 template <class C, int NCT, int PD>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M2LDestOcc<C>::waves))) k_m2l_dest(const int4 *units, const int4 *ent, const int32_t *off,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M2LDestOcc<C>::waves))) k_m2l_dest(const int4 *units, int nunits, const int4 *ent, const int32_t *off,
                                                   const int32_t *nst, const int32_t *dst, const M2LLevelArgs *args,
                                                   const C *Zs, int nrhs) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int li = lane & 15, lk = lane >> 4;
-    const int4 un = units[blockIdx.x];  // (state, first row tile, level slot, 0)
+    const int u = (int)blockIdx.x * 4 + wave;
+    if (u >= nunits) return;
+    const int4 un = units[u];  // (state, row tile, level slot, 0)
     const M2LLevelArgs &la = args[un.z];
     const int kd = la.kd, rmax = la.rmax;
-    const int rt = un.y + wave;
-    if (rt * 16 >= kd) return;
+    const int rt = un.y;
     const int t = un.x;
     const int c0 = (int)blockIdx.y * 16 * NCT;
     const int64_t zp = (int64_t)nrhs * rmax;  // Z elements per pair
@@ -1139,6 +1163,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M2LDes
         int fe = off[t];
         const int last = off[t + 1] - 1;
         int4 en = ent[fe];  // (pair, translation, rank / 4, 0)
+        int4 nx = ent[min(fe + 1, last)];
         int fk = 0;
         const C *fa = U + en.y * ukd + arow + (int64_t)lk * kd;
         const C *fb = Zl + en.x * zp;
@@ -1148,7 +1173,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M2LDes
             for (int c = 0; c < NCT; ++c) b[c] = gload(fb + bo[c] + 4 * fk);
             if (++fk == en.z) {
                 if (fe < last) {
-                    en = ent[++fe];
+                    ++fe;
+                    en = nx;
+                    nx = ent[min(fe + 1, last)];
                     fk = 0;
                     fa = U + en.y * ukd + arow + (int64_t)lk * kd;
                     fb = Zl + en.x * zp;
@@ -1673,7 +1700,7 @@ template <class C>
 static hipError_t m2l_merged_t(const M2LMerged &mm, int nrhs, hipStream_t st, hipEvent_t *ev) {
     const dim3 g2 = rhs_grid(mm.nwork, nrhs);  // items ordered for XCD dispatch (or in translation order)
     if (ev) hipEventRecord(ev[0], st);
-    if (nrhs >= kM2LManyCols && mm.nzunits > 0) {
+    if (nrhs >= (std::is_same<C, double2>::value ? kM2LManyCols64 : kM2LManyCols32) && mm.nzunits > 0) {
         // many-column form: Z per pair, then the destination-major U^ Z
         hipLaunchKernelGGL((k_m2l_lowrank<C, 0, true>), g2, dim3(256), 0, st, mm.hdr, mm.src, mm.args, (C *)mm.tmp,
                            mm.nscratch, mm.nwork, nrhs);
@@ -1682,13 +1709,13 @@ static hipError_t m2l_merged_t(const M2LMerged &mm, int nrhs, hipStream_t st, hi
         constexpr int PD = FDA_M2L_DEST_PD;
         auto go = [&](auto nc) -> hipError_t {
             constexpr int NCT = decltype(nc)::value;
-            const dim3 g((unsigned)mm.nzunits, (unsigned)((nrhs + 16 * NCT - 1) / (16 * NCT)));
-            hipLaunchKernelGGL((k_m2l_dest<C, NCT, PD>), g, dim3(256), 0, st, mm.zunits, mm.rd_ent, mm.rd_off,
+            const dim3 g((unsigned)((mm.nzunits + 3) / 4), (unsigned)((nrhs + 16 * NCT - 1) / (16 * NCT)));
+            hipLaunchKernelGGL((k_m2l_dest<C, NCT, PD>), g, dim3(256), 0, st, mm.zunits, mm.nzunits, mm.rd_ent, mm.rd_off,
                                mm.rd_nst, mm.rd_dst, mm.args, (const C *)mm.tmp, nrhs);
             CHECK_LAUNCH();
             return hipSuccess;
         };
-        if (nrhs >= 64) return go(std::integral_constant<int, 4>{});
+        if (nrhs >= 64 && FDA_M2L_DEST_NCT >= 4) return go(std::integral_constant<int, 4>{});
         if (nrhs >= 32) return go(std::integral_constant<int, 2>{});
         return go(std::integral_constant<int, 1>{});
     }

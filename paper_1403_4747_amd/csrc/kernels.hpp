@@ -47,10 +47,16 @@ struct M2LLevelArgs {
 // phase 1 stores Z = V^ S per pair, and a destination-major kernel sums
 // U^ Z over each incoming state's list on the matrix cores (the columns
 // make that product dense), so no kd-row scratch column is written per pair.
-#ifndef FDA_M2L_MANY_COLS
-#define FDA_M2L_MANY_COLS 16
+// Products at N = 81,920, kD = 100: FP64 8 columns 6.60 ms against 7.10 in
+// the per-pair form, 16 columns 11.5 against 14.1; FP32 8 columns 4.29
+// against 4.24, 16 columns 7.50 against 8.18.
+#ifndef FDA_M2L_MANY_COLS64
+#define FDA_M2L_MANY_COLS64 8
 #endif
-constexpr int kM2LManyCols = FDA_M2L_MANY_COLS;
+#ifndef FDA_M2L_MANY_COLS32
+#define FDA_M2L_MANY_COLS32 16
+#endif
+constexpr int kM2LManyCols64 = FDA_M2L_MANY_COLS64, kM2LManyCols32 = FDA_M2L_MANY_COLS32;
 constexpr int kM2LVariants = 4;  // ring-depth variants of the low-rank M2L kernel
 #ifndef FDA_P2P_SHORT_COLS
 #define FDA_P2P_SHORT_COLS 1024
@@ -74,7 +80,7 @@ struct M2LMerged {
     int nredblocks = 0;
     // many-column form: per reduction-list entry (pair, translation, rank / 4,
     // 0), per state the sum of its entries' rank / 4, and the units of the
-    // destination-major kernel (state, first of 4 row tiles, level slot, 0);
+    // destination-major kernel, one per wave (state, row tile, level slot, 0);
     // nzunits = 0 when the form is not available
     int4 *rd_ent = nullptr;
     int32_t *rd_nst = nullptr;
