@@ -149,7 +149,9 @@ struct GWorkHost {
     }
 };
 
-GWork upload_gwork(fda_plan *p, const GWorkHost &g) {
+// m: rows of the list's matrices (the destination-major units are 16-row
+// tiles of every destination)
+GWork upload_gwork(fda_plan *p, const GWorkHost &g, int m) {
     GWork w;
     w.nwork = (int)(g.hdr.size() / 4);
     w.ncol = g.ncol;
@@ -170,6 +172,23 @@ GWork upload_gwork(fda_plan *p, const GWorkHost &g) {
     w.rd_dst = upload(p, g.dest);
     w.rd_off = upload(p, off);
     w.rd_list = upload(p, list);
+    // destination-major form: (matrix, source state) of every list entry
+    // (scratch column c is column c - first of its item)
+    std::vector<int32_t> mat(g.ncol), srcst(g.ncol), ent, units;
+    for (size_t i = 0; i < g.hdr.size() / 4; ++i)
+        for (int32_t b = 0; b < g.hdr[4 * i + 2]; ++b) {
+            mat[g.hdr[4 * i + 1] + b] = g.hdr[4 * i];
+            srcst[g.hdr[4 * i + 1] + b] = g.src[i * kGemmCols + b];
+        }
+    for (int32_t c : list) ent.insert(ent.end(), {mat[c], srcst[c]});
+    const int nt = (m + 15) / 16;
+    for (int32_t t = 0; t < w.nred; ++t)
+        for (int32_t rt = 0; rt < nt; ++rt) units.insert(units.end(), {t, rt});
+    if (p->d.prec != FDA_PREC_FP32 && !ent.empty() && !units.empty()) {  // FP64 plans only
+        w.dm_ent = (int2 *)upload(p, ent);
+        w.dm_units = (int2 *)upload(p, units);
+        w.dm_nunits = (int)(units.size() / 2);
+    }
     return w;
 }
 
@@ -665,7 +684,7 @@ void upload_plan(fda_plan *p, const HostOps &ops, DevTranslations &tr) {
                         g.add((int32_t)op, srcs, dsts);
                     }
                 }
-                dl.m2l = upload_gwork(p, g);
+                dl.m2l = upload_gwork(p, g, lv.kd);
             }
         }
         if (l < L) {
@@ -692,7 +711,7 @@ void upload_plan(fda_plan *p, const HostOps &ops, DevTranslations &tr) {
                             }
                     flush();
                 }
-            dl.m2m = upload_gwork(p, gm);
+            dl.m2m = upload_gwork(p, gm, lv.ku);
             p->m2m_flops += 8.0 * lv.ku * C.ku * (double)gm.ncol;
             // L2L: per (child octant, parent slot), the children in that
             // octant, in chunks; summed into the child slot fed by the parent slot
@@ -714,7 +733,7 @@ void upload_plan(fda_plan *p, const HostOps &ops, DevTranslations &tr) {
                         }
                     flush();
                 }
-            dl.l2l = upload_gwork(p, gl);
+            dl.l2l = upload_gwork(p, gl, C.kd);
             p->l2l_flops += 8.0 * C.kd * lv.kd * (double)gl.ncol;
         }
     }

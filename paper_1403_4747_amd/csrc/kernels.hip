@@ -327,6 +327,15 @@ __device__ __forceinline__ RhsBlock rhs_block_grouped(int nrhs, int nq, int G) {
     const int t = rem / gg;
     return {t * 8 + x, g * G + (rem - t * gg)};
 }
+// rhs_block_chunked taken in groups of G right-hand sides (every item of the
+// XCD's chunk for the group's columns, then the next group).
+__device__ __forceinline__ RhsBlock rhs_block_chunked_grouped(int nrhs, int per, int G) {
+    const int b = blockIdx.x, x = b & 7, j = b >> 3;
+    const int g = j / (per * G), rem = j - g * per * G;
+    const int gg = min(G, nrhs - g * G);
+    const int t = rem / gg;
+    return {x * per + t, g * G + (rem - t * gg)};
+}
 static inline dim3 rhs_grid(int64_t n, int nrhs) { return dim3((unsigned)(((n + 7) / 8) * 8 * nrhs)); }
 
 // Near field, S2M and L2T take R right-hand sides per workgroup (the
@@ -709,6 +718,9 @@ __device__ __forceinline__ void ggemm_body_staged(const int4 h, const int32_t *s
 }
 
 
+#ifndef FDA_GEMM_ZGROUP
+#define FDA_GEMM_ZGROUP 16  // right-hand sides per group of the gathered GEMM's block order
+#endif
 // Waves per SIMD the GEMM kernels are compiled for: FP64 needs more
 // registers per complex accumulator than FP32.
 #ifndef FDA_GEMM_WAVES64
@@ -770,7 +782,7 @@ k_ggemm(const int4 *hdr, const int32_t *src, const int32_t *dst, const C *A, int
     // one contiguous chunk of the work list per XCD (consecutive items
     // share their translation matrix; the bands of an item are consecutive)
     const int nunit = nwork * nband;
-    const RhsBlock rb = rhs_block_chunked(nrhs, (nunit + 7) / 8);
+    const RhsBlock rb = rhs_block_chunked_grouped(nrhs, (nunit + 7) / 8, FDA_GEMM_ZGROUP);
     if (rb.item >= nunit) return;
     const int w = rb.item / nband, bnd = rb.item - w * nband;
     const int band0 = nband == 1 ? 0 : bnd * SB, band1 = nband == 1 ? m : min(m, band0 + SB);
@@ -788,6 +800,126 @@ k_ggemm(const int4 *hdr, const int32_t *src, const int32_t *dst, const C *A, int
         ggemm_body_staged<C, 2, RT>(h, sidx, sd, At, m, kin, Xr, Tr, Yr, accumulate, band0, band1, S, As);
     else
         ggemm_body_staged<C, 1, RT>(h, sidx, sd, At, m, kin, Xr, Tr, Yr, accumulate, band0, band1, S, As);
+}
+
+// The destination-major kernels (k_ggemm_dest, k_m2l_dest): k-steps in
+// flight in the register ring, largest column-tile count per wave, and
+// waves per SIMD (FP64 keeps 96 accumulator registers at 64 columns).
+#ifndef FDA_M2L_DEST_PD
+#define FDA_M2L_DEST_PD 4
+#endif
+#ifndef FDA_M2L_DEST_NCT
+#define FDA_M2L_DEST_NCT 4
+#endif
+template <class C>
+struct M2LDestOcc {
+    static constexpr int waves = 2;
+};
+template <>
+struct M2LDestOcc<float2> {
+    static constexpr int waves = 4;
+};
+
+// The gathered GEMM of a list with a reduction, destination-major, for many
+// right-hand sides: y_t (+)= sum over the entries (matrix a, source s) of
+// destination t of A_a x_s, accumulated on the matrix cores across the
+// entries in list order and written once (no scratch columns, no
+// reduction launch).  Wave w of workgroup b owns unit 4 b + w, one
+// (destination, 16-row tile), and columns 16 NCT blockIdx.y ..; its k loop
+// runs over the entries, kin / 4 steps each (rounded up: the lanes past kin
+// load a clamped element and multiply it by a zero A fragment), with the A
+// and x fragments loaded PD steps ahead as in k_m2l_dest.
+template <class C, int NCT, int PD>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M2LDestOcc<C>::waves)))
+k_ggemm_dest(const int2 *units, int nunits, const int2 *ent, const int32_t *off, const int32_t *dstl, const C *A,
+             int m, int kin, const C *X, int64_t xstride, C *Y, int64_t ystride, int accumulate, int nrhs) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int li = lane & 15, lk = lane >> 4;
+    const int u = (int)blockIdx.x * 4 + wave;
+    if (u >= nunits) return;
+    const int2 un = units[u];  // (destination entry, row tile)
+    const int t = un.x, rt = un.y;
+    const int c0 = (int)blockIdx.y * 16 * NCT;
+    const int64_t mk = (int64_t)m * kin;
+    const int arow = min(rt * 16 + li, m - 1);
+    int64_t bo[NCT];
+#pragma unroll
+    for (int c = 0; c < NCT; ++c) bo[c] = (int64_t)min(c0 + c * 16 + li, nrhs - 1) * xstride;
+    CAcc<C> acc[NCT];
+#pragma unroll
+    for (int c = 0; c < NCT; ++c) acc[c].zero();
+    const int ks = (kin + 3) >> 2;  // k-steps per entry
+    const int e0 = off[t], last = off[t + 1] - 1;
+    const int ns = (last - e0 + 1) * ks;
+    if (ns > 0) {
+        int fe = e0, fk = 0;
+        int2 en = ent[fe];  // (matrix, source state)
+        int2 nx = ent[min(fe + 1, last)];
+        const C *fa = A + en.x * mk + arow;
+        const C *fb = X + (int64_t)en.y * kin;
+        auto fetch = [&](C &a, C (&b)[NCT], bool &live) {
+            const int k = 4 * fk + lk;
+            live = k < kin;
+            const int kc = min(k, kin - 1);
+            a = gload(fa + (int64_t)kc * m);
+#pragma unroll
+            for (int c = 0; c < NCT; ++c) b[c] = gload(fb + bo[c] + kc);
+            if (++fk == ks) {
+                if (fe < last) {
+                    ++fe;
+                    en = nx;
+                    nx = ent[min(fe + 1, last)];
+                    fk = 0;
+                    fa = A + en.x * mk + arow;
+                    fb = X + (int64_t)en.y * kin;
+                } else {
+                    fk = ks - 1;
+                }
+            }
+        };
+        auto use = [&](const C &a, const C (&b)[NCT], bool live) {
+            const C av = live ? a : czero<C>();
+#pragma unroll
+            for (int c = 0; c < NCT; ++c) acc[c].mac(av, b[c]);
+        };
+        C ar[PD], br[PD][NCT];
+        bool lv[PD];
+#pragma unroll
+        for (int d = 0; d < PD; ++d) fetch(ar[d], br[d], lv[d]);
+        int s = 0;
+        for (; s + PD <= ns; s += PD) {
+#pragma unroll
+            for (int d = 0; d < PD; ++d) {
+                use(ar[d], br[d], lv[d]);
+                fetch(ar[d], br[d], lv[d]);
+            }
+        }
+#pragma unroll
+        for (int d = 0; d < PD; ++d)
+            if (s + d < ns) use(ar[d], br[d], lv[d]);
+    }
+    C *yt = Y + (int64_t)dstl[t] * m;
+#pragma unroll
+    for (int c = 0; c < NCT; ++c) {
+        const int col = c0 + c * 16 + li;
+        if (col >= nrhs) continue;
+        C *o = yt + (int64_t)col * ystride;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = rt * 16 + CT<C>::row(lk, v);
+            if (row < m) {
+                C y;
+                y.x = acc[c].re(v);
+                y.y = acc[c].im(v);
+                if (accumulate) {
+                    const C old = o[row];
+                    y.x = old.x + y.x;
+                    y.y = old.y + y.y;
+                }
+                o[row] = y;
+            }
+        }
+    }
 }
 
 // Phase 1 of the low-rank M2L in the direct form: NQ row tiles of V^ (rows
@@ -1119,24 +1251,10 @@ k_m2l_lowrank(const int4 *hdr, const int32_t *src, const M2LLevelArgs *args, C *
 // (a fetch cursor walks the entries, the next entry's scalar load issued one
 // pair ahead; past the last step it re-reads that step, never used).  No
 // LDS, no barriers.
-#ifndef FDA_M2L_DEST_PD
-#define FDA_M2L_DEST_PD 4
-#endif
-#ifndef FDA_M2L_DEST_NCT
-#define FDA_M2L_DEST_NCT 4  // largest column-tile count per wave
-#endif
-template <class C>
-struct M2LDestOcc {
-    static constexpr int waves = 2;  // FP64: 96 accumulator registers at 64 columns
-};
-template <>
-struct M2LDestOcc<float2> {
-    static constexpr int waves = 4;
-};
 template <class C, int NCT, int PD>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M2LDestOcc<C>::waves))) k_m2l_dest(const int4 *units, int nunits, const int4 *ent, const int32_t *off,
-                                                  const int32_t *nst, const int32_t *dst, const M2LLevelArgs *args,
-                                                  const C *Zs, int nrhs) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M2LDestOcc<C>::waves)))
+k_m2l_dest(const int4 *units, int nunits, const int4 *ent, const int32_t *off, const int32_t *nst, const int32_t *dst,
+           const M2LLevelArgs *args, const C *Zs, int nrhs) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int li = lane & 15, lk = lane >> 4;
     const int u = (int)blockIdx.x * 4 + wave;
@@ -1675,6 +1793,26 @@ template <class C>
 static hipError_t ggemm_t(const GWork &g, const void *A, int m, int kin, const void *X, int64_t xstride, void *Y,
                           int64_t ystride, int accumulate, int nrhs, hipStream_t st, hipEvent_t *ev) {
     if (g.nwork == 0) return hipSuccess;
+    if constexpr (std::is_same<C, double2>::value) {
+        if (!g.dst && g.dm_nunits > 0 && nrhs >= kGemmDestCols64) {
+            // many columns (FP64): destination-major, no scratch and no reduction
+            if (ev) hipEventRecord(ev[0], st);
+            constexpr int PD = FDA_M2L_DEST_PD;
+            auto go = [&](auto nc) -> hipError_t {
+                constexpr int NCT = decltype(nc)::value;
+                const dim3 gr((unsigned)((g.dm_nunits + 3) / 4), (unsigned)((nrhs + 16 * NCT - 1) / (16 * NCT)));
+                hipLaunchKernelGGL((k_ggemm_dest<C, NCT, PD>), gr, dim3(256), 0, st, g.dm_units, g.dm_nunits, g.dm_ent,
+                                   g.rd_off, g.rd_dst, (const C *)A, m, kin, (const C *)X, xstride, (C *)Y, ystride,
+                                   accumulate, nrhs);
+                CHECK_LAUNCH();
+                if (ev) hipEventRecord(ev[1], st);
+                return hipSuccess;
+            };
+            if (nrhs >= 64 && FDA_M2L_DEST_NCT >= 4) return go(std::integral_constant<int, 4>{});
+            if (nrhs >= 32) return go(std::integral_constant<int, 2>{});
+            return go(std::integral_constant<int, 1>{});
+        }
+    }
     constexpr int SB = 64 * GemmShape<C>::rt;
     const int nband = GemmShape<C>::band_split ? (m + SB - 1) / SB : 1;
     // a multiple of 8 workgroups so every XCD runs the same share

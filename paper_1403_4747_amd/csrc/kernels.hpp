@@ -15,12 +15,17 @@ namespace fda {
 // When every destination receives exactly one product, dst lists each
 // item's destination states (kGemmCols per item) and the products are
 // written to them directly (no scratch, no reduction).
+// For many right-hand sides a list with a reduction runs destination-major
+// instead (k_ggemm_dest, FP64 plans): per reduction-list entry its (matrix,
+// source state), and one unit per wave (destination entry, 16-row tile).
 struct GWork {
     int nwork = 0, nred = 0;
     int64_t ncol = 0;
     int4 *hdr = nullptr;
     int32_t *src = nullptr, *dst = nullptr, *rd_dst = nullptr, *rd_off = nullptr, *rd_list = nullptr;
     void *tmp = nullptr;  // storage type of the plan (double2 or float2)
+    int2 *dm_ent = nullptr, *dm_units = nullptr;
+    int dm_nunits = 0;
 };
 
 constexpr int kGemmCols = 32;
@@ -57,6 +62,18 @@ struct M2LLevelArgs {
 #define FDA_M2L_MANY_COLS32 16
 #endif
 constexpr int kM2LManyCols64 = FDA_M2L_MANY_COLS64, kM2LManyCols32 = FDA_M2L_MANY_COLS32;
+// Right-hand sides from which M2M / L2L lists with a reduction run
+// destination-major (k_ggemm_dest) in FP64 plans.  At N = 81,920, kD = 100:
+// 64 columns 36.1 ms per product against 40.4 (M2M 8.9 against 11.3 ms,
+// L2L 10.1 against 12.2), 32 columns 19.0 against 20.7; at 16 columns
+// 11.1 against 10.9 and at 8 columns 7.7 against 6.3 (half of each 16-column
+// tile idle).  FP32 plans keep the staged gathered GEMM: the
+// destination-major form was slower at every column count (64 columns: M2M
+// 7.5 against 7.1 ms, L2L 8.5 against 7.7).
+#ifndef FDA_GEMM_DEST_COLS64
+#define FDA_GEMM_DEST_COLS64 32
+#endif
+constexpr int kGemmDestCols64 = FDA_GEMM_DEST_COLS64;
 constexpr int kM2LVariants = 4;  // ring-depth variants of the low-rank M2L kernel
 #ifndef FDA_P2P_SHORT_COLS
 #define FDA_P2P_SHORT_COLS 1024
