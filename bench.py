@@ -474,6 +474,17 @@ def main():
         multi = dict(nrhs=args.nrhs_multi, ms_per_matvec=round(msm, 4),
                      columns_per_s=round(args.nrhs_multi * 1000.0 / msm, 2),
                      col0_rel_diff_vs_single=float(torch.linalg.norm(ym[0] - y0) / torch.linalg.norm(y0)))
+        # per-stage times of the same product (every stage alone on one
+        # stream) and the matrix-core rate of its M2L, M2M and L2L stages:
+        # algorithmic flops of one column times the column count
+        pm = plan.profile(xm, reps=2, out=ym)
+        multi["stages_ms"] = {q: round(pm[q], 3) for q in ("near", "s2m", "m2m", "m2l", "l2l", "l2t", "perm", "total")}
+        m2l_fl = args.nrhs_multi * sum(float(f) for f in st["m2l_level_flops"])
+        rate = {"m2l": m2l_fl, "m2m": args.nrhs_multi * float(st["m2m_flops"]),
+                "l2l": args.nrhs_multi * float(st["l2l_flops"])}
+        multi["mfma_rate"] = {q: dict(tflops=round(f / (pm[q] * 1e-3) / 1e12, 2),
+                                      frac_of_fp64_peak=round(f / (pm[q] * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4))
+                              for q, f in rate.items() if pm[q] > 0}
         log(f"[bench] nrhs={args.nrhs_multi}: {multi}")
         del xm, ym
         if not args.no_solve:
