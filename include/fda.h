@@ -183,6 +183,11 @@ int fda_inspect(const double *verts, int64_t nv, const int32_t *tris, int64_t nt
  * stream the plan owns, concurrently with the far field, but it is ordered
  * after the work already on `stream` and the product completes on `stream`
  * (while `stream` is being captured into a graph everything stays on it).
+ * From 8 columns (FP64 plans; 16 in FP32 plans) the low-rank M2L sums its
+ * terms per incoming state in another order (and, from 32 columns in FP64
+ * plans, so do M2M and L2L), so a column of such a product equals the
+ * single-column product to rounding, not bit for bit; a given nrhs always
+ * gives the same bits.
  * Errors: FDA_EINVAL (nrhs < 1, nrhs > nrhs_max, ld < N, null pointers),
  * FDA_EHIP. */
 int fda_matvec(fda_plan *plan, const void *x_dev, void *y_dev, int64_t nrhs, int64_t ld, void *stream);
