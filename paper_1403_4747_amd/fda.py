@@ -278,7 +278,9 @@ class Plan:
         return out
 
     def matvec(self, x, out=None):
-        """y = A x (fda_matvec)."""
+        """y = A x (fda_matvec).  x: (N,) or (nrhs, N) complex128 on the
+        device; columns of a product of many columns (from 8 in FP64 plans,
+        16 in FP32 ones) equal the single-column products to rounding."""
         nrhs = self._check_vec(x, self.n)
         y = self._check_out(out, x)
         rc = library().fda_matvec(self._h, x.data_ptr(), y.data_ptr(), nrhs, self.n, _stream())
